@@ -1,0 +1,90 @@
+"""Dominant-index rotation-invariant MIM descriptor (Sections 2.2 and 3).
+
+For each keypoint (x, y):
+1. take the P x P MIM patch, rows y - P/2 .. y + P/2 - 1 and the same for
+   columns (P = 96, Table 1);
+2. split it into G x G cells (G = 6, Section 2.2) and count, per cell, how
+   many pixels carry each MIM value b in 0..N_o-1 -> h[cy][cx][b];
+3. the patch histogram Hist[b] = sum over cells; its peak gives the dominant
+   index s (Eq. 1; ties -> lowest index);
+4. recode every MIM value relative to s (Eq. 2, which in 0-based form is
+   MIM_n = (MIM - s) mod N_o); the recoded cell histograms are the
+   descriptor, desc[cy][cx][b] = h[cy][cx][(b + s) mod N_o], laid out
+   (cy, cx, b) row-major, D = G*G*N_o values;
+5. if the second-highest bin s2 (lowest index among ties, s2 != s) reaches
+   the dominant ratio of the peak (0.8, Table 1; tested exactly as
+   5 Hist[s2] >= 4 Hist[s]) a second descriptor is built with s2 (Section 3,
+   last paragraph).
+
+Descriptor values are integer counts; distances use the L2-normalised vector.
+Row order: all primary rows in keypoint order, then all secondary rows in
+keypoint order.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .params import DescParams
+
+__all__ = ["cell_histograms", "dominant", "recode_histogram", "recode_mim", "describe"]
+
+
+def cell_histograms(mim: np.ndarray, x: int, y: int, p: DescParams) -> np.ndarray:
+    """h[cy, cx, b] counts of the P x P patch centred (in the [-P/2, P/2) sense) on (x, y)."""
+    half = p.patch_size // 2
+    patch = mim[y - half:y + half, x - half:x + half].astype(np.int64)
+    if patch.shape != (p.patch_size, p.patch_size):
+        raise ValueError("patch leaves the image")
+    cell = p.patch_size // p.grid
+    cy = (np.arange(p.patch_size) // cell)[:, None]
+    cx = (np.arange(p.patch_size) // cell)[None, :]
+    idx = (cy * p.grid + cx) * p.n_orient + patch
+    h = np.bincount(idx.ravel(), minlength=p.grid * p.grid * p.n_orient)
+    return h.reshape(p.grid, p.grid, p.n_orient)
+
+
+def dominant(hist: np.ndarray, p: DescParams):
+    """(s, s2, has_second) of a patch histogram (Eq. 1 plus the 80 % rule)."""
+    hist = np.asarray(hist, dtype=np.int64)
+    s = int(np.argmax(hist))
+    rest = hist.copy()
+    rest[s] = -1
+    s2 = int(np.argmax(rest))
+    has2 = p.dominant_den * int(hist[s2]) >= p.dominant_num * int(hist[s])
+    return s, s2, bool(has2)
+
+
+def recode_mim(values: np.ndarray, s: int, n_orient: int) -> np.ndarray:
+    """Eq. 2 in the paper's 1-based form: v - s + 1 if v >= s else v + N_o - s + 1."""
+    v = np.asarray(values, dtype=np.int64)
+    return np.where(v >= s, v - s + 1, v + n_orient - s + 1)
+
+
+def recode_histogram(h: np.ndarray, s: int) -> np.ndarray:
+    """Bins b of the recoded histogram take the count of original bin (b + s) mod N_o."""
+    n = h.shape[-1]
+    return h[..., (np.arange(n) + s) % n]
+
+
+def describe(mim: np.ndarray, kpts: np.ndarray, p: DescParams = DescParams()):
+    """Descriptors of keypoints `kpts` (n, 2) [x, y] on a 0-based MIM.
+
+    Returns (counts uint16 (rows, D), kp_index int32 (rows,), shift int32 (rows,)).
+    """
+    prim = []
+    sec = []
+    for i, (x, y) in enumerate(np.asarray(kpts, dtype=np.int64)):
+        h = cell_histograms(mim, int(x), int(y), p)
+        hist = h.sum(axis=(0, 1))
+        s, s2, has2 = dominant(hist, p)
+        prim.append((i, s, recode_histogram(h, s).ravel()))
+        if has2:
+            sec.append((i, s2, recode_histogram(h, s2).ravel()))
+    rows = prim + sec
+    d = p.grid * p.grid * p.n_orient
+    if not rows:
+        return np.zeros((0, d), np.uint16), np.zeros((0,), np.int32), np.zeros((0,), np.int32)
+    counts = np.stack([r[2] for r in rows]).astype(np.uint16)
+    kp = np.array([r[0] for r in rows], dtype=np.int32)
+    sh = np.array([r[1] for r in rows], dtype=np.int32)
+    return counts, kp, sh

@@ -1,0 +1,232 @@
+"""Pins of the oracle's FAST detector, dominant-index descriptor and matcher.
+
+Pins: hand-built corner / edge maps, pure-Python brute force on tiny inputs,
+full sorts, the paper's worked histogram example (tests/golden), count
+invariants and the exact 90 degree grid law of the descriptor.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import DetectParams, DescParams, MatchParams
+from oracle import detect as dt
+from oracle import describe as ds
+from oracle import match as mt
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- detection
+
+def test_single_bright_pixel_is_a_corner_and_edge_is_not():
+    d = np.zeros((21, 21))
+    d[10, 10] = 1.0
+    sc = dt.fast_scores(d)
+    assert sc[10, 10] == 1.0
+    assert (dt.nms(sc, 0.001)).sum() == 1
+    e = np.zeros((24, 24))
+    e[:, 12:] = 1.0
+    sc = dt.fast_scores(e)
+    assert np.all(sc[3:-3, 3:-3] <= 0.0)
+
+
+def test_corner_of_a_square_is_detected():
+    d = np.zeros((32, 32))
+    d[10:, 10:] = 1.0   # the pixel (10, 10) sees 5 bright circle pixels, 11 dark
+    sc = dt.fast_scores(d)
+    assert sc[10, 10] > 0.5
+    assert sc[20, 20] <= 0.0
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_fast_scores_match_bruteforce(dtype):
+    rng = np.random.default_rng(10)
+    d = rng.uniform(0, 1, size=(17, 19)).astype(dtype)
+    sc = dt.fast_scores(d)
+    assert sc.dtype == dtype
+    for y in range(17):
+        for x in range(19):
+            if 3 <= y < 14 and 3 <= x < 16:
+                assert sc[y, x] == dt.fast_score_bruteforce(d, y, x)
+            else:
+                assert sc[y, x] == 0
+
+
+def _nms_bruteforce(score, t):
+    h, w = score.shape
+    keep = np.zeros_like(score, dtype=bool)
+    for y in range(h):
+        for x in range(w):
+            if not score[y, x] > t:
+                continue
+            ok = True
+            for yy in range(max(0, y - 1), min(h, y + 2)):
+                for xx in range(max(0, x - 1), min(w, x + 2)):
+                    if (yy, xx) == (y, x) or not score[yy, xx] > t:
+                        continue
+                    if score[yy, xx] > score[y, x] or (score[yy, xx] == score[y, x] and yy * w + xx < y * w + x):
+                        ok = False
+            keep[y, x] = ok
+    return keep
+
+
+def test_nms_matches_bruteforce_with_ties():
+    rng = np.random.default_rng(11)
+    s = rng.integers(0, 4, size=(15, 13)).astype(np.float32) / 4.0  # many exact ties
+    assert np.array_equal(dt.nms(s, 0.1), _nms_bruteforce(s, 0.1))
+
+
+def test_top_k_is_a_full_sort_prefix():
+    rng = np.random.default_rng(12)
+    h, w = 40, 30
+    s = rng.integers(1, 50, size=(h, w)).astype(np.float32) / 50.0
+    keep = rng.uniform(size=(h, w)) < 0.3
+    pts, sc = dt.top_k(s, keep, 25)
+    items = sorted(((-float(s[y, x]), y * w + x) for y in range(h) for x in range(w) if keep[y, x]))[:25]
+    assert [(int(p[1]) * w + int(p[0])) for p in pts] == [r for _, r in items]
+    assert np.array_equal(sc, np.array([-v for v, _ in items], dtype=np.float32))
+
+
+def test_border_mask_keeps_exactly_full_patches():
+    m = dt.border_mask(200, 180, 96)
+    ys, xs = np.nonzero(m)
+    assert ys.min() == 48 and ys.max() == 200 - 48 and xs.min() == 48 and xs.max() == 180 - 48
+
+
+def test_flat_map_has_no_keypoints():
+    pts, sc = dt.detect(np.full((128, 128), 3.0), DetectParams(max_keypoints=10))
+    assert pts.shape == (0, 2)
+
+
+# ---------------------------------------------------------------- description
+
+def test_paper_worked_histogram_example():
+    g = json.load(open(os.path.join(GOLDEN, "paper_histogram_example.json")))
+    p = DescParams(patch_size=36, grid=6, n_orient=g["n_orient"])
+    h1 = np.array(g["hist_initial_layer_1"])
+    h2 = np.array(g["hist_initial_layer_2"])
+    assert h1.sum() == g["patch_pixels"] == 36 * 36
+    s1, s21, two1 = ds.dominant(h1, p)
+    s2, s22, two2 = ds.dominant(h2, p)
+    assert s1 + 1 == g["dominant_index_one_based_layer_1"]
+    assert s2 + 1 == g["dominant_index_one_based_layer_2"]
+    assert list(ds.recode_histogram(h1, s1)) == g["recoded_hist"]
+    assert list(ds.recode_histogram(h2, s2)) == g["recoded_hist"]
+    assert two1 == g["second_descriptor"] and two2 == g["second_descriptor"]
+    # Eq. 2 with the second layer as the initial one (s = 2, one-based): 2 -> 1, 4 -> 3
+    for before, after in g["pointwise_layer1_to_layer2_one_based"]:
+        assert ds.recode_mim(np.array([before]), 2, 6)[0] == after
+    # Eq. 2 (one-based values, one-based s) equals the 0-based cyclic shift used by recode_histogram
+    for s in range(1, 7):
+        for v in range(1, 7):
+            assert ds.recode_mim(np.array([v]), s, 6)[0] - 1 == (v - s) % 6
+
+
+def test_paper_example_as_a_real_patch_descriptor():
+    """Build a 36x36 MIM patch with the example's histogram; relabelling the
+    initial layer (MIM - 1 mod N_o) leaves the descriptor unchanged."""
+    g = json.load(open(os.path.join(GOLDEN, "paper_histogram_example.json")))
+    p = DescParams(patch_size=36, grid=6, n_orient=6)
+    rng = np.random.default_rng(13)
+    vals = np.repeat(np.arange(6), g["hist_initial_layer_1"])
+    rng.shuffle(vals)
+    mim = np.zeros((60, 60), dtype=np.uint8)
+    mim[12:48, 12:48] = vals.reshape(36, 36)
+    kp = np.array([[30, 30]])
+    c1, _, sh1 = ds.describe(mim, kp, p)
+    mim2 = ((mim.astype(int) - 1) % 6).astype(np.uint8)
+    c2, _, sh2 = ds.describe(mim2, kp, p)
+    assert c1.shape == (1, 216)
+    assert np.array_equal(c1, c2)
+    assert sh1[0] == 2 and sh2[0] == 1
+    assert list(c1.reshape(36, 6).sum(axis=0)) == g["recoded_hist"]
+
+
+def test_counts_sum_to_patch_and_cells():
+    rng = np.random.default_rng(14)
+    mim = rng.integers(0, 6, size=(200, 210)).astype(np.uint8)
+    kp = np.array([[60, 70], [100, 150], [48, 48], [162, 152]])
+    c, kpi, sh = ds.describe(mim, kp, DescParams())
+    assert np.all(c.astype(int).sum(axis=1) == 96 * 96)
+    assert np.all(c.reshape(-1, 36, 6).astype(int).sum(axis=2) == 256)
+    assert list(kpi[:4]) == [0, 1, 2, 3]
+
+
+def test_second_descriptor_rule_is_exact_at_80_percent():
+    p = DescParams()
+    assert ds.dominant(np.array([0, 500, 400, 0, 0, 0]), p) == (1, 2, True)     # exactly 0.8
+    assert ds.dominant(np.array([0, 500, 399, 0, 0, 0]), p) == (1, 2, False)
+    assert ds.dominant(np.array([7, 3, 7, 0, 0, 0]), p) == (0, 2, True)         # tie -> lowest index
+
+
+def test_descriptor_rot90_grid_law():
+    """For a keypoint (x, y) of f, the descriptor of rot90(f) taken at
+    (x', y') = (y, W - x) is the original with its cell grid rotated:
+    desc'[ci][cj][b] = desc[cj][G-1-ci][b] (MIM values shifted by N_o/2)."""
+    rng = np.random.default_rng(15)
+    n = 160
+    mim = rng.integers(0, 6, size=(n, n))
+    mim[mim == 5] = 2  # make histograms uneven so dominant indices are untied
+    mim = mim.astype(np.uint8)
+    rmim = ((np.rot90(mim).astype(int) + 3) % 6).astype(np.uint8)
+    p = DescParams()
+    checked = 0
+    for (x, y) in [(60, 70), (80, 80), (100, 64), (70, 100)]:
+        c, _, _ = ds.describe(mim, np.array([[x, y]]), p)
+        hist = c[0].reshape(36, 6).sum(axis=0)
+        if np.sort(hist)[-1] == np.sort(hist)[-2]:
+            continue
+        cr, _, _ = ds.describe(rmim, np.array([[y, n - x]]), p)
+        a = c[0].reshape(6, 6, 6)
+        b = cr[0].reshape(6, 6, 6)
+        for ci in range(6):
+            for cj in range(6):
+                assert np.array_equal(b[ci, cj], a[cj, 5 - ci])
+        checked += 1
+    assert checked >= 3
+
+
+# ---------------------------------------------------------------- matching
+
+def _random_descriptors(rng, n_kp, d=216, dup=0.3):
+    base = rng.integers(0, 40, size=(n_kp, d))
+    rows = [base]
+    kp = list(range(n_kp))
+    extra = [i for i in range(n_kp) if rng.uniform() < dup]
+    if extra:
+        rows.append(np.roll(base[extra], 6, axis=1))
+        kp += extra
+    return np.concatenate(rows).astype(np.uint16), np.array(kp, dtype=np.int32)
+
+
+def test_match_equals_pure_python_bruteforce():
+    rng = np.random.default_rng(16)
+    ca, ka = _random_descriptors(rng, 25, d=24)
+    cb, kb = _random_descriptors(rng, 30, d=24)
+    # plant near-duplicates so that some rows pass the ratio test
+    cb[:10] = ca[:10] + rng.integers(0, 2, size=(10, 24))
+    got = mt.match(ca, ka, cb, kb, MatchParams())
+    ref = mt.match_bruteforce(ca, ka, cb, kb, MatchParams())
+    assert list(got[0]) == ref[0] and list(got[1]) == ref[1]
+    assert np.allclose(got[2], ref[2], rtol=1e-12, atol=1e-15)
+    assert len(ref[0]) >= 5
+
+
+def test_match_float32_agrees_with_float64_away_from_ties():
+    rng = np.random.default_rng(17)
+    ca, ka = _random_descriptors(rng, 200)
+    cb, kb = _random_descriptors(rng, 180)
+    cb[:50] = ca[:50]
+    a64 = mt.match(ca, ka, cb, kb, dtype=np.float64)
+    a32 = mt.match(ca, ka, cb, kb, dtype=np.float32)
+    assert list(a64[0]) == list(a32[0]) and list(a64[1]) == list(a32[1])
+
+
+def test_exact_dots_are_exact():
+    rng = np.random.default_rng(18)
+    c = rng.integers(0, 257, size=(6, 216))
+    d64 = c.astype(np.float64) @ c.astype(np.float64).T
+    d_int = c.astype(np.int64) @ c.astype(np.int64).T
+    assert np.array_equal(d64.astype(np.int64), d_int)
