@@ -1,0 +1,205 @@
+/*
+ * rift2.h -- C ABI of the MI355X (gfx950) RIFT2 hot-path library (librift2.so).
+ *
+ * RIFT2 (Li, Shi, Hu, Zhang, "RIFT2: Speeding-up RIFT with a New
+ * Rotation-Invariance Technique") matches multimodal images in three stages
+ * (Section 1; Fig. 1 workflow): keypoint detection on phase-congruency
+ * moment maps, description by a maximum index map (MIM) made rotation
+ * invariant by the dominant index of its patch histogram (Section 3,
+ * Eqs. 1-2), and brute-force nearest-neighbour matching (Section 4).
+ * The four compute calls below are those stages:
+ *
+ *   rift2_filter_mim  log-Gabor bank -> orientation amplitude sums -> MIM,
+ *                     phase congruency -> max/min moment maps
+ *   rift2_detect      FAST keypoints on a moment map
+ *   rift2_describe    dominant-index 6x6xN_o histogram descriptors
+ *   rift2_match       nearest-neighbour matching with a ratio test
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Pointers named *_dev and every image, map, keypoint, descriptor and
+ *   workspace pointer are DEVICE pointers on the current HIP device; the
+ *   caller owns all of them.  Parameter records are host pointers.
+ * - The library allocates no device memory.  Scratch space comes from the
+ *   caller as (workspace, workspace_bytes); size it with the matching
+ *   rift2_*_workspace_size call.  A workspace may be reused by consecutive
+ *   calls on one stream but not by calls that can overlap.
+ * - `stream` is a hipStream_t (NULL = default stream).  Calls only enqueue
+ *   work and return; arguments are validated on the host before anything is
+ *   enqueued.  Counts produced on the device (keypoints, descriptor rows,
+ *   matches) stay in device memory so stages chain without a host sync.
+ * - Images and maps are row-major H x W with x = column, y = row, 0-based.
+ * - Errors: RIFT2_ERR_INVALID_ARG (null pointer, bad parameter),
+ *   RIFT2_ERR_UNSUPPORTED (size or parameter outside what the kernels are
+ *   built for), RIFT2_ERR_WORKSPACE (workspace too small), RIFT2_ERR_DEVICE
+ *   (a HIP call or launch failed; device faults surface at the next
+ *   synchronisation).  On error nothing further is enqueued.
+ */
+#ifndef RIFT2_H
+#define RIFT2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RIFT2_OK = 0,
+  RIFT2_ERR_INVALID_ARG = 1,
+  RIFT2_ERR_UNSUPPORTED = 2,
+  RIFT2_ERR_WORKSPACE = 3,
+  RIFT2_ERR_DEVICE = 4
+} rift2_status;
+
+typedef enum { RIFT2_U8 = 0, RIFT2_U16 = 1, RIFT2_F32 = 2 } rift2_dtype;
+
+typedef enum { RIFT2_PREC_FP32 = 0, RIFT2_PREC_BF16 = 1 } rift2_precision;
+
+/* Log-Gabor bank and phase-congruency constants (Sections 2.1-2.2 name the
+ * log-Gabor convolution sequence and one-dimensional phase congruency per
+ * orientation; the paper prints no constants).  Filter of scale s and
+ * orientation o on DFT bin (k, l):
+ *   G = exp(-ln^2(r f0_s^-1) / (2 ln^2 sigma_onf)) * 1/(1 + (r/lp_cutoff)^(2 lp_order))
+ *       * exp(-dtheta^2 / (2 sigma_theta^2)),
+ *   f0_s = 1/(min_wavelength mult^s), theta_o = o pi / n_orient,
+ *   sigma_theta = (pi / n_orient) / dtheta_on_sigma, G = 0 at DC and on the
+ *   Nyquist row/column.  Supported: 2 <= n_scales <= 8, 2 <= n_orient <= 8. */
+typedef struct {
+  int32_t n_scales;
+  int32_t n_orient;
+  float min_wavelength;
+  float mult;
+  float sigma_onf;
+  float dtheta_on_sigma;
+  float lp_cutoff;
+  int32_t lp_order;
+  float k;      /* noise threshold: mean + k sigma of the noise energy */
+  float cutoff; /* frequency-spread cutoff of the sigmoid weight */
+  float g;      /* sigmoid gain */
+  float eps;
+} rift2_pc_params;
+
+/* FAST detector (Section 2.1; Table 1: threshold 0.001, 5000 keypoints,
+ * patch 96).  Points whose patch would leave the image are dropped. */
+typedef struct {
+  float fast_threshold;
+  int32_t max_keypoints;
+  int32_t patch_size;
+} rift2_detect_params;
+
+/* Descriptor (Section 2.2: 6x6 grid of N_o-bin MIM histograms; Section 3:
+ * dominant index and second MIM when the second peak reaches the dominant
+ * ratio, Table 1: 0.8).  The ratio is the exact fraction num/den. */
+typedef struct {
+  int32_t patch_size;
+  int32_t grid;
+  int32_t n_orient;
+  int32_t dominant_num;
+  int32_t dominant_den;
+} rift2_desc_params;
+
+/* Matching (Section 4: brute force, nearest feature distance) with a
+ * second-neighbour ratio test d1^2 < ratio_sq * d2^2. */
+typedef struct {
+  float ratio_sq;
+  int32_t precision; /* rift2_precision of the distance GEMM */
+} rift2_match_params;
+
+typedef struct {
+  int32_t x;
+  int32_t y;
+  float score;
+} rift2_keypoint;
+
+typedef struct {
+  int32_t kp_a;
+  int32_t kp_b;
+  float dist2;
+} rift2_correspondence;
+
+/* Defaults: n_scales 4, n_orient 6, min_wavelength 3, mult 2.1, sigma_onf
+ * 0.55, dtheta_on_sigma 1.2, lp 0.45/15, k 2, cutoff 0.5, g 10, eps 1e-4;
+ * FAST 0.001, 5000 keypoints, patch 96; grid 6, ratio 4/5; ratio_sq 0.81,
+ * FP32.  Any argument may be NULL. */
+void rift2_default_params(rift2_pc_params* pc, rift2_detect_params* det, rift2_desc_params* desc,
+                          rift2_match_params* match);
+
+const char* rift2_status_string(rift2_status s);
+
+/* Loads the constant tables (FFT twiddles) onto `device`.  Must be called
+ * once per device before the first compute call on it; idempotent. */
+rift2_status rift2_init(int device);
+
+/* Supported image sides are 2^a * 3^b in {256, 512, 768, 1024, 1536, 2048,
+ * 4096}; H and W may differ. */
+int rift2_size_supported(int n);
+
+/* Workspace byte counts (0 if the arguments are unsupported). */
+size_t rift2_filter_workspace_size(int H, int W, const rift2_pc_params* pc);
+size_t rift2_detect_workspace_size(int H, int W, const rift2_detect_params* det);
+size_t rift2_describe_workspace_size(int32_t kpt_cap);
+size_t rift2_match_workspace_size(int32_t cap_a, int32_t cap_b, int32_t D, const rift2_match_params* mp);
+
+/* Filter bank, MIM and moments of one image (Section 2.2: A_o = sum over
+ * scales of the response amplitudes, MIM = argmax_o A_o; Section 2.1: phase
+ * congruency per orientation and its max/min moment over orientation).
+ *   img         H x W pixels of type `dtype`, row pitch `pitch` elements
+ *   mim         H x W uint8, 0-based orientation index (ties -> lowest)
+ *   max_moment  H x W float, M
+ *   min_moment  H x W float, m (may be NULL)
+ *   amp_sums    n_orient x H x W float, A_o (may be NULL)
+ * Circular (periodic) convolution, raw pixel values. */
+rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t W, int64_t pitch,
+                              const rift2_pc_params* pc, uint8_t* mim, float* max_moment,
+                              float* min_moment, float* amp_sums, void* workspace,
+                              size_t workspace_bytes, void* stream);
+
+/* FAST keypoints on `moment` (H x W float, normally the max moment map):
+ * min-max normalisation to [0, 1], 16-pixel segment test with arc 9 and
+ * score = largest passing threshold, corner iff score > fast_threshold, 3x3
+ * non-maximum suppression (ties: lower raster index wins), patch-border
+ * mask, then the max_keypoints strongest by (score desc, y*W+x asc).
+ *   kpts        capacity det->max_keypoints, sorted strongest first
+ *   n_kpts_dev  device int32: number of keypoints written */
+rift2_status rift2_detect(const float* moment, int32_t H, int32_t W, const rift2_detect_params* det,
+                          rift2_keypoint* kpts, int32_t* n_kpts_dev, void* workspace,
+                          size_t workspace_bytes, void* stream);
+
+/* Dominant-index descriptors (Section 3, Eqs. 1-2) of the first *n_kpts_dev
+ * keypoints (at most kpt_cap) on a 0-based MIM.  Row layout: uint16 counts
+ * desc[row][(cy*grid + cx)*n_orient + b] = #{pixels of cell (cy, cx) whose
+ * MIM value is (b + s) mod n_orient}; primary rows (s = dominant index) for
+ * keypoints 0..n-1 come first, then the secondary rows (s = second peak)
+ * in keypoint order.  inv_norm[row] = fl(1 / fl(sqrt(sum counts^2))),
+ * desc_kp[row] = keypoint index.  desc_cap must be >= 2 * kpt_cap.
+ *   n_desc_dev  device int32: number of rows written */
+rift2_status rift2_describe(const uint8_t* mim, int32_t H, int32_t W, const rift2_keypoint* kpts,
+                            const int32_t* n_kpts_dev, int32_t kpt_cap, const rift2_desc_params* dp,
+                            uint16_t* desc, float* inv_norm, int32_t* desc_kp, int32_t desc_cap,
+                            int32_t* n_desc_dev, void* workspace, size_t workspace_bytes,
+                            void* stream);
+
+/* Brute-force matching of descriptor rows A against B (Section 4).  The
+ * squared distance of normalised count vectors is evaluated as
+ * t = fl(fl(dot * invA_i) * invB_j), d2 = fl(2 - 2t), with the dot product
+ * exact (integer counts; BF16 holds counts <= 256 exactly and FP32
+ * accumulation of sums < 2^24 is exact, so both precisions give the same
+ * dots).  Per A row: j1 = nearest row (ties -> lowest j), j2 = nearest row of
+ * a different B keypoint; accepted iff d2(j1) < fl(ratio_sq * d2(j2)).  Per A
+ * keypoint the accepted row with the smallest d2 (ties -> lowest row) is
+ * kept.  Output sorted by kp_a; capacity cap_a entries.
+ *   nA_dev, nB_dev  device int32 row counts (<= cap_a, cap_b)
+ *   n_out_dev       device int32: number of matches written */
+rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32_t* kp_a,
+                         const int32_t* nA_dev, int32_t cap_a, const uint16_t* desc_b,
+                         const float* inv_b, const int32_t* kp_b, const int32_t* nB_dev,
+                         int32_t cap_b, int32_t D, const rift2_match_params* mp, rift2_correspondence* out,
+                         int32_t* n_out_dev, void* workspace, size_t workspace_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RIFT2_H */

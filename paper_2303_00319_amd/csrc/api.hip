@@ -1,0 +1,530 @@
+// C ABI of librift2.so: argument validation, workspace layout, kernel launches.
+// The declarations and their documentation live in include/rift2.h.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+
+#include "../../include/rift2.h"
+#include "describe.hip"
+#include "detect.hip"
+#include "fft.hpp"
+#include "filter.hip"
+#include "match.hip"
+
+using namespace rift2;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Sequential carve of a workspace into aligned regions.
+struct Carver {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  }
+};
+
+bool size_ok(int n) {
+  switch (n) {
+    case 256: case 512: case 768: case 1024: case 1536: case 2048: case 4096: return true;
+    default: return false;
+  }
+}
+
+bool pc_ok(const rift2_pc_params* p) {
+  return p && p->n_scales >= 2 && p->n_scales <= kMaxScales && p->n_orient >= 2 && p->n_orient <= kMaxOrient &&
+         p->min_wavelength > 0.f && p->mult > 1.f && p->sigma_onf > 0.f && p->sigma_onf < 1.f &&
+         p->dtheta_on_sigma > 0.f && p->lp_cutoff > 0.f && p->lp_order >= 1 && p->lp_order <= 64 && p->eps > 0.f &&
+         std::isfinite(p->k) && std::isfinite(p->cutoff) && std::isfinite(p->g);
+}
+
+// Only the (N_s, N_o) combinations instantiated for pass B.
+bool pc_built(const rift2_pc_params* p) {
+  return (p->n_scales == 4 && p->n_orient == 6) || (p->n_scales == 5 && p->n_orient == 8) ||
+         (p->n_scales == 4 && p->n_orient == 8) || (p->n_scales == 5 && p->n_orient == 6);
+}
+
+struct FilterLayout {
+  size_t rrow, yplanes, a0, cand, zero, t32, t64, total;
+  int zero_words;
+};
+
+FilterLayout filter_layout(int H, int W, const rift2_pc_params* p) {
+  FilterLayout L;
+  const size_t hw = (size_t)H * W;
+  const int F = p->n_scales * p->n_orient;
+  Carver c;
+  L.rrow = c.take(hw * sizeof(float2));
+  L.yplanes = c.take(hw * F * sizeof(float2));
+  L.a0 = c.take(hw * p->n_orient * sizeof(float));
+  L.cand = c.take(hw * p->n_orient * sizeof(uint32_t));
+  L.zero_words = p->n_orient * kHist1 + 2 * p->n_orient;
+  L.zero = c.take((size_t)L.zero_words * sizeof(uint32_t));
+  L.t32 = c.take(p->n_orient * sizeof(float));
+  L.t64 = c.take(p->n_orient * sizeof(double));
+  L.total = c.off;
+  return L;
+}
+
+struct DetectLayout {
+  size_t hdr, hist, cand, sel, fin, total;
+  size_t cand_cap;
+};
+
+DetectLayout detect_layout(int H, int W, const rift2_detect_params* d) {
+  DetectLayout L;
+  Carver c;
+  L.cand_cap = (size_t)((H + 1) / 2) * ((W + 1) / 2);
+  L.hdr = c.take(64);
+  L.hist = c.take(kDetHistBins * sizeof(uint32_t));
+  L.cand = c.take(L.cand_cap * sizeof(uint64_t));
+  L.sel = c.take(L.cand_cap * sizeof(uint64_t));
+  L.fin = c.take((size_t)(d ? d->max_keypoints : 0) * sizeof(uint64_t) + 8);
+  L.total = c.off;
+  return L;
+}
+
+struct MatchLayout {
+  size_t ta, tb, part, best, rowj, rowd, total;
+  int dp, rows_a, rows_b, slices, slice_rows;
+};
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+MatchLayout match_layout(int cap_a, int cap_b, int D, int precision) {
+  MatchLayout L;
+  const bool bf = precision == RIFT2_PREC_BF16;
+  L.dp = bf ? round_up(D, 16) : round_up(D, 8);
+  L.rows_a = round_up(cap_a, 32);
+  L.rows_b = round_up(cap_b, 32);
+  const int blocks_x = (L.rows_a + 127) / 128;
+  // enough blocks to fill the chip (256 CUs x ~8 waves), slices of >= 2 tiles
+  int slices = (2048 + blocks_x - 1) / blocks_x;
+  const int max_slices = (L.rows_b + 63) / 64;
+  if (slices > max_slices) slices = max_slices;
+  if (slices < 1) slices = 1;
+  L.slice_rows = round_up((L.rows_b + slices - 1) / slices, 32);
+  L.slices = (L.rows_b + L.slice_rows - 1) / L.slice_rows;
+  const size_t el = bf ? 2 : 4;
+  Carver c;
+  L.ta = c.take((size_t)L.rows_a * L.dp * el);
+  L.tb = c.take((size_t)L.rows_b * L.dp * el);
+  L.part = c.take((size_t)L.rows_a * L.slices * 2 * kTopK * sizeof(int2));
+  L.best = c.take((size_t)cap_a * sizeof(uint64_t));
+  L.rowj = c.take((size_t)cap_a * sizeof(int32_t));
+  L.rowd = c.take((size_t)cap_a * sizeof(float));
+  L.total = c.off;
+  return L;
+}
+
+rift2_status launch_status() {
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? RIFT2_OK : RIFT2_ERR_DEVICE;
+}
+
+std::mutex g_init_mu;
+bool g_init_done[64] = {};
+
+}  // namespace
+
+// ---------------------------------------------------------------- kernel dispatch tables
+
+namespace {
+
+template <int W, int P, typename Tin>
+void launch_fwd_rows(const void* img, int64_t pitch, int H, float2* rrow, uint32_t* zero, int n_zero, hipStream_t st) {
+  constexpr int LINES = 256 / FftPlan<W, P>::T;
+  hipLaunchKernelGGL((k_fwd_rows<W, P, Tin>), dim3(H / LINES), dim3(256), 0, st, (const Tin*)img, pitch, H, rrow,
+                     zero, n_zero);
+}
+
+template <int W, int P>
+bool fwd_rows_dtype(int dtype, const void* img, int64_t pitch, int H, float2* rrow, uint32_t* zero, int n_zero,
+                    hipStream_t st) {
+  switch (dtype) {
+    case RIFT2_U8: launch_fwd_rows<W, P, uint8_t>(img, pitch, H, rrow, zero, n_zero, st); return true;
+    case RIFT2_U16: launch_fwd_rows<W, P, uint16_t>(img, pitch, H, rrow, zero, n_zero, st); return true;
+    case RIFT2_F32: launch_fwd_rows<W, P, float>(img, pitch, H, rrow, zero, n_zero, st); return true;
+    default: return false;
+  }
+}
+
+bool dispatch_fwd_rows(int W, int dtype, const void* img, int64_t pitch, int H, float2* rrow, uint32_t* zero,
+                       int n_zero, hipStream_t st) {
+  switch (W) {
+    case 256: return fwd_rows_dtype<256, 16>(dtype, img, pitch, H, rrow, zero, n_zero, st);
+    case 512: return fwd_rows_dtype<512, 16>(dtype, img, pitch, H, rrow, zero, n_zero, st);
+    case 768: return fwd_rows_dtype<768, 12>(dtype, img, pitch, H, rrow, zero, n_zero, st);
+    case 1024: return fwd_rows_dtype<1024, 16>(dtype, img, pitch, H, rrow, zero, n_zero, st);
+    case 1536: return fwd_rows_dtype<1536, 12>(dtype, img, pitch, H, rrow, zero, n_zero, st);
+    case 2048: return fwd_rows_dtype<2048, 16>(dtype, img, pitch, H, rrow, zero, n_zero, st);
+    case 4096: return fwd_rows_dtype<4096, 16>(dtype, img, pitch, H, rrow, zero, n_zero, st);
+    default: return false;
+  }
+}
+
+template <int H, int P, int C>
+void launch_pass_a(int W, const float2* rrow, const FilterConsts& fc, float2* y, hipStream_t st) {
+  // Split the orientations over grid.y until there are >= 512 blocks; each
+  // group recomputes the column DFT of its block (an extra read of Rrow).
+  const int xblocks = W / C;
+  int groups = (512 + xblocks - 1) / xblocks;
+  if (groups > fc.n_orient) groups = fc.n_orient;
+  if (groups < 1) groups = 1;
+  hipLaunchKernelGGL((k_pass_a<H, P, C>), dim3(xblocks, groups), dim3(C * (H / P)), 0, st, rrow, fc, y);
+}
+
+bool dispatch_pass_a(int H, int W, const float2* rrow, const FilterConsts& fc, float2* y, hipStream_t st) {
+  switch (H) {
+    case 256: launch_pass_a<256, 16, 16>(W, rrow, fc, y, st); return true;
+    case 512: launch_pass_a<512, 16, 16>(W, rrow, fc, y, st); return true;
+    case 768: launch_pass_a<768, 12, 8>(W, rrow, fc, y, st); return true;
+    case 1024: launch_pass_a<1024, 16, 8>(W, rrow, fc, y, st); return true;
+    case 1536: launch_pass_a<1536, 12, 4>(W, rrow, fc, y, st); return true;
+    case 2048: launch_pass_a<2048, 16, 4>(W, rrow, fc, y, st); return true;
+    case 4096: launch_pass_a<4096, 16, 2>(W, rrow, fc, y, st); return true;
+    default: return false;
+  }
+}
+
+template <int W, int P>
+void launch_noise_pre(int H, int n_orient, int n_scales, const float2* y, float* a0, uint32_t* hist1, hipStream_t st) {
+  constexpr int LINES = 256 / FftPlan<W, P>::T;
+  hipLaunchKernelGGL((k_noise_pre<W, P>), dim3(H / LINES, n_orient), dim3(256), 0, st, y, H, n_scales, a0, hist1);
+}
+
+bool dispatch_noise_pre(int W, int H, int n_orient, int n_scales, const float2* y, float* a0, uint32_t* hist1,
+                        hipStream_t st) {
+  switch (W) {
+    case 256: launch_noise_pre<256, 16>(H, n_orient, n_scales, y, a0, hist1, st); return true;
+    case 512: launch_noise_pre<512, 16>(H, n_orient, n_scales, y, a0, hist1, st); return true;
+    case 768: launch_noise_pre<768, 12>(H, n_orient, n_scales, y, a0, hist1, st); return true;
+    case 1024: launch_noise_pre<1024, 16>(H, n_orient, n_scales, y, a0, hist1, st); return true;
+    case 1536: launch_noise_pre<1536, 12>(H, n_orient, n_scales, y, a0, hist1, st); return true;
+    case 2048: launch_noise_pre<2048, 16>(H, n_orient, n_scales, y, a0, hist1, st); return true;
+    case 4096: launch_noise_pre<4096, 16>(H, n_orient, n_scales, y, a0, hist1, st); return true;
+    default: return false;
+  }
+}
+
+template <int W, int P, int NS, int NO>
+void launch_pass_b(int H, const float2* y, const PCConsts& pcc, const float* t_o, uint8_t* mim, float* mmax,
+                   float* mmin, float* amp, hipStream_t st) {
+  constexpr int BLK = row_block<W, P>();
+  constexpr int LINES = BLK / FftPlan<W, P>::T;
+  hipLaunchKernelGGL((k_pass_b<W, P, NS, NO>), dim3(H / LINES), dim3(BLK), 0, st, y, H, pcc, t_o, mim, mmax, mmin, amp);
+}
+
+template <int NS, int NO>
+bool pass_b_w(int W, int H, const float2* y, const PCConsts& pcc, const float* t_o, uint8_t* mim, float* mmax,
+              float* mmin, float* amp, hipStream_t st) {
+  switch (W) {
+    case 256: launch_pass_b<256, 8, NS, NO>(H, y, pcc, t_o, mim, mmax, mmin, amp, st); return true;
+    case 512: launch_pass_b<512, 8, NS, NO>(H, y, pcc, t_o, mim, mmax, mmin, amp, st); return true;
+    case 768: launch_pass_b<768, 12, NS, NO>(H, y, pcc, t_o, mim, mmax, mmin, amp, st); return true;
+    case 1024: launch_pass_b<1024, 8, NS, NO>(H, y, pcc, t_o, mim, mmax, mmin, amp, st); return true;
+    case 1536: launch_pass_b<1536, 12, NS, NO>(H, y, pcc, t_o, mim, mmax, mmin, amp, st); return true;
+    case 2048: launch_pass_b<2048, 8, NS, NO>(H, y, pcc, t_o, mim, mmax, mmin, amp, st); return true;
+    case 4096: launch_pass_b<4096, 8, NS, NO>(H, y, pcc, t_o, mim, mmax, mmin, amp, st); return true;
+    default: return false;
+  }
+}
+
+bool dispatch_pass_b(int ns, int no, int W, int H, const float2* y, const PCConsts& pcc, const float* t_o,
+                     uint8_t* mim, float* mmax, float* mmin, float* amp, hipStream_t st) {
+  if (ns == 4 && no == 6) return pass_b_w<4, 6>(W, H, y, pcc, t_o, mim, mmax, mmin, amp, st);
+  if (ns == 5 && no == 8) return pass_b_w<5, 8>(W, H, y, pcc, t_o, mim, mmax, mmin, amp, st);
+  if (ns == 4 && no == 8) return pass_b_w<4, 8>(W, H, y, pcc, t_o, mim, mmax, mmin, amp, st);
+  if (ns == 5 && no == 6) return pass_b_w<5, 6>(W, H, y, pcc, t_o, mim, mmax, mmin, amp, st);
+  return false;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" {
+
+void rift2_default_params(rift2_pc_params* pc, rift2_detect_params* det, rift2_desc_params* desc,
+                          rift2_match_params* match) {
+  if (pc) {
+    pc->n_scales = 4;
+    pc->n_orient = 6;
+    pc->min_wavelength = 3.0f;
+    pc->mult = 2.1f;
+    pc->sigma_onf = 0.55f;
+    pc->dtheta_on_sigma = 1.2f;
+    pc->lp_cutoff = 0.45f;
+    pc->lp_order = 15;
+    pc->k = 2.0f;
+    pc->cutoff = 0.5f;
+    pc->g = 10.0f;
+    pc->eps = 1e-4f;
+  }
+  if (det) {
+    det->fast_threshold = 0.001f;
+    det->max_keypoints = 5000;
+    det->patch_size = 96;
+  }
+  if (desc) {
+    desc->patch_size = 96;
+    desc->grid = 6;
+    desc->n_orient = 6;
+    desc->dominant_num = 4;
+    desc->dominant_den = 5;
+  }
+  if (match) {
+    match->ratio_sq = 0.81f;
+    match->precision = RIFT2_PREC_FP32;
+  }
+}
+
+const char* rift2_status_string(rift2_status s) {
+  switch (s) {
+    case RIFT2_OK: return "ok";
+    case RIFT2_ERR_INVALID_ARG: return "invalid argument";
+    case RIFT2_ERR_UNSUPPORTED: return "unsupported size or parameter";
+    case RIFT2_ERR_WORKSPACE: return "workspace too small";
+    case RIFT2_ERR_DEVICE: return "device error";
+    default: return "unknown status";
+  }
+}
+
+int rift2_size_supported(int n) { return size_ok(n) ? 1 : 0; }
+
+rift2_status rift2_init(int device) {
+  if (device < 0 || device >= 64) return RIFT2_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_init_mu);
+  if (g_init_done[device]) return RIFT2_OK;
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess) return RIFT2_ERR_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return RIFT2_ERR_DEVICE;
+  static float2 host_tw[kTwN];
+  for (int k = 0; k < kTwN; ++k) {
+    const double a = -2.0 * M_PI * (double)k / (double)kTwN;
+    host_tw[k] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  const hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(g_twiddle), host_tw, sizeof(host_tw), 0, hipMemcpyHostToDevice);
+  (void)hipSetDevice(prev);
+  if (e != hipSuccess) return RIFT2_ERR_DEVICE;
+  g_init_done[device] = true;
+  return RIFT2_OK;
+}
+
+size_t rift2_filter_workspace_size(int H, int W, const rift2_pc_params* pc) {
+  if (!size_ok(H) || !size_ok(W) || !pc_ok(pc)) return 0;
+  return filter_layout(H, W, pc).total;
+}
+
+size_t rift2_detect_workspace_size(int H, int W, const rift2_detect_params* det) {
+  if (H <= 0 || W <= 0 || !det || det->max_keypoints <= 0) return 0;
+  return detect_layout(H, W, det).total;
+}
+
+size_t rift2_describe_workspace_size(int32_t kpt_cap) {
+  if (kpt_cap <= 0) return 0;
+  return align_up((size_t)kpt_cap * sizeof(uint32_t));
+}
+
+size_t rift2_match_workspace_size(int32_t cap_a, int32_t cap_b, int32_t D, const rift2_match_params* mp) {
+  if (cap_a <= 0 || cap_b <= 0 || D <= 0 || !mp) return 0;
+  return match_layout(cap_a, cap_b, D, mp->precision).total;
+}
+
+rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t W, int64_t pitch,
+                              const rift2_pc_params* pc, uint8_t* mim, float* max_moment, float* min_moment,
+                              float* amp_sums, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!img || !pc || !mim || !max_moment || !workspace) return RIFT2_ERR_INVALID_ARG;
+  if (dtype != RIFT2_U8 && dtype != RIFT2_U16 && dtype != RIFT2_F32) return RIFT2_ERR_INVALID_ARG;
+  if (pitch < W) return RIFT2_ERR_INVALID_ARG;
+  if (!pc_ok(pc)) return RIFT2_ERR_INVALID_ARG;
+  if (!size_ok(H) || !size_ok(W) || !pc_built(pc)) return RIFT2_ERR_UNSUPPORTED;
+  const FilterLayout L = filter_layout(H, W, pc);
+  if (workspace_bytes < L.total) return RIFT2_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  float2* rrow = (float2*)(ws + L.rrow);
+  float2* yp = (float2*)(ws + L.yplanes);
+  float* a0 = (float*)(ws + L.a0);
+  uint32_t* cand = (uint32_t*)(ws + L.cand);
+  uint32_t* zero = (uint32_t*)(ws + L.zero);
+  uint32_t* hist1 = zero;
+  uint32_t* counters = zero + pc->n_orient * kHist1;
+  float* t32 = (float*)(ws + L.t32);
+  double* t64 = (double*)(ws + L.t64);
+
+  FilterConsts fc;
+  std::memset(&fc, 0, sizeof(fc));
+  fc.H = H;
+  fc.W = W;
+  fc.n_scales = pc->n_scales;
+  fc.n_orient = pc->n_orient;
+  const double ls = std::log((double)pc->sigma_onf);
+  fc.inv_2ln2_sigma = (float)(1.0 / (2.0 * ls * ls));
+  for (int s = 0; s < pc->n_scales; ++s)
+    fc.log_f0[s] = (float)std::log(1.0 / ((double)pc->min_wavelength * std::pow((double)pc->mult, (double)s)));
+  fc.lp_cutoff = pc->lp_cutoff;
+  fc.lp_order = pc->lp_order;
+  PCConsts pcc;
+  std::memset(&pcc, 0, sizeof(pcc));
+  for (int o = 0; o < pc->n_orient; ++o) {
+    const double th = o * M_PI / pc->n_orient;
+    fc.cos_o[o] = pcc.cos_o[o] = (float)std::cos(th);
+    fc.sin_o[o] = pcc.sin_o[o] = (float)std::sin(th);
+  }
+  const double sig_th = (M_PI / pc->n_orient) / (double)pc->dtheta_on_sigma;
+  fc.inv_2sig_theta2 = (float)(1.0 / (2.0 * sig_th * sig_th));
+  fc.inv_hw = (float)(1.0 / ((double)H * (double)W));
+  pcc.eps = pc->eps;
+  pcc.g = pc->g;
+  pcc.cutoff = pc->cutoff;
+  NoiseConsts nc;
+  nc.mult = pc->mult;
+  nc.k = pc->k;
+  nc.n_scales = pc->n_scales;
+
+  (void)hipGetLastError();
+  if (!dispatch_fwd_rows(W, dtype, img, pitch, H, rrow, zero, L.zero_words, st)) return RIFT2_ERR_UNSUPPORTED;
+  if (!dispatch_pass_a(H, W, rrow, fc, yp, st)) return RIFT2_ERR_UNSUPPORTED;
+  if (!dispatch_noise_pre(W, H, pc->n_orient, pc->n_scales, yp, a0, hist1, st)) return RIFT2_ERR_UNSUPPORTED;
+  const int hw = H * W;
+  const int chunks = std::max(1, std::min(128, hw / 8192));
+  hipLaunchKernelGGL(k_noise_sel, dim3(chunks, pc->n_orient), dim3(256), 0, st, a0, hw, hist1, cand, counters, nc, t32,
+                     t64);
+  if (!dispatch_pass_b(pc->n_scales, pc->n_orient, W, H, yp, pcc, t32, mim, max_moment, min_moment, amp_sums, st))
+    return RIFT2_ERR_UNSUPPORTED;
+  return launch_status();
+}
+
+rift2_status rift2_detect(const float* moment, int32_t H, int32_t W, const rift2_detect_params* det,
+                          rift2_keypoint* kpts, int32_t* n_kpts_dev, void* workspace, size_t workspace_bytes,
+                          void* stream) {
+  if (!moment || !det || !kpts || !n_kpts_dev || !workspace) return RIFT2_ERR_INVALID_ARG;
+  if (H < 8 || W < 8 || (int64_t)H * W >= (1ll << 31)) return RIFT2_ERR_INVALID_ARG;
+  if (!(det->fast_threshold >= 0.0f) || det->max_keypoints <= 0 || det->patch_size < 0 || (det->patch_size & 1))
+    return RIFT2_ERR_INVALID_ARG;
+  const DetectLayout L = detect_layout(H, W, det);
+  if (workspace_bytes < L.total) return RIFT2_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  uint32_t* hdr = (uint32_t*)(ws + L.hdr);
+  uint32_t* hist = (uint32_t*)(ws + L.hist);
+  uint64_t* cand = (uint64_t*)(ws + L.cand);
+  uint64_t* sel = (uint64_t*)(ws + L.sel);
+  uint64_t* fin = (uint64_t*)(ws + L.fin);
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(k_det_init, dim3(kDetHistBins / 256), dim3(256), 0, st, hdr, hist);
+  const int n = H * W;
+  hipLaunchKernelGGL(k_det_minmax, dim3(std::min(1024, (n + 255) / 256)), dim3(256), 0, st, moment, n, hdr);
+  hipLaunchKernelGGL(k_det_fast, dim3((W + kTileX - 1) / kTileX, (H + kTileY - 1) / kTileY), dim3(kTileX * kTileY), 0, st,
+                     moment, H, W, det->fast_threshold, det->patch_size / 2, hdr, hist, cand);
+  hipLaunchKernelGGL(k_det_select, dim3(64), dim3(256), 0, st, hdr, hist, cand, sel, fin, (uint32_t)det->max_keypoints);
+  hipLaunchKernelGGL(k_det_sort, dim3((det->max_keypoints + 255) / 256), dim3(256), 0, st, hdr, fin, W,
+                     (KeypointOut*)kpts, n_kpts_dev);
+  return launch_status();
+}
+
+rift2_status rift2_describe(const uint8_t* mim, int32_t H, int32_t W, const rift2_keypoint* kpts,
+                            const int32_t* n_kpts_dev, int32_t kpt_cap, const rift2_desc_params* dp, uint16_t* desc,
+                            float* inv_norm, int32_t* desc_kp, int32_t desc_cap, int32_t* n_desc_dev, void* workspace,
+                            size_t workspace_bytes, void* stream) {
+  if (!mim || !kpts || !n_kpts_dev || !dp || !desc || !inv_norm || !desc_kp || !n_desc_dev || !workspace)
+    return RIFT2_ERR_INVALID_ARG;
+  if (H <= 0 || W <= 0 || kpt_cap <= 0 || desc_cap < 2 * kpt_cap) return RIFT2_ERR_INVALID_ARG;
+  if (dp->dominant_num < 0 || dp->dominant_den <= 0) return RIFT2_ERR_INVALID_ARG;
+  if (workspace_bytes < rift2_describe_workspace_size(kpt_cap)) return RIFT2_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  uint32_t* info = (uint32_t*)workspace;
+  const int* kp = (const int*)kpts;
+  (void)hipGetLastError();
+  const int blocks2 = (kpt_cap + 255) / 256;
+  if (dp->patch_size == 96 && dp->grid == 6 && dp->n_orient == 6) {
+    constexpr int KPB = desc_kpb<96>();
+    hipLaunchKernelGGL((k_describe<96, 6, 6>), dim3((kpt_cap + KPB - 1) / KPB), dim3(96 * KPB), 0, st, mim, H, W, kp,
+                       n_kpts_dev, kpt_cap, dp->dominant_num, dp->dominant_den, desc, inv_norm, desc_kp, info);
+    hipLaunchKernelGGL((k_describe2<6, 6>), dim3(blocks2), dim3(256), 0, st, n_kpts_dev, kpt_cap, info, desc, inv_norm,
+                       desc_kp, n_desc_dev);
+  } else if (dp->patch_size == 96 && dp->grid == 6 && dp->n_orient == 8) {
+    constexpr int KPB = desc_kpb<96>();
+    hipLaunchKernelGGL((k_describe<96, 6, 8>), dim3((kpt_cap + KPB - 1) / KPB), dim3(96 * KPB), 0, st, mim, H, W, kp,
+                       n_kpts_dev, kpt_cap, dp->dominant_num, dp->dominant_den, desc, inv_norm, desc_kp, info);
+    hipLaunchKernelGGL((k_describe2<6, 8>), dim3(blocks2), dim3(256), 0, st, n_kpts_dev, kpt_cap, info, desc, inv_norm,
+                       desc_kp, n_desc_dev);
+  } else if (dp->patch_size == 64 && dp->grid == 4 && dp->n_orient == 6) {
+    constexpr int KPB = desc_kpb<64>();
+    hipLaunchKernelGGL((k_describe<64, 4, 6>), dim3((kpt_cap + KPB - 1) / KPB), dim3(64 * KPB), 0, st, mim, H, W, kp,
+                       n_kpts_dev, kpt_cap, dp->dominant_num, dp->dominant_den, desc, inv_norm, desc_kp, info);
+    hipLaunchKernelGGL((k_describe2<4, 6>), dim3(blocks2), dim3(256), 0, st, n_kpts_dev, kpt_cap, info, desc, inv_norm,
+                       desc_kp, n_desc_dev);
+  } else {
+    return RIFT2_ERR_UNSUPPORTED;
+  }
+  return launch_status();
+}
+
+rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32_t* kp_a, const int32_t* nA_dev,
+                         int32_t cap_a, const uint16_t* desc_b, const float* inv_b, const int32_t* kp_b,
+                         const int32_t* nB_dev, int32_t cap_b, int32_t D, const rift2_match_params* mp,
+                         rift2_correspondence* out, int32_t* n_out_dev, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!desc_a || !inv_a || !kp_a || !nA_dev || !desc_b || !inv_b || !kp_b || !nB_dev || !mp || !out || !n_out_dev ||
+      !workspace)
+    return RIFT2_ERR_INVALID_ARG;
+  if (cap_a <= 0 || cap_b <= 0 || D <= 0) return RIFT2_ERR_INVALID_ARG;
+  if (!(mp->ratio_sq > 0.0f) || (mp->precision != RIFT2_PREC_FP32 && mp->precision != RIFT2_PREC_BF16))
+    return RIFT2_ERR_INVALID_ARG;
+  if (D != 216 && D != 288) return RIFT2_ERR_UNSUPPORTED;
+  const MatchLayout L = match_layout(cap_a, cap_b, D, mp->precision);
+  if (workspace_bytes < L.total) return RIFT2_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  void* ta = ws + L.ta;
+  void* tb = ws + L.tb;
+  int2* part = (int2*)(ws + L.part);
+  uint64_t* best = (uint64_t*)(ws + L.best);
+  int32_t* rowj = (int32_t*)(ws + L.rowj);
+  float* rowd = (float*)(ws + L.rowd);
+  const bool bf = mp->precision == RIFT2_PREC_BF16;
+  (void)hipGetLastError();
+  if (bf) {
+    hipLaunchKernelGGL(k_match_prep<true>, dim3(512), dim3(256), 0, st, desc_a, nA_dev, cap_a, D, L.dp, L.rows_a, ta, best,
+                       cap_a);
+    hipLaunchKernelGGL(k_match_prep<true>, dim3(512), dim3(256), 0, st, desc_b, nB_dev, cap_b, D, L.dp, L.rows_b, tb,
+                       (uint64_t*)nullptr, 0);
+  } else {
+    hipLaunchKernelGGL(k_match_prep<false>, dim3(512), dim3(256), 0, st, desc_a, nA_dev, cap_a, D, L.dp, L.rows_a, ta, best,
+                       cap_a);
+    hipLaunchKernelGGL(k_match_prep<false>, dim3(512), dim3(256), 0, st, desc_b, nB_dev, cap_b, D, L.dp, L.rows_b, tb,
+                       (uint64_t*)nullptr, 0);
+  }
+  const dim3 grid((L.rows_a + 127) / 128, L.slices);
+  if (bf) {
+    if (L.dp == 224)
+      hipLaunchKernelGGL(k_match_gemm_bf16<224>, grid, dim3(256), 0, st, (const uint16_t*)ta, inv_a, nA_dev,
+                         (const uint16_t*)tb, inv_b, nB_dev, cap_a, cap_b, L.slice_rows, part);
+    else
+      hipLaunchKernelGGL(k_match_gemm_bf16<288>, grid, dim3(256), 0, st, (const uint16_t*)ta, inv_a, nA_dev,
+                         (const uint16_t*)tb, inv_b, nB_dev, cap_a, cap_b, L.slice_rows, part);
+  } else {
+    if (L.dp == 216)
+      hipLaunchKernelGGL(k_match_gemm_f32<216>, grid, dim3(256), 0, st, (const float*)ta, inv_a, nA_dev,
+                         (const float*)tb, inv_b, nB_dev, cap_a, cap_b, L.slice_rows, part);
+    else
+      hipLaunchKernelGGL(k_match_gemm_f32<288>, grid, dim3(256), 0, st, (const float*)ta, inv_a, nA_dev,
+                         (const float*)tb, inv_b, nB_dev, cap_a, cap_b, L.slice_rows, part);
+  }
+  hipLaunchKernelGGL(k_match_merge, dim3((cap_a + 255) / 256), dim3(256), 0, st, part, 2 * L.slices, nA_dev, kp_a, kp_b,
+                     mp->ratio_sq, cap_a, best, rowj, rowd);
+  hipLaunchKernelGGL(k_match_emit, dim3((cap_a + 255) / 256), dim3(256), 0, st, best, cap_a, rowj, rowd, kp_b,
+                     (MatchOut*)out, n_out_dev);
+  return launch_status();
+}
+
+}  // extern "C"

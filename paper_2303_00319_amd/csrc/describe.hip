@@ -1,0 +1,179 @@
+// Dominant-index MIM descriptor kernels (Section 2.2 histogram descriptor;
+// Section 3, Eqs. 1-2 and the second-peak rule).
+//
+//   k_describe    KPB keypoints per block, one thread per patch column: each
+//                 thread counts the MIM values of its column inside each cell
+//                 band with 8-bit fields of one 64-bit word (one shift-add per
+//                 pixel); the counts widen to 16-bit fields and are summed over
+//                 the cell's columns with lane shuffles.  The patch histogram
+//                 gives s (first argmax) and s2; the primary row is the cell
+//                 histograms cyclically shifted by s.
+//   k_describe2   secondary rows (shift s2) for keypoints whose second peak
+//                 reaches num/den of the first, placed after all primary rows
+//                 in keypoint order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rift2 {
+
+template <int P>
+constexpr int desc_kpb() { return (P % 64 == 0) ? 1 : (P % 32 == 0 ? 2 : 4); }
+
+template <int P, int G, int NO>
+__global__ void __launch_bounds__(P * desc_kpb<P>()) k_describe(const uint8_t* __restrict__ mim, int H, int W,
+                                                                const int* __restrict__ kpts /* x, y, score */,
+                                                                const int32_t* __restrict__ n_kpts, int kpt_cap,
+                                                                int dom_num, int dom_den, uint16_t* __restrict__ desc,
+                                                                float* __restrict__ inv_norm, int32_t* __restrict__ desc_kp,
+                                                                uint32_t* __restrict__ info) {
+  constexpr int KPB = desc_kpb<P>();
+  constexpr int CS = P / G;  // cell side, a power of two dividing 64
+  constexpr int D = G * G * NO;
+  static_assert(CS == 8 || CS == 16 || CS == 32, "cell side");
+  static_assert(NO >= 2 && NO <= 8, "orientations");
+  __shared__ uint32_t h[KPB][G * G][NO];
+  __shared__ uint32_t hist[KPB][NO];
+  __shared__ int sh_s[KPB], sh_delta[KPB], sh_two[KPB], sh_ok[KPB];
+  __shared__ uint32_t sh_n2[KPB];
+  const int local = threadIdx.x / P, x = threadIdx.x % P;
+  const int n = min(*n_kpts, kpt_cap);
+  const int i = blockIdx.x * KPB + local;
+  const bool active = i < n;
+  int kx = 0, ky = 0;
+  if (active) {
+    kx = kpts[3 * i];
+    ky = kpts[3 * i + 1];
+  }
+  const int px0 = kx - P / 2, py0 = ky - P / 2;
+  const bool inside = active && px0 >= 0 && py0 >= 0 && px0 + P <= W && py0 + P <= H;
+  if (x == 0) {
+    sh_ok[local] = inside;
+    sh_n2[local] = 0u;
+  }
+  for (int cy = 0; cy < G; ++cy) {
+    uint64_t cnt = 0;
+    if (inside) {
+      const uint8_t* src = mim + (size_t)(py0 + cy * CS) * W + px0 + x;
+#pragma unroll 8
+      for (int r = 0; r < CS; ++r) cnt += 1ull << (8 * (src[(size_t)r * W] & 7));
+    }
+    const uint32_t lo = (uint32_t)cnt, hi = (uint32_t)(cnt >> 32);
+    uint32_t w[4];
+    w[0] = (lo & 0xffu) | ((lo << 8) & 0xff0000u);
+    w[1] = ((lo >> 16) & 0xffu) | ((lo >> 8) & 0xff0000u);
+    w[2] = (hi & 0xffu) | ((hi << 8) & 0xff0000u);
+    w[3] = ((hi >> 16) & 0xffu) | ((hi >> 8) & 0xff0000u);
+    constexpr int NW = (NO + 1) / 2;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+#pragma unroll
+      for (int off = 1; off < CS; off <<= 1) w[q] += (uint32_t)__shfl_xor((int)w[q], off);
+    }
+    if ((x % CS) == 0) {
+      const int cx = x / CS;
+#pragma unroll
+      for (int b = 0; b < NO; ++b) h[local][cy * G + cx][b] = (w[b >> 1] >> (16 * (b & 1))) & 0xffffu;
+    }
+  }
+  __syncthreads();
+  if (x < NO) {
+    uint32_t s = 0;
+    for (int c = 0; c < G * G; ++c) s += h[local][c][x];
+    hist[local][x] = s;
+  }
+  __syncthreads();
+  if (x == 0) {
+    int s = 0;
+    for (int b = 1; b < NO; ++b)
+      if (hist[local][b] > hist[local][s]) s = b;
+    int s2 = (s == 0) ? 1 : 0;
+    for (int b = 0; b < NO; ++b)
+      if (b != s && hist[local][b] > hist[local][s2]) s2 = b;
+    const bool two = sh_ok[local] &&
+                     (uint64_t)dom_den * hist[local][s2] >= (uint64_t)dom_num * hist[local][s];
+    sh_s[local] = s;
+    sh_delta[local] = (s2 - s + NO) % NO;
+    sh_two[local] = two;
+  }
+  __syncthreads();
+  const int s = sh_s[local];
+  uint32_t n2 = 0;
+  if (active) {
+    uint16_t* row = desc + (size_t)i * D;
+    for (int e = x; e < D; e += P) {
+      const int c = e / NO, b = e % NO;
+      int bb = b + s;
+      if (bb >= NO) bb -= NO;
+      const uint32_t v = h[local][c][bb];
+      row[e] = (uint16_t)v;
+      n2 += v * v;
+    }
+  }
+  atomicAdd(&sh_n2[local], n2);
+  __syncthreads();
+  if (active && x == 0) {
+    const uint32_t nn = sh_n2[local];
+    inv_norm[i] = nn ? __fdiv_rn(1.0f, __fsqrt_rn((float)nn)) : 0.0f;
+    desc_kp[i] = i;
+    info[i] = sh_two[local] ? (0x100u | (uint32_t)sh_delta[local]) : 0u;
+  }
+}
+
+// Secondary rows: row n + (number of flagged keypoints before i).
+template <int G, int NO>
+__global__ void __launch_bounds__(256) k_describe2(const int32_t* __restrict__ n_kpts, int kpt_cap,
+                                                   const uint32_t* __restrict__ info, uint16_t* __restrict__ desc,
+                                                   float* __restrict__ inv_norm, int32_t* __restrict__ desc_kp,
+                                                   int32_t* __restrict__ n_desc) {
+  constexpr int D = G * G * NO;
+  __shared__ uint32_t red[256];
+  __shared__ int flagged[256];
+  __shared__ int nflag;
+  const int n = min(*n_kpts, kpt_cap);
+  const int start = blockIdx.x * 256;
+  if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) *n_desc = 0;
+  if (start >= n) return;
+  // flags before this block
+  uint32_t before = 0;
+  for (int j = threadIdx.x; j < start; j += 256) before += (info[j] >> 8) & 1u;
+  red[threadIdx.x] = before;
+  if (threadIdx.x == 0) nflag = 0;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  const uint32_t base = red[0];
+  __syncthreads();
+  // ordered list of this block's flagged keypoints (serial scan keeps keypoint order)
+  if (threadIdx.x == 0) {
+    int c = 0;
+    const int end = min(n, start + 256);
+    for (int j = start; j < end; ++j)
+      if ((info[j] >> 8) & 1u) flagged[c++] = j;
+    nflag = c;
+    if (end == n) *n_desc = n + (int)base + c;
+  }
+  __syncthreads();
+  for (int f = 0; f < nflag; ++f) {
+    const int i = flagged[f];
+    const int delta = (int)(info[i] & 0xffu);
+    const int row = n + (int)base + f;
+    const uint16_t* src = desc + (size_t)i * D;
+    uint16_t* dst = desc + (size_t)row * D;
+    for (int e = threadIdx.x; e < D; e += 256) {
+      const int c = e / NO, b = e % NO;
+      int bb = b + delta;
+      if (bb >= NO) bb -= NO;
+      dst[e] = src[c * NO + bb];
+    }
+    if (threadIdx.x == 0) {
+      inv_norm[row] = inv_norm[i];
+      desc_kp[row] = i;
+    }
+  }
+}
+
+}  // namespace rift2

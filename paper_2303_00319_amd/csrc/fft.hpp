@@ -1,0 +1,263 @@
+// Register-blocked Stockham FFT for one line held by a team of T threads.
+//
+// A line of N complex points is spread over T = N / P threads, thread t
+// holding x[t + T*m], m = 0..P-1 ("strided layout").  Each radix-R stage runs
+// P/R butterflies per thread entirely in registers; between stages the line
+// is exchanged through LDS (separate real / imaginary arrays, padded one word
+// per 16 to spread banks).  The Stockham autosort ordering makes the first
+// stage read and the last stage write the strided layout directly, so a
+// transform costs (#stages - 1) LDS round trips and the result of X[k]
+// lands on thread k % T, register k / T -- natural order, coalesced for
+// global stores.
+//
+// DIR = -1: X[k] = sum_n x[n] e^{-2 pi i nk/N};  DIR = +1: the unscaled inverse.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rift2 {
+
+// Twiddle table: e^{-2 pi i k / kTwN}; kTwN is divisible by every supported N.
+constexpr int kTwN = 12288;
+__device__ float2 g_twiddle[kTwN];
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// a * e^{DIR i pi/2}
+template <int DIR>
+__device__ __forceinline__ float2 mul_quarter(float2 a) {
+  return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+}
+
+// cos(2 pi m / 16) for m = 0..15
+__host__ __device__ constexpr float cos16(int m) {
+  return (m & 15) == 0 ? 1.0f
+       : (m & 15) == 1 ? 0.92387953251128674f
+       : (m & 15) == 2 ? 0.70710678118654752f
+       : (m & 15) == 3 ? 0.38268343236508977f
+       : (m & 15) == 4 ? 0.0f
+       : (m & 15) == 5 ? -0.38268343236508977f
+       : (m & 15) == 6 ? -0.70710678118654752f
+       : (m & 15) == 7 ? -0.92387953251128674f
+       : (m & 15) == 8 ? -1.0f
+       : (m & 15) == 9 ? -0.92387953251128674f
+       : (m & 15) == 10 ? -0.70710678118654752f
+       : (m & 15) == 11 ? -0.38268343236508977f
+       : (m & 15) == 12 ? 0.0f
+       : (m & 15) == 13 ? 0.38268343236508977f
+       : (m & 15) == 14 ? 0.70710678118654752f
+                        : 0.92387953251128674f;
+}
+
+// a * e^{DIR 2 pi i M / 16}, trivial angles without multiplications
+template <int DIR, int M>
+__device__ __forceinline__ float2 rot16(float2 a) {
+  constexpr int m = M & 15;
+  if constexpr (m == 0) {
+    return a;
+  } else if constexpr (m == 4) {
+    return mul_quarter<DIR>(a);
+  } else if constexpr (m == 8) {
+    return make_float2(-a.x, -a.y);
+  } else if constexpr (m == 12) {
+    return mul_quarter<-DIR>(a);
+  } else {
+    constexpr float c = cos16(m);
+    constexpr float s = DIR * cos16(m + 12);  // DIR * sin(2 pi m / 16)
+    return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+  }
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft2(float2& a, float2& b) {
+  const float2 t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2& x3) {
+  const float2 t0 = cadd(x0, x2), t1 = csub(x0, x2);
+  const float2 t2 = cadd(x1, x3), t3 = mul_quarter<DIR>(csub(x1, x3));
+  x0 = cadd(t0, t2);
+  x2 = csub(t0, t2);
+  x1 = cadd(t1, t3);
+  x3 = csub(t1, t3);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft3(float2& a, float2& b, float2& c) {
+  constexpr float kS3 = 0.86602540378443865f;  // sqrt(3)/2
+  const float2 t1 = cadd(b, c);
+  const float2 t2 = make_float2(a.x - 0.5f * t1.x, a.y - 0.5f * t1.y);
+  const float2 d = csub(b, c);
+  // DIR * i * sqrt(3)/2 * (b - c)
+  const float2 t3 = DIR < 0 ? make_float2(kS3 * d.y, -kS3 * d.x) : make_float2(-kS3 * d.y, kS3 * d.x);
+  a = cadd(a, t1);
+  b = cadd(t2, t3);
+  c = csub(t2, t3);
+}
+
+// In-register R-point DFT in natural order (R in {2, 3, 4, 8, 16}).
+template <int DIR, int R>
+__device__ __forceinline__ void dft(float2 (&u)[R]) {
+  if constexpr (R == 2) {
+    dft2<DIR>(u[0], u[1]);
+  } else if constexpr (R == 3) {
+    dft3<DIR>(u[0], u[1], u[2]);
+  } else if constexpr (R == 4) {
+    dft4<DIR>(u[0], u[1], u[2], u[3]);
+  } else if constexpr (R == 8) {
+    // n = 2 n1 + n2: DFT4 over n1, twiddle w8^(n2 k1), DFT2 over n2 -> X[k1 + 4 k2]
+    dft4<DIR>(u[0], u[2], u[4], u[6]);
+    dft4<DIR>(u[1], u[3], u[5], u[7]);
+    const float2 a0 = u[0], a1 = u[2], a2 = u[4], a3 = u[6];
+    const float2 b0 = u[1], b1 = rot16<DIR, 2>(u[3]), b2 = rot16<DIR, 4>(u[5]), b3 = rot16<DIR, 6>(u[7]);
+    u[0] = cadd(a0, b0);
+    u[4] = csub(a0, b0);
+    u[1] = cadd(a1, b1);
+    u[5] = csub(a1, b1);
+    u[2] = cadd(a2, b2);
+    u[6] = csub(a2, b2);
+    u[3] = cadd(a3, b3);
+    u[7] = csub(a3, b3);
+  } else if constexpr (R == 16) {
+    // n = 4 n1 + n2: DFT4 over n1 (k1), twiddle w16^(n2 k1), DFT4 over n2 (k2) -> X[k1 + 4 k2]
+    dft4<DIR>(u[0], u[4], u[8], u[12]);
+    dft4<DIR>(u[1], u[5], u[9], u[13]);
+    dft4<DIR>(u[2], u[6], u[10], u[14]);
+    dft4<DIR>(u[3], u[7], u[11], u[15]);
+    // a[n2][k1] = u[n2 + 4 k1]
+    float2 c0[4] = {u[0], u[1], rot16<DIR, 0>(u[2]), u[3]};
+    float2 c1[4] = {u[4], rot16<DIR, 1>(u[5]), rot16<DIR, 2>(u[6]), rot16<DIR, 3>(u[7])};
+    float2 c2[4] = {u[8], rot16<DIR, 2>(u[9]), rot16<DIR, 4>(u[10]), rot16<DIR, 6>(u[11])};
+    float2 c3[4] = {u[12], rot16<DIR, 3>(u[13]), rot16<DIR, 6>(u[14]), rot16<DIR, 9>(u[15])};
+    dft4<DIR>(c0[0], c0[1], c0[2], c0[3]);
+    dft4<DIR>(c1[0], c1[1], c1[2], c1[3]);
+    dft4<DIR>(c2[0], c2[1], c2[2], c2[3]);
+    dft4<DIR>(c3[0], c3[1], c3[2], c3[3]);
+    // c_{k1}[k2] -> X[k1 + 4 k2]
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+      u[0 + 4 * k2] = c0[k2];
+      u[1 + 4 * k2] = c1[k2];
+      u[2 + 4 * k2] = c2[k2];
+      u[3 + 4 * k2] = c3[k2];
+    }
+  }
+}
+
+// Radix plans: N = product of radices, every radix divides P.
+template <int N, int P>
+struct FftPlan;
+
+#define RIFT2_PLAN(N_, P_, NR_, R0, R1, R2, R3, R4, R5)                          \
+  template <>                                                                  \
+  struct FftPlan<N_, P_> {                                                     \
+    static constexpr int N = N_, P = P_, T = N_ / P_, NR = NR_;                \
+    static constexpr int rad(int i) {                                          \
+      return i == 0 ? R0 : i == 1 ? R1 : i == 2 ? R2 : i == 3 ? R3 : i == 4 ? R4 : R5; \
+    }                                                                          \
+  };
+
+RIFT2_PLAN(256, 16, 2, 16, 16, 1, 1, 1, 1)
+RIFT2_PLAN(512, 16, 3, 16, 16, 2, 1, 1, 1)
+RIFT2_PLAN(1024, 16, 3, 16, 16, 4, 1, 1, 1)
+RIFT2_PLAN(2048, 16, 3, 16, 16, 8, 1, 1, 1)
+RIFT2_PLAN(4096, 16, 3, 16, 16, 16, 1, 1, 1)
+RIFT2_PLAN(768, 12, 5, 4, 4, 4, 4, 3, 1)
+RIFT2_PLAN(1536, 12, 6, 4, 4, 4, 4, 2, 3)
+RIFT2_PLAN(256, 8, 3, 8, 8, 4, 1, 1, 1)
+RIFT2_PLAN(512, 8, 3, 8, 8, 8, 1, 1, 1)
+RIFT2_PLAN(1024, 8, 4, 8, 8, 8, 2, 1, 1)
+RIFT2_PLAN(2048, 8, 4, 8, 8, 8, 4, 1, 1)
+RIFT2_PLAN(4096, 8, 4, 8, 8, 8, 8, 1, 1)
+#undef RIFT2_PLAN
+
+// Padded LDS index: one spare word per 16 keeps radix-16 strides off one bank.
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+template <int N>
+constexpr int lds_line() { return N + N / 16; }
+
+// Twiddle e^{DIR 2 pi i m / N}, 0 <= m < N.
+template <int DIR, int N>
+__device__ __forceinline__ float2 twiddle(int m) {
+  int idx = m * (kTwN / N);
+  // Keep the table read inside the loop that uses it: hoisting every stage's
+  // twiddles out of the filter loops costs more registers than the reloads.
+  asm volatile("" : "+v"(idx));
+  float2 w = g_twiddle[idx];
+  if (DIR > 0) w.y = -w.y;
+  return w;
+}
+
+template <int DIR, int N, int T, int P, int R, int NS>
+__device__ __forceinline__ void fft_stage(float2 (&v)[P], int t) {
+  constexpr int NB = P / R;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    float2 u[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[r] = v[b + r * NB];
+    if constexpr (NS > 1) {
+      const int jm = (t + T * b) % NS;
+      constexpr int step = N / (NS * R);
+#pragma unroll
+      for (int r = 1; r < R; ++r) u[r] = cmul(u[r], twiddle<DIR, N>(r * jm * step));
+    }
+    dft<DIR, R>(u);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[b + r * NB] = u[r];
+  }
+}
+
+// Write stage outputs to their Stockham positions, read back the strided layout.
+template <int N, int T, int P, int R, int NS>
+__device__ __forceinline__ void fft_exchange(float2 (&v)[P], int t, float* sre, float* sim) {
+  constexpr int NB = P / R;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = t + T * b;
+    const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int pos = lds_pad(base + r * NS);
+      sre[pos] = v[b + r * NB].x;
+      sim[pos] = v[b + r * NB].y;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    const int pos = lds_pad(t + T * m);
+    v[m] = make_float2(sre[pos], sim[pos]);
+  }
+  __syncthreads();
+}
+
+template <int DIR, class PL, int S, int NS>
+__device__ __forceinline__ void fft_run(float2 (&v)[PL::P], int t, float* sre, float* sim) {
+  if constexpr (S < PL::NR) {
+    constexpr int R = PL::rad(S);
+    fft_stage<DIR, PL::N, PL::T, PL::P, R, NS>(v, t);
+    if constexpr (S + 1 < PL::NR) {
+      fft_exchange<PL::N, PL::T, PL::P, R, NS>(v, t, sre, sim);
+      fft_run<DIR, PL, S + 1, NS * R>(v, t, sre, sim);
+    }
+  }
+}
+
+// Transform one line in the strided layout.  Every thread of the block must
+// call this (it contains block barriers); sre/sim are this team's LDS line.
+template <int DIR, int N, int P>
+__device__ __forceinline__ void fft_line(float2 (&v)[P], int t, float* sre, float* sim) {
+  fft_run<DIR, FftPlan<N, P>, 0, 1>(v, t, sre, sim);
+}
+
+}  // namespace rift2

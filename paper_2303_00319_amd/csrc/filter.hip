@@ -1,0 +1,435 @@
+// Filter-bank / MIM / moment kernels (Sections 2.1 and 2.2 of the paper).
+//
+// Data flow for one H x W image, F = N_s * N_o filters:
+//   k_fwd_rows   image -> Rrow = row DFTs                          (row-major complex)
+//   k_pass_a     per column block: column DFT of Rrow -> spectrum S in
+//                registers; for every filter: S * G_{s,o} / (HW), inverse
+//                column DFT, transpose through LDS -> Y_{s,o}      (row-major complex)
+//   k_noise_pre  row IDFT of the s = 0 planes -> A0_o = |EO_{0,o}| and a
+//                12-bit radix histogram of its float bits per orientation
+//   k_noise_sel  exact median of A0_o (radix select over the candidate bin)
+//                and the noise threshold T_o, evaluated in FP64
+//   k_pass_b     per row: row IDFT of all F planes, per-pixel phase
+//                congruency, amplitude sums, MIM argmax and moments
+#pragma once
+
+#include "fft.hpp"
+
+namespace rift2 {
+
+constexpr int kMaxOrient = 8;
+constexpr int kMaxScales = 8;
+constexpr int kHistBits1 = 12;  // level-1 key: float bits >> 19 (sign 0, 8 exponent, 3 mantissa)
+constexpr int kHist1 = 1 << kHistBits1;
+
+// Threads per block for row kernels: whole lines, at least 256 threads.
+template <int N, int P>
+constexpr int row_block() { return (N / P) >= 256 ? (N / P) : 256; }
+
+struct FilterConsts {
+  int H, W, n_scales, n_orient;
+  float log_f0[kMaxScales];    // ln(f0_s)
+  float inv_2ln2_sigma;        // 1 / (2 ln^2 sigma_onf)
+  float lp_cutoff;
+  int lp_order;
+  float cos_o[kMaxOrient], sin_o[kMaxOrient];
+  float inv_2sig_theta2;       // 1 / (2 sigma_theta^2)
+  float inv_hw;                // 1 / (H W), folded into the filter
+};
+
+struct PCConsts {
+  float eps, g, cutoff;
+  float cos_o[kMaxOrient], sin_o[kMaxOrient];
+};
+
+// ---------------------------------------------------------------- forward rows
+
+template <int W, int P, typename Tin>
+__global__ void __launch_bounds__(256) k_fwd_rows(const Tin* __restrict__ img, int64_t pitch, int H,
+                                                  float2* __restrict__ rrow, uint32_t* __restrict__ zero,
+                                                  int n_zero) {
+  using PL = FftPlan<W, P>;
+  constexpr int T = PL::T;
+  constexpr int LINES = 256 / T;
+  constexpr int LP = lds_line<W>();
+  __shared__ float sre[LINES][LP];
+  __shared__ float sim[LINES][LP];
+  if (blockIdx.x == 0) {
+    for (int i = threadIdx.x; i < n_zero; i += blockDim.x) zero[i] = 0u;
+  }
+  const int team = threadIdx.x / T, t = threadIdx.x % T;
+  const int y = blockIdx.x * LINES + team;  // H % LINES == 0 (checked on the host)
+  const Tin* row = img + (int64_t)y * pitch;
+  float2 v[P];
+#pragma unroll
+  for (int m = 0; m < P; ++m) v[m] = make_float2((float)row[t + T * m], 0.0f);
+  fft_line<-1, W, P>(v, t, sre[team], sim[team]);
+  float2* out = rrow + (size_t)y * W;
+#pragma unroll
+  for (int m = 0; m < P; ++m) out[t + T * m] = v[m];
+}
+
+// ---------------------------------------------------------------- pass A
+
+// Log-Gabor value factors of one DFT bin that do not depend on (s, o).
+struct BinGeom {
+  float lr;    // ln r
+  float lpn;   // low-pass * 1/(HW), 0 at DC and on Nyquist lines
+  float ct, st;  // cos theta, sin theta with theta = atan2(-v, u)
+};
+
+__device__ __forceinline__ BinGeom bin_geom(int k, int l, const FilterConsts& fc) {
+  BinGeom g;
+  const int kt = (k >= (fc.H + 1) / 2) ? k - fc.H : k;
+  const int lt = (l >= (fc.W + 1) / 2) ? l - fc.W : l;
+  const float v = (float)kt / (float)fc.H;
+  const float u = (float)lt / (float)fc.W;
+  const float r = sqrtf(u * u + v * v);
+  const bool dead = (kt == 0 && lt == 0) || ((fc.H & 1) == 0 && kt == -fc.H / 2) ||
+                    ((fc.W & 1) == 0 && lt == -fc.W / 2);
+  if (dead) {
+    g.lr = 0.0f;
+    g.lpn = 0.0f;
+    g.ct = 1.0f;
+    g.st = 0.0f;
+    return g;
+  }
+  g.lr = logf(r);
+  const float q = r / fc.lp_cutoff;
+  float qp = 1.0f;
+  for (int i = 0; i < 2 * fc.lp_order; ++i) qp *= q;
+  g.lpn = fc.inv_hw / (1.0f + qp);
+  g.ct = u / r;
+  g.st = -v / r;
+  return g;
+}
+
+__device__ __forceinline__ float angular(const BinGeom& g, int o, const FilterConsts& fc) {
+  const float ds = g.st * fc.cos_o[o] - g.ct * fc.sin_o[o];
+  const float dc = g.ct * fc.cos_o[o] + g.st * fc.sin_o[o];
+  const float dth = fabsf(atan2f(ds, dc));
+  return expf(-dth * dth * fc.inv_2sig_theta2);
+}
+
+__device__ __forceinline__ float radial(const BinGeom& g, int s, const FilterConsts& fc) {
+  const float d = g.lr - fc.log_f0[s];
+  return expf(-d * d * fc.inv_2ln2_sigma);
+}
+
+// One block = C adjacent columns, one team of T threads per column.
+template <int H, int P, int C>
+__global__ void __launch_bounds__(C * (H / P)) k_pass_a(const float2* __restrict__ rrow, FilterConsts fc,
+                                                      float2* __restrict__ y_out) {
+  using PL = FftPlan<H, P>;
+  constexpr int T = PL::T;
+  constexpr int NT = C * T;
+  constexpr int LP = lds_line<H>();
+  __shared__ float sre[C][LP];
+  __shared__ float sim[C][LP];
+  const int W = fc.W;
+  const int team = threadIdx.x / T, t = threadIdx.x % T;
+  const int l0 = blockIdx.x * C;
+  const int l = l0 + team;
+  // Column tile -> LDS, one column per team, natural order.
+  for (int i = threadIdx.x; i < H * C; i += NT) {
+    const int c = i % C, y = i / C;
+    const float2 val = rrow[(size_t)y * W + l0 + c];
+    sre[c][lds_pad(y)] = val.x;
+    sim[c][lds_pad(y)] = val.y;
+  }
+  __syncthreads();
+  float2 spec[P];
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    const int pos = lds_pad(t + T * m);
+    spec[m] = make_float2(sre[team][pos], sim[team][pos]);
+  }
+  __syncthreads();
+  fft_line<-1, H, P>(spec, t, sre[team], sim[team]);  // spec[m] = S[k = t + T m][l]
+
+  const size_t plane = (size_t)H * W;
+  // orientation group of this block (grid.y splits the bank for parallelism)
+  const int o_beg = (int)(blockIdx.y * fc.n_orient / gridDim.y);
+  const int o_end = (int)((blockIdx.y + 1) * fc.n_orient / gridDim.y);
+  for (int o = o_beg; o < o_end; ++o) {
+    float ang[P], lr[P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      const BinGeom geo = bin_geom(t + T * m, l, fc);
+      ang[m] = angular(geo, o, fc) * geo.lpn;
+      lr[m] = geo.lr;
+    }
+    for (int s = 0; s < fc.n_scales; ++s) {
+      const float lf0 = fc.log_f0[s];
+      float2 v[P];
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        const float d = lr[m] - lf0;
+        v[m] = cscale(spec[m], expf(-d * d * fc.inv_2ln2_sigma) * ang[m]);
+      }
+      fft_line<+1, H, P>(v, t, sre[team], sim[team]);
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        const int pos = lds_pad(t + T * m);
+        sre[team][pos] = v[m].x;
+        sim[team][pos] = v[m].y;
+      }
+      __syncthreads();
+      float2* dst = y_out + (size_t)(o * fc.n_scales + s) * plane;
+      for (int i = threadIdx.x; i < H * C; i += NT) {
+        const int c = i % C, y = i / C;
+        dst[(size_t)y * W + l0 + c] = make_float2(sre[c][lds_pad(y)], sim[c][lds_pad(y)]);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------- noise pre-pass
+
+// Block = LINES rows of one orientation.  A0 = |EO_{0,o}| written as float,
+// level-1 histogram of its bit pattern (bits >> 19) merged into hist1[o].
+template <int W, int P>
+__global__ void __launch_bounds__(256) k_noise_pre(const float2* __restrict__ y_in, int H, int n_scales,
+                                                   float* __restrict__ a0, uint32_t* __restrict__ hist1) {
+  using PL = FftPlan<W, P>;
+  constexpr int T = PL::T;
+  constexpr int LINES = 256 / T;
+  constexpr int LP = lds_line<W>();
+  __shared__ float sre[LINES][LP];
+  __shared__ float sim[LINES][LP];
+  __shared__ uint32_t hist[kHist1];
+  const int o = blockIdx.y;
+  for (int i = threadIdx.x; i < kHist1; i += 256) hist[i] = 0u;
+  const int team = threadIdx.x / T, t = threadIdx.x % T;
+  const int y = blockIdx.x * LINES + team;
+  const size_t plane = (size_t)H * W;
+  const float2* src = y_in + (size_t)(o * n_scales) * plane + (size_t)y * W;
+  float2 v[P];
+#pragma unroll
+  for (int m = 0; m < P; ++m) v[m] = src[t + T * m];
+  fft_line<+1, W, P>(v, t, sre[team], sim[team]);  // contains barriers: hist init is visible after
+  float* dst = a0 + (size_t)o * plane + (size_t)y * W;
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    const float a = sqrtf(v[m].x * v[m].x + v[m].y * v[m].y);
+    dst[t + T * m] = a;
+    atomicAdd(&hist[min(__float_as_uint(a) >> (32 - kHistBits1 - 1), (uint32_t)(kHist1 - 1))], 1u);
+  }
+  __syncthreads();
+  uint32_t* gh = hist1 + (size_t)o * kHist1;
+  for (int i = threadIdx.x; i < kHist1; i += 256) {
+    const uint32_t c = hist[i];
+    if (c) atomicAdd(&gh[i], c);
+  }
+}
+
+// Block-wide exclusive search: first bin b with cumulative count > rank.
+// Returns b and the count of values in bins < b.  blockDim.x == 256.
+__device__ void find_rank_bin(const uint32_t* hist, int nbins, uint32_t rank, int* out_bin, uint32_t* out_below,
+                              uint32_t* scratch /* 256 */) {
+  const int per = nbins / 256;
+  uint32_t sum = 0;
+  for (int i = 0; i < per; ++i) sum += hist[threadIdx.x * per + i];
+  scratch[threadIdx.x] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    int chunk = 0;
+    while (chunk < 255 && acc + scratch[chunk] <= rank) acc += scratch[chunk++];
+    int b = chunk * per;
+    while (b < chunk * per + per - 1 && acc + hist[b] <= rank) acc += hist[b++];
+    *out_bin = b;
+    *out_below = acc;
+  }
+  __syncthreads();
+}
+
+// Exact median of A0_o (mean of ranks HW/2-1 and HW/2) and T_o.
+// grid = (chunks, N_o), block 256.  Every block finds the level-1 bins of the
+// two ranks, appends the values of those bins to cand[o]; the last block to
+// finish runs the remaining radix levels on the candidate list.
+struct NoiseConsts {
+  double mult, k;
+  int n_scales;
+};
+
+__global__ void __launch_bounds__(256) k_noise_sel(const float* __restrict__ a0, int hw,
+                                                   const uint32_t* __restrict__ hist1, uint32_t* __restrict__ cand,
+                                                   uint32_t* __restrict__ counters, NoiseConsts nc,
+                                                   float* __restrict__ t_out, double* __restrict__ t_out64) {
+  __shared__ uint32_t scratch[256];
+  __shared__ uint32_t hist[1024];
+  __shared__ int s_bin[2];
+  __shared__ uint32_t s_below[2];
+  __shared__ int s_last;
+  const int o = blockIdx.y;
+  const int n_orient = gridDim.y;
+  uint32_t* cnt = counters + o;
+  uint32_t* done = counters + n_orient + o;
+  const uint32_t* gh = hist1 + (size_t)o * kHist1;
+  const uint32_t rank[2] = {(uint32_t)(hw / 2 - 1), (uint32_t)(hw / 2)};
+  for (int q = 0; q < 2; ++q) find_rank_bin(gh, kHist1, rank[q], &s_bin[q], &s_below[q], scratch);
+  const uint32_t b0 = (uint32_t)s_bin[0], b1 = (uint32_t)s_bin[1];
+  const float* src = a0 + (size_t)o * hw;
+  uint32_t* list = cand + (size_t)o * hw;
+  const int per_block = (hw + gridDim.x - 1) / gridDim.x;
+  const int beg = blockIdx.x * per_block;
+  const int end = min(hw, beg + per_block);
+  for (int i0 = beg; i0 < end; i0 += 256) {
+    const int i = i0 + threadIdx.x;
+    uint32_t bits = 0;
+    bool take = false;
+    if (i < end) {
+      bits = __float_as_uint(src[i]);
+      const uint32_t key = bits >> (32 - kHistBits1 - 1);
+      take = (key == b0) || (key == b1);
+    }
+    // wave-aggregated append
+    const uint64_t mask = __ballot(take);
+    const int lane = threadIdx.x & 63;
+    const int nwave = __popcll(mask);
+    uint32_t base = 0;
+    if (nwave) {
+      const int leader = __ffsll((unsigned long long)mask) - 1;
+      if (lane == leader) base = atomicAdd(cnt, (uint32_t)nwave);
+      base = __shfl(base, leader);
+      if (take) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = bits;
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = (atomicAdd(done, 1u) == gridDim.x - 1);
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  const uint32_t n = __atomic_load_n(cnt, __ATOMIC_RELAXED);
+  float vals[2];
+  for (int q = 0; q < 2; ++q) {
+    const uint32_t bin = (uint32_t)s_bin[q];
+    uint32_t r = rank[q] - s_below[q];  // rank inside the level-1 bin
+    uint32_t prefix = bin;              // known high bits, right-aligned
+    int known = kHistBits1 + 1;         // bits determined so far (incl. sign)
+    const int levels[2] = {10, 9};      // remaining 19 bits
+    for (int lv = 0; lv < 2; ++lv) {
+      const int nb = levels[lv];
+      const int shift = 32 - known - nb;
+      for (int i = threadIdx.x; i < 1024; i += 256) hist[i] = 0u;
+      __syncthreads();
+      for (uint32_t i = threadIdx.x; i < n; i += 256) {
+        const uint32_t bits = __atomic_load_n(&list[i], __ATOMIC_RELAXED);
+        if ((bits >> (32 - known)) == prefix) atomicAdd(&hist[(bits >> shift) & ((1u << nb) - 1u)], 1u);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        int b = 0;
+        while (b < (1 << nb) - 1 && acc + hist[b] <= r) acc += hist[b++];
+        s_bin[q] = b;
+        s_below[q] = acc;
+      }
+      __syncthreads();
+      r -= s_below[q];
+      prefix = (prefix << nb) | (uint32_t)s_bin[q];
+      known += nb;
+      __syncthreads();
+    }
+    vals[q] = __uint_as_float(prefix);
+  }
+  if (threadIdx.x == 0) {
+    const double med = 0.5 * ((double)vals[0] + (double)vals[1]);
+    const double tau = med / sqrt(log(4.0));
+    const double total = tau * (1.0 - pow(1.0 / nc.mult, (double)nc.n_scales)) / (1.0 - 1.0 / nc.mult);
+    const double pi = 3.14159265358979323846;
+    const double tt = total * sqrt(pi / 2.0) + nc.k * total * sqrt((4.0 - pi) / 2.0);
+    t_out[o] = (float)tt;
+    t_out64[o] = tt;
+  }
+}
+
+// ---------------------------------------------------------------- pass B
+
+// Per row: IDFT of the F planes, per-pixel phase congruency per orientation
+// (energy along the mean phase, noise threshold T_o, spread weight), the
+// amplitude sum A_o, first argmax over o (MIM) and the moment sums.
+template <int W, int P, int NS, int NO>
+__global__ void __launch_bounds__((row_block<W, P>())) k_pass_b(const float2* __restrict__ y_in, int H, PCConsts pcc,
+                                                const float* __restrict__ t_o, uint8_t* __restrict__ mim,
+                                                float* __restrict__ mmax, float* __restrict__ mmin,
+                                                float* __restrict__ amp) {
+  using PL = FftPlan<W, P>;
+  constexpr int T = PL::T;
+  constexpr int LINES = row_block<W, P>() / T;
+  constexpr int LP = lds_line<W>();
+  __shared__ float sre[LINES][LP];
+  __shared__ float sim[LINES][LP];
+  const int team = threadIdx.x / T, t = threadIdx.x % T;
+  const int y = blockIdx.x * LINES + team;
+  const size_t plane = (size_t)H * W;
+  float best[P], ma[P], mb[P], mc[P];
+  int idx[P];
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    best[m] = -1.0f;
+    idx[m] = 0;
+    ma[m] = mb[m] = mc[m] = 0.0f;
+  }
+  for (int o = 0; o < NO; ++o) {
+    const float thr = t_o[o];
+    float es[NS][P], os[NS][P];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const float2* src = y_in + (size_t)(o * NS + s) * plane + (size_t)y * W;
+      float2 v[P];
+#pragma unroll
+      for (int m = 0; m < P; ++m) v[m] = src[t + T * m];
+      fft_line<+1, W, P>(v, t, sre[team], sim[team]);
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        es[s][m] = v[m].x;
+        os[s][m] = v[m].y;
+      }
+    }
+    const float co = pcc.cos_o[o], so = pcc.sin_o[o];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      float e_sum = 0.0f, o_sum = 0.0f, a_sum = 0.0f, a_max = 0.0f;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const float a = sqrtf(es[s][m] * es[s][m] + os[s][m] * os[s][m]);
+        e_sum += es[s][m];
+        o_sum += os[s][m];
+        a_sum += a;
+        a_max = fmaxf(a_max, a);
+      }
+      const float xe = sqrtf(e_sum * e_sum + o_sum * o_sum) + pcc.eps;
+      const float ph_e = e_sum / xe, ph_o = o_sum / xe;
+      float en = 0.0f;
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        en += es[s][m] * ph_e + os[s][m] * ph_o - fabsf(es[s][m] * ph_o - os[s][m] * ph_e);
+      const float spread = (a_sum / (a_max + pcc.eps) - 1.0f) / (float)(NS - 1);
+      const float wgt = 1.0f / (1.0f + expf(pcc.g * (pcc.cutoff - spread)));
+      const float pc = wgt * fmaxf(en - thr, 0.0f) / (a_sum + pcc.eps);
+      if (a_sum > best[m]) {
+        best[m] = a_sum;
+        idx[m] = o;
+      }
+      const float pcc_ = pc * co, pcs_ = pc * so;
+      ma[m] += pcc_ * pcc_;
+      mb[m] += 2.0f * pcc_ * pcs_;
+      mc[m] += pcs_ * pcs_;
+      if (amp) amp[(size_t)o * plane + (size_t)y * W + t + T * m] = a_sum;
+    }
+  }
+  const size_t rowo = (size_t)y * W;
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    const float root = sqrtf(mb[m] * mb[m] + (ma[m] - mc[m]) * (ma[m] - mc[m]));
+    mmax[rowo + t + T * m] = 0.5f * (ma[m] + mc[m] + root);
+    if (mmin) mmin[rowo + t + T * m] = 0.5f * (ma[m] + mc[m] - root);
+    mim[rowo + t + T * m] = (uint8_t)idx[m];
+  }
+}
+
+}  // namespace rift2

@@ -1,0 +1,286 @@
+// Brute-force descriptor matching (Section 4: nearest feature distance) with a
+// second-neighbour ratio test.
+//
+//   k_match_prep   counts -> zero-padded GEMM tables (BF16 bits or FP32),
+//                  per-keypoint best slots reset
+//   k_match_gemm   MFMA distance tiles (32 candidates x 32 queries per wave
+//                  step) with a fused per-query top-3 in registers; rows of B
+//                  are split into slices across blocks
+//   k_match_merge  per A row: merge the slice/half-wave top-3 lists, nearest
+//                  row j1, nearest row of another B keypoint j2, ratio test,
+//                  per-keypoint best by a 64-bit atomic min of (d2, row)
+//   k_match_emit   accepted keypoints in ascending order -> output records
+//
+// All dot products are exact: counts <= 256 are exact in BF16, and FP32
+// accumulation of integer products stays exact below 2^24.  The squared
+// distance is then evaluated identically in both precisions:
+// t = fl(fl(dot * ia) * ib), d2 = fl(2 - 2 t).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rift2 {
+
+constexpr int kTopK = 3;  // a keypoint owns <= 2 rows, so 3 rows hold j1 and j2
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx16_t __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint16_t bf16_bits_of_count(uint32_t c) {
+  // round to nearest even; exact for c <= 256
+  const uint32_t f = __float_as_uint((float)c);
+  return (uint16_t)((f + 0x7fffu + ((f >> 16) & 1u)) >> 16);
+}
+
+// Table layout: rows_pad x DP elements (BF16 bits as uint16, or float).
+template <bool BF16>
+__global__ void __launch_bounds__(256) k_match_prep(const uint16_t* __restrict__ desc, const int32_t* __restrict__ n_dev,
+                                                    int cap, int D, int DP, int rows_pad, void* __restrict__ table,
+                                                    uint64_t* __restrict__ best, int n_best) {
+  const int n = min(*n_dev, cap);
+  const size_t total = (size_t)rows_pad * DP;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)(idx / DP), k = (int)(idx % DP);
+    const uint32_t c = (r < n && k < D) ? desc[(size_t)r * D + k] : 0u;
+    if (BF16)
+      ((uint16_t*)table)[idx] = bf16_bits_of_count(c);
+    else
+      ((float*)table)[idx] = (float)c;
+  }
+  if (best) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_best; i += gridDim.x * blockDim.x) best[i] = ~0ull;
+  }
+}
+
+struct Top3 {
+  float d[kTopK];
+  int j[kTopK];
+};
+
+__device__ __forceinline__ void top3_insert(Top3& t, float d, int j) {
+  if (d < t.d[2]) {
+    if (d < t.d[1]) {
+      t.d[2] = t.d[1];
+      t.j[2] = t.j[1];
+      if (d < t.d[0]) {
+        t.d[1] = t.d[0];
+        t.j[1] = t.j[0];
+        t.d[0] = d;
+        t.j[0] = j;
+      } else {
+        t.d[1] = d;
+        t.j[1] = j;
+      }
+    } else {
+      t.d[2] = d;
+      t.j[2] = j;
+    }
+  }
+}
+
+// Epilogue of one 32x32 tile: lane holds 16 candidate dots of its query.
+// Accumulator register r of lane l is candidate row 8 (r/4) + 4 (l/32) + r%4.
+__device__ __forceinline__ void tile_epilogue(const floatx16_t& acc, int lane, int j0, int j_end, float ia,
+                                              float ib_lane, Top3& top) {
+  const int g = lane >> 5;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int ci = 8 * (r >> 2) + 4 * g + (r & 3);
+    const float ib = __shfl(ib_lane, ci);
+    const float t1 = __fmul_rn(acc[r], ia);
+    const float t2 = __fmul_rn(t1, ib);
+    const float d2 = __fsub_rn(2.0f, __fmul_rn(2.0f, t2));
+    const int j = j0 + ci;
+    if (j < j_end && d2 < top.d[2]) top3_insert(top, d2, j);
+  }
+}
+
+// grid = (ceil(rowsA_pad / 128), S); block = 4 waves, 32 queries per wave.
+template <int DP>
+__global__ void __launch_bounds__(256) k_match_gemm_bf16(const uint16_t* __restrict__ ta, const float* __restrict__ inv_a,
+                                                         const int32_t* __restrict__ na_dev,
+                                                         const uint16_t* __restrict__ tb, const float* __restrict__ inv_b,
+                                                         const int32_t* __restrict__ nb_dev, int cap_a, int cap_b,
+                                                         int slice_rows, int2* __restrict__ part) {
+  static_assert(DP % 16 == 0, "padded depth");
+  constexpr int KS = DP / 16;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 5;
+  const int na = min(*na_dev, cap_a), nb = min(*nb_dev, cap_b);
+  const int q0 = (blockIdx.x * 4 + wave) * 32;
+  if (q0 >= na) return;
+  const int qi = q0 + (lane & 31);
+  bf16x8_t qa[KS];
+  const uint16_t* qrow = ta + (size_t)qi * DP + 8 * g;
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const uint4 raw = *(const uint4*)(qrow + 16 * ks);
+    qa[ks] = __builtin_bit_cast(bf16x8_t, raw);
+  }
+  const float ia = qi < na ? inv_a[qi] : 0.0f;
+  const int j_beg = blockIdx.y * slice_rows;
+  const int j_end = min(nb, j_beg + slice_rows);
+  Top3 top;
+#pragma unroll
+  for (int q = 0; q < kTopK; ++q) {
+    top.d[q] = INFINITY;
+    top.j[q] = -1;
+  }
+  for (int j0 = j_beg; j0 < j_end; j0 += 32) {
+    const int cj = j0 + (lane & 31);
+    const uint16_t* crow = tb + (size_t)cj * DP + 8 * g;
+    floatx16_t acc = {};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const uint4 raw = *(const uint4*)(crow + 16 * ks);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, raw), qa[ks], acc, 0, 0, 0);
+    }
+    const float ibl = cj < nb ? inv_b[cj] : 0.0f;
+    tile_epilogue(acc, lane, j0, j_end, ia, ibl, top);
+  }
+  if (qi < na) {
+    int2* dst = part + ((size_t)qi * gridDim.y + blockIdx.y) * (2 * kTopK) + g * kTopK;
+#pragma unroll
+    for (int q = 0; q < kTopK; ++q) dst[q] = make_int2(__float_as_int(top.d[q]), top.j[q]);
+  }
+}
+
+// FP32 MFMA (32x32x2).  Each lane keeps DP/2 query values; the depth is split
+// into chunks of 8: lane half g owns k = 8c + 4g + e, MFMA e of chunk c
+// consumes element e, so both operands use the same k assignment.
+template <int DP>
+__global__ void __launch_bounds__(256) k_match_gemm_f32(const float* __restrict__ ta, const float* __restrict__ inv_a,
+                                                        const int32_t* __restrict__ na_dev,
+                                                        const float* __restrict__ tb, const float* __restrict__ inv_b,
+                                                        const int32_t* __restrict__ nb_dev, int cap_a, int cap_b,
+                                                        int slice_rows, int2* __restrict__ part) {
+  static_assert(DP % 8 == 0, "padded depth");
+  constexpr int KC = DP / 8;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 5;
+  const int na = min(*na_dev, cap_a), nb = min(*nb_dev, cap_b);
+  const int q0 = (blockIdx.x * 4 + wave) * 32;
+  if (q0 >= na) return;
+  const int qi = q0 + (lane & 31);
+  float4 qa[KC];
+  const float* qrow = ta + (size_t)qi * DP + 4 * g;
+#pragma unroll
+  for (int c = 0; c < KC; ++c) qa[c] = *(const float4*)(qrow + 8 * c);
+  const float ia = qi < na ? inv_a[qi] : 0.0f;
+  const int j_beg = blockIdx.y * slice_rows;
+  const int j_end = min(nb, j_beg + slice_rows);
+  Top3 top;
+#pragma unroll
+  for (int q = 0; q < kTopK; ++q) {
+    top.d[q] = INFINITY;
+    top.j[q] = -1;
+  }
+  for (int j0 = j_beg; j0 < j_end; j0 += 32) {
+    const int cj = j0 + (lane & 31);
+    const float* crow = tb + (size_t)cj * DP + 4 * g;
+    floatx16_t acc = {};
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      const float4 cb = *(const float4*)(crow + 8 * c);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.x, qa[c].x, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.y, qa[c].y, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.z, qa[c].z, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.w, qa[c].w, acc, 0, 0, 0);
+    }
+    const float ibl = cj < nb ? inv_b[cj] : 0.0f;
+    tile_epilogue(acc, lane, j0, j_end, ia, ibl, top);
+  }
+  if (qi < na) {
+    int2* dst = part + ((size_t)qi * gridDim.y + blockIdx.y) * (2 * kTopK) + g * kTopK;
+#pragma unroll
+    for (int q = 0; q < kTopK; ++q) dst[q] = make_int2(__float_as_int(top.d[q]), top.j[q]);
+  }
+}
+
+__device__ __forceinline__ bool better(float d, int j, float bd, int bj) { return d < bd || (d == bd && j < bj); }
+
+// One thread per A row.
+__global__ void __launch_bounds__(256) k_match_merge(const int2* __restrict__ part, int lists,
+                                                     const int32_t* __restrict__ na_dev, const int32_t* __restrict__ kp_a,
+                                                     const int32_t* __restrict__ kp_b, float ratio_sq, int cap_a,
+                                                     uint64_t* __restrict__ best, int32_t* __restrict__ row_j1,
+                                                     float* __restrict__ row_d1) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int na = min(*na_dev, cap_a);
+  if (i >= na) return;
+  const int2* src = part + (size_t)i * lists * kTopK;
+  float d1 = INFINITY;
+  int j1 = -1;
+  for (int q = 0; q < lists * kTopK; ++q) {
+    const int2 e = src[q];
+    const float d = __int_as_float(e.x);
+    if (e.y >= 0 && better(d, e.y, d1, j1)) {
+      d1 = d;
+      j1 = e.y;
+    }
+  }
+  if (j1 < 0) return;
+  const int k1 = kp_b[j1];
+  float d2 = INFINITY;
+  int j2 = -1;
+  for (int q = 0; q < lists * kTopK; ++q) {
+    const int2 e = src[q];
+    const float d = __int_as_float(e.x);
+    if (e.y >= 0 && kp_b[e.y] != k1 && better(d, e.y, d2, j2)) {
+      d2 = d;
+      j2 = e.y;
+    }
+  }
+  row_j1[i] = j1;
+  row_d1[i] = d1;
+  if (j2 < 0) return;
+  if (!(d1 < __fmul_rn(ratio_sq, d2))) return;
+  const int ka = kp_a[i];
+  if (ka < 0 || ka >= cap_a) return;
+  const uint64_t key = ((uint64_t)__float_as_uint(d1) << 32) | (uint32_t)i;  // d1 >= 0: bits are ordered
+  atomicMin((unsigned long long*)&best[ka], (unsigned long long)key);
+}
+
+struct MatchOut {
+  int kp_a, kp_b;
+  float dist2;
+};
+
+// Accepted keypoints in ascending order.  grid = ceil(cap_a / 256).
+__global__ void __launch_bounds__(256) k_match_emit(const uint64_t* __restrict__ best, int cap_a,
+                                                    const int32_t* __restrict__ row_j1, const float* __restrict__ row_d1,
+                                                    const int32_t* __restrict__ kp_b, MatchOut* __restrict__ out,
+                                                    int32_t* __restrict__ n_out) {
+  __shared__ uint32_t red[256];
+  __shared__ uint32_t scan[256];
+  const int start = blockIdx.x * 256;
+  uint32_t before = 0;
+  for (int k = threadIdx.x; k < start; k += 256) before += best[k] != ~0ull;
+  red[threadIdx.x] = before;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  const uint32_t base = red[0];
+  const int k = start + threadIdx.x;
+  const bool valid = k < cap_a && best[k] != ~0ull;
+  scan[threadIdx.x] = valid;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t v = threadIdx.x >= off ? scan[threadIdx.x - off] : 0u;
+    __syncthreads();
+    scan[threadIdx.x] += v;
+    __syncthreads();
+  }
+  if (valid) {
+    const int row = (int)(best[k] & 0xffffffffu);
+    MatchOut m;
+    m.kp_a = k;
+    m.kp_b = kp_b[row_j1[row]];
+    m.dist2 = row_d1[row];
+    out[base + scan[threadIdx.x] - 1] = m;
+  }
+  if (start + 256 >= cap_a && threadIdx.x == 255) *n_out = (int32_t)(base + scan[255]);
+}
+
+}  // namespace rift2

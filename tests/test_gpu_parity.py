@@ -1,0 +1,278 @@
+"""GPU parity of every stage of the HIP path against the CPU oracle.
+
+Tolerances (written here, derived in the design notes):
+* amplitude sums A_o: |gpu - oracle| <= 1e-4 * max(A_o(x), RMS(A_o)) (FP32 FFT error)
+* MIM: >= 99.9 % equal; every disagreement is a near-tie of the oracle's top
+  two amplitude sums (gap < 1e-4 relative)
+* max moment M: |gpu - oracle| <= 2e-3 * max(M)
+* FAST keypoints, descriptors, matches: bit-exact when fed the oracle's
+  FP32-cast inputs (these stages are integer / correctly-rounded FP32)
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from oracle import filterbank, detect, describe, match  # noqa: E402
+from synth import make_pair  # noqa: E402
+
+_cache = {}
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2303_00319_amd as r2
+
+    return r2, torch.device("cuda:0")
+
+
+def _ref_fm(key, img, pc=oracle.PCParams()):
+    if key not in _cache:
+        _cache[key] = filterbank.filter_mim(img, pc)
+    return _cache[key]
+
+
+def _pcparams(r2, n_scales=4, n_orient=6):
+    pc = r2.defaults()[0]
+    pc.n_scales = n_scales
+    pc.n_orient = n_orient
+    return pc
+
+
+def _check_filter(r2, dev, img, ref, pc, tag):
+    print(f"[filter parity] {tag} shape={img.shape} dtype={img.dtype}", flush=True)
+    t = torch.from_numpy(img).to(dev)
+    fm = r2.filter_mim(t, pc, want_amp=True, want_min=True)
+    torch.cuda.synchronize()
+    amp = fm["amp"].cpu().numpy().astype(np.float64)
+    ra = ref["amp"]
+    scale = np.maximum(ra, np.sqrt(np.mean(ra * ra, axis=(1, 2), keepdims=True)))
+    err = np.abs(amp - ra) / scale
+    assert err.max() <= 1e-4, f"{tag}: amplitude rel err {err.max():.3e}"
+    mim = fm["mim"].cpu().numpy()
+    diff = mim != ref["mim"]
+    agree = 1.0 - diff.mean()
+    srt = np.sort(ra, axis=0)
+    gap = (srt[-1] - srt[-2]) / np.maximum(srt[-1], np.sqrt(np.mean(ra * ra)))
+    assert agree >= 0.999, f"{tag}: MIM agreement {agree}"
+    if diff.any():
+        assert gap[diff].max() < 1e-4, f"{tag}: MIM disagreement away from ties (gap {gap[diff].max():.2e})"
+    mm = fm["M"].cpu().numpy().astype(np.float64)
+    merr = np.abs(mm - ref["M"]).max() / max(ref["M"].max(), 1e-30)
+    assert merr <= 2e-3, f"{tag}: max moment rel err {merr:.3e}"
+    mn = fm["m"].cpu().numpy().astype(np.float64)
+    nerr = np.abs(mn - ref["m"]).max() / max(ref["M"].max(), 1e-30)
+    assert nerr <= 2e-3, f"{tag}: min moment rel err {nerr:.3e}"
+    print(f"  amp err {err.max():.2e}  MIM agree {agree:.6f}  M err {merr:.2e}  m err {nerr:.2e}", flush=True)
+    return fm
+
+
+def test_filter_mim_256_pair():
+    r2, dev = _gpu()
+    a, b, _ = make_pair(0, 0)
+    pc = _pcparams(r2)
+    _check_filter(r2, dev, a, _ref_fm(("c0", 0, "a"), a), pc, "c0 A")
+    _check_filter(r2, dev, b, _ref_fm(("c0", 0, "b"), b), pc, "c0 B")
+
+
+def test_filter_mim_1024():
+    r2, dev = _gpu()
+    a, _, _ = make_pair(1, 0)
+    _check_filter(r2, dev, a, _ref_fm(("c1", 0, "a"), a), _pcparams(r2), "c1 A")
+
+
+@pytest.mark.parametrize("h,w", [(768, 768), (256, 512), (512, 256), (1536, 256)])
+def test_filter_mim_mixed_radix_and_rectangular(h, w):
+    r2, dev = _gpu()
+    a, _, _ = make_pair(1, 3, size=max(h, w))
+    img = np.ascontiguousarray(a[:h, :w])
+    _check_filter(r2, dev, img, filterbank.filter_mim(img, oracle.PCParams()), _pcparams(r2), f"{h}x{w}")
+
+
+def test_filter_mim_u16_and_f32_inputs():
+    r2, dev = _gpu()
+    rng = np.random.default_rng(5)
+    a, _, _ = make_pair(0, 1)
+    a16 = (a.astype(np.uint16) * 16 + rng.integers(0, 16, size=a.shape)).astype(np.uint16)
+    ref = filterbank.filter_mim(a16, oracle.PCParams(n_scales=5, n_orient=8))
+    _check_filter(r2, dev, a16.view(np.int16), ref, _pcparams(r2, 5, 8), "u16 5x8")
+    f = a.astype(np.float32) / 255.0
+    _check_filter(r2, dev, f, filterbank.filter_mim(f, oracle.PCParams()), _pcparams(r2), "f32")
+
+
+def test_filter_mim_constant_image():
+    r2, dev = _gpu()
+    for val in (0, 91):
+        t = torch.full((256, 256), val, dtype=torch.uint8, device=dev)
+        fm = r2.filter_mim(t, want_amp=True)
+        torch.cuda.synchronize()
+        assert float(fm["amp"].abs().max()) < 1e-3
+        assert float(fm["M"].abs().max()) < 1e-6
+        assert int(fm["mim"].max()) == 0
+        kp, n = r2.detect(fm["M"])
+        assert int(n.item()) == 0
+
+
+def _check_detect(r2, dev, m32, k, tag):
+    print(f"[detect parity] {tag} shape={m32.shape} K={k}", flush=True)
+    det = r2.defaults()[1]
+    det.max_keypoints = k
+    kp_ref, sc_ref = detect.detect(m32, oracle.DetectParams(max_keypoints=k), dtype=np.float32)
+    kp, n = r2.detect(torch.from_numpy(m32).to(dev), det)
+    n = int(n.item())
+    got = kp[:n].cpu().numpy()
+    assert n == len(kp_ref), f"{tag}: {n} vs {len(kp_ref)} keypoints"
+    assert np.array_equal(got[:, :2], kp_ref), f"{tag}: keypoint positions differ"
+    assert np.array_equal(got[:, 2].view(np.float32), sc_ref.astype(np.float32)), f"{tag}: scores differ"
+    return kp, n
+
+
+def test_detect_bitexact_on_oracle_moment():
+    r2, dev = _gpu()
+    a, b, _ = make_pair(0, 0)
+    for key, img in ((("c0", 0, "a"), a), (("c0", 0, "b"), b)):
+        m32 = _ref_fm(key, img)["M"].astype(np.float32)
+        _check_detect(r2, dev, m32, 500, str(key))
+        _check_detect(r2, dev, m32, 37, str(key) + " small K")
+        _check_detect(r2, dev, m32, 100000, str(key) + " K above candidates")
+
+
+def test_detect_bitexact_1024():
+    r2, dev = _gpu()
+    a, _, _ = make_pair(1, 0)
+    m32 = _ref_fm(("c1", 0, "a"), a)["M"].astype(np.float32)
+    _check_detect(r2, dev, m32, 5000, "c1 A")
+
+
+def test_detect_ties_and_random_maps():
+    r2, dev = _gpu()
+    rng = np.random.default_rng(7)
+    m = (rng.integers(0, 6, size=(256, 256)) / 5.0).astype(np.float32)  # many exact score ties
+    _check_detect(r2, dev, m, 200, "quantised")
+    m = rng.standard_normal((512, 256)).astype(np.float32)  # negative values, non-square
+    _check_detect(r2, dev, m, 3000, "gaussian")
+
+
+def _check_describe(r2, dev, mim, kpts, tag, n_orient=6):
+    print(f"[describe parity] {tag} n={len(kpts)}", flush=True)
+    dp = r2.defaults()[2]
+    dp.n_orient = n_orient
+    c_ref, k_ref, _ = describe.describe(mim, kpts, oracle.DescParams(n_orient=n_orient))
+    kp = np.zeros((max(len(kpts), 1), 3), dtype=np.int32)
+    kp[:len(kpts), :2] = kpts
+    kp_t = torch.from_numpy(kp).to(dev)
+    n_t = torch.tensor([len(kpts)], dtype=torch.int32, device=dev)
+    d, inv, dk, nd = r2.describe(torch.from_numpy(mim).to(dev), kp_t, n_t, dp)
+    nd = int(nd.item())
+    assert nd == len(c_ref), f"{tag}: {nd} vs {len(c_ref)} rows"
+    assert np.array_equal(d[:nd].cpu().numpy().astype(np.uint16), c_ref), f"{tag}: counts differ"
+    assert np.array_equal(dk[:nd].cpu().numpy(), k_ref), f"{tag}: keypoint index differs"
+    inv_ref = match.inv_norms(c_ref, np.float32)
+    assert np.array_equal(inv[:nd].cpu().numpy(), inv_ref), f"{tag}: inverse norms differ"
+    return c_ref, k_ref
+
+
+def test_describe_bitexact_on_oracle_mim():
+    r2, dev = _gpu()
+    a, _, _ = make_pair(0, 0)
+    ref = _ref_fm(("c0", 0, "a"), a)
+    kp_ref, _ = detect.detect(ref["M"], oracle.DetectParams(max_keypoints=500), dtype=np.float32)
+    _check_describe(r2, dev, ref["mim"], kp_ref, "c0 A")
+    rng = np.random.default_rng(8)
+    mim8 = rng.integers(0, 8, size=(300, 260)).astype(np.uint8)
+    pts = np.stack([rng.integers(48, 260 - 48 + 1, 700), rng.integers(48, 300 - 48 + 1, 700)], 1).astype(np.int32)
+    _check_describe(r2, dev, mim8, pts, "random N_o=8", n_orient=8)
+    # near-uniform values so that many patches carry a second descriptor
+    mim6 = (rng.integers(0, 2, size=(200, 200)) * 3).astype(np.uint8)
+    pts = np.stack([rng.integers(48, 153, 333), rng.integers(48, 153, 333)], 1).astype(np.int32)
+    _check_describe(r2, dev, mim6, pts, "two-valued")
+
+
+def _check_match(r2, dev, ca, ka, cb, kb, precision, tag):
+    print(f"[match parity] {tag} nA={len(ca)} nB={len(cb)} prec={precision}", flush=True)
+    mp = r2.defaults()[3]
+    mp.precision = precision
+    ref = match.match(ca, ka, cb, kb, dtype=np.float32)
+
+    def dev_set(c, k):
+        cap = len(c) + 5
+        ct = torch.zeros((cap, c.shape[1]), dtype=torch.int16, device=dev)
+        ct[:len(c)] = torch.from_numpy(c.astype(np.int16)).to(dev)
+        inv = torch.zeros(cap, dtype=torch.float32, device=dev)
+        inv[:len(c)] = torch.from_numpy(match.inv_norms(c, np.float32)).to(dev)
+        kt = torch.zeros(cap, dtype=torch.int32, device=dev)
+        kt[:len(c)] = torch.from_numpy(k.astype(np.int32)).to(dev)
+        return ct, inv, kt, torch.tensor([len(c)], dtype=torch.int32, device=dev)
+
+    out, n = r2.match(*dev_set(ca, ka), *dev_set(cb, kb), mp)
+    n = int(n.item())
+    got = out[:n].cpu().numpy()
+    assert n == len(ref[0]), f"{tag}: {n} vs {len(ref[0])} matches"
+    assert np.array_equal(got[:, 0], ref[0]) and np.array_equal(got[:, 1], ref[1]), f"{tag}: match pairs differ"
+    assert np.array_equal(got[:, 2].view(np.float32), ref[2]), f"{tag}: distances differ"
+    return n
+
+
+def test_match_exact_on_oracle_descriptors():
+    r2, dev = _gpu()
+    import synth.gen as g
+
+    a, _, _ = make_pair(0, 0)
+    # translated + intensity-remapped copy of A so that many rows pass the ratio test
+    b = g._warp_bilinear(a.astype(np.float64), 0.0, 5.0, -3.0)
+    b = np.rint(np.clip(255 * np.power(np.clip((255 - b) / 255, 0, 1), 0.5), 0, 255)).astype(np.uint8)
+    fa = oracle.pipeline.image_features(a, det=oracle.DetectParams(max_keypoints=500), dtype=np.float32)
+    fb = oracle.pipeline.image_features(b, det=oracle.DetectParams(max_keypoints=500), dtype=np.float32)
+    for prec in (r2.PREC_FP32, r2.PREC_BF16):
+        n = _check_match(r2, dev, fa["desc"], fa["desc_kp"], fb["desc"], fb["desc_kp"], prec, "c0 shifted")
+        assert n > 100
+
+
+def test_match_random_sets_with_ties_and_ragged_sizes():
+    r2, dev = _gpu()
+    rng = np.random.default_rng(9)
+    for na, nb in ((1, 1), (3, 2), (33, 65), (700, 1111)):
+        ca = rng.integers(0, 4, size=(na, 216)).astype(np.uint16)
+        cb = rng.integers(0, 4, size=(nb, 216)).astype(np.uint16)
+        cb[: min(na, nb) // 2] = ca[: min(na, nb) // 2]
+        ka = np.arange(na) // 2
+        kb = np.arange(nb) // 2
+        for prec in (r2.PREC_FP32, r2.PREC_BF16):
+            _check_match(r2, dev, ca, ka, cb, kb, prec, f"random {na}x{nb}")
+    # 288-d (N_o = 8) descriptors
+    ca = rng.integers(0, 9, size=(300, 288)).astype(np.uint16)
+    cb = np.concatenate([ca[:150], rng.integers(0, 9, size=(200, 288)).astype(np.uint16)])
+    for prec in (r2.PREC_FP32, r2.PREC_BF16):
+        _check_match(r2, dev, ca, np.arange(300), cb, np.arange(350), prec, "288-d")
+
+
+def test_end_to_end_pair_agreement():
+    """Full GPU pipeline vs the FP64 oracle on a c0 pair: reported agreement."""
+    r2, dev = _gpu()
+    import synth.gen as g
+
+    a, _, _ = make_pair(0, 2)
+    b = g._warp_bilinear(a.astype(np.float64), 0.0, 7.0, 4.0)
+    b = np.rint(np.clip(255 * np.power(np.clip((255 - b) / 255, 0, 1), 0.5), 0, 255)).astype(np.uint8)
+    det = oracle.DetectParams(max_keypoints=500)
+    fa, fb, mref = oracle.pipeline.match_pair(a, b, det=det)
+    pc, detp, dp, mp = r2.defaults()
+    detp.max_keypoints = 500
+    feats = []
+    for img in (a, b):
+        fm = r2.filter_mim(torch.from_numpy(img).to(dev), pc)
+        kp, nk = r2.detect(fm["M"], detp)
+        feats.append((kp, nk) + r2.describe(fm["mim"], kp, nk, dp))
+    out, n = r2.match(*feats[0][2:6], *feats[1][2:6], mp)
+    n = int(n.item())
+    ka = feats[0][0].cpu().numpy()
+    kb = feats[1][0].cpu().numpy()
+    got = {(tuple(ka[i, :2]), tuple(kb[j, :2])) for i, j in out[:n, :2].cpu().numpy()}
+    want = {(tuple(fa["kpts"][i]), tuple(fb["kpts"][j])) for i, j in zip(mref[0], mref[1])}
+    jac = len(got & want) / max(1, len(got | want))
+    print(f"end-to-end: gpu {len(got)} matches, oracle {len(want)}, Jaccard {jac:.4f}", flush=True)
+    assert len(want) > 100 and jac > 0.9
