@@ -10,11 +10,13 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import PCParams, DetectParams, DescParams, MatchParams, PREC_FP32, PREC_BF16, Rift2Error  # noqa: F401
+from ._lib import (PCParams, DetectParams, DescParams, MatchParams, PREC_FP32, PREC_BF16,  # noqa: F401
+                   Rift2Error, STAGES)
 
 __all__ = [
-    "defaults", "init", "filter_mim", "detect", "describe", "match", "Rift2Error",
-    "PCParams", "DetectParams", "DescParams", "MatchParams", "PREC_FP32", "PREC_BF16",
+    "defaults", "init", "filter_mim", "detect", "describe", "match", "Rift2Error", "PairPipeline",
+    "profile_enable", "profile_read", "PCParams", "DetectParams", "DescParams", "MatchParams",
+    "PREC_FP32", "PREC_BF16", "STAGES",
 ]
 
 
@@ -52,27 +54,88 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
-def _workspace(nbytes: int, device, ws=None):
-    torch = _torch()
-    if ws is not None:
-        if ws.numel() * ws.element_size() < nbytes:
-            raise ValueError("workspace too small")
-        return ws
-    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+def _nbytes(t):
+    return t.numel() * t.element_size()
 
+
+def _image_dtype(img):
+    torch = _torch()
+    code = {torch.uint8: _lib.U8, torch.int16: _lib.U16, torch.uint16: _lib.U16, torch.float32: _lib.F32}.get(img.dtype)
+    if code is None:
+        raise ValueError(f"unsupported image dtype {img.dtype}")
+    return code
+
+
+# ----------------------------------------------------------------- workspace sizes
+
+def filter_workspace_bytes(h, w, pc):
+    n = _lib.load().rift2_filter_workspace_size(h, w, ctypes.byref(pc))
+    if n == 0:
+        raise Rift2Error(_lib.ERR_UNSUPPORTED, "rift2_filter_workspace_size")
+    return n
+
+
+def detect_workspace_bytes(h, w, det):
+    return _lib.load().rift2_detect_workspace_size(h, w, ctypes.byref(det))
+
+
+def describe_workspace_bytes(cap):
+    return _lib.load().rift2_describe_workspace_size(cap)
+
+
+def match_workspace_bytes(cap_a, cap_b, d, mp):
+    n = _lib.load().rift2_match_workspace_size(cap_a, cap_b, d, ctypes.byref(mp))
+    if n == 0:
+        raise Rift2Error(_lib.ERR_INVALID_ARG, "rift2_match_workspace_size")
+    return n
+
+
+# ----------------------------------------------------------------- calls on caller buffers
+
+def filter_mim_into(img, pc, mim, mmax, mmin, amp, ws, stream=None):
+    lib = _lib.load()
+    h, w = img.shape
+    st = lib.rift2_filter_mim(_ptr(img), _image_dtype(img), h, w, img.stride(0), ctypes.byref(pc), _ptr(mim),
+                              _ptr(mmax), _ptr(mmin), _ptr(amp), _ptr(ws), _nbytes(ws), _stream(stream))
+    _lib.check(st, "rift2_filter_mim")
+
+
+def detect_into(moment, det, kpts, n, ws, stream=None):
+    lib = _lib.load()
+    h, w = moment.shape
+    st = lib.rift2_detect(_ptr(moment), h, w, ctypes.byref(det), _ptr(kpts), _ptr(n), _ptr(ws), _nbytes(ws),
+                          _stream(stream))
+    _lib.check(st, "rift2_detect")
+
+
+def describe_into(mim, kpts, n_kpts, dp, desc, inv, dkp, nd, ws, stream=None):
+    lib = _lib.load()
+    h, w = mim.shape
+    cap = kpts.shape[0]
+    st = lib.rift2_describe(_ptr(mim), h, w, _ptr(kpts), _ptr(n_kpts), cap, ctypes.byref(dp), _ptr(desc), _ptr(inv),
+                            _ptr(dkp), desc.shape[0], _ptr(nd), _ptr(ws), _nbytes(ws), _stream(stream))
+    _lib.check(st, "rift2_describe")
+
+
+def match_into(desc_a, inv_a, kp_a, n_a, desc_b, inv_b, kp_b, n_b, mp, out, n_out, ws, stream=None):
+    lib = _lib.load()
+    cap_a, d = desc_a.shape
+    st = lib.rift2_match(_ptr(desc_a), _ptr(inv_a), _ptr(kp_a), _ptr(n_a), cap_a, _ptr(desc_b), _ptr(inv_b),
+                         _ptr(kp_b), _ptr(n_b), desc_b.shape[0], d, ctypes.byref(mp), _ptr(out), _ptr(n_out),
+                         _ptr(ws), _nbytes(ws), _stream(stream))
+    _lib.check(st, "rift2_match")
+
+
+# ----------------------------------------------------------------- allocating convenience calls
 
 def filter_mim(img, pc: PCParams | None = None, want_min: bool = False, want_amp: bool = False,
                workspace=None, stream=None):
     """MIM, max moment (and optionally min moment and A_o) of one H x W device image."""
     torch = _torch()
-    lib = _lib.load()
     if pc is None:
         pc = defaults()[0]
     if img.dim() != 2 or not img.is_cuda:
         raise ValueError("img must be a 2-D device tensor")
-    dtype = {torch.uint8: _lib.U8, torch.int16: _lib.U16, torch.uint16: _lib.U16, torch.float32: _lib.F32}.get(img.dtype)
-    if dtype is None:
-        raise ValueError(f"unsupported image dtype {img.dtype}")
     init(img.device.index or 0)
     h, w = img.shape
     dev = img.device
@@ -80,13 +143,9 @@ def filter_mim(img, pc: PCParams | None = None, want_min: bool = False, want_amp
     mmax = torch.empty((h, w), dtype=torch.float32, device=dev)
     mmin = torch.empty((h, w), dtype=torch.float32, device=dev) if want_min else None
     amp = torch.empty((pc.n_orient, h, w), dtype=torch.float32, device=dev) if want_amp else None
-    nbytes = lib.rift2_filter_workspace_size(h, w, ctypes.byref(pc))
-    if nbytes == 0:
-        raise Rift2Error(_lib.ERR_UNSUPPORTED, "rift2_filter_workspace_size")
-    ws = _workspace(nbytes, dev, workspace)
-    st = lib.rift2_filter_mim(_ptr(img), dtype, h, w, img.stride(0), ctypes.byref(pc), _ptr(mim), _ptr(mmax),
-                              _ptr(mmin), _ptr(amp), _ptr(ws), nbytes, _stream(stream))
-    _lib.check(st, "rift2_filter_mim")
+    ws = workspace if workspace is not None else torch.empty(filter_workspace_bytes(h, w, pc), dtype=torch.uint8,
+                                                             device=dev)
+    filter_mim_into(img, pc, mim, mmax, mmin, amp, ws, stream)
     out = {"mim": mim, "M": mmax}
     if want_min:
         out["m"] = mmin
@@ -98,7 +157,6 @@ def filter_mim(img, pc: PCParams | None = None, want_min: bool = False, want_amp
 def detect(moment, det: DetectParams | None = None, workspace=None, stream=None):
     """(kpts int32 [K, 3] = x, y, score bits; n int32 [1]) on the device, strongest first."""
     torch = _torch()
-    lib = _lib.load()
     if det is None:
         det = defaults()[1]
     init(moment.device.index or 0)
@@ -106,21 +164,18 @@ def detect(moment, det: DetectParams | None = None, workspace=None, stream=None)
     dev = moment.device
     kpts = torch.empty((det.max_keypoints, 3), dtype=torch.int32, device=dev)
     n = torch.zeros((1,), dtype=torch.int32, device=dev)
-    nbytes = lib.rift2_detect_workspace_size(h, w, ctypes.byref(det))
-    ws = _workspace(nbytes, dev, workspace)
-    st = lib.rift2_detect(_ptr(moment), h, w, ctypes.byref(det), _ptr(kpts), _ptr(n), _ptr(ws), nbytes, _stream(stream))
-    _lib.check(st, "rift2_detect")
+    ws = workspace if workspace is not None else torch.empty(detect_workspace_bytes(h, w, det), dtype=torch.uint8,
+                                                             device=dev)
+    detect_into(moment, det, kpts, n, ws, stream)
     return kpts, n
 
 
 def describe(mim, kpts, n_kpts, dp: DescParams | None = None, workspace=None, stream=None):
     """(desc int16 [2K, D] holding uint16 counts, inv_norm f32 [2K], desc_kp int32 [2K], n_desc int32 [1])."""
     torch = _torch()
-    lib = _lib.load()
     if dp is None:
         dp = defaults()[2]
     init(mim.device.index or 0)
-    h, w = mim.shape
     dev = mim.device
     cap = kpts.shape[0]
     d = dp.grid * dp.grid * dp.n_orient
@@ -128,11 +183,9 @@ def describe(mim, kpts, n_kpts, dp: DescParams | None = None, workspace=None, st
     inv = torch.empty((2 * cap,), dtype=torch.float32, device=dev)
     dkp = torch.empty((2 * cap,), dtype=torch.int32, device=dev)
     nd = torch.zeros((1,), dtype=torch.int32, device=dev)
-    nbytes = lib.rift2_describe_workspace_size(cap)
-    ws = _workspace(nbytes, dev, workspace)
-    st = lib.rift2_describe(_ptr(mim), h, w, _ptr(kpts), _ptr(n_kpts), cap, ctypes.byref(dp), _ptr(desc), _ptr(inv),
-                            _ptr(dkp), 2 * cap, _ptr(nd), _ptr(ws), nbytes, _stream(stream))
-    _lib.check(st, "rift2_describe")
+    ws = workspace if workspace is not None else torch.empty(describe_workspace_bytes(cap), dtype=torch.uint8,
+                                                             device=dev)
+    describe_into(mim, kpts, n_kpts, dp, desc, inv, dkp, nd, ws, stream)
     return desc, inv, dkp, nd
 
 
@@ -140,21 +193,113 @@ def match(desc_a, inv_a, kp_a, n_a, desc_b, inv_b, kp_b, n_b, mp: MatchParams | 
           workspace=None, stream=None):
     """(matches int32 [cap_a, 3] = kp_a, kp_b, d2 bits; n int32 [1]) sorted by kp_a."""
     torch = _torch()
-    lib = _lib.load()
     if mp is None:
         mp = defaults()[3]
     init(desc_a.device.index or 0)
     cap_a, d = desc_a.shape
-    cap_b = desc_b.shape[0]
     dev = desc_a.device
     out = torch.empty((cap_a, 3), dtype=torch.int32, device=dev)
     n = torch.zeros((1,), dtype=torch.int32, device=dev)
-    nbytes = lib.rift2_match_workspace_size(cap_a, cap_b, d, ctypes.byref(mp))
-    if nbytes == 0:
-        raise Rift2Error(_lib.ERR_INVALID_ARG, "rift2_match_workspace_size")
-    ws = _workspace(nbytes, dev, workspace)
-    st = lib.rift2_match(_ptr(desc_a), _ptr(inv_a), _ptr(kp_a), _ptr(n_a), cap_a, _ptr(desc_b), _ptr(inv_b),
-                         _ptr(kp_b), _ptr(n_b), cap_b, d, ctypes.byref(mp), _ptr(out), _ptr(n), _ptr(ws), nbytes,
-                         _stream(stream))
-    _lib.check(st, "rift2_match")
+    ws = workspace if workspace is not None else torch.empty(match_workspace_bytes(cap_a, desc_b.shape[0], d, mp),
+                                                             dtype=torch.uint8, device=dev)
+    match_into(desc_a, inv_a, kp_a, n_a, desc_b, inv_b, kp_b, n_b, mp, out, n, ws, stream)
     return out, n
+
+
+# ----------------------------------------------------------------- whole pair with resident buffers
+
+class _ImageBuffers:
+    def __init__(self, h, w, pc, det, dp, dev):
+        torch = _torch()
+        cap = det.max_keypoints
+        d = dp.grid * dp.grid * dp.n_orient
+        self.mim = torch.empty((h, w), dtype=torch.uint8, device=dev)
+        self.M = torch.empty((h, w), dtype=torch.float32, device=dev)
+        self.kpts = torch.empty((cap, 3), dtype=torch.int32, device=dev)
+        self.nk = torch.zeros((1,), dtype=torch.int32, device=dev)
+        self.desc = torch.empty((2 * cap, d), dtype=torch.int16, device=dev)
+        self.inv = torch.empty((2 * cap,), dtype=torch.float32, device=dev)
+        self.dkp = torch.empty((2 * cap,), dtype=torch.int32, device=dev)
+        self.nd = torch.zeros((1,), dtype=torch.int32, device=dev)
+        self.ws_filter = torch.empty(filter_workspace_bytes(h, w, pc), dtype=torch.uint8, device=dev)
+        self.ws_detect = torch.empty(detect_workspace_bytes(h, w, det), dtype=torch.uint8, device=dev)
+        self.ws_desc = torch.empty(describe_workspace_bytes(cap), dtype=torch.uint8, device=dev)
+
+
+class PairPipeline:
+    """All stages of one image pair on buffers that stay resident in HBM.
+
+    run(img_a, img_b) only enqueues kernels (no host synchronisation, no
+    allocation), so it can be captured into a HIP graph and replayed.
+    """
+
+    def __init__(self, h, w, pc=None, det=None, dp=None, mp=None, device=0):
+        torch = _torch()
+        d_pc, d_det, d_dp, d_mp = defaults()
+        self.pc = pc or d_pc
+        self.det = det or d_det
+        self.dp = dp or d_dp
+        self.mp = mp or d_mp
+        self.dev = torch.device("cuda", device)
+        init(device)
+        self.h, self.w = h, w
+        self.a = _ImageBuffers(h, w, self.pc, self.det, self.dp, self.dev)
+        self.b = _ImageBuffers(h, w, self.pc, self.det, self.dp, self.dev)
+        cap = 2 * self.det.max_keypoints
+        d = self.dp.grid * self.dp.grid * self.dp.n_orient
+        self.out = torch.empty((cap, 3), dtype=torch.int32, device=self.dev)
+        self.n_out = torch.zeros((1,), dtype=torch.int32, device=self.dev)
+        self.ws_match = torch.empty(match_workspace_bytes(cap, cap, d, self.mp), dtype=torch.uint8, device=self.dev)
+        self.graph = None
+
+    def _image(self, img, buf, stream):
+        filter_mim_into(img, self.pc, buf.mim, buf.M, None, None, buf.ws_filter, stream)
+        detect_into(buf.M, self.det, buf.kpts, buf.nk, buf.ws_detect, stream)
+        describe_into(buf.mim, buf.kpts, buf.nk, self.dp, buf.desc, buf.inv, buf.dkp, buf.nd, buf.ws_desc, stream)
+
+    def run(self, img_a, img_b, stream=None):
+        self._image(img_a, self.a, stream)
+        self._image(img_b, self.b, stream)
+        a, b = self.a, self.b
+        match_into(a.desc, a.inv, a.dkp, a.nd, b.desc, b.inv, b.dkp, b.nd, self.mp, self.out, self.n_out,
+                   self.ws_match, stream)
+
+    def capture(self, img_a, img_b):
+        """Capture run() on static input buffers into a graph; replay() re-runs it."""
+        torch = _torch()
+        s = torch.cuda.Stream(device=self.dev)
+        s.wait_stream(torch.cuda.current_stream(self.dev))
+        with torch.cuda.stream(s):
+            self.run(img_a, img_b, s)  # warm (module load, first-touch)
+        torch.cuda.current_stream(self.dev).wait_stream(s)
+        torch.cuda.synchronize(self.dev)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            self.run(img_a, img_b, s)
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+
+    def matches(self):
+        """Host copy of the matches: list of (kp_a, kp_b, d2)."""
+        n = int(self.n_out.item())
+        o = self.out[:n].cpu()
+        return o
+
+
+# ----------------------------------------------------------------- diagnostics
+
+def profile_enable(on: bool = True) -> None:
+    _lib.check(_lib.load().rift2_profile_enable(1 if on else 0), "rift2_profile_enable")
+
+
+def profile_read():
+    """{stage: (total_ms, launches)} accumulated since the last read (waits for the events)."""
+    lib = _lib.load()
+    n = len(STAGES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    lib.rift2_profile_read(ms, cnt, n)
+    return {STAGES[i]: (ms[i], cnt[i]) for i in range(n)}

@@ -51,7 +51,10 @@ EXPORTS = [
     "rift2_default_params", "rift2_status_string", "rift2_init", "rift2_size_supported",
     "rift2_filter_workspace_size", "rift2_detect_workspace_size", "rift2_describe_workspace_size",
     "rift2_match_workspace_size", "rift2_filter_mim", "rift2_detect", "rift2_describe", "rift2_match",
+    "rift2_profile_enable", "rift2_profile_read",
 ]
+STAGES = ["row_dft", "pass_a", "noise_pre", "noise_sel", "pass_b", "detect", "describe", "match_prep",
+          "match_gemm", "match_merge"]
 
 _LIB = None
 
@@ -90,6 +93,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rift2_describe.restype = ctypes.c_int
     lib.rift2_match.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, i32, i32, P(MatchParams), vp, vp, vp, sz, vp]
     lib.rift2_match.restype = ctypes.c_int
+    lib.rift2_profile_enable.argtypes = [ctypes.c_int]
+    lib.rift2_profile_enable.restype = ctypes.c_int
+    lib.rift2_profile_read.argtypes = [P(ctypes.c_double), P(ctypes.c_int64), ctypes.c_int]
+    lib.rift2_profile_read.restype = ctypes.c_int
     _LIB = lib
     return lib
 

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "../../include/rift2.h"
 #include "describe.hip"
@@ -132,6 +133,42 @@ rift2_status launch_status() {
 
 std::mutex g_init_mu;
 bool g_init_done[64] = {};
+
+// ---- stage timing (diagnostics)
+constexpr int kProfGroups = 10;
+struct ProfRec {
+  int group;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+
+// Records an event pair around the kernels enqueued during its lifetime.
+struct ProfScope {
+  int group;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(int g, hipStream_t s) : group(g), st(s) {
+    if (!g_prof_on) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess ||
+        hipEventRecord(a, st) != hipSuccess) {
+      a = b = nullptr;
+    }
+  }
+  void finish() {
+    if (!a) return;
+    if (hipEventRecord(b, st) == hipSuccess) {
+      std::lock_guard<std::mutex> lock(g_prof_mu);
+      g_prof.push_back({group, a, b});
+    } else {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+    a = b = nullptr;
+  }
+  ~ProfScope() { finish(); }
+};
 
 }  // namespace
 
@@ -392,15 +429,29 @@ rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t
   nc.n_scales = pc->n_scales;
 
   (void)hipGetLastError();
-  if (!dispatch_fwd_rows(W, dtype, img, pitch, H, rrow, zero, L.zero_words, st)) return RIFT2_ERR_UNSUPPORTED;
-  if (!dispatch_pass_a(H, W, rrow, fc, yp, st)) return RIFT2_ERR_UNSUPPORTED;
-  if (!dispatch_noise_pre(W, H, pc->n_orient, pc->n_scales, yp, a0, hist1, st)) return RIFT2_ERR_UNSUPPORTED;
+  {
+    ProfScope ps(0, st);
+    dispatch_fwd_rows(W, dtype, img, pitch, H, rrow, zero, L.zero_words, st);
+  }
+  {
+    ProfScope ps(1, st);
+    dispatch_pass_a(H, W, rrow, fc, yp, st);
+  }
+  {
+    ProfScope ps(2, st);
+    dispatch_noise_pre(W, H, pc->n_orient, pc->n_scales, yp, a0, hist1, st);
+  }
   const int hw = H * W;
   const int chunks = std::max(1, std::min(128, hw / 8192));
-  hipLaunchKernelGGL(k_noise_sel, dim3(chunks, pc->n_orient), dim3(256), 0, st, a0, hw, hist1, cand, counters, nc, t32,
-                     t64);
-  if (!dispatch_pass_b(pc->n_scales, pc->n_orient, W, H, yp, pcc, t32, mim, max_moment, min_moment, amp_sums, st))
-    return RIFT2_ERR_UNSUPPORTED;
+  {
+    ProfScope ps(3, st);
+    hipLaunchKernelGGL(k_noise_sel, dim3(chunks, pc->n_orient), dim3(256), 0, st, a0, hw, hist1, cand, counters, nc,
+                       t32, t64);
+  }
+  {
+    ProfScope ps(4, st);
+    dispatch_pass_b(pc->n_scales, pc->n_orient, W, H, yp, pcc, t32, mim, max_moment, min_moment, amp_sums, st);
+  }
   return launch_status();
 }
 
@@ -421,6 +472,7 @@ rift2_status rift2_detect(const float* moment, int32_t H, int32_t W, const rift2
   uint64_t* sel = (uint64_t*)(ws + L.sel);
   uint64_t* fin = (uint64_t*)(ws + L.fin);
   (void)hipGetLastError();
+  ProfScope ps(5, st);
   hipLaunchKernelGGL(k_det_init, dim3(kDetHistBins / 256), dim3(256), 0, st, hdr, hist);
   const int n = H * W;
   hipLaunchKernelGGL(k_det_minmax, dim3(std::min(1024, (n + 255) / 256)), dim3(256), 0, st, moment, n, hdr);
@@ -446,6 +498,7 @@ rift2_status rift2_describe(const uint8_t* mim, int32_t H, int32_t W, const rift
   const int* kp = (const int*)kpts;
   (void)hipGetLastError();
   const int blocks2 = (kpt_cap + 255) / 256;
+  ProfScope ps(6, st);
   if (dp->patch_size == 96 && dp->grid == 6 && dp->n_orient == 6) {
     constexpr int KPB = desc_kpb<96>();
     hipLaunchKernelGGL((k_describe<96, 6, 6>), dim3((kpt_cap + KPB - 1) / KPB), dim3(96 * KPB), 0, st, mim, H, W, kp,
@@ -493,6 +546,7 @@ rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32
   float* rowd = (float*)(ws + L.rowd);
   const bool bf = mp->precision == RIFT2_PREC_BF16;
   (void)hipGetLastError();
+  ProfScope ps7(7, st);
   if (bf) {
     hipLaunchKernelGGL(k_match_prep<true>, dim3(512), dim3(256), 0, st, desc_a, nA_dev, cap_a, D, L.dp, L.rows_a, ta, best,
                        cap_a);
@@ -504,7 +558,9 @@ rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32
     hipLaunchKernelGGL(k_match_prep<false>, dim3(512), dim3(256), 0, st, desc_b, nB_dev, cap_b, D, L.dp, L.rows_b, tb,
                        (uint64_t*)nullptr, 0);
   }
+  ps7.finish();
   const dim3 grid((L.rows_a + 127) / 128, L.slices);
+  ProfScope ps8(8, st);
   if (bf) {
     if (L.dp == 224)
       hipLaunchKernelGGL(k_match_gemm_bf16<224>, grid, dim3(256), 0, st, (const uint16_t*)ta, inv_a, nA_dev,
@@ -520,11 +576,38 @@ rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32
       hipLaunchKernelGGL(k_match_gemm_f32<288>, grid, dim3(256), 0, st, (const float*)ta, inv_a, nA_dev,
                          (const float*)tb, inv_b, nB_dev, cap_a, cap_b, L.slice_rows, part);
   }
+  ps8.finish();
+  ProfScope ps9(9, st);
   hipLaunchKernelGGL(k_match_merge, dim3((cap_a + 255) / 256), dim3(256), 0, st, part, 2 * L.slices, nA_dev, kp_a, kp_b,
                      mp->ratio_sq, cap_a, best, rowj, rowd);
   hipLaunchKernelGGL(k_match_emit, dim3((cap_a + 255) / 256), dim3(256), 0, st, best, cap_a, rowj, rowd, kp_b,
                      (MatchOut*)out, n_out_dev);
   return launch_status();
+}
+
+rift2_status rift2_profile_enable(int on) {
+  std::lock_guard<std::mutex> lock(g_prof_mu);
+  g_prof_on = on != 0;
+  return RIFT2_OK;
+}
+
+int rift2_profile_read(double* ms, int64_t* count, int n_groups) {
+  std::vector<ProfRec> recs;
+  {
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    recs.swap(g_prof);
+  }
+  for (const ProfRec& r : recs) {
+    float t = 0.0f;
+    const bool ok = hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess;
+    if (ok && r.group < n_groups) {
+      if (ms) ms[r.group] += (double)t;
+      if (count) count[r.group] += 1;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  return kProfGroups;
 }
 
 }  // extern "C"

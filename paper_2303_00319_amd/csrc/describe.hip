@@ -18,6 +18,35 @@
 
 namespace rift2 {
 
+// fl32(1 / fl32(sqrt(n))) correctly rounded, for 0 < n < 2^24.  The hardware
+// square root and reciprocal are only faithful, so both roundings are fixed
+// by exact midpoint tests in FP64 (every product below is exact there).
+__device__ __forceinline__ float inv_sqrt_rn(uint32_t n) {
+  const double dn = (double)n;
+  float s = sqrtf((float)n);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const float up = __uint_as_float(__float_as_uint(s) + 1u);
+    const float dnx = __uint_as_float(__float_as_uint(s) - 1u);
+    const double mu = 0.5 * ((double)s + (double)up);
+    const double md = 0.5 * ((double)s + (double)dnx);
+    if (dn > mu * mu) s = up;
+    else if (dn < md * md) s = dnx;
+  }
+  float q = 1.0f / s;
+  const double ds = (double)s;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const float up = __uint_as_float(__float_as_uint(q) + 1u);
+    const float dnx = __uint_as_float(__float_as_uint(q) - 1u);
+    const double mu = 0.5 * ((double)q + (double)up);
+    const double md = 0.5 * ((double)q + (double)dnx);
+    if (mu * ds < 1.0) q = up;        // 1/s lies above the upper midpoint
+    else if (md * ds > 1.0) q = dnx;  // 1/s lies below the lower midpoint
+  }
+  return q;
+}
+
 template <int P>
 constexpr int desc_kpb() { return (P % 64 == 0) ? 1 : (P % 32 == 0 ? 2 : 4); }
 
@@ -115,7 +144,7 @@ __global__ void __launch_bounds__(P * desc_kpb<P>()) k_describe(const uint8_t* _
   __syncthreads();
   if (active && x == 0) {
     const uint32_t nn = sh_n2[local];
-    inv_norm[i] = nn ? __fdiv_rn(1.0f, __fsqrt_rn((float)nn)) : 0.0f;
+    inv_norm[i] = nn ? inv_sqrt_rn(nn) : 0.0f;
     desc_kp[i] = i;
     info[i] = sh_two[local] ? (0x100u | (uint32_t)sh_delta[local]) : 0u;
   }

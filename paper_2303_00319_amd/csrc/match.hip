@@ -236,7 +236,10 @@ __global__ void __launch_bounds__(256) k_match_merge(const int2* __restrict__ pa
   if (!(d1 < __fmul_rn(ratio_sq, d2))) return;
   const int ka = kp_a[i];
   if (ka < 0 || ka >= cap_a) return;
-  const uint64_t key = ((uint64_t)__float_as_uint(d1) << 32) | (uint32_t)i;  // d1 >= 0: bits are ordered
+  // order-preserving key: rounding can make d1 slightly negative for identical rows
+  const uint32_t b = __float_as_uint(d1);
+  const uint32_t ok = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+  const uint64_t key = ((uint64_t)ok << 32) | (uint32_t)i;
   atomicMin((unsigned long long*)&best[ka], (unsigned long long)key);
 }
 
