@@ -67,7 +67,7 @@ FilterLayout filter_layout(int H, int W, const rift2_pc_params* p) {
   L.yplanes = c.take(hw * F * sizeof(float2));
   L.a0 = c.take(hw * p->n_orient * sizeof(float));
   L.cand = c.take(hw * p->n_orient * sizeof(uint32_t));
-  L.zero_words = p->n_orient * kHist1 + 2 * p->n_orient;
+  L.zero_words = p->n_orient * (kHist1 + 2 * kHist2 + 2 * kHist3 + 2);
   L.zero = c.take((size_t)L.zero_words * sizeof(uint32_t));
   L.t32 = c.take(p->n_orient * sizeof(float));
   L.t64 = c.take(p->n_orient * sizeof(double));
@@ -76,8 +76,9 @@ FilterLayout filter_layout(int H, int W, const rift2_pc_params* p) {
 }
 
 struct DetectLayout {
-  size_t hdr, hist, cand, sel, fin, total;
+  size_t hdr, hist, cand, sel, fin, part, total;
   size_t cand_cap;
+  int n_part;
 };
 
 DetectLayout detect_layout(int H, int W, const rift2_detect_params* d) {
@@ -88,7 +89,11 @@ DetectLayout detect_layout(int H, int W, const rift2_detect_params* d) {
   L.hist = c.take(kDetHistBins * sizeof(uint32_t));
   L.cand = c.take(L.cand_cap * sizeof(uint64_t));
   L.sel = c.take(L.cand_cap * sizeof(uint64_t));
-  L.fin = c.take((size_t)(d ? d->max_keypoints : 0) * sizeof(uint64_t) + 8);
+  const size_t kmax = d ? (size_t)d->max_keypoints : 0;
+  L.fin = c.take(kmax * sizeof(uint64_t) + 8);
+  const int blocks = (int)((kmax + 255) / 256);
+  L.n_part = std::max(1, std::min(32, 512 / std::max(1, blocks)));
+  L.part = c.take((size_t)L.n_part * kmax * sizeof(uint32_t) + 8);
   L.total = c.off;
   return L;
 }
@@ -393,8 +398,13 @@ rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t
   float* a0 = (float*)(ws + L.a0);
   uint32_t* cand = (uint32_t*)(ws + L.cand);
   uint32_t* zero = (uint32_t*)(ws + L.zero);
-  uint32_t* hist1 = zero;
-  uint32_t* counters = zero + pc->n_orient * kHist1;
+  NoiseWs nws;
+  nws.hist1 = zero;
+  nws.hist2 = nws.hist1 + pc->n_orient * kHist1;
+  nws.hist3 = nws.hist2 + pc->n_orient * 2 * kHist2;
+  nws.cnt = nws.hist3 + pc->n_orient * 2 * kHist3;
+  nws.done = nws.cnt + pc->n_orient;
+  nws.cand = cand;
   float* t32 = (float*)(ws + L.t32);
   double* t64 = (double*)(ws + L.t64);
 
@@ -439,14 +449,14 @@ rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t
   }
   {
     ProfScope ps(2, st);
-    dispatch_noise_pre(W, H, pc->n_orient, pc->n_scales, yp, a0, hist1, st);
+    dispatch_noise_pre(W, H, pc->n_orient, pc->n_scales, yp, a0, nws.hist1, st);
   }
   const int hw = H * W;
-  const int chunks = std::max(1, std::min(128, hw / 8192));
   {
     ProfScope ps(3, st);
-    hipLaunchKernelGGL(k_noise_sel, dim3(chunks, pc->n_orient), dim3(256), 0, st, a0, hw, hist1, cand, counters, nc,
-                       t32, t64);
+    const int chunks = std::max(1, std::min(64, hw / 16384));
+    hipLaunchKernelGGL(k_noise_sel1, dim3(chunks, pc->n_orient), dim3(256), 0, st, a0, hw, nws);
+    hipLaunchKernelGGL(k_noise_sel2, dim3(32, pc->n_orient), dim3(256), 0, st, hw, nws, nc, t32, t64);
   }
   {
     ProfScope ps(4, st);
@@ -475,11 +485,16 @@ rift2_status rift2_detect(const float* moment, int32_t H, int32_t W, const rift2
   ProfScope ps(5, st);
   hipLaunchKernelGGL(k_det_init, dim3(kDetHistBins / 256), dim3(256), 0, st, hdr, hist);
   const int n = H * W;
-  hipLaunchKernelGGL(k_det_minmax, dim3(std::min(1024, (n + 255) / 256)), dim3(256), 0, st, moment, n, hdr);
+  hipLaunchKernelGGL(k_det_minmax, dim3(std::min(256, (n + 255) / 256)), dim3(256), 0, st, moment, n, hdr);
   hipLaunchKernelGGL(k_det_fast, dim3((W + kTileX - 1) / kTileX, (H + kTileY - 1) / kTileY), dim3(kTileX * kTileY), 0, st,
                      moment, H, W, det->fast_threshold, det->patch_size / 2, hdr, hist, cand);
-  hipLaunchKernelGGL(k_det_select, dim3(64), dim3(256), 0, st, hdr, hist, cand, sel, fin, (uint32_t)det->max_keypoints);
-  hipLaunchKernelGGL(k_det_sort, dim3((det->max_keypoints + 255) / 256), dim3(256), 0, st, hdr, fin, W,
+  uint32_t* part = (uint32_t*)(ws + L.part);
+  const uint32_t kmax = (uint32_t)det->max_keypoints;
+  hipLaunchKernelGGL(k_det_select1, dim3(64), dim3(256), 0, st, hdr, hist, cand, sel, kmax);
+  hipLaunchKernelGGL(k_det_select2, dim3(1), dim3(1024), 0, st, hdr, sel, fin, kmax);
+  const int blocks = (int)((kmax + 255) / 256);
+  hipLaunchKernelGGL(k_det_rank, dim3(blocks, L.n_part), dim3(256), 0, st, hdr, fin, part, kmax);
+  hipLaunchKernelGGL(k_det_emit, dim3(blocks), dim3(256), 0, st, hdr, fin, part, L.n_part, kmax, W,
                      (KeypointOut*)kpts, n_kpts_dev);
   return launch_status();
 }
@@ -578,7 +593,7 @@ rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32
   }
   ps8.finish();
   ProfScope ps9(9, st);
-  hipLaunchKernelGGL(k_match_merge, dim3((cap_a + 255) / 256), dim3(256), 0, st, part, 2 * L.slices, nA_dev, kp_a, kp_b,
+  hipLaunchKernelGGL(k_match_merge, dim3((cap_a + 3) / 4), dim3(256), 0, st, part, 2 * L.slices, nA_dev, kp_a, kp_b,
                      mp->ratio_sq, cap_a, best, rowj, rowd);
   hipLaunchKernelGGL(k_match_emit, dim3((cap_a + 255) / 256), dim3(256), 0, st, best, cap_a, rowj, rowd, kp_b,
                      (MatchOut*)out, n_out_dev);

@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "scan.hpp"
+
 namespace rift2 {
 
 // fl32(1 / fl32(sqrt(n))) correctly rounded, for 0 < n < 2^24.  The hardware
@@ -157,51 +159,39 @@ __global__ void __launch_bounds__(256) k_describe2(const int32_t* __restrict__ n
                                                    float* __restrict__ inv_norm, int32_t* __restrict__ desc_kp,
                                                    int32_t* __restrict__ n_desc) {
   constexpr int D = G * G * NO;
-  __shared__ uint32_t red[256];
+  __shared__ uint32_t scratch[256];
   __shared__ int flagged[256];
-  __shared__ int nflag;
+  __shared__ uint32_t sh_base, sh_nflag;
   const int n = min(*n_kpts, kpt_cap);
   const int start = blockIdx.x * 256;
   if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) *n_desc = 0;
   if (start >= n) return;
-  // flags before this block
   uint32_t before = 0;
   for (int j = threadIdx.x; j < start; j += 256) before += (info[j] >> 8) & 1u;
-  red[threadIdx.x] = before;
-  if (threadIdx.x == 0) nflag = 0;
+  const uint32_t tot = block_inclusive_scan<256>(before, scratch);
+  if (threadIdx.x == 255) sh_base = tot;
+  const int i = start + threadIdx.x;
+  const uint32_t f = (i < n) ? ((info[i] >> 8) & 1u) : 0u;
+  const uint32_t incl = block_inclusive_scan<256>(f, scratch);
+  if (f) flagged[incl - 1] = i;
+  if (threadIdx.x == 255) sh_nflag = incl;
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
+  const uint32_t base = sh_base;
+  const int nflag = (int)sh_nflag;
+  if (threadIdx.x == 0 && min(n, start + 256) == n) *n_desc = n + (int)base + nflag;
+  for (int idx = threadIdx.x; idx < nflag * D; idx += 256) {
+    const int fi = idx / D, e = idx - fi * D;
+    const int src_kp = flagged[fi];
+    const int delta = (int)(info[src_kp] & 0xffu);
+    const int c = e / NO, b = e - c * NO;
+    int bb = b + delta;
+    if (bb >= NO) bb -= NO;
+    desc[(size_t)(n + base + fi) * D + e] = desc[(size_t)src_kp * D + c * NO + bb];
   }
-  const uint32_t base = red[0];
-  __syncthreads();
-  // ordered list of this block's flagged keypoints (serial scan keeps keypoint order)
-  if (threadIdx.x == 0) {
-    int c = 0;
-    const int end = min(n, start + 256);
-    for (int j = start; j < end; ++j)
-      if ((info[j] >> 8) & 1u) flagged[c++] = j;
-    nflag = c;
-    if (end == n) *n_desc = n + (int)base + c;
-  }
-  __syncthreads();
-  for (int f = 0; f < nflag; ++f) {
-    const int i = flagged[f];
-    const int delta = (int)(info[i] & 0xffu);
-    const int row = n + (int)base + f;
-    const uint16_t* src = desc + (size_t)i * D;
-    uint16_t* dst = desc + (size_t)row * D;
-    for (int e = threadIdx.x; e < D; e += 256) {
-      const int c = e / NO, b = e % NO;
-      int bb = b + delta;
-      if (bb >= NO) bb -= NO;
-      dst[e] = src[c * NO + bb];
-    }
-    if (threadIdx.x == 0) {
-      inv_norm[row] = inv_norm[i];
-      desc_kp[row] = i;
-    }
+  for (int fi = threadIdx.x; fi < nflag; fi += 256) {
+    const int row = n + (int)base + fi;
+    inv_norm[row] = inv_norm[flagged[fi]];
+    desc_kp[row] = flagged[fi];
   }
 }
 

@@ -7,14 +7,19 @@
 //                 tie-break, patch-border mask; survivors appended as 64-bit
 //                 keys (score bits << 32 | ~raster) plus a histogram of the
 //                 top 16 score bits
-//   k_det_select  threshold bin of rank K, candidates at or above it gathered;
-//                 the last block radix-selects the exact K-th key on the
-//                 boundary bin and compacts the K winners
-//   k_det_sort    rank of every winner by counting larger keys -> output order
+//   k_det_select1 score bin of rank K (block-wide prefix search), candidates
+//                 of that bin and above gathered
+//   k_det_select2 one block: exact K-th key by a 4 x 12-bit radix selection
+//                 over the boundary bin (staged in LDS), winners compacted
+//   k_det_rank    rank of every winner = number of larger keys, counted over
+//                 key chunks in parallel
+//   k_det_emit    output record at its rank
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "scan.hpp"
 
 namespace rift2 {
 
@@ -24,7 +29,7 @@ constexpr int kHalo = 4;  // FAST radius 3 + NMS 1
 
 struct DetWs {
   // header (uint32 words), zeroed per call
-  uint32_t* hdr;      // [0] n_cand, [1] done, [2] n_sel, [3] n_final, [4] min key, [5] max key, [6] done2
+  uint32_t* hdr;      // [0] n_cand, [2] n_sel, [3] n_final, [4] min key, [5] max key, [8] bin, [9] above
   uint32_t* hist;     // kDetHistBins
   uint64_t* cand;     // candidate keys
   uint64_t* sel;      // keys at or above the threshold bin
@@ -47,6 +52,7 @@ __global__ void k_det_init(uint32_t* __restrict__ hdr, uint32_t* __restrict__ hi
 }
 
 __global__ void __launch_bounds__(256) k_det_minmax(const float* __restrict__ d, int n, uint32_t* __restrict__ hdr) {
+  __shared__ uint32_t red[2][4];
   uint32_t lo = 0xffffffffu, hi = 0u;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const uint32_t k = float_order_key(d[i]);
@@ -58,6 +64,15 @@ __global__ void __launch_bounds__(256) k_det_minmax(const float* __restrict__ d,
     hi = max(hi, (uint32_t)__shfl_xor((int)hi, off));
   }
   if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = lo;
+    red[1][threadIdx.x >> 6] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) {
+      lo = min(lo, red[0][w]);
+      hi = max(hi, red[1][w]);
+    }
     atomicMin(&hdr[4], lo);
     atomicMax(&hdr[5], hi);
   }
@@ -164,39 +179,35 @@ __global__ void __launch_bounds__(kTileX * kTileY) k_det_fast(const float* __res
   }
 }
 
-// Find the score bin of rank K (counted from the top), gather candidates of
-// that bin and above; the last block finishes the exact selection.
-__global__ void __launch_bounds__(256) k_det_select(uint32_t* __restrict__ hdr, const uint32_t* __restrict__ hist,
-                                                    const uint64_t* __restrict__ cand, uint64_t* __restrict__ sel,
-                                                    uint64_t* __restrict__ fin, uint32_t kmax) {
-  __shared__ uint32_t part[256];
-  __shared__ uint32_t sh_bin, sh_above, sh_last;
-  __shared__ uint32_t lh[4096];
+// Score bin holding the K-th best candidate; gather every candidate of that
+// bin and above into `sel`.
+__global__ void __launch_bounds__(256) k_det_select1(uint32_t* __restrict__ hdr, const uint32_t* __restrict__ hist,
+                                                     const uint64_t* __restrict__ cand, uint64_t* __restrict__ sel,
+                                                     uint32_t kmax) {
+  __shared__ uint32_t scratch[256];
+  __shared__ int sh_bin;
+  __shared__ uint32_t sh_above;
   const uint32_t n = hdr[0];
   const uint32_t k = min(kmax, n);
-  // Suffix search: thread t owns bins [PER t, PER t + PER).
-  constexpr int PER = kDetHistBins / 256;
-  uint32_t sum = 0;
-  for (int i = 0; i < PER; ++i) sum += hist[threadIdx.x * PER + i];
-  part[threadIdx.x] = sum;
-  __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t bin = 0, above = 0;
-    if (k > 0 && k < n) {
-      int c = 255;
-      while (c > 0 && above + part[c] < k) above += part[c--];
-      int b = c * PER + PER - 1;
-      while (b > c * PER && above + hist[b] < k) above += hist[b--];
-      bin = (uint32_t)b;
-    }
-    sh_bin = bin;      // candidates with (score bits >> 16) >= bin are gathered
-    sh_above = above;  // count strictly above bin
+    sh_bin = 0;
+    sh_above = 0;
   }
   __syncthreads();
-  const uint32_t bin = sh_bin;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const uint64_t key = cand[i];
-    const bool take = (uint32_t)(key >> 48) >= bin;
+  if (k > 0 && k < n) block_find_rank<kDetHistBins, 256, true>(hist, k - 1, &sh_bin, &sh_above, scratch);
+  const uint32_t bin = (uint32_t)sh_bin;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    hdr[8] = bin;
+    hdr[9] = sh_above;
+  }
+  for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < n; i0 += gridDim.x * blockDim.x) {
+    const uint32_t i = i0 + threadIdx.x;
+    uint64_t key = 0;
+    bool take = false;
+    if (i < n) {
+      key = cand[i];
+      take = (uint32_t)(key >> 48) >= bin;
+    }
     const uint64_t mask = __ballot(take);
     if (mask) {
       const int lane = threadIdx.x & 63;
@@ -207,52 +218,65 @@ __global__ void __launch_bounds__(256) k_det_select(uint32_t* __restrict__ hdr, 
       if (take) sel[base + __popcll(mask & ((1ull << lane) - 1ull))] = key;
     }
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) sh_last = (atomicAdd(&hdr[1], 1u) == gridDim.x - 1);
-  __syncthreads();
-  if (!sh_last) return;
-  __threadfence();
-  const uint32_t ns = __atomic_load_n(&hdr[2], __ATOMIC_RELAXED);
-  // Exact K-th largest key among sel: keys of bins above `bin` are all in;
-  // within `bin` select rank (k - above - 1) from the top by 4 levels of 12 bits
-  // over the low 48 bits (16 score bits + 32 inverted raster bits).
-  uint64_t kth = 0;  // every key >= kth is a winner
+}
+
+constexpr int kEdgeMax = 4096;
+
+// One block of 1024 threads: exact K-th key inside the boundary bin, then the
+// winners (keys >= K-th key) compacted into `fin` (exactly min(K, n) keys,
+// the keys being distinct).
+__global__ void __launch_bounds__(1024) k_det_select2(uint32_t* __restrict__ hdr, const uint64_t* __restrict__ sel,
+                                                      uint64_t* __restrict__ fin, uint32_t kmax) {
+  __shared__ uint32_t scratch[1024];
+  __shared__ uint32_t lh[4096];
+  __shared__ uint64_t edge[kEdgeMax];
+  __shared__ uint32_t n_edge;
+  __shared__ int sh_b;
+  __shared__ uint32_t sh_before;
+  const uint32_t n = hdr[0];
+  const uint32_t k = min(kmax, n);
+  const uint32_t ns = hdr[2];
+  const uint64_t bin = hdr[8];
+  uint64_t kth = 0;
   if (k > 0 && k < n) {
-    uint32_t r = k - sh_above - 1;  // 0-based rank from the top inside the bin
-    uint64_t prefix = bin;           // known high bits
+    if (threadIdx.x == 0) n_edge = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < ns; i += 1024) {
+      const uint64_t key = sel[i];
+      if ((key >> 48) == bin) {
+        const uint32_t pos = atomicAdd(&n_edge, 1u);
+        if (pos < kEdgeMax) edge[pos] = key;
+      }
+    }
+    __syncthreads();
+    const uint32_t ne = n_edge;
+    const bool staged = ne <= kEdgeMax;
+    uint32_t r = k - hdr[9] - 1;  // rank from the top inside the bin
+    uint64_t prefix = bin;
     int known = 16;
     for (int lv = 0; lv < 4; ++lv) {
       const int shift = 64 - known - 12;
-      for (int i = threadIdx.x; i < 4096; i += 256) lh[i] = 0u;
+      for (int i = threadIdx.x; i < 4096; i += 1024) lh[i] = 0u;
       __syncthreads();
-      for (uint32_t i = threadIdx.x; i < ns; i += 256) {
-        const uint64_t key = __atomic_load_n(&sel[i], __ATOMIC_RELAXED);
+      const uint32_t cnt = staged ? ne : ns;
+      for (uint32_t i = threadIdx.x; i < cnt; i += 1024) {
+        const uint64_t key = staged ? edge[i] : sel[i];
         if ((key >> (64 - known)) == prefix) atomicAdd(&lh[(key >> shift) & 4095u], 1u);
       }
       __syncthreads();
-      if (threadIdx.x == 0) {
-        uint32_t acc = 0;
-        int b = 4095;
-        while (b > 0 && acc + lh[b] <= r) acc += lh[b--];
-        sh_bin = (uint32_t)b;
-        sh_above = acc;
-      }
-      __syncthreads();
-      r -= sh_above;
-      prefix = (prefix << 12) | sh_bin;
+      block_find_rank<4096, 1024, true>(lh, r, &sh_b, &sh_before, scratch);
+      r -= sh_before;
+      prefix = (prefix << 12) | (uint64_t)sh_b;
       known += 12;
-      __syncthreads();
     }
     kth = prefix;
   }
-  // Compact the winners.
-  for (uint32_t i0 = 0; i0 < ns; i0 += 256) {
+  for (uint32_t i0 = 0; i0 < ns; i0 += 1024) {
     const uint32_t i = i0 + threadIdx.x;
     uint64_t key = 0;
     bool take = false;
     if (i < ns) {
-      key = __atomic_load_n(&sel[i], __ATOMIC_RELAXED);
+      key = sel[i];
       take = key >= kth;
     }
     const uint64_t mask = __ballot(take);
@@ -272,31 +296,45 @@ struct KeypointOut {
   float score;
 };
 
-// Output position of each winner = number of winners with a larger key.
-__global__ void __launch_bounds__(256) k_det_sort(const uint32_t* __restrict__ hdr, const uint64_t* __restrict__ fin,
-                                                  int W, KeypointOut* __restrict__ out, int32_t* __restrict__ n_out) {
+// Partial ranks: grid = (ceil(kmax / 256), S); block y counts, for each of its
+// 256 winners, the larger keys among winners [y n / S, (y + 1) n / S).
+__global__ void __launch_bounds__(256) k_det_rank(const uint32_t* __restrict__ hdr, const uint64_t* __restrict__ fin,
+                                                  uint32_t* __restrict__ part, uint32_t kmax) {
   __shared__ uint64_t tile[1024];
   const uint32_t n = hdr[3];
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *n_out = (int32_t)n;
-  if (blockIdx.x * blockDim.x >= n) return;
+  if (blockIdx.x * 256 >= n) return;
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
   const uint64_t mine = i < n ? fin[i] : 0;
+  const uint32_t beg = (uint32_t)((uint64_t)n * blockIdx.y / gridDim.y);
+  const uint32_t end = (uint32_t)((uint64_t)n * (blockIdx.y + 1) / gridDim.y);
   uint32_t rank = 0;
-  for (uint32_t t0 = 0; t0 < n; t0 += 1024) {
-    const uint32_t cnt = min(1024u, n - t0);
+  for (uint32_t t0 = beg; t0 < end; t0 += 1024) {
+    const uint32_t cnt = min(1024u, end - t0);
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < cnt; j += 256) tile[j] = fin[t0 + j];
     __syncthreads();
+#pragma unroll 8
     for (uint32_t j = 0; j < cnt; ++j) rank += tile[j] > mine ? 1u : 0u;
   }
-  if (i < n) {
-    const uint32_t raster = ~(uint32_t)(mine & 0xffffffffu);
-    KeypointOut kp;
-    kp.x = (int)(raster % (uint32_t)W);
-    kp.y = (int)(raster / (uint32_t)W);
-    kp.score = __uint_as_float((uint32_t)(mine >> 32));
-    out[rank] = kp;
-  }
+  if (i < n) part[(size_t)blockIdx.y * kmax + i] = rank;
+}
+
+__global__ void __launch_bounds__(256) k_det_emit(const uint32_t* __restrict__ hdr, const uint64_t* __restrict__ fin,
+                                                  const uint32_t* __restrict__ part, int n_part, uint32_t kmax, int W,
+                                                  KeypointOut* __restrict__ out, int32_t* __restrict__ n_out) {
+  const uint32_t n = hdr[3];
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *n_out = (int32_t)n;
+  if (i >= n) return;
+  uint32_t rank = 0;
+  for (int s = 0; s < n_part; ++s) rank += part[(size_t)s * kmax + i];
+  const uint64_t key = fin[i];
+  const uint32_t raster = ~(uint32_t)(key & 0xffffffffu);
+  KeypointOut kp;
+  kp.x = (int)(raster % (uint32_t)W);
+  kp.y = (int)(raster / (uint32_t)W);
+  kp.score = __uint_as_float((uint32_t)(key >> 32));
+  out[rank] = kp;
 }
 
 }  // namespace rift2

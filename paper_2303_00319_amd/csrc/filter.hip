@@ -14,6 +14,7 @@
 #pragma once
 
 #include "fft.hpp"
+#include "scan.hpp"
 
 namespace rift2 {
 
@@ -224,55 +225,52 @@ __global__ void __launch_bounds__(256) k_noise_pre(const float2* __restrict__ y_
   }
 }
 
-// Block-wide exclusive search: first bin b with cumulative count > rank.
-// Returns b and the count of values in bins < b.  blockDim.x == 256.
-__device__ void find_rank_bin(const uint32_t* hist, int nbins, uint32_t rank, int* out_bin, uint32_t* out_below,
-                              uint32_t* scratch /* 256 */) {
-  const int per = nbins / 256;
-  uint32_t sum = 0;
-  for (int i = 0; i < per; ++i) sum += hist[threadIdx.x * per + i];
-  scratch[threadIdx.x] = sum;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    int chunk = 0;
-    while (chunk < 255 && acc + scratch[chunk] <= rank) acc += scratch[chunk++];
-    int b = chunk * per;
-    while (b < chunk * per + per - 1 && acc + hist[b] <= rank) acc += hist[b++];
-    *out_bin = b;
-    *out_below = acc;
-  }
-  __syncthreads();
-}
+// Exact median of A0_o (mean of the order statistics of rank HW/2-1 and HW/2)
+// by a three-level radix selection on the float bit patterns (values are
+// non-negative, so the bits order like the values): 13 bits (level 1, built
+// by k_noise_pre), 10 bits, 9 bits.
+constexpr int kHist2 = 1024, kHist3 = 512;
 
-// Exact median of A0_o (mean of ranks HW/2-1 and HW/2) and T_o.
-// grid = (chunks, N_o), block 256.  Every block finds the level-1 bins of the
-// two ranks, appends the values of those bins to cand[o]; the last block to
-// finish runs the remaining radix levels on the candidate list.
 struct NoiseConsts {
   double mult, k;
   int n_scales;
 };
 
-__global__ void __launch_bounds__(256) k_noise_sel(const float* __restrict__ a0, int hw,
-                                                   const uint32_t* __restrict__ hist1, uint32_t* __restrict__ cand,
-                                                   uint32_t* __restrict__ counters, NoiseConsts nc,
-                                                   float* __restrict__ t_out, double* __restrict__ t_out64) {
+struct NoiseWs {
+  uint32_t* hist1;  // [N_o][kHist1]
+  uint32_t* hist2;  // [N_o][2][kHist2]
+  uint32_t* hist3;  // [N_o][2][kHist3]
+  uint32_t* cnt;    // [N_o] candidate list lengths
+  uint32_t* done;   // [N_o] finished blocks of k_noise_sel2
+  uint32_t* cand;   // [N_o][HW] candidate bit patterns
+};
+
+__device__ __forceinline__ void wave_append(bool take, uint32_t value, uint32_t* counter, uint32_t* list) {
+  const uint64_t mask = __ballot(take);
+  if (!mask) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+  base = __shfl(base, leader);
+  if (take) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = value;
+}
+
+// Level 2: every block finds the level-1 bins of both ranks, appends the
+// values of those bins to the candidate list and histograms their next 10 bits.
+__global__ void __launch_bounds__(256) k_noise_sel1(const float* __restrict__ a0, int hw, NoiseWs ws) {
   __shared__ uint32_t scratch[256];
-  __shared__ uint32_t hist[1024];
+  __shared__ uint32_t h2[2][kHist2];
   __shared__ int s_bin[2];
   __shared__ uint32_t s_below[2];
-  __shared__ int s_last;
   const int o = blockIdx.y;
-  const int n_orient = gridDim.y;
-  uint32_t* cnt = counters + o;
-  uint32_t* done = counters + n_orient + o;
-  const uint32_t* gh = hist1 + (size_t)o * kHist1;
+  for (int i = threadIdx.x; i < 2 * kHist2; i += 256) (&h2[0][0])[i] = 0u;
   const uint32_t rank[2] = {(uint32_t)(hw / 2 - 1), (uint32_t)(hw / 2)};
-  for (int q = 0; q < 2; ++q) find_rank_bin(gh, kHist1, rank[q], &s_bin[q], &s_below[q], scratch);
+  const uint32_t* gh1 = ws.hist1 + (size_t)o * kHist1;
+  for (int q = 0; q < 2; ++q) block_find_rank<kHist1, 256, false>(gh1, rank[q], &s_bin[q], &s_below[q], scratch);
   const uint32_t b0 = (uint32_t)s_bin[0], b1 = (uint32_t)s_bin[1];
   const float* src = a0 + (size_t)o * hw;
-  uint32_t* list = cand + (size_t)o * hw;
+  uint32_t* list = ws.cand + (size_t)o * hw;
   const int per_block = (hw + gridDim.x - 1) / gridDim.x;
   const int beg = blockIdx.x * per_block;
   const int end = min(hw, beg + per_block);
@@ -282,59 +280,69 @@ __global__ void __launch_bounds__(256) k_noise_sel(const float* __restrict__ a0,
     bool take = false;
     if (i < end) {
       bits = __float_as_uint(src[i]);
-      const uint32_t key = bits >> (32 - kHistBits1 - 1);
+      const uint32_t key = bits >> 19;
+      const uint32_t sub = (bits >> 9) & (kHist2 - 1);
+      if (key == b0) atomicAdd(&h2[0][sub], 1u);
+      if (key == b1) atomicAdd(&h2[1][sub], 1u);
       take = (key == b0) || (key == b1);
     }
-    // wave-aggregated append
-    const uint64_t mask = __ballot(take);
-    const int lane = threadIdx.x & 63;
-    const int nwave = __popcll(mask);
-    uint32_t base = 0;
-    if (nwave) {
-      const int leader = __ffsll((unsigned long long)mask) - 1;
-      if (lane == leader) base = atomicAdd(cnt, (uint32_t)nwave);
-      base = __shfl(base, leader);
-      if (take) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = bits;
-    }
+    wave_append(take, bits, ws.cnt + o, list);
+  }
+  __syncthreads();
+  uint32_t* gh2 = ws.hist2 + (size_t)o * 2 * kHist2;
+  for (int i = threadIdx.x; i < 2 * kHist2; i += 256) {
+    const uint32_t c = (&h2[0][0])[i];
+    if (c) atomicAdd(&gh2[i], c);
+  }
+}
+
+// Level 3 over the candidate list, then the last block resolves both ranks
+// and evaluates the noise threshold in FP64.
+__global__ void __launch_bounds__(256) k_noise_sel2(int hw, NoiseWs ws, NoiseConsts nc, float* __restrict__ t_out,
+                                                    double* __restrict__ t_out64) {
+  __shared__ uint32_t scratch[256];
+  __shared__ uint32_t h3[2][kHist3];
+  __shared__ int s_bin[2], s_bin2[2], s_bin3[2];
+  __shared__ uint32_t s_below[2], s_below2[2], s_below3[2];
+  __shared__ int s_last;
+  const int o = blockIdx.y;
+  for (int i = threadIdx.x; i < 2 * kHist3; i += 256) (&h3[0][0])[i] = 0u;
+  const uint32_t rank[2] = {(uint32_t)(hw / 2 - 1), (uint32_t)(hw / 2)};
+  const uint32_t* gh1 = ws.hist1 + (size_t)o * kHist1;
+  const uint32_t* gh2 = ws.hist2 + (size_t)o * 2 * kHist2;
+  for (int q = 0; q < 2; ++q) {
+    block_find_rank<kHist1, 256, false>(gh1, rank[q], &s_bin[q], &s_below[q], scratch);
+    block_find_rank<kHist2, 256, false>(gh2 + q * kHist2, rank[q] - s_below[q], &s_bin2[q], &s_below2[q], scratch);
+  }
+  const uint32_t p0 = ((uint32_t)s_bin[0] << 10) | (uint32_t)s_bin2[0];
+  const uint32_t p1 = ((uint32_t)s_bin[1] << 10) | (uint32_t)s_bin2[1];
+  const uint32_t n = ws.cnt[o];
+  const uint32_t* list = ws.cand + (size_t)o * hw;
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const uint32_t bits = list[i];
+    const uint32_t pre = bits >> 9;
+    if (pre == p0) atomicAdd(&h3[0][bits & (kHist3 - 1)], 1u);
+    if (pre == p1) atomicAdd(&h3[1][bits & (kHist3 - 1)], 1u);
+  }
+  __syncthreads();
+  uint32_t* gh3 = ws.hist3 + (size_t)o * 2 * kHist3;
+  for (int i = threadIdx.x; i < 2 * kHist3; i += 256) {
+    const uint32_t c = (&h3[0][0])[i];
+    if (c) atomicAdd(&gh3[i], c);
   }
   __threadfence();
   __syncthreads();
-  if (threadIdx.x == 0) s_last = (atomicAdd(done, 1u) == gridDim.x - 1);
+  if (threadIdx.x == 0) s_last = (atomicAdd(ws.done + o, 1u) == gridDim.x - 1);
   __syncthreads();
   if (!s_last) return;
   __threadfence();
-  const uint32_t n = __atomic_load_n(cnt, __ATOMIC_RELAXED);
+  for (int i = threadIdx.x; i < 2 * kHist3; i += 256) (&h3[0][0])[i] = __atomic_load_n(&gh3[i], __ATOMIC_RELAXED);
+  __syncthreads();
   float vals[2];
   for (int q = 0; q < 2; ++q) {
-    const uint32_t bin = (uint32_t)s_bin[q];
-    uint32_t r = rank[q] - s_below[q];  // rank inside the level-1 bin
-    uint32_t prefix = bin;              // known high bits, right-aligned
-    int known = kHistBits1 + 1;         // bits determined so far (incl. sign)
-    const int levels[2] = {10, 9};      // remaining 19 bits
-    for (int lv = 0; lv < 2; ++lv) {
-      const int nb = levels[lv];
-      const int shift = 32 - known - nb;
-      for (int i = threadIdx.x; i < 1024; i += 256) hist[i] = 0u;
-      __syncthreads();
-      for (uint32_t i = threadIdx.x; i < n; i += 256) {
-        const uint32_t bits = __atomic_load_n(&list[i], __ATOMIC_RELAXED);
-        if ((bits >> (32 - known)) == prefix) atomicAdd(&hist[(bits >> shift) & ((1u << nb) - 1u)], 1u);
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        uint32_t acc = 0;
-        int b = 0;
-        while (b < (1 << nb) - 1 && acc + hist[b] <= r) acc += hist[b++];
-        s_bin[q] = b;
-        s_below[q] = acc;
-      }
-      __syncthreads();
-      r -= s_below[q];
-      prefix = (prefix << nb) | (uint32_t)s_bin[q];
-      known += nb;
-      __syncthreads();
-    }
-    vals[q] = __uint_as_float(prefix);
+    block_find_rank<kHist3, 256, false>(h3[q], rank[q] - s_below[q] - s_below2[q], &s_bin3[q], &s_below3[q],
+                                        scratch);
+    vals[q] = __uint_as_float((((uint32_t)s_bin[q] << 10 | (uint32_t)s_bin2[q]) << 9) | (uint32_t)s_bin3[q]);
   }
   if (threadIdx.x == 0) {
     const double med = 0.5 * ((double)vals[0] + (double)vals[1]);

@@ -198,38 +198,56 @@ __global__ void __launch_bounds__(256) k_match_gemm_f32(const float* __restrict_
 
 __device__ __forceinline__ bool better(float d, int j, float bd, int bj) { return d < bd || (d == bd && j < bj); }
 
-// One thread per A row.
+// Lexicographic (d, j) minimum over a wave.
+__device__ __forceinline__ void wave_argmin(float& d, int& j) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const float od = __shfl_xor(d, off);
+    const int oj = __shfl_xor(j, off);
+    if (oj >= 0 && (j < 0 || better(od, oj, d, j))) {
+      d = od;
+      j = oj;
+    }
+  }
+}
+
+// One wave per A row: merge the 2 x S top-3 lists, ratio test, keypoint best.
 __global__ void __launch_bounds__(256) k_match_merge(const int2* __restrict__ part, int lists,
                                                      const int32_t* __restrict__ na_dev, const int32_t* __restrict__ kp_a,
                                                      const int32_t* __restrict__ kp_b, float ratio_sq, int cap_a,
                                                      uint64_t* __restrict__ best, int32_t* __restrict__ row_j1,
                                                      float* __restrict__ row_d1) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int na = min(*na_dev, cap_a);
   if (i >= na) return;
   const int2* src = part + (size_t)i * lists * kTopK;
+  const int total = lists * kTopK;
   float d1 = INFINITY;
   int j1 = -1;
-  for (int q = 0; q < lists * kTopK; ++q) {
+  for (int q = lane; q < total; q += 64) {
     const int2 e = src[q];
     const float d = __int_as_float(e.x);
-    if (e.y >= 0 && better(d, e.y, d1, j1)) {
+    if (e.y >= 0 && (j1 < 0 || better(d, e.y, d1, j1))) {
       d1 = d;
       j1 = e.y;
     }
   }
+  wave_argmin(d1, j1);
   if (j1 < 0) return;
   const int k1 = kp_b[j1];
   float d2 = INFINITY;
   int j2 = -1;
-  for (int q = 0; q < lists * kTopK; ++q) {
+  for (int q = lane; q < total; q += 64) {
     const int2 e = src[q];
     const float d = __int_as_float(e.x);
-    if (e.y >= 0 && kp_b[e.y] != k1 && better(d, e.y, d2, j2)) {
+    if (e.y >= 0 && kp_b[e.y] != k1 && (j2 < 0 || better(d, e.y, d2, j2))) {
       d2 = d;
       j2 = e.y;
     }
   }
+  wave_argmin(d2, j2);
+  if (lane != 0) return;
   row_j1[i] = j1;
   row_d1[i] = d1;
   if (j2 < 0) return;
