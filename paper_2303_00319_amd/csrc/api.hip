@@ -33,6 +33,8 @@ struct Carver {
   }
 };
 
+constexpr int kNoiseRegions = 64;  // k_noise_sel1 blocks (candidate list regions) per orientation
+
 bool size_ok(int n) {
   switch (n) {
     case 256: case 512: case 768: case 1024: case 1536: case 2048: case 4096: return true;
@@ -67,7 +69,7 @@ FilterLayout filter_layout(int H, int W, const rift2_pc_params* p) {
   L.yplanes = c.take(hw * F * sizeof(float2));
   L.a0 = c.take(hw * p->n_orient * sizeof(float));
   L.cand = c.take(hw * p->n_orient * sizeof(uint32_t));
-  L.zero_words = p->n_orient * (kHist1 + 2 * kHist2 + 2 * kHist3 + 2);
+  L.zero_words = p->n_orient * (kHist1 + 2 * kHist2 + 2 * kHist3 + 1 + kNoiseRegions);
   L.zero = c.take((size_t)L.zero_words * sizeof(uint32_t));
   L.t32 = c.take(p->n_orient * sizeof(float));
   L.t64 = c.take(p->n_orient * sizeof(double));
@@ -76,19 +78,23 @@ FilterLayout filter_layout(int H, int W, const rift2_pc_params* p) {
 }
 
 struct DetectLayout {
-  size_t hdr, hist, cand, sel, fin, part, total;
-  size_t cand_cap;
-  int n_part;
+  size_t hdr, hist, tile_cnt, cand, sel_cnt, sel, fin, part, total;
+  int n_tiles, n_part;
+  uint32_t region;
 };
 
 DetectLayout detect_layout(int H, int W, const rift2_detect_params* d) {
   DetectLayout L;
   Carver c;
-  L.cand_cap = (size_t)((H + 1) / 2) * ((W + 1) / 2);
+  L.n_tiles = ((W + kTileX - 1) / kTileX) * ((H + kTileY - 1) / kTileY);
+  const size_t slots = (size_t)L.n_tiles * kTileCap;
+  L.region = (uint32_t)((slots + kSelBlocks - 1) / kSelBlocks);
   L.hdr = c.take(64);
   L.hist = c.take(kDetHistBins * sizeof(uint32_t));
-  L.cand = c.take(L.cand_cap * sizeof(uint64_t));
-  L.sel = c.take(L.cand_cap * sizeof(uint64_t));
+  L.tile_cnt = c.take((size_t)L.n_tiles * sizeof(uint32_t));
+  L.cand = c.take(slots * sizeof(uint64_t));
+  L.sel_cnt = c.take(kSelBlocks * sizeof(uint32_t));
+  L.sel = c.take((size_t)L.region * kSelBlocks * sizeof(uint64_t));
   const size_t kmax = d ? (size_t)d->max_keypoints : 0;
   L.fin = c.take(kmax * sizeof(uint64_t) + 8);
   const int blocks = (int)((kmax + 255) / 256);
@@ -402,8 +408,9 @@ rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t
   nws.hist1 = zero;
   nws.hist2 = nws.hist1 + pc->n_orient * kHist1;
   nws.hist3 = nws.hist2 + pc->n_orient * 2 * kHist2;
-  nws.cnt = nws.hist3 + pc->n_orient * 2 * kHist3;
-  nws.done = nws.cnt + pc->n_orient;
+  nws.done = nws.hist3 + pc->n_orient * 2 * kHist3;
+  nws.cnt = nws.done + pc->n_orient;
+  nws.regions = kNoiseRegions;
   nws.cand = cand;
   float* t32 = (float*)(ws + L.t32);
   double* t64 = (double*)(ws + L.t64);
@@ -454,8 +461,7 @@ rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t
   const int hw = H * W;
   {
     ProfScope ps(3, st);
-    const int chunks = std::max(1, std::min(64, hw / 16384));
-    hipLaunchKernelGGL(k_noise_sel1, dim3(chunks, pc->n_orient), dim3(256), 0, st, a0, hw, nws);
+    hipLaunchKernelGGL(k_noise_sel1, dim3(kNoiseRegions, pc->n_orient), dim3(256), 0, st, a0, hw, nws);
     hipLaunchKernelGGL(k_noise_sel2, dim3(32, pc->n_orient), dim3(256), 0, st, hw, nws, nc, t32, t64);
   }
   {
@@ -478,20 +484,23 @@ rift2_status rift2_detect(const float* moment, int32_t H, int32_t W, const rift2
   char* ws = (char*)workspace;
   uint32_t* hdr = (uint32_t*)(ws + L.hdr);
   uint32_t* hist = (uint32_t*)(ws + L.hist);
+  uint32_t* tile_cnt = (uint32_t*)(ws + L.tile_cnt);
   uint64_t* cand = (uint64_t*)(ws + L.cand);
+  uint32_t* sel_cnt = (uint32_t*)(ws + L.sel_cnt);
   uint64_t* sel = (uint64_t*)(ws + L.sel);
   uint64_t* fin = (uint64_t*)(ws + L.fin);
+  uint32_t* part = (uint32_t*)(ws + L.part);
   (void)hipGetLastError();
   ProfScope ps(5, st);
   hipLaunchKernelGGL(k_det_init, dim3(kDetHistBins / 256), dim3(256), 0, st, hdr, hist);
   const int n = H * W;
   hipLaunchKernelGGL(k_det_minmax, dim3(std::min(256, (n + 255) / 256)), dim3(256), 0, st, moment, n, hdr);
   hipLaunchKernelGGL(k_det_fast, dim3((W + kTileX - 1) / kTileX, (H + kTileY - 1) / kTileY), dim3(kTileX * kTileY), 0, st,
-                     moment, H, W, det->fast_threshold, det->patch_size / 2, hdr, hist, cand);
-  uint32_t* part = (uint32_t*)(ws + L.part);
+                     moment, H, W, det->fast_threshold, det->patch_size / 2, hdr, hist, tile_cnt, cand);
   const uint32_t kmax = (uint32_t)det->max_keypoints;
-  hipLaunchKernelGGL(k_det_select1, dim3(64), dim3(256), 0, st, hdr, hist, cand, sel, kmax);
-  hipLaunchKernelGGL(k_det_select2, dim3(1), dim3(1024), 0, st, hdr, sel, fin, kmax);
+  hipLaunchKernelGGL(k_det_select1, dim3(kSelBlocks), dim3(256), 0, st, hdr, hist, tile_cnt, L.n_tiles, cand, sel,
+                     sel_cnt, kmax);
+  hipLaunchKernelGGL(k_det_select2, dim3(1), dim3(1024), 0, st, hdr, sel, sel_cnt, L.region, fin, kmax);
   const int blocks = (int)((kmax + 255) / 256);
   hipLaunchKernelGGL(k_det_rank, dim3(blocks, L.n_part), dim3(256), 0, st, hdr, fin, part, kmax);
   hipLaunchKernelGGL(k_det_emit, dim3(blocks), dim3(256), 0, st, hdr, fin, part, L.n_part, kmax, W,

@@ -173,25 +173,30 @@ __global__ void __launch_bounds__(256) k_describe2(const int32_t* __restrict__ n
   const int i = start + threadIdx.x;
   const uint32_t f = (i < n) ? ((info[i] >> 8) & 1u) : 0u;
   const uint32_t incl = block_inclusive_scan<256>(f, scratch);
-  if (f) flagged[incl - 1] = i;
+  // flagged[] holds (keypoint | delta << 24); keypoint indices stay below 2^24
+  if (f) flagged[incl - 1] = i | (int)((info[i] & 0xffu) << 24);
   if (threadIdx.x == 255) sh_nflag = incl;
   __syncthreads();
   const uint32_t base = sh_base;
   const int nflag = (int)sh_nflag;
   if (threadIdx.x == 0 && min(n, start + 256) == n) *n_desc = n + (int)base + nflag;
-  for (int idx = threadIdx.x; idx < nflag * D; idx += 256) {
-    const int fi = idx / D, e = idx - fi * D;
-    const int src_kp = flagged[fi];
-    const int delta = (int)(info[src_kp] & 0xffu);
+  // each thread owns descriptor elements e of every secondary row of the block
+  for (int e = threadIdx.x; e < D; e += 256) {
     const int c = e / NO, b = e - c * NO;
-    int bb = b + delta;
-    if (bb >= NO) bb -= NO;
-    desc[(size_t)(n + base + fi) * D + e] = desc[(size_t)src_kp * D + c * NO + bb];
+#pragma unroll 4
+    for (int fi = 0; fi < nflag; ++fi) {
+      const int packed = flagged[fi];
+      const int src_kp = packed & 0xffffff, delta = (packed >> 24) & 0xff;
+      int bb = b + delta;
+      if (bb >= NO) bb -= NO;
+      desc[(size_t)(n + base + fi) * D + e] = desc[(size_t)src_kp * D + c * NO + bb];
+    }
   }
   for (int fi = threadIdx.x; fi < nflag; fi += 256) {
     const int row = n + (int)base + fi;
-    inv_norm[row] = inv_norm[flagged[fi]];
-    desc_kp[row] = flagged[fi];
+    const int src_kp = flagged[fi] & 0xffffff;
+    inv_norm[row] = inv_norm[src_kp];
+    desc_kp[row] = src_kp;
   }
 }
 

@@ -27,14 +27,8 @@ constexpr int kDetHistBins = 1 << 14;  // score bits >> 16 for scores in (0, 1]
 constexpr int kTileX = 32, kTileY = 8;
 constexpr int kHalo = 4;  // FAST radius 3 + NMS 1
 
-struct DetWs {
-  // header (uint32 words), zeroed per call
-  uint32_t* hdr;      // [0] n_cand, [2] n_sel, [3] n_final, [4] min key, [5] max key, [8] bin, [9] above
-  uint32_t* hist;     // kDetHistBins
-  uint64_t* cand;     // candidate keys
-  uint64_t* sel;      // keys at or above the threshold bin
-  uint64_t* fin;      // exactly min(K, n_cand) winners
-};
+// Header words (zeroed per call): [0] candidates, [3] winners, [4] min key,
+// [5] max key, [8] boundary bin, [9] candidates above it.
 
 __device__ __forceinline__ uint32_t float_order_key(float f) {
   const uint32_t b = __float_as_uint(f);
@@ -105,16 +99,27 @@ __device__ __forceinline__ float fast_score(const float (&c)[16], float p) {
   return fmaxf(bright, dark);
 }
 
+// A tile keeps at most (kTileX/2) (kTileY/2) points: survivors of the 3x3
+// suppression are never 8-neighbours.
+constexpr int kTileCap = (kTileX / 2) * (kTileY / 2);
+
 __global__ void __launch_bounds__(kTileX * kTileY) k_det_fast(const float* __restrict__ d, int H, int W, float thr,
-                                                              int half_patch, uint32_t* __restrict__ hdr,
-                                                              uint32_t* __restrict__ hist, uint64_t* __restrict__ cand) {
+                                                              int half_patch, const uint32_t* __restrict__ hdr,
+                                                              uint32_t* __restrict__ hist, uint32_t* __restrict__ tile_cnt,
+                                                              uint64_t* __restrict__ cand) {
   constexpr int LX = kTileX + 2 * kHalo, LY = kTileY + 2 * kHalo;
   constexpr int SX = kTileX + 2, SY = kTileY + 2;
   __shared__ float sd[LY][LX];
   __shared__ float ss[SY][SX];
+  __shared__ uint32_t s_count;
+  const int tile = blockIdx.y * gridDim.x + blockIdx.x;
   const float lo = float_from_order_key(hdr[4]);
   const float hi = float_from_order_key(hdr[5]);
-  if (!(hi > lo)) return;  // flat map: no keypoints (uniform across the grid)
+  if (!(hi > lo)) {  // flat map: no keypoints (uniform across the grid)
+    if (threadIdx.x == 0) tile_cnt[tile] = 0u;
+    return;
+  }
+  if (threadIdx.x == 0) s_count = 0u;
   const float rng = __fsub_rn(hi, lo);
   const int x0 = blockIdx.x * kTileX - kHalo, y0 = blockIdx.y * kTileY - kHalo;
   for (int i = threadIdx.x; i < LX * LY; i += blockDim.x) {
@@ -168,56 +173,81 @@ __global__ void __launch_bounds__(kTileX * kTileY) k_det_fast(const float* __res
     const int lane = threadIdx.x & 63;
     const int leader = __ffsll((unsigned long long)mask) - 1;
     uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&hdr[0], (uint32_t)__popcll(mask));
+    if (lane == leader) base = atomicAdd(&s_count, (uint32_t)__popcll(mask));
     base = __shfl(base, leader);
     if (keep) {
       const uint32_t raster = (uint32_t)gy * (uint32_t)W + (uint32_t)gx;
       const uint32_t sb = __float_as_uint(sc);
-      cand[base + __popcll(mask & ((1ull << lane) - 1ull))] = ((uint64_t)sb << 32) | (uint64_t)(~raster);
+      cand[(size_t)tile * kTileCap + base + __popcll(mask & ((1ull << lane) - 1ull))] =
+          ((uint64_t)sb << 32) | (uint64_t)(~raster);
       atomicAdd(&hist[min(sb >> 16, (uint32_t)(kDetHistBins - 1))], 1u);
     }
   }
+  __syncthreads();
+  if (threadIdx.x == 0) tile_cnt[tile] = s_count;
 }
 
-// Score bin holding the K-th best candidate; gather every candidate of that
-// bin and above into `sel`.
+// Score bin holding the K-th best candidate; every candidate of that bin and
+// above is copied into this block's region of `sel` (region b covers the
+// candidate slots block b scans, so it cannot overflow).  Block 0 publishes
+// the candidate total, the bin and the count above it in hdr[0], [8], [9].
+constexpr int kSelBlocks = 64;
+
 __global__ void __launch_bounds__(256) k_det_select1(uint32_t* __restrict__ hdr, const uint32_t* __restrict__ hist,
+                                                     const uint32_t* __restrict__ tile_cnt, int n_tiles,
                                                      const uint64_t* __restrict__ cand, uint64_t* __restrict__ sel,
-                                                     uint32_t kmax) {
+                                                     uint32_t* __restrict__ sel_cnt, uint32_t kmax) {
   __shared__ uint32_t scratch[256];
   __shared__ int sh_bin;
-  __shared__ uint32_t sh_above;
-  const uint32_t n = hdr[0];
-  const uint32_t k = min(kmax, n);
+  __shared__ uint32_t sh_above, sh_total, s_count;
+  constexpr int PER = kDetHistBins / 256;
+  uint32_t sum = 0;
+  for (int i = 0; i < PER; ++i) sum += hist[threadIdx.x * PER + i];
+  const uint32_t incl = block_inclusive_scan<256>(sum, scratch);
+  if (threadIdx.x == 255) sh_total = incl;
   if (threadIdx.x == 0) {
     sh_bin = 0;
     sh_above = 0;
+    s_count = 0;
   }
   __syncthreads();
+  const uint32_t n = sh_total;
+  const uint32_t k = min(kmax, n);
   if (k > 0 && k < n) block_find_rank<kDetHistBins, 256, true>(hist, k - 1, &sh_bin, &sh_above, scratch);
   const uint32_t bin = (uint32_t)sh_bin;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
+    hdr[0] = n;
     hdr[8] = bin;
     hdr[9] = sh_above;
   }
-  for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < n; i0 += gridDim.x * blockDim.x) {
-    const uint32_t i = i0 + threadIdx.x;
+  const uint32_t slots = (uint32_t)n_tiles * kTileCap;
+  const uint32_t per = (slots + gridDim.x - 1) / gridDim.x;
+  const uint32_t beg = blockIdx.x * per;
+  const uint32_t end = min(slots, beg + per);
+  uint64_t* region = sel + beg;
+  for (uint32_t f0 = beg; f0 < end; f0 += 256) {
+    const uint32_t f = f0 + threadIdx.x;
     uint64_t key = 0;
     bool take = false;
-    if (i < n) {
-      key = cand[i];
-      take = (uint32_t)(key >> 48) >= bin;
+    if (f < end) {
+      const uint32_t t = f / kTileCap, i = f % kTileCap;
+      if (i < tile_cnt[t]) {
+        key = cand[f];
+        take = (uint32_t)(key >> 48) >= bin;
+      }
     }
     const uint64_t mask = __ballot(take);
     if (mask) {
       const int lane = threadIdx.x & 63;
       const int leader = __ffsll((unsigned long long)mask) - 1;
       uint32_t base = 0;
-      if (lane == leader) base = atomicAdd(&hdr[2], (uint32_t)__popcll(mask));
+      if (lane == leader) base = atomicAdd(&s_count, (uint32_t)__popcll(mask));
       base = __shfl(base, leader);
-      if (take) sel[base + __popcll(mask & ((1ull << lane) - 1ull))] = key;
+      if (take) region[base + __popcll(mask & ((1ull << lane) - 1ull))] = key;
     }
   }
+  __syncthreads();
+  if (threadIdx.x == 0) sel_cnt[blockIdx.x] = s_count;
 }
 
 constexpr int kEdgeMax = 4096;
@@ -226,26 +256,33 @@ constexpr int kEdgeMax = 4096;
 // winners (keys >= K-th key) compacted into `fin` (exactly min(K, n) keys,
 // the keys being distinct).
 __global__ void __launch_bounds__(1024) k_det_select2(uint32_t* __restrict__ hdr, const uint64_t* __restrict__ sel,
+                                                      const uint32_t* __restrict__ sel_cnt, uint32_t region_size,
                                                       uint64_t* __restrict__ fin, uint32_t kmax) {
   __shared__ uint32_t scratch[1024];
   __shared__ uint32_t lh[4096];
   __shared__ uint64_t edge[kEdgeMax];
-  __shared__ uint32_t n_edge;
+  __shared__ uint32_t n_edge, s_final;
   __shared__ int sh_b;
   __shared__ uint32_t sh_before;
   const uint32_t n = hdr[0];
   const uint32_t k = min(kmax, n);
-  const uint32_t ns = hdr[2];
   const uint64_t bin = hdr[8];
   uint64_t kth = 0;
+  if (threadIdx.x == 0) {
+    n_edge = 0;
+    s_final = 0;
+  }
+  __syncthreads();
   if (k > 0 && k < n) {
-    if (threadIdx.x == 0) n_edge = 0;
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < ns; i += 1024) {
-      const uint64_t key = sel[i];
-      if ((key >> 48) == bin) {
-        const uint32_t pos = atomicAdd(&n_edge, 1u);
-        if (pos < kEdgeMax) edge[pos] = key;
+    for (int rg = 0; rg < kSelBlocks; ++rg) {
+      const uint32_t cnt = sel_cnt[rg];
+      const uint64_t* list = sel + (size_t)rg * region_size;
+      for (uint32_t i = threadIdx.x; i < cnt; i += 1024) {
+        const uint64_t key = list[i];
+        if ((key >> 48) == bin) {
+          const uint32_t pos = atomicAdd(&n_edge, 1u);
+          if (pos < kEdgeMax) edge[pos] = key;
+        }
       }
     }
     __syncthreads();
@@ -258,10 +295,20 @@ __global__ void __launch_bounds__(1024) k_det_select2(uint32_t* __restrict__ hdr
       const int shift = 64 - known - 12;
       for (int i = threadIdx.x; i < 4096; i += 1024) lh[i] = 0u;
       __syncthreads();
-      const uint32_t cnt = staged ? ne : ns;
-      for (uint32_t i = threadIdx.x; i < cnt; i += 1024) {
-        const uint64_t key = staged ? edge[i] : sel[i];
-        if ((key >> (64 - known)) == prefix) atomicAdd(&lh[(key >> shift) & 4095u], 1u);
+      if (staged) {
+        for (uint32_t i = threadIdx.x; i < ne; i += 1024) {
+          const uint64_t key = edge[i];
+          if ((key >> (64 - known)) == prefix) atomicAdd(&lh[(key >> shift) & 4095u], 1u);
+        }
+      } else {
+        for (int rg = 0; rg < kSelBlocks; ++rg) {
+          const uint32_t cnt = sel_cnt[rg];
+          const uint64_t* list = sel + (size_t)rg * region_size;
+          for (uint32_t i = threadIdx.x; i < cnt; i += 1024) {
+            const uint64_t key = list[i];
+            if ((key >> (64 - known)) == prefix) atomicAdd(&lh[(key >> shift) & 4095u], 1u);
+          }
+        }
       }
       __syncthreads();
       block_find_rank<4096, 1024, true>(lh, r, &sh_b, &sh_before, scratch);
@@ -271,24 +318,30 @@ __global__ void __launch_bounds__(1024) k_det_select2(uint32_t* __restrict__ hdr
     }
     kth = prefix;
   }
-  for (uint32_t i0 = 0; i0 < ns; i0 += 1024) {
-    const uint32_t i = i0 + threadIdx.x;
-    uint64_t key = 0;
-    bool take = false;
-    if (i < ns) {
-      key = sel[i];
-      take = key >= kth;
-    }
-    const uint64_t mask = __ballot(take);
-    if (mask) {
-      const int lane = threadIdx.x & 63;
-      const int leader = __ffsll((unsigned long long)mask) - 1;
-      uint32_t base = 0;
-      if (lane == leader) base = atomicAdd(&hdr[3], (uint32_t)__popcll(mask));
-      base = __shfl(base, leader);
-      if (take) fin[base + __popcll(mask & ((1ull << lane) - 1ull))] = key;
+  for (int rg = 0; rg < kSelBlocks; ++rg) {
+    const uint32_t cnt = sel_cnt[rg];
+    const uint64_t* list = sel + (size_t)rg * region_size;
+    for (uint32_t i0 = 0; i0 < cnt; i0 += 1024) {
+      const uint32_t i = i0 + threadIdx.x;
+      uint64_t key = 0;
+      bool take = false;
+      if (i < cnt) {
+        key = list[i];
+        take = key >= kth;
+      }
+      const uint64_t mask = __ballot(take);
+      if (mask) {
+        const int lane = threadIdx.x & 63;
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&s_final, (uint32_t)__popcll(mask));
+        base = __shfl(base, leader);
+        if (take) fin[base + __popcll(mask & ((1ull << lane) - 1ull))] = key;
+      }
     }
   }
+  __syncthreads();
+  if (threadIdx.x == 0) hdr[3] = s_final;
 }
 
 struct KeypointOut {

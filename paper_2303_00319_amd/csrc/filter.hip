@@ -240,40 +240,46 @@ struct NoiseWs {
   uint32_t* hist1;  // [N_o][kHist1]
   uint32_t* hist2;  // [N_o][2][kHist2]
   uint32_t* hist3;  // [N_o][2][kHist3]
-  uint32_t* cnt;    // [N_o] candidate list lengths
+  uint32_t* cnt;    // [N_o][regions] candidate counts of each k_noise_sel1 block
+  int regions;      // k_noise_sel1 blocks per orientation
   uint32_t* done;   // [N_o] finished blocks of k_noise_sel2
   uint32_t* cand;   // [N_o][HW] candidate bit patterns
 };
 
-__device__ __forceinline__ void wave_append(bool take, uint32_t value, uint32_t* counter, uint32_t* list) {
+// Appends the taking lanes' values to this block's own list region; the
+// position comes from a block-local LDS counter (no global atomics).
+__device__ __forceinline__ void block_append(bool take, uint32_t value, uint32_t* lds_count, uint32_t* region) {
   const uint64_t mask = __ballot(take);
   if (!mask) return;
   const int lane = threadIdx.x & 63;
   const int leader = __ffsll((unsigned long long)mask) - 1;
   uint32_t base = 0;
-  if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+  if (lane == leader) base = atomicAdd(lds_count, (uint32_t)__popcll(mask));
   base = __shfl(base, leader);
-  if (take) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = value;
+  if (take) region[base + __popcll(mask & ((1ull << lane) - 1ull))] = value;
 }
 
-// Level 2: every block finds the level-1 bins of both ranks, appends the
-// values of those bins to the candidate list and histograms their next 10 bits.
+// Level 2: every block finds the level-1 bins of both ranks, copies the
+// values of those bins into its own region of the candidate list (region b
+// = its chunk of A0, so it cannot overflow) and histograms their next 10 bits.
 __global__ void __launch_bounds__(256) k_noise_sel1(const float* __restrict__ a0, int hw, NoiseWs ws) {
   __shared__ uint32_t scratch[256];
   __shared__ uint32_t h2[2][kHist2];
   __shared__ int s_bin[2];
   __shared__ uint32_t s_below[2];
+  __shared__ uint32_t s_count;
   const int o = blockIdx.y;
   for (int i = threadIdx.x; i < 2 * kHist2; i += 256) (&h2[0][0])[i] = 0u;
+  if (threadIdx.x == 0) s_count = 0u;
   const uint32_t rank[2] = {(uint32_t)(hw / 2 - 1), (uint32_t)(hw / 2)};
   const uint32_t* gh1 = ws.hist1 + (size_t)o * kHist1;
   for (int q = 0; q < 2; ++q) block_find_rank<kHist1, 256, false>(gh1, rank[q], &s_bin[q], &s_below[q], scratch);
   const uint32_t b0 = (uint32_t)s_bin[0], b1 = (uint32_t)s_bin[1];
   const float* src = a0 + (size_t)o * hw;
-  uint32_t* list = ws.cand + (size_t)o * hw;
   const int per_block = (hw + gridDim.x - 1) / gridDim.x;
   const int beg = blockIdx.x * per_block;
   const int end = min(hw, beg + per_block);
+  uint32_t* region = ws.cand + (size_t)o * hw + beg;
   for (int i0 = beg; i0 < end; i0 += 256) {
     const int i = i0 + threadIdx.x;
     uint32_t bits = 0;
@@ -286,9 +292,10 @@ __global__ void __launch_bounds__(256) k_noise_sel1(const float* __restrict__ a0
       if (key == b1) atomicAdd(&h2[1][sub], 1u);
       take = (key == b0) || (key == b1);
     }
-    wave_append(take, bits, ws.cnt + o, list);
+    block_append(take, bits, &s_count, region);
   }
   __syncthreads();
+  if (threadIdx.x == 0) ws.cnt[(size_t)o * gridDim.x + blockIdx.x] = s_count;
   uint32_t* gh2 = ws.hist2 + (size_t)o * 2 * kHist2;
   for (int i = threadIdx.x; i < 2 * kHist2; i += 256) {
     const uint32_t c = (&h2[0][0])[i];
@@ -316,13 +323,16 @@ __global__ void __launch_bounds__(256) k_noise_sel2(int hw, NoiseWs ws, NoiseCon
   }
   const uint32_t p0 = ((uint32_t)s_bin[0] << 10) | (uint32_t)s_bin2[0];
   const uint32_t p1 = ((uint32_t)s_bin[1] << 10) | (uint32_t)s_bin2[1];
-  const uint32_t n = ws.cnt[o];
-  const uint32_t* list = ws.cand + (size_t)o * hw;
-  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-    const uint32_t bits = list[i];
-    const uint32_t pre = bits >> 9;
-    if (pre == p0) atomicAdd(&h3[0][bits & (kHist3 - 1)], 1u);
-    if (pre == p1) atomicAdd(&h3[1][bits & (kHist3 - 1)], 1u);
+  const int per_region = (hw + ws.regions - 1) / ws.regions;
+  for (int rg = blockIdx.x; rg < ws.regions; rg += gridDim.x) {
+    const uint32_t n = ws.cnt[(size_t)o * ws.regions + rg];
+    const uint32_t* list = ws.cand + (size_t)o * hw + (size_t)rg * per_region;
+    for (uint32_t i = threadIdx.x; i < n; i += 256) {
+      const uint32_t bits = list[i];
+      const uint32_t pre = bits >> 9;
+      if (pre == p0) atomicAdd(&h3[0][bits & (kHist3 - 1)], 1u);
+      if (pre == p1) atomicAdd(&h3[1][bits & (kHist3 - 1)], 1u);
+    }
   }
   __syncthreads();
   uint32_t* gh3 = ws.hist3 + (size_t)o * 2 * kHist3;
