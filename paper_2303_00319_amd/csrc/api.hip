@@ -425,14 +425,15 @@ rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t
   fc.inv_2ln2_sigma = (float)(1.0 / (2.0 * ls * ls));
   for (int s = 0; s < pc->n_scales; ++s)
     fc.log_f0[s] = (float)std::log(1.0 / ((double)pc->min_wavelength * std::pow((double)pc->mult, (double)s)));
-  fc.lp_cutoff = pc->lp_cutoff;
-  fc.lp_order = pc->lp_order;
+  fc.log_lp_cutoff = (float)std::log((double)pc->lp_cutoff);
+  fc.two_n = (float)(2 * pc->lp_order);
   PCConsts pcc;
   std::memset(&pcc, 0, sizeof(pcc));
   for (int o = 0; o < pc->n_orient; ++o) {
     const double th = o * M_PI / pc->n_orient;
-    fc.cos_o[o] = pcc.cos_o[o] = (float)std::cos(th);
-    fc.sin_o[o] = pcc.sin_o[o] = (float)std::sin(th);
+    fc.theta_o[o] = (float)th;
+    pcc.cos_o[o] = (float)std::cos(th);
+    pcc.sin_o[o] = (float)std::sin(th);
   }
   const double sig_th = (M_PI / pc->n_orient) / (double)pc->dtheta_on_sigma;
   fc.inv_2sig_theta2 = (float)(1.0 / (2.0 * sig_th * sig_th));

@@ -3,8 +3,7 @@
 // A line of N complex points is spread over T = N / P threads, thread t
 // holding x[t + T*m], m = 0..P-1 ("strided layout").  Each radix-R stage runs
 // P/R butterflies per thread entirely in registers; between stages the line
-// is exchanged through LDS (separate real / imaginary arrays, padded one word
-// per 16 to spread banks).  The Stockham autosort ordering makes the first
+// is exchanged through LDS (interleaved complex, padded to spread banks).  The Stockham autosort ordering makes the first
 // stage read and the last stage write the strided layout directly, so a
 // transform costs (#stages - 1) LDS round trips and the result of X[k]
 // lands on thread k % T, register k / T -- natural order, coalesced for
@@ -180,10 +179,15 @@ RIFT2_PLAN(2048, 8, 4, 8, 8, 8, 4, 1, 1)
 RIFT2_PLAN(4096, 8, 4, 8, 8, 8, 8, 1, 1)
 #undef RIFT2_PLAN
 
-// Padded LDS index: one spare word per 16 keeps radix-16 strides off one bank.
+// LDS lines hold interleaved complex values (one float2 per point).  The
+// padded index puts one spare point after every 16 so radix-16 strides do not
+// land on one bank; a line is padded to 8 (mod 32) points so that lines of
+// adjacent teams start on different banks.
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
 template <int N>
-constexpr int lds_line() { return N + N / 16; }
+constexpr int lds_line() {
+  return ((N + N / 16 + 31) / 32) * 32 + 8;
+}
 
 // Twiddle e^{DIR 2 pi i m / N}, 0 <= m < N.
 template <int DIR, int N>
@@ -219,45 +223,39 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[P], int t) {
 
 // Write stage outputs to their Stockham positions, read back the strided layout.
 template <int N, int T, int P, int R, int NS>
-__device__ __forceinline__ void fft_exchange(float2 (&v)[P], int t, float* sre, float* sim) {
+__device__ __forceinline__ void fft_exchange(float2 (&v)[P], int t, float2* line) {
   constexpr int NB = P / R;
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int j = t + T * b;
     const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int pos = lds_pad(base + r * NS);
-      sre[pos] = v[b + r * NB].x;
-      sim[pos] = v[b + r * NB].y;
-    }
+    for (int r = 0; r < R; ++r) line[lds_pad(base + r * NS)] = v[b + r * NB];
   }
   __syncthreads();
 #pragma unroll
-  for (int m = 0; m < P; ++m) {
-    const int pos = lds_pad(t + T * m);
-    v[m] = make_float2(sre[pos], sim[pos]);
-  }
+  for (int m = 0; m < P; ++m) v[m] = line[lds_pad(t + T * m)];
   __syncthreads();
 }
 
 template <int DIR, class PL, int S, int NS>
-__device__ __forceinline__ void fft_run(float2 (&v)[PL::P], int t, float* sre, float* sim) {
+__device__ __forceinline__ void fft_run(float2 (&v)[PL::P], int t, float2* line) {
   if constexpr (S < PL::NR) {
     constexpr int R = PL::rad(S);
     fft_stage<DIR, PL::N, PL::T, PL::P, R, NS>(v, t);
     if constexpr (S + 1 < PL::NR) {
-      fft_exchange<PL::N, PL::T, PL::P, R, NS>(v, t, sre, sim);
-      fft_run<DIR, PL, S + 1, NS * R>(v, t, sre, sim);
+      fft_exchange<PL::N, PL::T, PL::P, R, NS>(v, t, line);
+      fft_run<DIR, PL, S + 1, NS * R>(v, t, line);
     }
   }
 }
 
 // Transform one line in the strided layout.  Every thread of the block must
-// call this (it contains block barriers); sre/sim are this team's LDS line.
+// call this (it contains block barriers); `line` is this team's LDS line of
+// lds_line<N>() points.
 template <int DIR, int N, int P>
-__device__ __forceinline__ void fft_line(float2 (&v)[P], int t, float* sre, float* sim) {
-  fft_run<DIR, FftPlan<N, P>, 0, 1>(v, t, sre, sim);
+__device__ __forceinline__ void fft_line(float2 (&v)[P], int t, float2* line) {
+  fft_run<DIR, FftPlan<N, P>, 0, 1>(v, t, line);
 }
 
 }  // namespace rift2

@@ -2,15 +2,19 @@
 //
 // Data flow for one H x W image, F = N_s * N_o filters:
 //   k_fwd_rows   image -> Rrow = row DFTs                          (row-major complex)
-//   k_pass_a     per column block: column DFT of Rrow -> spectrum S in
-//                registers; for every filter: S * G_{s,o} / (HW), inverse
-//                column DFT, transpose through LDS -> Y_{s,o}      (row-major complex)
+//   k_pass_a     per block of C columns (each wave spans C columns, so every
+//                global access is a C-point row segment): column DFT of Rrow
+//                -> spectrum S in registers; for every filter of the block's
+//                orientation group: S * G_{s,o} / (HW), inverse column DFT
+//                -> Y_{s,o}                                        (row-major complex)
 //   k_noise_pre  row IDFT of the s = 0 planes -> A0_o = |EO_{0,o}| and a
 //                12-bit radix histogram of its float bits per orientation
 //   k_noise_sel  exact median of A0_o (radix select over the candidate bin)
 //                and the noise threshold T_o, evaluated in FP64
-//   k_pass_b     per row: row IDFT of all F planes, per-pixel phase
-//                congruency, amplitude sums, MIM argmax and moments
+//   k_pass_b     per row and orientation: one row IDFT of the sum over scales
+//                (the total response E + iO, by linearity), then the row IDFT
+//                of each scale; per-pixel phase congruency, amplitude sums,
+//                MIM argmax and moments
 #pragma once
 
 #include "fft.hpp"
@@ -31,9 +35,9 @@ struct FilterConsts {
   int H, W, n_scales, n_orient;
   float log_f0[kMaxScales];    // ln(f0_s)
   float inv_2ln2_sigma;        // 1 / (2 ln^2 sigma_onf)
-  float lp_cutoff;
-  int lp_order;
-  float cos_o[kMaxOrient], sin_o[kMaxOrient];
+  float log_lp_cutoff;         // ln(lp_cutoff)
+  float two_n;                 // 2 * lp_order
+  float theta_o[kMaxOrient];   // o pi / N_o
   float inv_2sig_theta2;       // 1 / (2 sigma_theta^2)
   float inv_hw;                // 1 / (H W), folded into the filter
 };
@@ -52,9 +56,7 @@ __global__ void __launch_bounds__(256) k_fwd_rows(const Tin* __restrict__ img, i
   using PL = FftPlan<W, P>;
   constexpr int T = PL::T;
   constexpr int LINES = 256 / T;
-  constexpr int LP = lds_line<W>();
-  __shared__ float sre[LINES][LP];
-  __shared__ float sim[LINES][LP];
+  __shared__ float2 lines[LINES][lds_line<W>()];
   if (blockIdx.x == 0) {
     for (int i = threadIdx.x; i < n_zero; i += blockDim.x) zero[i] = 0u;
   }
@@ -64,7 +66,7 @@ __global__ void __launch_bounds__(256) k_fwd_rows(const Tin* __restrict__ img, i
   float2 v[P];
 #pragma unroll
   for (int m = 0; m < P; ++m) v[m] = make_float2((float)row[t + T * m], 0.0f);
-  fft_line<-1, W, P>(v, t, sre[team], sim[team]);
+  fft_line<-1, W, P>(v, t, lines[team]);
   float2* out = rrow + (size_t)y * W;
 #pragma unroll
   for (int m = 0; m < P; ++m) out[t + T * m] = v[m];
@@ -72,116 +74,85 @@ __global__ void __launch_bounds__(256) k_fwd_rows(const Tin* __restrict__ img, i
 
 // ---------------------------------------------------------------- pass A
 
-// Log-Gabor value factors of one DFT bin that do not depend on (s, o).
-struct BinGeom {
-  float lr;    // ln r
-  float lpn;   // low-pass * 1/(HW), 0 at DC and on Nyquist lines
-  float ct, st;  // cos theta, sin theta with theta = atan2(-v, u)
+// Polar coordinates of DFT bin (k, l): ln r and theta = atan2(-v, u).  DC and
+// the Nyquist row/column carry no filter response (dead).
+struct BinPolar {
+  float lr, th;
+  bool dead;
 };
 
-__device__ __forceinline__ BinGeom bin_geom(int k, int l, const FilterConsts& fc) {
-  BinGeom g;
+__device__ __forceinline__ BinPolar bin_polar(int k, int l, const FilterConsts& fc) {
+  BinPolar b;
   const int kt = (k >= (fc.H + 1) / 2) ? k - fc.H : k;
   const int lt = (l >= (fc.W + 1) / 2) ? l - fc.W : l;
   const float v = (float)kt / (float)fc.H;
   const float u = (float)lt / (float)fc.W;
-  const float r = sqrtf(u * u + v * v);
-  const bool dead = (kt == 0 && lt == 0) || ((fc.H & 1) == 0 && kt == -fc.H / 2) ||
-                    ((fc.W & 1) == 0 && lt == -fc.W / 2);
-  if (dead) {
-    g.lr = 0.0f;
-    g.lpn = 0.0f;
-    g.ct = 1.0f;
-    g.st = 0.0f;
-    return g;
-  }
-  g.lr = logf(r);
-  const float q = r / fc.lp_cutoff;
-  float qp = 1.0f;
-  for (int i = 0; i < 2 * fc.lp_order; ++i) qp *= q;
-  g.lpn = fc.inv_hw / (1.0f + qp);
-  g.ct = u / r;
-  g.st = -v / r;
-  return g;
+  b.dead = (kt == 0 && lt == 0) || ((fc.H & 1) == 0 && kt == -fc.H / 2) || ((fc.W & 1) == 0 && lt == -fc.W / 2);
+  b.lr = b.dead ? 0.0f : 0.5f * __logf(u * u + v * v);
+  b.th = atan2f(-v, u);
+  return b;
 }
 
-__device__ __forceinline__ float angular(const BinGeom& g, int o, const FilterConsts& fc) {
-  const float ds = g.st * fc.cos_o[o] - g.ct * fc.sin_o[o];
-  const float dc = g.ct * fc.cos_o[o] + g.st * fc.sin_o[o];
-  const float dth = fabsf(atan2f(ds, dc));
-  return expf(-dth * dth * fc.inv_2sig_theta2);
+// angular(o) * lowpass * 1/(HW) of one bin; the angular distance is theta -
+// theta_o wrapped to [-pi, pi].
+__device__ __forceinline__ float ang_lowpass(float lr, float th, bool dead, int o, const FilterConsts& fc) {
+  constexpr float kPi = 3.14159265358979323846f;
+  float d = th - fc.theta_o[o];
+  d = d > kPi ? d - 2.0f * kPi : (d < -kPi ? d + 2.0f * kPi : d);
+  const float ang = __expf(-d * d * fc.inv_2sig_theta2);
+  const float lp = 1.0f / (1.0f + __expf(fc.two_n * (lr - fc.log_lp_cutoff)));
+  return dead ? 0.0f : ang * lp * fc.inv_hw;
 }
 
-__device__ __forceinline__ float radial(const BinGeom& g, int s, const FilterConsts& fc) {
-  const float d = g.lr - fc.log_f0[s];
-  return expf(-d * d * fc.inv_2ln2_sigma);
-}
-
-// One block = C adjacent columns, one team of T threads per column.
+// One block = C adjacent columns; lane l of wave w works on column l % C and
+// column index t = l / C + (64 / C) w of its column's FFT team, so a wave's
+// global accesses are 64/C rows x C contiguous points.
 template <int H, int P, int C>
 __global__ void __launch_bounds__(C * (H / P)) k_pass_a(const float2* __restrict__ rrow, FilterConsts fc,
                                                       float2* __restrict__ y_out) {
   using PL = FftPlan<H, P>;
   constexpr int T = PL::T;
-  constexpr int NT = C * T;
-  constexpr int LP = lds_line<H>();
-  __shared__ float sre[C][LP];
-  __shared__ float sim[C][LP];
+  static_assert(64 % C == 0 && (C * T) % 64 == 0, "column mapping");
+  __shared__ float2 lines[C][lds_line<H>()];
   const int W = fc.W;
-  const int team = threadIdx.x / T, t = threadIdx.x % T;
-  const int l0 = blockIdx.x * C;
-  const int l = l0 + team;
-  // Column tile -> LDS, one column per team, natural order.
-  for (int i = threadIdx.x; i < H * C; i += NT) {
-    const int c = i % C, y = i / C;
-    const float2 val = rrow[(size_t)y * W + l0 + c];
-    sre[c][lds_pad(y)] = val.x;
-    sim[c][lds_pad(y)] = val.y;
-  }
-  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = lane % C;
+  const int t = lane / C + (64 / C) * wave;
+  const int l = blockIdx.x * C + c;
   float2 spec[P];
 #pragma unroll
-  for (int m = 0; m < P; ++m) {
-    const int pos = lds_pad(t + T * m);
-    spec[m] = make_float2(sre[team][pos], sim[team][pos]);
-  }
-  __syncthreads();
-  fft_line<-1, H, P>(spec, t, sre[team], sim[team]);  // spec[m] = S[k = t + T m][l]
+  for (int m = 0; m < P; ++m) spec[m] = rrow[(size_t)(t + T * m) * W + l];
+  fft_line<-1, H, P>(spec, t, lines[c]);  // spec[m] = S[k = t + T m][l]
 
+  float lr[P], th[P];
+  unsigned dead = 0u;
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    const BinPolar b = bin_polar(t + T * m, l, fc);
+    lr[m] = b.lr;
+    th[m] = b.th;
+    dead |= (unsigned)b.dead << m;
+  }
   const size_t plane = (size_t)H * W;
   // orientation group of this block (grid.y splits the bank for parallelism)
   const int o_beg = (int)(blockIdx.y * fc.n_orient / gridDim.y);
   const int o_end = (int)((blockIdx.y + 1) * fc.n_orient / gridDim.y);
   for (int o = o_beg; o < o_end; ++o) {
-    float ang[P], lr[P];
+    float ang[P];
 #pragma unroll
-    for (int m = 0; m < P; ++m) {
-      const BinGeom geo = bin_geom(t + T * m, l, fc);
-      ang[m] = angular(geo, o, fc) * geo.lpn;
-      lr[m] = geo.lr;
-    }
+    for (int m = 0; m < P; ++m) ang[m] = ang_lowpass(lr[m], th[m], (dead >> m) & 1u, o, fc);
     for (int s = 0; s < fc.n_scales; ++s) {
       const float lf0 = fc.log_f0[s];
       float2 v[P];
 #pragma unroll
       for (int m = 0; m < P; ++m) {
         const float d = lr[m] - lf0;
-        v[m] = cscale(spec[m], expf(-d * d * fc.inv_2ln2_sigma) * ang[m]);
+        v[m] = cscale(spec[m], __expf(-d * d * fc.inv_2ln2_sigma) * ang[m]);
       }
-      fft_line<+1, H, P>(v, t, sre[team], sim[team]);
+      fft_line<+1, H, P>(v, t, lines[c]);
+      float2* dst = y_out + (size_t)(o * fc.n_scales + s) * plane + l;
 #pragma unroll
-      for (int m = 0; m < P; ++m) {
-        const int pos = lds_pad(t + T * m);
-        sre[team][pos] = v[m].x;
-        sim[team][pos] = v[m].y;
-      }
-      __syncthreads();
-      float2* dst = y_out + (size_t)(o * fc.n_scales + s) * plane;
-      for (int i = threadIdx.x; i < H * C; i += NT) {
-        const int c = i % C, y = i / C;
-        dst[(size_t)y * W + l0 + c] = make_float2(sre[c][lds_pad(y)], sim[c][lds_pad(y)]);
-      }
-      __syncthreads();
+      for (int m = 0; m < P; ++m) dst[(size_t)(t + T * m) * W] = v[m];
     }
   }
 }
@@ -196,9 +167,7 @@ __global__ void __launch_bounds__(256) k_noise_pre(const float2* __restrict__ y_
   using PL = FftPlan<W, P>;
   constexpr int T = PL::T;
   constexpr int LINES = 256 / T;
-  constexpr int LP = lds_line<W>();
-  __shared__ float sre[LINES][LP];
-  __shared__ float sim[LINES][LP];
+  __shared__ float2 lines[LINES][lds_line<W>()];
   __shared__ uint32_t hist[kHist1];
   const int o = blockIdx.y;
   for (int i = threadIdx.x; i < kHist1; i += 256) hist[i] = 0u;
@@ -209,7 +178,7 @@ __global__ void __launch_bounds__(256) k_noise_pre(const float2* __restrict__ y_
   float2 v[P];
 #pragma unroll
   for (int m = 0; m < P; ++m) v[m] = src[t + T * m];
-  fft_line<+1, W, P>(v, t, sre[team], sim[team]);  // contains barriers: hist init is visible after
+  fft_line<+1, W, P>(v, t, lines[team]);  // contains barriers: hist init is visible after
   float* dst = a0 + (size_t)o * plane + (size_t)y * W;
 #pragma unroll
   for (int m = 0; m < P; ++m) {
@@ -367,23 +336,25 @@ __global__ void __launch_bounds__(256) k_noise_sel2(int hw, NoiseWs ws, NoiseCon
 
 // ---------------------------------------------------------------- pass B
 
-// Per row: IDFT of the F planes, per-pixel phase congruency per orientation
-// (energy along the mean phase, noise threshold T_o, spread weight), the
-// amplitude sum A_o, first argmax over o (MIM) and the moment sums.
+// Per row and orientation: Z = E + iO is the row IDFT of the scale-summed
+// planes (the IDFT is linear); then each scale's row IDFT z_s gives the
+// amplitude sum, the largest amplitude and sum_s |Im(z_s conj(Z))|, so that
+// the energy along the mean phase is En = (|Z|^2 - sum_s |Im(z_s conj Z)|) / X
+// with X = |Z| + eps -- the same quantity as sum_s (e_s phi_e + o_s phi_o -
+// |e_s phi_o - o_s phi_e|) without keeping every scale's response.
 template <int W, int P, int NS, int NO>
 __global__ void __launch_bounds__((row_block<W, P>())) k_pass_b(const float2* __restrict__ y_in, int H, PCConsts pcc,
-                                                const float* __restrict__ t_o, uint8_t* __restrict__ mim,
-                                                float* __restrict__ mmax, float* __restrict__ mmin,
-                                                float* __restrict__ amp) {
+                                                                const float* __restrict__ t_o, uint8_t* __restrict__ mim,
+                                                                float* __restrict__ mmax, float* __restrict__ mmin,
+                                                                float* __restrict__ amp) {
   using PL = FftPlan<W, P>;
   constexpr int T = PL::T;
   constexpr int LINES = row_block<W, P>() / T;
-  constexpr int LP = lds_line<W>();
-  __shared__ float sre[LINES][LP];
-  __shared__ float sim[LINES][LP];
+  __shared__ float2 lines[LINES][lds_line<W>()];
   const int team = threadIdx.x / T, t = threadIdx.x % T;
   const int y = blockIdx.x * LINES + team;
   const size_t plane = (size_t)H * W;
+  const size_t rowo = (size_t)y * W;
   float best[P], ma[P], mb[P], mc[P];
   int idx[P];
 #pragma unroll
@@ -393,54 +364,53 @@ __global__ void __launch_bounds__((row_block<W, P>())) k_pass_b(const float2* __
     ma[m] = mb[m] = mc[m] = 0.0f;
   }
   for (int o = 0; o < NO; ++o) {
-    const float thr = t_o[o];
-    float es[NS][P], os[NS][P];
+    const float2* base = y_in + (size_t)(o * NS) * plane + rowo + t;
+    float2 z[P];
 #pragma unroll
+    for (int m = 0; m < P; ++m) z[m] = base[T * m];
+#pragma unroll
+    for (int s = 1; s < NS; ++s) {
+#pragma unroll
+      for (int m = 0; m < P; ++m) z[m] = cadd(z[m], base[(size_t)s * plane + T * m]);
+    }
+    fft_line<+1, W, P>(z, t, lines[team]);
+    float sa[P], mx[P], si[P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) sa[m] = mx[m] = si[m] = 0.0f;
     for (int s = 0; s < NS; ++s) {
-      const float2* src = y_in + (size_t)(o * NS + s) * plane + (size_t)y * W;
       float2 v[P];
 #pragma unroll
-      for (int m = 0; m < P; ++m) v[m] = src[t + T * m];
-      fft_line<+1, W, P>(v, t, sre[team], sim[team]);
+      for (int m = 0; m < P; ++m) v[m] = base[(size_t)s * plane + T * m];
+      fft_line<+1, W, P>(v, t, lines[team]);
 #pragma unroll
       for (int m = 0; m < P; ++m) {
-        es[s][m] = v[m].x;
-        os[s][m] = v[m].y;
+        const float a = sqrtf(v[m].x * v[m].x + v[m].y * v[m].y);
+        sa[m] += a;
+        mx[m] = fmaxf(mx[m], a);
+        si[m] += fabsf(v[m].y * z[m].x - v[m].x * z[m].y);
       }
     }
+    const float thr = t_o[o];
     const float co = pcc.cos_o[o], so = pcc.sin_o[o];
 #pragma unroll
     for (int m = 0; m < P; ++m) {
-      float e_sum = 0.0f, o_sum = 0.0f, a_sum = 0.0f, a_max = 0.0f;
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const float a = sqrtf(es[s][m] * es[s][m] + os[s][m] * os[s][m]);
-        e_sum += es[s][m];
-        o_sum += os[s][m];
-        a_sum += a;
-        a_max = fmaxf(a_max, a);
-      }
-      const float xe = sqrtf(e_sum * e_sum + o_sum * o_sum) + pcc.eps;
-      const float ph_e = e_sum / xe, ph_o = o_sum / xe;
-      float en = 0.0f;
-#pragma unroll
-      for (int s = 0; s < NS; ++s)
-        en += es[s][m] * ph_e + os[s][m] * ph_o - fabsf(es[s][m] * ph_o - os[s][m] * ph_e);
-      const float spread = (a_sum / (a_max + pcc.eps) - 1.0f) / (float)(NS - 1);
-      const float wgt = 1.0f / (1.0f + expf(pcc.g * (pcc.cutoff - spread)));
-      const float pc = wgt * fmaxf(en - thr, 0.0f) / (a_sum + pcc.eps);
-      if (a_sum > best[m]) {
-        best[m] = a_sum;
+      const float z2 = z[m].x * z[m].x + z[m].y * z[m].y;
+      const float xe = sqrtf(z2) + pcc.eps;
+      const float en = (z2 - si[m]) / xe;
+      const float spread = (sa[m] / (mx[m] + pcc.eps) - 1.0f) / (float)(NS - 1);
+      const float wgt = 1.0f / (1.0f + __expf(pcc.g * (pcc.cutoff - spread)));
+      const float pc = wgt * fmaxf(en - thr, 0.0f) / (sa[m] + pcc.eps);
+      if (sa[m] > best[m]) {
+        best[m] = sa[m];
         idx[m] = o;
       }
       const float pcc_ = pc * co, pcs_ = pc * so;
       ma[m] += pcc_ * pcc_;
       mb[m] += 2.0f * pcc_ * pcs_;
       mc[m] += pcs_ * pcs_;
-      if (amp) amp[(size_t)o * plane + (size_t)y * W + t + T * m] = a_sum;
+      if (amp) amp[(size_t)o * plane + rowo + t + T * m] = sa[m];
     }
   }
-  const size_t rowo = (size_t)y * W;
 #pragma unroll
   for (int m = 0; m < P; ++m) {
     const float root = sqrtf(mb[m] * mb[m] + (ma[m] - mc[m]) * (ma[m] - mc[m]));
