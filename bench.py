@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="enqueue kernels directly instead of graph replay")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 256 MiB read + 256 MiB write elementwise kernel first (HBM counter scale)")
     return ap.parse_args()
 
 
@@ -99,12 +101,16 @@ def time_form(r2, torch, imgs, args, precision):
 
 
 def profile_stages(r2, torch, pipe, imgs, steps):
-    """Per-kernel-group GPU time with HIP events recorded on the launch stream."""
+    """Per-kernel-group GPU time with HIP events recorded on the launch stream.
+
+    The stages run serially on one stream here so that each event pair times
+    its own kernels only (the timed loop overlaps the two images' stages).
+    """
     r2.profile_read()
     r2.profile_enable(True)
     for k in range(steps):
         a, b = imgs[k % len(imgs)]
-        pipe.run(a, b)
+        pipe.run_serial(a, b)
     torch.cuda.synchronize()
     r2.profile_enable(False)
     raw = r2.profile_read()
@@ -174,6 +180,12 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.add(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     imgs = []
     for i in range(args.pairs):
         a, b, _ = make_pair(1, i, size=args.size)

@@ -251,18 +251,35 @@ class PairPipeline:
         self.n_out = torch.zeros((1,), dtype=torch.int32, device=self.dev)
         self.ws_match = torch.empty(match_workspace_bytes(cap, cap, d, self.mp), dtype=torch.uint8, device=self.dev)
         self.graph = None
+        self._side = None
 
     def _image(self, img, buf, stream):
         filter_mim_into(img, self.pc, buf.mim, buf.M, None, None, buf.ws_filter, stream)
         detect_into(buf.M, self.det, buf.kpts, buf.nk, buf.ws_detect, stream)
         describe_into(buf.mim, buf.kpts, buf.nk, self.dp, buf.desc, buf.inv, buf.dkp, buf.nd, buf.ws_desc, stream)
 
-    def run(self, img_a, img_b, stream=None):
+    def run_serial(self, img_a, img_b, stream=None):
+        """Every stage on one stream, in order (used to time kernels one at a time)."""
         self._image(img_a, self.a, stream)
         self._image(img_b, self.b, stream)
         a, b = self.a, self.b
         match_into(a.desc, a.inv, a.dkp, a.nd, b.desc, b.inv, b.dkp, b.nd, self.mp, self.out, self.n_out,
                    self.ws_match, stream)
+
+    def run(self, img_a, img_b, stream=None):
+        """Image B's stages run on a second stream, overlapping image A's; matching waits for both."""
+        torch = _torch()
+        main = stream if stream is not None else torch.cuda.current_stream(self.dev)
+        if self._side is None:
+            self._side = torch.cuda.Stream(device=self.dev)
+        side = self._side
+        side.wait_stream(main)
+        self._image(img_a, self.a, main)
+        self._image(img_b, self.b, side)
+        main.wait_stream(side)
+        a, b = self.a, self.b
+        match_into(a.desc, a.inv, a.dkp, a.nd, b.desc, b.inv, b.dkp, b.nd, self.mp, self.out, self.n_out,
+                   self.ws_match, main)
 
     def capture(self, img_a, img_b):
         """Capture run() on static input buffers into a graph; replay() re-runs it."""

@@ -66,6 +66,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         return _LIB
     if not os.path.exists(path):
         raise RuntimeError(f"librift2.so not found at {path}: build it with python -m paper_2303_00319_amd.build")
+    try:
+        # torch ships its own HIP runtime; load it first so that the library
+        # binds to the same runtime instance instead of a second copy
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P = ctypes.POINTER
     vp, sz, i32, i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64

@@ -9,7 +9,7 @@
 #include <mutex>
 #include <vector>
 
-#include "../../include/rift2.h"
+#include "rift2.h"
 #include "describe.hip"
 #include "detect.hip"
 #include "fft.hpp"

@@ -181,12 +181,13 @@ RIFT2_PLAN(4096, 8, 4, 8, 8, 8, 8, 1, 1)
 
 // LDS lines hold interleaved complex values (one float2 per point).  The
 // padded index puts one spare point after every 16 so radix-16 strides do not
-// land on one bank; a line is padded to 8 (mod 32) points so that lines of
-// adjacent teams start on different banks.
+// land on one bank.  When L consecutive lanes of a wave work on one line and
+// the next L lanes on the next line, lines are L points apart modulo 32 so
+// that neighbouring lines start on different banks.
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
-template <int N>
+template <int N, int L = 32>
 constexpr int lds_line() {
-  return ((N + N / 16 + 31) / 32) * 32 + 8;
+  return ((N + N / 16 + 31) / 32) * 32 + (L % 32);
 }
 
 // Twiddle e^{DIR 2 pi i m / N}, 0 <= m < N.

@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(256) k_fwd_rows(const Tin* __restrict__ img, i
   using PL = FftPlan<W, P>;
   constexpr int T = PL::T;
   constexpr int LINES = 256 / T;
-  __shared__ float2 lines[LINES][lds_line<W>()];
+  __shared__ float2 lines[LINES][lds_line<W, T>()];
   if (blockIdx.x == 0) {
     for (int i = threadIdx.x; i < n_zero; i += blockDim.x) zero[i] = 0u;
   }
@@ -104,20 +104,23 @@ __device__ __forceinline__ float ang_lowpass(float lr, float th, bool dead, int 
   return dead ? 0.0f : ang * lp * fc.inv_hw;
 }
 
-// One block = C adjacent columns; lane l of wave w works on column l % C and
-// column index t = l / C + (64 / C) w of its column's FFT team, so a wave's
-// global accesses are 64/C rows x C contiguous points.
+// One block = C adjacent columns.  Each wave spans all C columns: its lanes
+// form C groups of L = 64/C consecutive lanes, group c working on column c at
+// FFT team positions t = (lane % L) + L w.  A wave's global accesses are
+// therefore L rows x C contiguous points, and in LDS each group walks its
+// own column line with unit stride.
 template <int H, int P, int C>
 __global__ void __launch_bounds__(C * (H / P)) k_pass_a(const float2* __restrict__ rrow, FilterConsts fc,
                                                       float2* __restrict__ y_out) {
   using PL = FftPlan<H, P>;
   constexpr int T = PL::T;
+  constexpr int L = 64 / C;
   static_assert(64 % C == 0 && (C * T) % 64 == 0, "column mapping");
-  __shared__ float2 lines[C][lds_line<H>()];
+  __shared__ float2 lines[C][lds_line<H, L>()];
   const int W = fc.W;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int c = lane % C;
-  const int t = lane / C + (64 / C) * wave;
+  const int c = lane / L;
+  const int t = lane % L + L * wave;
   const int l = blockIdx.x * C + c;
   float2 spec[P];
 #pragma unroll
@@ -167,7 +170,7 @@ __global__ void __launch_bounds__(256) k_noise_pre(const float2* __restrict__ y_
   using PL = FftPlan<W, P>;
   constexpr int T = PL::T;
   constexpr int LINES = 256 / T;
-  __shared__ float2 lines[LINES][lds_line<W>()];
+  __shared__ float2 lines[LINES][lds_line<W, T>()];
   __shared__ uint32_t hist[kHist1];
   const int o = blockIdx.y;
   for (int i = threadIdx.x; i < kHist1; i += 256) hist[i] = 0u;
@@ -350,7 +353,7 @@ __global__ void __launch_bounds__((row_block<W, P>())) k_pass_b(const float2* __
   using PL = FftPlan<W, P>;
   constexpr int T = PL::T;
   constexpr int LINES = row_block<W, P>() / T;
-  __shared__ float2 lines[LINES][lds_line<W>()];
+  __shared__ float2 lines[LINES][lds_line<W, T>()];
   const int team = threadIdx.x / T, t = threadIdx.x % T;
   const int y = blockIdx.x * LINES + team;
   const size_t plane = (size_t)H * W;
@@ -373,14 +376,23 @@ __global__ void __launch_bounds__((row_block<W, P>())) k_pass_b(const float2* __
 #pragma unroll
       for (int m = 0; m < P; ++m) z[m] = cadd(z[m], base[(size_t)s * plane + T * m]);
     }
+    // the first scale's row (an L2 re-read) is in flight during the Z transform
+    float2 nxt[P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) nxt[m] = base[T * m];
     fft_line<+1, W, P>(z, t, lines[team]);
     float sa[P], mx[P], si[P];
 #pragma unroll
     for (int m = 0; m < P; ++m) sa[m] = mx[m] = si[m] = 0.0f;
+#pragma unroll 1
     for (int s = 0; s < NS; ++s) {
       float2 v[P];
 #pragma unroll
-      for (int m = 0; m < P; ++m) v[m] = base[(size_t)s * plane + T * m];
+      for (int m = 0; m < P; ++m) v[m] = nxt[m];
+      if (s + 1 < NS) {
+#pragma unroll
+        for (int m = 0; m < P; ++m) nxt[m] = base[(size_t)(s + 1) * plane + T * m];
+      }
       fft_line<+1, W, P>(v, t, lines[team]);
 #pragma unroll
       for (int m = 0; m < P; ++m) {

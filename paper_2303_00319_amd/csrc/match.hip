@@ -4,8 +4,9 @@
 //   k_match_prep   counts -> zero-padded GEMM tables (BF16 bits or FP32),
 //                  per-keypoint best slots reset
 //   k_match_gemm   MFMA distance tiles (32 candidates x 32 queries per wave
-//                  step) with a fused per-query top-3 in registers; rows of B
-//                  are split into slices across blocks
+//                  step, candidate tiles shared by the block through LDS)
+//                  with a fused per-query top-3 in registers; rows of B are
+//                  split into slices across blocks
 //   k_match_merge  per A row: merge the slice/half-wave top-3 lists, nearest
 //                  row j1, nearest row of another B keypoint j2, ratio test,
 //                  per-keypoint best by a 64-bit atomic min of (d2, row)
@@ -26,6 +27,7 @@ constexpr int kTopK = 3;  // a keypoint owns <= 2 rows, so 3 rows hold j1 and j2
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float floatx16_t __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));  // plain 16-byte vector (promotable)
 
 __device__ __forceinline__ uint16_t bf16_bits_of_count(uint32_t c) {
   // round to nearest even; exact for c <= 256
@@ -96,7 +98,45 @@ __device__ __forceinline__ void tile_epilogue(const floatx16_t& acc, int lane, i
   }
 }
 
-// grid = (ceil(rowsA_pad / 128), S); block = 4 waves, 32 queries per wave.
+// Candidate tiles of 32 rows are staged through LDS once per block (double
+// buffered: the next tile's global loads are in flight in registers while the
+// current tile is multiplied) and read by the block's 4 waves, each holding
+// 32 queries in registers.  grid = (ceil(rows_a / 128), S).
+template <typename TE, int DP>
+struct TileShape {
+  static constexpr int VEC = 16 / (int)sizeof(TE);  // elements per 16-byte load
+  static constexpr int PER_ROW = DP / VEC;
+  static constexpr int TOTAL = 32 * PER_ROW;          // 16-byte loads per tile
+  static constexpr int PER_THREAD = (TOTAL + 255) / 256;
+};
+
+// Unconditional loads (slots past the tile re-read a valid element) keep the
+// staging registers promotable while the loads are in flight.
+template <typename TE, int DP, int N>
+__device__ __forceinline__ void tile_load(u32x4_t (&r)[N], const TE* __restrict__ tb, int j0) {
+  using S = TileShape<TE, DP>;
+#pragma unroll
+  for (int q = 0; q < S::PER_THREAD; ++q) {
+    int idx = threadIdx.x + 256 * q;
+    idx = idx < S::TOTAL ? idx : idx - S::TOTAL;
+    const int row = idx / S::PER_ROW, col = idx % S::PER_ROW;
+    r[q] = *(const u32x4_t*)(tb + (size_t)(j0 + row) * DP + col * S::VEC);
+  }
+}
+
+template <typename TE, int DP, int RS, int N>
+__device__ __forceinline__ void tile_store(const u32x4_t (&r)[N], TE* tile) {
+  using S = TileShape<TE, DP>;
+#pragma unroll
+  for (int q = 0; q < S::PER_THREAD; ++q) {
+    const int idx = threadIdx.x + 256 * q;
+    if (idx < S::TOTAL) {
+      const int row = idx / S::PER_ROW, col = idx % S::PER_ROW;
+      *(u32x4_t*)(tile + row * RS + col * S::VEC) = r[q];
+    }
+  }
+}
+
 template <int DP>
 __global__ void __launch_bounds__(256) k_match_gemm_bf16(const uint16_t* __restrict__ ta, const float* __restrict__ inv_a,
                                                          const int32_t* __restrict__ na_dev,
@@ -105,40 +145,55 @@ __global__ void __launch_bounds__(256) k_match_gemm_bf16(const uint16_t* __restr
                                                          int slice_rows, int2* __restrict__ part) {
   static_assert(DP % 16 == 0, "padded depth");
   constexpr int KS = DP / 16;
+  constexpr int RS = DP + 8;  // row stride in LDS (elements): rows start 16 bytes apart mod 128
+  __shared__ __attribute__((aligned(16))) uint16_t tile[2][32 * RS];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 5;
   const int na = min(*na_dev, cap_a), nb = min(*nb_dev, cap_b);
   const int q0 = (blockIdx.x * 4 + wave) * 32;
-  if (q0 >= na) return;
+  const bool active = q0 < na;
   const int qi = q0 + (lane & 31);
   bf16x8_t qa[KS];
-  const uint16_t* qrow = ta + (size_t)qi * DP + 8 * g;
+  if (active) {
+    const uint16_t* qrow = ta + (size_t)qi * DP + 8 * g;
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) {
-    const uint4 raw = *(const uint4*)(qrow + 16 * ks);
-    qa[ks] = __builtin_bit_cast(bf16x8_t, raw);
+    for (int ks = 0; ks < KS; ++ks) qa[ks] = __builtin_bit_cast(bf16x8_t, *(const uint4*)(qrow + 16 * ks));
   }
-  const float ia = qi < na ? inv_a[qi] : 0.0f;
+  const float ia = (active && qi < na) ? inv_a[qi] : 0.0f;
   const int j_beg = blockIdx.y * slice_rows;
   const int j_end = min(nb, j_beg + slice_rows);
+  const int ntile = j_end > j_beg ? (j_end - j_beg + 31) / 32 : 0;
   Top3 top;
 #pragma unroll
   for (int q = 0; q < kTopK; ++q) {
     top.d[q] = INFINITY;
     top.j[q] = -1;
   }
-  for (int j0 = j_beg; j0 < j_end; j0 += 32) {
-    const int cj = j0 + (lane & 31);
-    const uint16_t* crow = tb + (size_t)cj * DP + 8 * g;
-    floatx16_t acc = {};
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const uint4 raw = *(const uint4*)(crow + 16 * ks);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, raw), qa[ks], acc, 0, 0, 0);
-    }
-    const float ibl = cj < nb ? inv_b[cj] : 0.0f;
-    tile_epilogue(acc, lane, j0, j_end, ia, ibl, top);
+  u32x4_t stage[TileShape<uint16_t, DP>::PER_THREAD];
+  if (ntile > 0) {
+    tile_load<uint16_t, DP>(stage, tb, j_beg);
+    tile_store<uint16_t, DP, RS>(stage, tile[0]);
   }
-  if (qi < na) {
+  __syncthreads();
+  for (int it = 0; it < ntile; ++it) {
+    const int cur = it & 1;
+    const int j0 = j_beg + 32 * it;
+    if (it + 1 < ntile) tile_load<uint16_t, DP>(stage, tb, j0 + 32);
+    if (active) {
+      const uint16_t* crow = tile[cur] + (lane & 31) * RS + 8 * g;
+      floatx16_t acc = {};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const uint4 raw = *(const uint4*)(crow + 16 * ks);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, raw), qa[ks], acc, 0, 0, 0);
+      }
+      const int cj = j0 + (lane & 31);
+      const float ibl = cj < nb ? inv_b[cj] : 0.0f;
+      tile_epilogue(acc, lane, j0, j_end, ia, ibl, top);
+    }
+    if (it + 1 < ntile) tile_store<uint16_t, DP, RS>(stage, tile[cur ^ 1]);
+    __syncthreads();
+  }
+  if (active && qi < na) {
     int2* dst = part + ((size_t)qi * gridDim.y + blockIdx.y) * (2 * kTopK) + g * kTopK;
 #pragma unroll
     for (int q = 0; q < kTopK; ++q) dst[q] = make_int2(__float_as_int(top.d[q]), top.j[q]);
@@ -156,40 +211,58 @@ __global__ void __launch_bounds__(256) k_match_gemm_f32(const float* __restrict_
                                                         int slice_rows, int2* __restrict__ part) {
   static_assert(DP % 8 == 0, "padded depth");
   constexpr int KC = DP / 8;
+  constexpr int RS = DP + 4;  // row stride in LDS (floats)
+  __shared__ __attribute__((aligned(16))) float tile[2][32 * RS];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 5;
   const int na = min(*na_dev, cap_a), nb = min(*nb_dev, cap_b);
   const int q0 = (blockIdx.x * 4 + wave) * 32;
-  if (q0 >= na) return;
+  const bool active = q0 < na;
   const int qi = q0 + (lane & 31);
   float4 qa[KC];
-  const float* qrow = ta + (size_t)qi * DP + 4 * g;
+  if (active) {
+    const float* qrow = ta + (size_t)qi * DP + 4 * g;
 #pragma unroll
-  for (int c = 0; c < KC; ++c) qa[c] = *(const float4*)(qrow + 8 * c);
-  const float ia = qi < na ? inv_a[qi] : 0.0f;
+    for (int c = 0; c < KC; ++c) qa[c] = *(const float4*)(qrow + 8 * c);
+  }
+  const float ia = (active && qi < na) ? inv_a[qi] : 0.0f;
   const int j_beg = blockIdx.y * slice_rows;
   const int j_end = min(nb, j_beg + slice_rows);
+  const int ntile = j_end > j_beg ? (j_end - j_beg + 31) / 32 : 0;
   Top3 top;
 #pragma unroll
   for (int q = 0; q < kTopK; ++q) {
     top.d[q] = INFINITY;
     top.j[q] = -1;
   }
-  for (int j0 = j_beg; j0 < j_end; j0 += 32) {
-    const int cj = j0 + (lane & 31);
-    const float* crow = tb + (size_t)cj * DP + 4 * g;
-    floatx16_t acc = {};
-#pragma unroll
-    for (int c = 0; c < KC; ++c) {
-      const float4 cb = *(const float4*)(crow + 8 * c);
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.x, qa[c].x, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.y, qa[c].y, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.z, qa[c].z, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.w, qa[c].w, acc, 0, 0, 0);
-    }
-    const float ibl = cj < nb ? inv_b[cj] : 0.0f;
-    tile_epilogue(acc, lane, j0, j_end, ia, ibl, top);
+  u32x4_t stage[TileShape<float, DP>::PER_THREAD];
+  if (ntile > 0) {
+    tile_load<float, DP>(stage, tb, j_beg);
+    tile_store<float, DP, RS>(stage, tile[0]);
   }
-  if (qi < na) {
+  __syncthreads();
+  for (int it = 0; it < ntile; ++it) {
+    const int cur = it & 1;
+    const int j0 = j_beg + 32 * it;
+    if (it + 1 < ntile) tile_load<float, DP>(stage, tb, j0 + 32);
+    if (active) {
+      const float* crow = tile[cur] + (lane & 31) * RS + 4 * g;
+      floatx16_t acc = {};
+#pragma unroll
+      for (int c = 0; c < KC; ++c) {
+        const float4 cb = *(const float4*)(crow + 8 * c);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.x, qa[c].x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.y, qa[c].y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.z, qa[c].z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.w, qa[c].w, acc, 0, 0, 0);
+      }
+      const int cj = j0 + (lane & 31);
+      const float ibl = cj < nb ? inv_b[cj] : 0.0f;
+      tile_epilogue(acc, lane, j0, j_end, ia, ibl, top);
+    }
+    if (it + 1 < ntile) tile_store<float, DP, RS>(stage, tile[cur ^ 1]);
+    __syncthreads();
+  }
+  if (active && qi < na) {
     int2* dst = part + ((size_t)qi * gridDim.y + blockIdx.y) * (2 * kTopK) + g * kTopK;
 #pragma unroll
     for (int q = 0; q < kTopK; ++q) dst[q] = make_int2(__float_as_int(top.d[q]), top.j[q]);
