@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--size", type=int, default=1024)
     ap.add_argument("--keypoints", type=int, default=5000)
     ap.add_argument("--no-graph", action="store_true", help="enqueue kernels directly instead of graph replay")
+    ap.add_argument("--serial", action="store_true",
+                    help="run both images' stages on one stream (no overlap; per-kernel durations for rocprofv3)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -62,7 +64,7 @@ def time_form(r2, torch, imgs, args, precision):
     pc, det, dp, mp = r2.defaults()
     det.max_keypoints = args.keypoints
     mp.precision = precision
-    pipe = r2.PairPipeline(args.size, args.size, pc, det, dp, mp)
+    pipe = r2.PairPipeline(args.size, args.size, pc, det, dp, mp, serial=args.serial)
     graphs = []
     if not args.no_graph:
         for a, b in imgs:
@@ -234,6 +236,7 @@ def main():
                         f"216-d descriptors, exhaustive NN + ratio 0.9",
             "pairs": args.pairs,
             "graph": not args.no_graph,
+            "streams": 1 if args.serial else 2,
             "last_pair": fp32["last_pair"],
         },
         "mixed": {

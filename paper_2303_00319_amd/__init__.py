@@ -233,7 +233,7 @@ class PairPipeline:
     allocation), so it can be captured into a HIP graph and replayed.
     """
 
-    def __init__(self, h, w, pc=None, det=None, dp=None, mp=None, device=0):
+    def __init__(self, h, w, pc=None, det=None, dp=None, mp=None, device=0, serial=False):
         torch = _torch()
         d_pc, d_det, d_dp, d_mp = defaults()
         self.pc = pc or d_pc
@@ -252,6 +252,7 @@ class PairPipeline:
         self.ws_match = torch.empty(match_workspace_bytes(cap, cap, d, self.mp), dtype=torch.uint8, device=self.dev)
         self.graph = None
         self._side = None
+        self.serial = serial
 
     def _image(self, img, buf, stream):
         filter_mim_into(img, self.pc, buf.mim, buf.M, None, None, buf.ws_filter, stream)
@@ -268,6 +269,8 @@ class PairPipeline:
 
     def run(self, img_a, img_b, stream=None):
         """Image B's stages run on a second stream, overlapping image A's; matching waits for both."""
+        if self.serial:
+            return self.run_serial(img_a, img_b, stream)
         torch = _torch()
         main = stream if stream is not None else torch.cuda.current_stream(self.dev)
         if self._side is None:

@@ -463,7 +463,7 @@ rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t
   {
     ProfScope ps(3, st);
     hipLaunchKernelGGL(k_noise_sel1, dim3(kNoiseRegions, pc->n_orient), dim3(256), 0, st, a0, hw, nws);
-    hipLaunchKernelGGL(k_noise_sel2, dim3(32, pc->n_orient), dim3(256), 0, st, hw, nws, nc, t32, t64);
+    hipLaunchKernelGGL(k_noise_sel2, dim3(kNoiseRegions, pc->n_orient), dim3(256), 0, st, hw, nws, nc, t32, t64);
   }
   {
     ProfScope ps(4, st);

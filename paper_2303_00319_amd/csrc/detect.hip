@@ -255,34 +255,51 @@ constexpr int kEdgeMax = 4096;
 // One block of 1024 threads: exact K-th key inside the boundary bin, then the
 // winners (keys >= K-th key) compacted into `fin` (exactly min(K, n) keys,
 // the keys being distinct).
+// Key `i` of the concatenation of the select1 regions (sizes sel_cnt, prefix
+// sums in `pre`, pre[kSelBlocks] = total).
+__device__ __forceinline__ uint64_t sel_key(const uint64_t* __restrict__ sel, const uint32_t* pre, uint32_t region_size,
+                                            uint32_t i) {
+  int lo = 0, hi = kSelBlocks - 1;  // last region with pre[r] <= i
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return sel[(size_t)lo * region_size + (i - pre[lo])];
+}
+
 __global__ void __launch_bounds__(1024) k_det_select2(uint32_t* __restrict__ hdr, const uint64_t* __restrict__ sel,
                                                       const uint32_t* __restrict__ sel_cnt, uint32_t region_size,
                                                       uint64_t* __restrict__ fin, uint32_t kmax) {
   __shared__ uint32_t scratch[1024];
   __shared__ uint32_t lh[4096];
   __shared__ uint64_t edge[kEdgeMax];
+  __shared__ uint32_t pre[kSelBlocks + 1];
   __shared__ uint32_t n_edge, s_final;
   __shared__ int sh_b;
   __shared__ uint32_t sh_before;
   const uint32_t n = hdr[0];
   const uint32_t k = min(kmax, n);
   const uint64_t bin = hdr[8];
-  uint64_t kth = 0;
   if (threadIdx.x == 0) {
     n_edge = 0;
     s_final = 0;
+    uint32_t acc = 0;
+    for (int r = 0; r < kSelBlocks; ++r) {
+      pre[r] = acc;
+      acc += sel_cnt[r];
+    }
+    pre[kSelBlocks] = acc;
   }
   __syncthreads();
+  const uint32_t ns = pre[kSelBlocks];
+  uint64_t kth = 0;
   if (k > 0 && k < n) {
-    for (int rg = 0; rg < kSelBlocks; ++rg) {
-      const uint32_t cnt = sel_cnt[rg];
-      const uint64_t* list = sel + (size_t)rg * region_size;
-      for (uint32_t i = threadIdx.x; i < cnt; i += 1024) {
-        const uint64_t key = list[i];
-        if ((key >> 48) == bin) {
-          const uint32_t pos = atomicAdd(&n_edge, 1u);
-          if (pos < kEdgeMax) edge[pos] = key;
-        }
+    for (uint32_t i = threadIdx.x; i < ns; i += 1024) {
+      const uint64_t key = sel_key(sel, pre, region_size, i);
+      if ((key >> 48) == bin) {
+        const uint32_t pos = atomicAdd(&n_edge, 1u);
+        if (pos < kEdgeMax) edge[pos] = key;
       }
     }
     __syncthreads();
@@ -295,20 +312,10 @@ __global__ void __launch_bounds__(1024) k_det_select2(uint32_t* __restrict__ hdr
       const int shift = 64 - known - 12;
       for (int i = threadIdx.x; i < 4096; i += 1024) lh[i] = 0u;
       __syncthreads();
-      if (staged) {
-        for (uint32_t i = threadIdx.x; i < ne; i += 1024) {
-          const uint64_t key = edge[i];
-          if ((key >> (64 - known)) == prefix) atomicAdd(&lh[(key >> shift) & 4095u], 1u);
-        }
-      } else {
-        for (int rg = 0; rg < kSelBlocks; ++rg) {
-          const uint32_t cnt = sel_cnt[rg];
-          const uint64_t* list = sel + (size_t)rg * region_size;
-          for (uint32_t i = threadIdx.x; i < cnt; i += 1024) {
-            const uint64_t key = list[i];
-            if ((key >> (64 - known)) == prefix) atomicAdd(&lh[(key >> shift) & 4095u], 1u);
-          }
-        }
+      const uint32_t cnt = staged ? ne : ns;
+      for (uint32_t i = threadIdx.x; i < cnt; i += 1024) {
+        const uint64_t key = staged ? edge[i] : sel_key(sel, pre, region_size, i);
+        if ((key >> (64 - known)) == prefix) atomicAdd(&lh[(key >> shift) & 4095u], 1u);
       }
       __syncthreads();
       block_find_rank<4096, 1024, true>(lh, r, &sh_b, &sh_before, scratch);
@@ -318,26 +325,22 @@ __global__ void __launch_bounds__(1024) k_det_select2(uint32_t* __restrict__ hdr
     }
     kth = prefix;
   }
-  for (int rg = 0; rg < kSelBlocks; ++rg) {
-    const uint32_t cnt = sel_cnt[rg];
-    const uint64_t* list = sel + (size_t)rg * region_size;
-    for (uint32_t i0 = 0; i0 < cnt; i0 += 1024) {
-      const uint32_t i = i0 + threadIdx.x;
-      uint64_t key = 0;
-      bool take = false;
-      if (i < cnt) {
-        key = list[i];
-        take = key >= kth;
-      }
-      const uint64_t mask = __ballot(take);
-      if (mask) {
-        const int lane = threadIdx.x & 63;
-        const int leader = __ffsll((unsigned long long)mask) - 1;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&s_final, (uint32_t)__popcll(mask));
-        base = __shfl(base, leader);
-        if (take) fin[base + __popcll(mask & ((1ull << lane) - 1ull))] = key;
-      }
+  for (uint32_t i0 = 0; i0 < ns; i0 += 1024) {
+    const uint32_t i = i0 + threadIdx.x;
+    uint64_t key = 0;
+    bool take = false;
+    if (i < ns) {
+      key = sel_key(sel, pre, region_size, i);
+      take = key >= kth;
+    }
+    const uint64_t mask = __ballot(take);
+    if (mask) {
+      const int lane = threadIdx.x & 63;
+      const int leader = __ffsll((unsigned long long)mask) - 1;
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(&s_final, (uint32_t)__popcll(mask));
+      base = __shfl(base, leader);
+      if (take) fin[base + __popcll(mask & ((1ull << lane) - 1ull))] = key;
     }
   }
   __syncthreads();

@@ -104,11 +104,10 @@ __device__ __forceinline__ float ang_lowpass(float lr, float th, bool dead, int 
   return dead ? 0.0f : ang * lp * fc.inv_hw;
 }
 
-// One block = C adjacent columns.  Each wave spans all C columns: its lanes
-// form C groups of L = 64/C consecutive lanes, group c working on column c at
-// FFT team positions t = (lane % L) + L w.  A wave's global accesses are
-// therefore L rows x C contiguous points, and in LDS each group walks its
-// own column line with unit stride.
+// One block = C adjacent columns.  Lane l of wave w works on column l % C at
+// FFT team position t = l / C + (64 / C) w, so a wave's global accesses are
+// 64/C rows x C contiguous points.  Column lines in LDS are 4 points apart
+// modulo 32, which measured fastest for this interleaving.
 template <int H, int P, int C>
 __global__ void __launch_bounds__(C * (H / P)) k_pass_a(const float2* __restrict__ rrow, FilterConsts fc,
                                                       float2* __restrict__ y_out) {
@@ -116,11 +115,11 @@ __global__ void __launch_bounds__(C * (H / P)) k_pass_a(const float2* __restrict
   constexpr int T = PL::T;
   constexpr int L = 64 / C;
   static_assert(64 % C == 0 && (C * T) % 64 == 0, "column mapping");
-  __shared__ float2 lines[C][lds_line<H, L>()];
+  __shared__ float2 lines[C][lds_line<H, 4>()];
   const int W = fc.W;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int c = lane / L;
-  const int t = lane % L + L * wave;
+  const int c = lane % C;
+  const int t = lane / C + L * wave;
   const int l = blockIdx.x * C + c;
   float2 spec[P];
 #pragma unroll
@@ -252,19 +251,22 @@ __global__ void __launch_bounds__(256) k_noise_sel1(const float* __restrict__ a0
   const int beg = blockIdx.x * per_block;
   const int end = min(hw, beg + per_block);
   uint32_t* region = ws.cand + (size_t)o * hw + beg;
-  for (int i0 = beg; i0 < end; i0 += 256) {
-    const int i = i0 + threadIdx.x;
-    uint32_t bits = 0;
-    bool take = false;
-    if (i < end) {
-      bits = __float_as_uint(src[i]);
+  // chunk bounds are multiples of 4 (HW is a multiple of 256): 16-byte loads
+  for (int i0 = beg; i0 < end; i0 += 1024) {
+    const int i = i0 + 4 * threadIdx.x;
+    const bool in = i < end;
+    const float4 q4 = in ? *(const float4*)(src + i) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float qv[4] = {q4.x, q4.y, q4.z, q4.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t bits = __float_as_uint(qv[e]);
       const uint32_t key = bits >> 19;
       const uint32_t sub = (bits >> 9) & (kHist2 - 1);
-      if (key == b0) atomicAdd(&h2[0][sub], 1u);
-      if (key == b1) atomicAdd(&h2[1][sub], 1u);
-      take = (key == b0) || (key == b1);
+      const bool t0 = in && key == b0, t1 = in && key == b1;
+      if (t0) atomicAdd(&h2[0][sub], 1u);
+      if (t1) atomicAdd(&h2[1][sub], 1u);
+      block_append(t0 || t1, bits, &s_count, region);
     }
-    block_append(take, bits, &s_count, region);
   }
   __syncthreads();
   if (threadIdx.x == 0) ws.cnt[(size_t)o * gridDim.x + blockIdx.x] = s_count;
@@ -298,12 +300,27 @@ __global__ void __launch_bounds__(256) k_noise_sel2(int hw, NoiseWs ws, NoiseCon
   const int per_region = (hw + ws.regions - 1) / ws.regions;
   for (int rg = blockIdx.x; rg < ws.regions; rg += gridDim.x) {
     const uint32_t n = ws.cnt[(size_t)o * ws.regions + rg];
-    const uint32_t* list = ws.cand + (size_t)o * hw + (size_t)rg * per_region;
-    for (uint32_t i = threadIdx.x; i < n; i += 256) {
-      const uint32_t bits = list[i];
-      const uint32_t pre = bits >> 9;
-      if (pre == p0) atomicAdd(&h3[0][bits & (kHist3 - 1)], 1u);
-      if (pre == p1) atomicAdd(&h3[1][bits & (kHist3 - 1)], 1u);
+    const uint32_t* list = ws.cand + (size_t)o * hw + (size_t)rg * per_region;  // 16-byte aligned
+    for (uint32_t i = 4 * threadIdx.x; i < n; i += 1024) {
+      uint32_t qv[4];
+      if (i + 4 <= n) {
+        const uint4 q4 = *(const uint4*)(list + i);
+        qv[0] = q4.x;
+        qv[1] = q4.y;
+        qv[2] = q4.z;
+        qv[3] = q4.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) qv[e] = i + e < n ? list[i + e] : 0u;
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (i + e >= n) break;
+        const uint32_t bits = qv[e];
+        const uint32_t pre = bits >> 9;
+        if (pre == p0) atomicAdd(&h3[0][bits & (kHist3 - 1)], 1u);
+        if (pre == p1) atomicAdd(&h3[1][bits & (kHist3 - 1)], 1u);
+      }
     }
   }
   __syncthreads();
