@@ -223,3 +223,27 @@ def test_rot90_equivariance_of_amplitudes_mim_and_moments():
     gap = (srt[-1] - srt[-2]) / np.maximum(srt[-1], 1e-300)
     assert np.all(gap[diff] < 1e-9)
     assert diff.mean() < 1e-3
+
+
+def test_noise_threshold_against_sampled_rayleigh_noise():
+    """Monte Carlo pin of the noise model, independent of the formula's constants.
+
+    Pure noise gives smallest-scale amplitudes that are Rayleigh distributed,
+    and each coarser scale's noise amplitude shrinks by 1/mult.  Taking the
+    scales' noise amplitudes as one common Rayleigh draw u scaled per scale,
+    the total noise amplitude is sum_s sigma mult^-s u, and the threshold must
+    be its mean plus k standard deviations.  Both statistics are taken from
+    numpy's Rayleigh sampler, so a wrong median-to-sigma factor, a wrong
+    geometric sum or wrong Rayleigh moments all fail here.
+    """
+    p = PCParams()
+    rng = np.random.default_rng(11)
+    sigma = 0.37
+    u = rng.rayleigh(scale=1.0, size=2_000_000)
+    a0 = sigma * u
+    total = sum(sigma * p.mult ** (-s) * u for s in range(p.n_scales))
+    want = total.mean() + p.k * total.std()
+    got = fb.noise_threshold(a0, p)
+    assert got == pytest.approx(want, rel=3e-3)
+    # the threshold scales linearly with the noise level
+    assert fb.noise_threshold(4.0 * a0, p) == pytest.approx(4.0 * got, rel=1e-12)
