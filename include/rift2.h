@@ -150,7 +150,9 @@ size_t rift2_match_workspace_size(int32_t cap_a, int32_t cap_b, int32_t D, const
  *   max_moment  H x W float, M
  *   min_moment  H x W float, m (may be NULL)
  *   amp_sums    n_orient x H x W float, A_o (may be NULL)
- * Circular (periodic) convolution, raw pixel values. */
+ * mim must be 4-byte aligned, max_moment and min_moment 16-byte aligned
+ * (RIFT2_ERR_INVALID_ARG otherwise).  Circular (periodic) convolution, raw
+ * pixel values. */
 rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t W, int64_t pitch,
                               const rift2_pc_params* pc, uint8_t* mim, float* max_moment,
                               float* min_moment, float* amp_sums, void* workspace,

@@ -56,7 +56,7 @@ bool pc_built(const rift2_pc_params* p) {
 }
 
 struct FilterLayout {
-  size_t rrow, yplanes, a0, cand, zero, t32, t64, total;
+  size_t rrow, yplanes, a0, cand, spc, zero, t32, t64, total;
   int zero_words;
 };
 
@@ -69,6 +69,7 @@ FilterLayout filter_layout(int H, int W, const rift2_pc_params* p) {
   L.yplanes = c.take(hw * F * sizeof(float2));
   L.a0 = c.take(hw * p->n_orient * sizeof(float));
   L.cand = c.take(hw * p->n_orient * sizeof(uint32_t));
+  L.spc = c.take(hw * p->n_orient * sizeof(float2));
   L.zero_words = p->n_orient * (kHist1 + 2 * kHist2 + 2 * kHist3 + 1 + kNoiseRegions);
   L.zero = c.take((size_t)L.zero_words * sizeof(uint32_t));
   L.t32 = c.take(p->n_orient * sizeof(float));
@@ -244,12 +245,12 @@ bool dispatch_pass_a(int H, int W, const float2* rrow, const FilterConsts& fc, f
 }
 
 template <int W, int P>
-void launch_noise_pre(int H, int n_orient, int n_scales, const float2* y, float* a0, uint32_t* hist1, hipStream_t st) {
+void launch_noise_pre(int H, int n_orient, int n_scales, float2* y, float* a0, uint32_t* hist1, hipStream_t st) {
   constexpr int LINES = 256 / FftPlan<W, P>::T;
   hipLaunchKernelGGL((k_noise_pre<W, P>), dim3(H / LINES, n_orient), dim3(256), 0, st, y, H, n_scales, a0, hist1);
 }
 
-bool dispatch_noise_pre(int W, int H, int n_orient, int n_scales, const float2* y, float* a0, uint32_t* hist1,
+bool dispatch_noise_pre(int W, int H, int n_orient, int n_scales, float2* y, float* a0, uint32_t* hist1,
                         hipStream_t st) {
   switch (W) {
     case 256: launch_noise_pre<256, 16>(H, n_orient, n_scales, y, a0, hist1, st); return true;
@@ -264,34 +265,34 @@ bool dispatch_noise_pre(int W, int H, int n_orient, int n_scales, const float2* 
 }
 
 template <int W, int P, int NS, int NO>
-void launch_pass_b(int H, const float2* y, const PCConsts& pcc, const float* t_o, uint8_t* mim, float* mmax,
-                   float* mmin, float* amp, hipStream_t st) {
-  constexpr int BLK = row_block<W, P>();
-  constexpr int LINES = BLK / FftPlan<W, P>::T;
-  hipLaunchKernelGGL((k_pass_b<W, P, NS, NO>), dim3(H / LINES), dim3(BLK), 0, st, y, H, pcc, t_o, mim, mmax, mmin, amp);
+void launch_pass_b_split(int H, const float2* y, const PCConsts& pcc, const float* t_o, float2* spc, uint8_t* mim,
+                         float* mmax, float* mmin, float* amp, hipStream_t st) {
+  hipLaunchKernelGGL((k_pass_b_orient<W, P, NS>), dim3(H, NO), dim3(W / P), 0, st, y, H, pcc, t_o, spc, amp);
+  const int hw = H * W;
+  hipLaunchKernelGGL((k_pass_b_reduce<NO>), dim3((hw / 4 + 255) / 256), dim3(256), 0, st, spc, hw, pcc, mim, mmax, mmin);
 }
 
 template <int NS, int NO>
-bool pass_b_w(int W, int H, const float2* y, const PCConsts& pcc, const float* t_o, uint8_t* mim, float* mmax,
-              float* mmin, float* amp, hipStream_t st) {
+bool pass_b_w(int W, int H, const float2* y, const PCConsts& pcc, const float* t_o, float2* spc, uint8_t* mim,
+              float* mmax, float* mmin, float* amp, hipStream_t st) {
   switch (W) {
-    case 256: launch_pass_b<256, 8, NS, NO>(H, y, pcc, t_o, mim, mmax, mmin, amp, st); return true;
-    case 512: launch_pass_b<512, 8, NS, NO>(H, y, pcc, t_o, mim, mmax, mmin, amp, st); return true;
-    case 768: launch_pass_b<768, 12, NS, NO>(H, y, pcc, t_o, mim, mmax, mmin, amp, st); return true;
-    case 1024: launch_pass_b<1024, 8, NS, NO>(H, y, pcc, t_o, mim, mmax, mmin, amp, st); return true;
-    case 1536: launch_pass_b<1536, 12, NS, NO>(H, y, pcc, t_o, mim, mmax, mmin, amp, st); return true;
-    case 2048: launch_pass_b<2048, 8, NS, NO>(H, y, pcc, t_o, mim, mmax, mmin, amp, st); return true;
-    case 4096: launch_pass_b<4096, 8, NS, NO>(H, y, pcc, t_o, mim, mmax, mmin, amp, st); return true;
+    case 256: launch_pass_b_split<256, 4, NS, NO>(H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st); return true;
+    case 512: launch_pass_b_split<512, 8, NS, NO>(H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st); return true;
+    case 768: launch_pass_b_split<768, 12, NS, NO>(H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st); return true;
+    case 1024: launch_pass_b_split<1024, 8, NS, NO>(H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st); return true;
+    case 1536: launch_pass_b_split<1536, 12, NS, NO>(H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st); return true;
+    case 2048: launch_pass_b_split<2048, 8, NS, NO>(H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st); return true;
+    case 4096: launch_pass_b_split<4096, 8, NS, NO>(H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st); return true;
     default: return false;
   }
 }
 
 bool dispatch_pass_b(int ns, int no, int W, int H, const float2* y, const PCConsts& pcc, const float* t_o,
-                     uint8_t* mim, float* mmax, float* mmin, float* amp, hipStream_t st) {
-  if (ns == 4 && no == 6) return pass_b_w<4, 6>(W, H, y, pcc, t_o, mim, mmax, mmin, amp, st);
-  if (ns == 5 && no == 8) return pass_b_w<5, 8>(W, H, y, pcc, t_o, mim, mmax, mmin, amp, st);
-  if (ns == 4 && no == 8) return pass_b_w<4, 8>(W, H, y, pcc, t_o, mim, mmax, mmin, amp, st);
-  if (ns == 5 && no == 6) return pass_b_w<5, 6>(W, H, y, pcc, t_o, mim, mmax, mmin, amp, st);
+                     float2* spc, uint8_t* mim, float* mmax, float* mmin, float* amp, hipStream_t st) {
+  if (ns == 4 && no == 6) return pass_b_w<4, 6>(W, H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st);
+  if (ns == 5 && no == 8) return pass_b_w<5, 8>(W, H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st);
+  if (ns == 4 && no == 8) return pass_b_w<4, 8>(W, H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st);
+  if (ns == 5 && no == 6) return pass_b_w<5, 6>(W, H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st);
   return false;
 }
 
@@ -393,6 +394,10 @@ rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t
   if (!img || !pc || !mim || !max_moment || !workspace) return RIFT2_ERR_INVALID_ARG;
   if (dtype != RIFT2_U8 && dtype != RIFT2_U16 && dtype != RIFT2_F32) return RIFT2_ERR_INVALID_ARG;
   if (pitch < W) return RIFT2_ERR_INVALID_ARG;
+  // the per-pixel reduction stores 4 pixels at a time
+  if (((uintptr_t)mim & 3u) || ((uintptr_t)max_moment & 15u) || ((uintptr_t)min_moment & 15u) ||
+      ((uintptr_t)amp_sums & 3u))
+    return RIFT2_ERR_INVALID_ARG;
   if (!pc_ok(pc)) return RIFT2_ERR_INVALID_ARG;
   if (!size_ok(H) || !size_ok(W) || !pc_built(pc)) return RIFT2_ERR_UNSUPPORTED;
   const FilterLayout L = filter_layout(H, W, pc);
@@ -467,7 +472,8 @@ rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t
   }
   {
     ProfScope ps(4, st);
-    dispatch_pass_b(pc->n_scales, pc->n_orient, W, H, yp, pcc, t32, mim, max_moment, min_moment, amp_sums, st);
+    dispatch_pass_b(pc->n_scales, pc->n_orient, W, H, yp, pcc, t32, (float2*)(ws + L.spc), mim, max_moment,
+                    min_moment, amp_sums, st);
   }
   return launch_status();
 }

@@ -173,6 +173,7 @@ RIFT2_PLAN(4096, 16, 3, 16, 16, 16, 1, 1, 1)
 RIFT2_PLAN(768, 12, 5, 4, 4, 4, 4, 3, 1)
 RIFT2_PLAN(1536, 12, 6, 4, 4, 4, 4, 2, 3)
 RIFT2_PLAN(256, 8, 3, 8, 8, 4, 1, 1, 1)
+RIFT2_PLAN(256, 4, 4, 4, 4, 4, 4, 1, 1)
 RIFT2_PLAN(512, 8, 3, 8, 8, 8, 1, 1, 1)
 RIFT2_PLAN(1024, 8, 4, 8, 8, 8, 2, 1, 1)
 RIFT2_PLAN(2048, 8, 4, 8, 8, 8, 4, 1, 1)
@@ -222,8 +223,28 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[P], int t) {
   }
 }
 
+// Orders this wave's LDS accesses before and after it (lanes of one wave
+// exchange data through LDS without a block barrier; the LDS serves one
+// wave's requests in issue order).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Team synchronisation: a block barrier, or a wave barrier when the team is
+// one wave (T = 64) and nobody else touches its line.
+template <bool WAVE>
+__device__ __forceinline__ void team_sync() {
+  if constexpr (WAVE) {
+    wave_sync();
+  } else {
+    __syncthreads();
+  }
+}
+
 // Write stage outputs to their Stockham positions, read back the strided layout.
-template <int N, int T, int P, int R, int NS>
+template <int N, int T, int P, int R, int NS, bool WAVE>
 __device__ __forceinline__ void fft_exchange(float2 (&v)[P], int t, float2* line) {
   constexpr int NB = P / R;
 #pragma unroll
@@ -233,30 +254,32 @@ __device__ __forceinline__ void fft_exchange(float2 (&v)[P], int t, float2* line
 #pragma unroll
     for (int r = 0; r < R; ++r) line[lds_pad(base + r * NS)] = v[b + r * NB];
   }
-  __syncthreads();
+  team_sync<WAVE>();
 #pragma unroll
   for (int m = 0; m < P; ++m) v[m] = line[lds_pad(t + T * m)];
-  __syncthreads();
+  team_sync<WAVE>();
 }
 
-template <int DIR, class PL, int S, int NS>
+template <int DIR, class PL, int S, int NS, bool WAVE>
 __device__ __forceinline__ void fft_run(float2 (&v)[PL::P], int t, float2* line) {
   if constexpr (S < PL::NR) {
     constexpr int R = PL::rad(S);
     fft_stage<DIR, PL::N, PL::T, PL::P, R, NS>(v, t);
     if constexpr (S + 1 < PL::NR) {
-      fft_exchange<PL::N, PL::T, PL::P, R, NS>(v, t, line);
-      fft_run<DIR, PL, S + 1, NS * R>(v, t, line);
+      fft_exchange<PL::N, PL::T, PL::P, R, NS, WAVE>(v, t, line);
+      fft_run<DIR, PL, S + 1, NS * R, WAVE>(v, t, line);
     }
   }
 }
 
-// Transform one line in the strided layout.  Every thread of the block must
-// call this (it contains block barriers); `line` is this team's LDS line of
-// lds_line<N>() points.
-template <int DIR, int N, int P>
+// Transform one line in the strided layout; `line` is this team's LDS line of
+// lds_line<N>() points.  With WAVE = false every thread of the block must
+// call this (it contains block barriers); with WAVE = true the team is one
+// whole wave (T = 64) that owns `line` alone, and no block barrier is used.
+template <int DIR, int N, int P, bool WAVE = false>
 __device__ __forceinline__ void fft_line(float2 (&v)[P], int t, float2* line) {
-  fft_run<DIR, FftPlan<N, P>, 0, 1>(v, t, line);
+  static_assert(!WAVE || N / P == 64, "a wave team is 64 threads");
+  fft_run<DIR, FftPlan<N, P>, 0, 1, WAVE>(v, t, line);
 }
 
 }  // namespace rift2

@@ -7,14 +7,14 @@
 //                -> spectrum S in registers; for every filter of the block's
 //                orientation group: S * G_{s,o} / (HW), inverse column DFT
 //                -> Y_{s,o}                                        (row-major complex)
-//   k_noise_pre  row IDFT of the s = 0 planes -> A0_o = |EO_{0,o}| and a
-//                12-bit radix histogram of its float bits per orientation
+//   k_noise_pre  row IDFT of the s = 0 planes, written back in place as
+//                EO_{0,o}, -> A0_o = |EO_{0,o}| and a 12-bit radix histogram
+//                of its float bits per orientation
 //   k_noise_sel  exact median of A0_o (radix select over the candidate bin)
 //                and the noise threshold T_o, evaluated in FP64
-//   k_pass_b     per row and orientation: one row IDFT of the sum over scales
-//                (the total response E + iO, by linearity), then the row IDFT
-//                of each scale; per-pixel phase congruency, amplitude sums,
-//                MIM argmax and moments
+//   k_pass_b_orient  per row and orientation: row IDFTs of the other scales;
+//                per-pixel amplitude sum and phase congruency
+//   k_pass_b_reduce  per pixel over orientations: MIM argmax and moments
 #pragma once
 
 #include "fft.hpp"
@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(C * (H / P)) k_pass_a(const float2* __restrict
 // Block = LINES rows of one orientation.  A0 = |EO_{0,o}| written as float,
 // level-1 histogram of its bit pattern (bits >> 19) merged into hist1[o].
 template <int W, int P>
-__global__ void __launch_bounds__(256) k_noise_pre(const float2* __restrict__ y_in, int H, int n_scales,
+__global__ void __launch_bounds__(256) k_noise_pre(float2* __restrict__ y_in, int H, int n_scales,
                                                    float* __restrict__ a0, uint32_t* __restrict__ hist1) {
   using PL = FftPlan<W, P>;
   constexpr int T = PL::T;
@@ -176,14 +176,17 @@ __global__ void __launch_bounds__(256) k_noise_pre(const float2* __restrict__ y_
   const int team = threadIdx.x / T, t = threadIdx.x % T;
   const int y = blockIdx.x * LINES + team;
   const size_t plane = (size_t)H * W;
-  const float2* src = y_in + (size_t)(o * n_scales) * plane + (size_t)y * W;
+  float2* src = y_in + (size_t)(o * n_scales) * plane + (size_t)y * W;
   float2 v[P];
 #pragma unroll
   for (int m = 0; m < P; ++m) v[m] = src[t + T * m];
   fft_line<+1, W, P>(v, t, lines[team]);  // contains barriers: hist init is visible after
   float* dst = a0 + (size_t)o * plane + (size_t)y * W;
+  // the transformed row replaces its input: pass B takes EO_{0,o} as is
+  float2* eo = src;
 #pragma unroll
   for (int m = 0; m < P; ++m) {
+    eo[t + T * m] = v[m];
     const float a = sqrtf(v[m].x * v[m].x + v[m].y * v[m].y);
     dst[t + T * m] = a;
     atomicAdd(&hist[min(__float_as_uint(a) >> (32 - kHistBits1 - 1), (uint32_t)(kHist1 - 1))], 1u);
@@ -356,97 +359,112 @@ __global__ void __launch_bounds__(256) k_noise_sel2(int hw, NoiseWs ws, NoiseCon
 
 // ---------------------------------------------------------------- pass B
 
-// Per row and orientation: Z = E + iO is the row IDFT of the scale-summed
-// planes (the IDFT is linear); then each scale's row IDFT z_s gives the
-// amplitude sum, the largest amplitude and sum_s |Im(z_s conj(Z))|, so that
-// the energy along the mean phase is En = (|Z|^2 - sum_s |Im(z_s conj Z)|) / X
-// with X = |Z| + eps -- the same quantity as sum_s (e_s phi_e + o_s phi_o -
-// |e_s phi_o - o_s phi_e|) without keeping every scale's response.
-template <int W, int P, int NS, int NO>
-__global__ void __launch_bounds__((row_block<W, P>())) k_pass_b(const float2* __restrict__ y_in, int H, PCConsts pcc,
-                                                                const float* __restrict__ t_o, uint8_t* __restrict__ mim,
-                                                                float* __restrict__ mmax, float* __restrict__ mmin,
-                                                                float* __restrict__ amp) {
-  using PL = FftPlan<W, P>;
-  constexpr int T = PL::T;
-  constexpr int LINES = row_block<W, P>() / T;
-  __shared__ float2 lines[LINES][lds_line<W, T>()];
-  const int team = threadIdx.x / T, t = threadIdx.x % T;
-  const int y = blockIdx.x * LINES + team;
+// One block per (row, orientation): the row IDFT z_s of every scale stays in
+// registers (z_0 was transformed in place by k_noise_pre); Z = E + iO = sum_s z_s, and the energy along the mean phase is
+// En = (|Z|^2 - sum_s |Im(z_s conj Z)|) / X with X = |Z| + eps -- the same
+// quantity as sum_s (e_s phi_e + o_s phi_o - |e_s phi_o - o_s phi_e|).  The
+// pixel's (A_o, PC_o) pair goes to `spc` (orientation-major) for
+// k_pass_b_reduce.
+template <int W, int P, int NS>
+__global__ void __launch_bounds__(W / P) k_pass_b_orient(const float2* __restrict__ y_in, int H, PCConsts pcc,
+                                                         const float* __restrict__ t_o, float2* __restrict__ spc,
+                                                         float* __restrict__ amp) {
+  constexpr int T = W / P;
+  __shared__ float2 line[lds_line<W, T>()];
+  const int t = threadIdx.x;
+  const int y = blockIdx.x, o = blockIdx.y;
   const size_t plane = (size_t)H * W;
   const size_t rowo = (size_t)y * W;
-  float best[P], ma[P], mb[P], mc[P];
-  int idx[P];
+  const float2* base = y_in + (size_t)(o * NS) * plane + rowo + t;
+  float2 zs[NS][P];
 #pragma unroll
-  for (int m = 0; m < P; ++m) {
-    best[m] = -1.0f;
-    idx[m] = 0;
-    ma[m] = mb[m] = mc[m] = 0.0f;
-  }
-  for (int o = 0; o < NO; ++o) {
-    const float2* base = y_in + (size_t)(o * NS) * plane + rowo + t;
-    float2 z[P];
+  for (int m = 0; m < P; ++m) zs[0][m] = base[T * m];
+  float sa[P], mx[P];
 #pragma unroll
-    for (int m = 0; m < P; ++m) z[m] = base[T * m];
+  for (int m = 0; m < P; ++m) sa[m] = mx[m] = 0.0f;
 #pragma unroll
-    for (int s = 1; s < NS; ++s) {
+  for (int s = 0; s < NS; ++s) {
+    if (s + 1 < NS) {
 #pragma unroll
-      for (int m = 0; m < P; ++m) z[m] = cadd(z[m], base[(size_t)s * plane + T * m]);
+      for (int m = 0; m < P; ++m) zs[s + 1][m] = base[(size_t)(s + 1) * plane + T * m];
     }
-    // the first scale's row (an L2 re-read) is in flight during the Z transform
-    float2 nxt[P];
-#pragma unroll
-    for (int m = 0; m < P; ++m) nxt[m] = base[T * m];
-    fft_line<+1, W, P>(z, t, lines[team]);
-    float sa[P], mx[P], si[P];
-#pragma unroll
-    for (int m = 0; m < P; ++m) sa[m] = mx[m] = si[m] = 0.0f;
-#pragma unroll 1
-    for (int s = 0; s < NS; ++s) {
-      float2 v[P];
-#pragma unroll
-      for (int m = 0; m < P; ++m) v[m] = nxt[m];
-      if (s + 1 < NS) {
-#pragma unroll
-        for (int m = 0; m < P; ++m) nxt[m] = base[(size_t)(s + 1) * plane + T * m];
-      }
-      fft_line<+1, W, P>(v, t, lines[team]);
-#pragma unroll
-      for (int m = 0; m < P; ++m) {
-        const float a = sqrtf(v[m].x * v[m].x + v[m].y * v[m].y);
-        sa[m] += a;
-        mx[m] = fmaxf(mx[m], a);
-        si[m] += fabsf(v[m].y * z[m].x - v[m].x * z[m].y);
-      }
-    }
-    const float thr = t_o[o];
-    const float co = pcc.cos_o[o], so = pcc.sin_o[o];
+    if (s > 0) fft_line<+1, W, P>(zs[s], t, line);
 #pragma unroll
     for (int m = 0; m < P; ++m) {
-      const float z2 = z[m].x * z[m].x + z[m].y * z[m].y;
-      const float xe = sqrtf(z2) + pcc.eps;
-      const float en = (z2 - si[m]) / xe;
-      const float spread = (sa[m] / (mx[m] + pcc.eps) - 1.0f) / (float)(NS - 1);
-      const float wgt = 1.0f / (1.0f + __expf(pcc.g * (pcc.cutoff - spread)));
-      const float pc = wgt * fmaxf(en - thr, 0.0f) / (sa[m] + pcc.eps);
-      if (sa[m] > best[m]) {
-        best[m] = sa[m];
-        idx[m] = o;
-      }
-      const float pcc_ = pc * co, pcs_ = pc * so;
-      ma[m] += pcc_ * pcc_;
-      mb[m] += 2.0f * pcc_ * pcs_;
-      mc[m] += pcs_ * pcs_;
-      if (amp) amp[(size_t)o * plane + rowo + t + T * m] = sa[m];
+      const float a = sqrtf(zs[s][m].x * zs[s][m].x + zs[s][m].y * zs[s][m].y);
+      sa[m] += a;
+      mx[m] = __uint_as_float(max(__float_as_uint(mx[m]), __float_as_uint(a)));
     }
   }
+  const float thr = t_o[o];
+  float2* out = spc + (size_t)o * plane + rowo + t;
 #pragma unroll
   for (int m = 0; m < P; ++m) {
-    const float root = sqrtf(mb[m] * mb[m] + (ma[m] - mc[m]) * (ma[m] - mc[m]));
-    mmax[rowo + t + T * m] = 0.5f * (ma[m] + mc[m] + root);
-    if (mmin) mmin[rowo + t + T * m] = 0.5f * (ma[m] + mc[m] - root);
-    mim[rowo + t + T * m] = (uint8_t)idx[m];
+    float2 z = zs[0][m];
+#pragma unroll
+    for (int s = 1; s < NS; ++s) z = cadd(z, zs[s][m]);
+    float si = 0.0f;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) si += fabsf(zs[s][m].y * z.x - zs[s][m].x * z.y);
+    const float z2 = z.x * z.x + z.y * z.y;
+    const float xe = sqrtf(z2) + pcc.eps;
+    const float en = (z2 - si) / xe;
+    const float spread = (sa[m] / (mx[m] + pcc.eps) - 1.0f) / (float)(NS - 1);
+    const float wgt = 1.0f / (1.0f + __expf(pcc.g * (pcc.cutoff - spread)));
+    const float pc = wgt * fmaxf(en - thr, 0.0f) / (sa[m] + pcc.eps);
+    out[T * m] = make_float2(sa[m], pc);
+    if (amp) amp[(size_t)o * plane + rowo + t + T * m] = sa[m];
   }
+}
+
+// Per pixel over orientations (ascending): MIM = first argmax of A_o,
+// moments of PC_o.  Four pixels per thread, 16-byte accesses.
+template <int NO>
+__global__ void __launch_bounds__(256) k_pass_b_reduce(const float2* __restrict__ spc, int hw, PCConsts pcc,
+                                                       uint8_t* __restrict__ mim, float* __restrict__ mmax,
+                                                       float* __restrict__ mmin) {
+  const int i = 4 * (blockIdx.x * 256 + threadIdx.x);
+  if (i >= hw) return;  // hw is a multiple of 4
+  float best[4], ma[4], mb[4], mc[4];
+  int idx[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    best[e] = -1.0f;
+    idx[e] = 0;
+    ma[e] = mb[e] = mc[e] = 0.0f;
+  }
+#pragma unroll
+  for (int q = 0; q < NO; ++q) {
+    const float4* src = (const float4*)(spc + (size_t)q * hw + i);
+    const float4 r01 = src[0], r23 = src[1];
+    const float av[4] = {r01.x, r01.z, r23.x, r23.z};
+    const float pv[4] = {r01.y, r01.w, r23.y, r23.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (av[e] > best[e]) {
+        best[e] = av[e];
+        idx[e] = q;
+      }
+      const float pcc_ = pv[e] * pcc.cos_o[q], pcs_ = pv[e] * pcc.sin_o[q];
+      ma[e] += pcc_ * pcc_;
+      mb[e] += 2.0f * pcc_ * pcs_;
+      mc[e] += pcs_ * pcs_;
+    }
+  }
+  float4 mxv, mnv;
+  float* mxp = &mxv.x;
+  float* mnp = &mnv.x;
+  uint32_t packed = 0u;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const float root = sqrtf(mb[e] * mb[e] + (ma[e] - mc[e]) * (ma[e] - mc[e]));
+    mxp[e] = 0.5f * (ma[e] + mc[e] + root);
+    mnp[e] = 0.5f * (ma[e] + mc[e] - root);
+    packed |= (uint32_t)idx[e] << (8 * e);
+  }
+  *(float4*)(mmax + i) = mxv;
+  if (mmin) *(float4*)(mmin + i) = mnv;
+  *(uint32_t*)(mim + i) = packed;
 }
 
 }  // namespace rift2
