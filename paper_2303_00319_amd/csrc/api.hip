@@ -221,11 +221,11 @@ bool dispatch_fwd_rows(int W, int dtype, const void* img, int64_t pitch, int H, 
 }
 
 template <int H, int P, int C>
-void launch_pass_a(int W, const float2* rrow, const FilterConsts& fc, float2* y, hipStream_t st) {
-  // Split the orientations over grid.y until there are >= 512 blocks; each
-  // group recomputes the column DFT of its block (an extra read of Rrow).
+void launch_pass_a(int W, const float2* rrow, const FilterConsts& fc, float2* y, hipStream_t st, int min_blocks = 512) {
+  // Split the orientations over grid.y until there are >= min_blocks blocks;
+  // each group recomputes the column DFT of its block (an extra read of Rrow).
   const int xblocks = W / C;
-  int groups = (512 + xblocks - 1) / xblocks;
+  int groups = (min_blocks + xblocks - 1) / xblocks;
   if (groups > fc.n_orient) groups = fc.n_orient;
   if (groups < 1) groups = 1;
   hipLaunchKernelGGL((k_pass_a<H, P, C>), dim3(xblocks, groups), dim3(C * (H / P)), 0, st, rrow, fc, y);
@@ -236,7 +236,7 @@ bool dispatch_pass_a(int H, int W, const float2* rrow, const FilterConsts& fc, f
     case 256: launch_pass_a<256, 16, 16>(W, rrow, fc, y, st); return true;
     case 512: launch_pass_a<512, 16, 16>(W, rrow, fc, y, st); return true;
     case 768: launch_pass_a<768, 12, 8>(W, rrow, fc, y, st); return true;
-    case 1024: launch_pass_a<1024, 16, 8>(W, rrow, fc, y, st); return true;
+    case 1024: launch_pass_a<1024, 8, 8>(W, rrow, fc, y, st, 256); return true;
     case 1536: launch_pass_a<1536, 12, 4>(W, rrow, fc, y, st); return true;
     case 2048: launch_pass_a<2048, 16, 4>(W, rrow, fc, y, st); return true;
     case 4096: launch_pass_a<4096, 16, 2>(W, rrow, fc, y, st); return true;
@@ -528,7 +528,7 @@ rift2_status rift2_describe(const uint8_t* mim, int32_t H, int32_t W, const rift
   uint32_t* info = (uint32_t*)workspace;
   const int* kp = (const int*)kpts;
   (void)hipGetLastError();
-  const int blocks2 = (kpt_cap + 255) / 256;
+  const int blocks2 = (kpt_cap + kDesc2Kpts - 1) / kDesc2Kpts;
   ProfScope ps(6, st);
   if (dp->patch_size == 96 && dp->grid == 6 && dp->n_orient == 6) {
     constexpr int KPB = desc_kpb<96>();

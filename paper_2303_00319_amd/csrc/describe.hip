@@ -152,49 +152,65 @@ __global__ void __launch_bounds__(P * desc_kpb<P>()) k_describe(const uint8_t* _
   }
 }
 
-// Secondary rows: row n + (number of flagged keypoints before i).
+// Secondary rows: row n + (number of flagged keypoints before i).  A block
+// covers kDesc2Kpts keypoints; its flagged keypoints are compacted by one
+// wave ballot, and every (flagged keypoint, cell) pair is one work item that
+// gathers the cell's counts from the primary row, rotated by s2 - s.
+// Keypoint index and rotation are kept in separate words: this compiler
+// drops a 24-bit mask (x & 0xffffff) in front of a 64-bit multiply-add, so a
+// packed (index | rotation << 24) word would address far outside the rows.
+constexpr int kDesc2Kpts = 64;
+
 template <int G, int NO>
 __global__ void __launch_bounds__(256) k_describe2(const int32_t* __restrict__ n_kpts, int kpt_cap,
                                                    const uint32_t* __restrict__ info, uint16_t* __restrict__ desc,
                                                    float* __restrict__ inv_norm, int32_t* __restrict__ desc_kp,
                                                    int32_t* __restrict__ n_desc) {
-  constexpr int D = G * G * NO;
-  __shared__ uint32_t scratch[256];
-  __shared__ int flagged[256];
+  constexpr int CELLS = G * G;
+  constexpr int D = CELLS * NO;
+  __shared__ uint32_t scratch[4];
+  __shared__ int flagged_kp[kDesc2Kpts];
+  __shared__ int flagged_delta[kDesc2Kpts];
   __shared__ uint32_t sh_base, sh_nflag;
   const int n = min(*n_kpts, kpt_cap);
-  const int start = blockIdx.x * 256;
+  const int start = blockIdx.x * kDesc2Kpts;
   if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) *n_desc = 0;
   if (start >= n) return;
   uint32_t before = 0;
   for (int j = threadIdx.x; j < start; j += 256) before += (info[j] >> 8) & 1u;
   const uint32_t tot = block_inclusive_scan<256>(before, scratch);
   if (threadIdx.x == 255) sh_base = tot;
-  const int i = start + threadIdx.x;
-  const uint32_t f = (i < n) ? ((info[i] >> 8) & 1u) : 0u;
-  const uint32_t incl = block_inclusive_scan<256>(f, scratch);
-  // flagged[] holds (keypoint | delta << 24); keypoint indices stay below 2^24
-  if (f) flagged[incl - 1] = i | (int)((info[i] & 0xffu) << 24);
-  if (threadIdx.x == 255) sh_nflag = incl;
+  if (threadIdx.x < kDesc2Kpts) {  // wave 0
+    const int i = start + threadIdx.x;
+    const uint32_t word = (i < n) ? info[i] : 0u;
+    const bool f = (word >> 8) & 1u;
+    const uint64_t mask = __ballot(f);
+    if (f) {
+      const int pos = __popcll(mask & ((1ull << threadIdx.x) - 1ull));
+      flagged_kp[pos] = i;
+      flagged_delta[pos] = (int)(word & 0xffu);
+    }
+    if (threadIdx.x == 0) sh_nflag = (uint32_t)__popcll(mask);
+  }
   __syncthreads();
-  const uint32_t base = sh_base;
+  const int base = (int)sh_base;
   const int nflag = (int)sh_nflag;
-  if (threadIdx.x == 0 && min(n, start + 256) == n) *n_desc = n + (int)base + nflag;
-  // each thread owns descriptor elements e of every secondary row of the block
-  for (int e = threadIdx.x; e < D; e += 256) {
-    const int c = e / NO, b = e - c * NO;
-#pragma unroll 4
-    for (int fi = 0; fi < nflag; ++fi) {
-      const int packed = flagged[fi];
-      const int src_kp = packed & 0xffffff, delta = (packed >> 24) & 0xff;
+  if (threadIdx.x == 0 && min(n, start + kDesc2Kpts) == n) *n_desc = n + base + nflag;
+  for (int w = threadIdx.x; w < nflag * CELLS; w += 256) {
+    const int fi = w / CELLS, c = w - fi * CELLS;
+    const int src_kp = flagged_kp[fi], delta = flagged_delta[fi];
+    const uint16_t* src = desc + (size_t)src_kp * D + c * NO;
+    uint16_t* dst = desc + (size_t)(n + base + fi) * D + c * NO;
+#pragma unroll
+    for (int b = 0; b < NO; ++b) {
       int bb = b + delta;
       if (bb >= NO) bb -= NO;
-      desc[(size_t)(n + base + fi) * D + e] = desc[(size_t)src_kp * D + c * NO + bb];
+      dst[b] = src[bb];
     }
   }
   for (int fi = threadIdx.x; fi < nflag; fi += 256) {
-    const int row = n + (int)base + fi;
-    const int src_kp = flagged[fi] & 0xffffff;
+    const int row = n + base + fi;
+    const int src_kp = flagged_kp[fi];
     inv_norm[row] = inv_norm[src_kp];
     desc_kp[row] = src_kp;
   }

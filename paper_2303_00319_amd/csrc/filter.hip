@@ -120,7 +120,13 @@ __global__ void __launch_bounds__(C * (H / P)) k_pass_a(const float2* __restrict
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c = lane % C;
   const int t = lane / C + L * wave;
-  const int l = blockIdx.x * C + c;
+  // Consecutive block ids run on different XCDs (round robin over 8), each
+  // with its own L2: hand every XCD a contiguous run of column blocks so that
+  // neighbouring C-point row segments of the planes are written through one
+  // L2 and leave it as whole lines.
+  const int nbx = gridDim.x;
+  const int cb = (nbx % 8 == 0) ? (int)(blockIdx.x % 8) * (nbx / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
+  const int l = cb * C + c;
   float2 spec[P];
 #pragma unroll
   for (int m = 0; m < P; ++m) spec[m] = rrow[(size_t)(t + T * m) * W + l];
