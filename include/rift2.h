@@ -192,6 +192,7 @@ rift2_status rift2_describe(const uint8_t* mim, int32_t H, int32_t W, const rift
  * a different B keypoint; accepted iff d2(j1) < fl(ratio_sq * d2(j2)).  Per A
  * keypoint the accepted row with the smallest d2 (ties -> lowest row) is
  * kept.  Output sorted by kp_a; capacity cap_a entries.
+ *   desc_a, desc_b  rows of D uint16 counts, 16-byte aligned
  *   nA_dev, nB_dev  device int32 row counts (<= cap_a, cap_b)
  *   n_out_dev       device int32: number of matches written */
 rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32_t* kp_a,

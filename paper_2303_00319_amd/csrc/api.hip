@@ -33,7 +33,7 @@ struct Carver {
   }
 };
 
-constexpr int kNoiseRegions = 64;  // k_noise_sel1 blocks (candidate list regions) per orientation
+constexpr int kNoiseRegions = 256;  // k_noise_sel1 / k_noise_sel2 blocks (candidate list regions) per orientation
 
 bool size_ok(int n) {
   switch (n) {
@@ -70,7 +70,7 @@ FilterLayout filter_layout(int H, int W, const rift2_pc_params* p) {
   L.a0 = c.take(hw * p->n_orient * sizeof(float));
   L.cand = c.take(hw * p->n_orient * sizeof(uint32_t));
   L.spc = c.take(hw * p->n_orient * sizeof(float2));
-  L.zero_words = p->n_orient * (kHist1 + 2 * kHist2 + 2 * kHist3 + 1 + kNoiseRegions);
+  L.zero_words = p->n_orient * (kHist1 + 2 * kHist2 + 2 * kHist3 + 8 + kNoiseRegions);
   L.zero = c.take((size_t)L.zero_words * sizeof(uint32_t));
   L.t32 = c.take(p->n_orient * sizeof(float));
   L.t64 = c.take(p->n_orient * sizeof(double));
@@ -245,21 +245,21 @@ bool dispatch_pass_a(int H, int W, const float2* rrow, const FilterConsts& fc, f
 }
 
 template <int W, int P>
-void launch_noise_pre(int H, int n_orient, int n_scales, float2* y, float* a0, uint32_t* hist1, hipStream_t st) {
+void launch_noise_pre(int H, int n_orient, int n_scales, float2* y, float* a0, const NoiseWs& ws, hipStream_t st) {
   constexpr int LINES = 256 / FftPlan<W, P>::T;
-  hipLaunchKernelGGL((k_noise_pre<W, P>), dim3(H / LINES, n_orient), dim3(256), 0, st, y, H, n_scales, a0, hist1);
+  hipLaunchKernelGGL((k_noise_pre<W, P>), dim3(H / LINES, n_orient), dim3(256), 0, st, y, H, n_scales, a0, ws);
 }
 
-bool dispatch_noise_pre(int W, int H, int n_orient, int n_scales, float2* y, float* a0, uint32_t* hist1,
+bool dispatch_noise_pre(int W, int H, int n_orient, int n_scales, float2* y, float* a0, const NoiseWs& ws,
                         hipStream_t st) {
   switch (W) {
-    case 256: launch_noise_pre<256, 16>(H, n_orient, n_scales, y, a0, hist1, st); return true;
-    case 512: launch_noise_pre<512, 16>(H, n_orient, n_scales, y, a0, hist1, st); return true;
-    case 768: launch_noise_pre<768, 12>(H, n_orient, n_scales, y, a0, hist1, st); return true;
-    case 1024: launch_noise_pre<1024, 16>(H, n_orient, n_scales, y, a0, hist1, st); return true;
-    case 1536: launch_noise_pre<1536, 12>(H, n_orient, n_scales, y, a0, hist1, st); return true;
-    case 2048: launch_noise_pre<2048, 16>(H, n_orient, n_scales, y, a0, hist1, st); return true;
-    case 4096: launch_noise_pre<4096, 16>(H, n_orient, n_scales, y, a0, hist1, st); return true;
+    case 256: launch_noise_pre<256, 16>(H, n_orient, n_scales, y, a0, ws, st); return true;
+    case 512: launch_noise_pre<512, 16>(H, n_orient, n_scales, y, a0, ws, st); return true;
+    case 768: launch_noise_pre<768, 12>(H, n_orient, n_scales, y, a0, ws, st); return true;
+    case 1024: launch_noise_pre<1024, 16>(H, n_orient, n_scales, y, a0, ws, st); return true;
+    case 1536: launch_noise_pre<1536, 12>(H, n_orient, n_scales, y, a0, ws, st); return true;
+    case 2048: launch_noise_pre<2048, 16>(H, n_orient, n_scales, y, a0, ws, st); return true;
+    case 4096: launch_noise_pre<4096, 16>(H, n_orient, n_scales, y, a0, ws, st); return true;
     default: return false;
   }
 }
@@ -413,8 +413,8 @@ rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t
   nws.hist1 = zero;
   nws.hist2 = nws.hist1 + pc->n_orient * kHist1;
   nws.hist3 = nws.hist2 + pc->n_orient * 2 * kHist2;
-  nws.done = nws.hist3 + pc->n_orient * 2 * kHist3;
-  nws.cnt = nws.done + pc->n_orient;
+  nws.state = nws.hist3 + pc->n_orient * 2 * kHist3;
+  nws.cnt = nws.state + 8 * pc->n_orient;
   nws.regions = kNoiseRegions;
   nws.cand = cand;
   float* t32 = (float*)(ws + L.t32);
@@ -462,13 +462,16 @@ rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t
   }
   {
     ProfScope ps(2, st);
-    dispatch_noise_pre(W, H, pc->n_orient, pc->n_scales, yp, a0, nws.hist1, st);
+    dispatch_noise_pre(W, H, pc->n_orient, pc->n_scales, yp, a0, nws, st);
   }
   const int hw = H * W;
   {
     ProfScope ps(3, st);
+    hipLaunchKernelGGL(k_noise_bins<1>, dim3(pc->n_orient), dim3(256), 0, st, hw, nws, nc, t32, t64);
     hipLaunchKernelGGL(k_noise_sel1, dim3(kNoiseRegions, pc->n_orient), dim3(256), 0, st, a0, hw, nws);
-    hipLaunchKernelGGL(k_noise_sel2, dim3(kNoiseRegions, pc->n_orient), dim3(256), 0, st, hw, nws, nc, t32, t64);
+    hipLaunchKernelGGL(k_noise_bins<2>, dim3(pc->n_orient), dim3(256), 0, st, hw, nws, nc, t32, t64);
+    hipLaunchKernelGGL(k_noise_sel2, dim3(kNoiseRegions, pc->n_orient), dim3(256), 0, st, hw, nws);
+    hipLaunchKernelGGL(k_noise_bins<3>, dim3(pc->n_orient), dim3(256), 0, st, hw, nws, nc, t32, t64);
   }
   {
     ProfScope ps(4, st);
@@ -565,6 +568,8 @@ rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32
   if (!(mp->ratio_sq > 0.0f) || (mp->precision != RIFT2_PREC_FP32 && mp->precision != RIFT2_PREC_BF16))
     return RIFT2_ERR_INVALID_ARG;
   if (D != 216 && D != 288) return RIFT2_ERR_UNSUPPORTED;
+  // the table preparation reads descriptor rows as 16-byte vectors
+  if (((uintptr_t)desc_a & 15u) || ((uintptr_t)desc_b & 15u)) return RIFT2_ERR_INVALID_ARG;
   const MatchLayout L = match_layout(cap_a, cap_b, D, mp->precision);
   if (workspace_bytes < L.total) return RIFT2_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;

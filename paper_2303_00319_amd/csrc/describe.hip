@@ -177,6 +177,7 @@ __global__ void __launch_bounds__(256) k_describe2(const int32_t* __restrict__ n
   if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) *n_desc = 0;
   if (start >= n) return;
   uint32_t before = 0;
+#pragma unroll 4
   for (int j = threadIdx.x; j < start; j += 256) before += (info[j] >> 8) & 1u;
   const uint32_t tot = block_inclusive_scan<256>(before, scratch);
   if (threadIdx.x == 255) sh_base = tot;

@@ -57,9 +57,8 @@ __global__ void __launch_bounds__(256) k_fwd_rows(const Tin* __restrict__ img, i
   constexpr int T = PL::T;
   constexpr int LINES = 256 / T;
   __shared__ float2 lines[LINES][lds_line<W, T>()];
-  if (blockIdx.x == 0) {
-    for (int i = threadIdx.x; i < n_zero; i += blockDim.x) zero[i] = 0u;
-  }
+  // clear the noise-selection counters and histograms (spread over the grid)
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_zero; i += gridDim.x * blockDim.x) zero[i] = 0u;
   const int team = threadIdx.x / T, t = threadIdx.x % T;
   const int y = blockIdx.x * LINES + team;  // H % LINES == 0 (checked on the host)
   const Tin* row = img + (int64_t)y * pitch;
@@ -165,13 +164,38 @@ __global__ void __launch_bounds__(C * (H / P)) k_pass_a(const float2* __restrict
   }
 }
 
-// ---------------------------------------------------------------- noise pre-pass
+// ---------------------------------------------------------------- noise threshold
+
+// Exact median of A0_o (mean of the order statistics of rank HW/2-1 and HW/2)
+// by a three-level radix selection on the float bit patterns (values are
+// non-negative, so the bits order like the values): 13 bits (histogram built
+// by k_noise_pre), 10 bits (k_noise_sel1), 9 bits (k_noise_sel2).  After each
+// histogram a one-block-per-orientation k_noise_bins resolves that level and
+// publishes the bins: the kernel boundary orders the histogram merges before
+// the search without a device-wide fence (which would write back every XCD's
+// L2, full of the freshly written planes).
+constexpr int kHist2 = 1024, kHist3 = 512;
+
+struct NoiseConsts {
+  double mult, k;
+  int n_scales;
+};
+
+struct NoiseWs {
+  uint32_t* hist1;  // [N_o][kHist1]
+  uint32_t* hist2;  // [N_o][2][kHist2]
+  uint32_t* hist3;  // [N_o][2][kHist3]
+  uint32_t* state;  // [N_o][8] level-1 bins, counts below them, level-2 bins, counts below (two ranks each)
+  uint32_t* cnt;    // [N_o][regions] candidate counts of each k_noise_sel1 block
+  int regions;      // k_noise_sel1 / k_noise_sel2 blocks per orientation
+  uint32_t* cand;   // [N_o][HW] candidate bit patterns
+};
 
 // Block = LINES rows of one orientation.  A0 = |EO_{0,o}| written as float,
 // level-1 histogram of its bit pattern (bits >> 19) merged into hist1[o].
 template <int W, int P>
 __global__ void __launch_bounds__(256) k_noise_pre(float2* __restrict__ y_in, int H, int n_scales,
-                                                   float* __restrict__ a0, uint32_t* __restrict__ hist1) {
+                                                   float* __restrict__ a0, NoiseWs ws) {
   using PL = FftPlan<W, P>;
   constexpr int T = PL::T;
   constexpr int LINES = 256 / T;
@@ -198,33 +222,63 @@ __global__ void __launch_bounds__(256) k_noise_pre(float2* __restrict__ y_in, in
     atomicAdd(&hist[min(__float_as_uint(a) >> (32 - kHistBits1 - 1), (uint32_t)(kHist1 - 1))], 1u);
   }
   __syncthreads();
-  uint32_t* gh = hist1 + (size_t)o * kHist1;
+  uint32_t* gh = ws.hist1 + (size_t)o * kHist1;
   for (int i = threadIdx.x; i < kHist1; i += 256) {
     const uint32_t c = hist[i];
     if (c) atomicAdd(&gh[i], c);
   }
 }
 
-// Exact median of A0_o (mean of the order statistics of rank HW/2-1 and HW/2)
-// by a three-level radix selection on the float bit patterns (values are
-// non-negative, so the bits order like the values): 13 bits (level 1, built
-// by k_noise_pre), 10 bits, 9 bits.
-constexpr int kHist2 = 1024, kHist3 = 512;
-
-struct NoiseConsts {
-  double mult, k;
-  int n_scales;
-};
-
-struct NoiseWs {
-  uint32_t* hist1;  // [N_o][kHist1]
-  uint32_t* hist2;  // [N_o][2][kHist2]
-  uint32_t* hist3;  // [N_o][2][kHist3]
-  uint32_t* cnt;    // [N_o][regions] candidate counts of each k_noise_sel1 block
-  int regions;      // k_noise_sel1 blocks per orientation
-  uint32_t* done;   // [N_o] finished blocks of k_noise_sel2
-  uint32_t* cand;   // [N_o][HW] candidate bit patterns
-};
+// One block per orientation: resolves level LEVEL of the selection for both
+// ranks and publishes it in state[o]; level 3 ends with the median and the
+// noise threshold, evaluated in FP64.
+template <int LEVEL>
+__global__ void __launch_bounds__(256) k_noise_bins(int hw, NoiseWs ws, NoiseConsts nc, float* __restrict__ t_out,
+                                                    double* __restrict__ t_out64) {
+  __shared__ uint32_t scratch[4];
+  __shared__ int s_bin[2];
+  __shared__ uint32_t s_below[2];
+  const int o = blockIdx.x;
+  uint32_t* st = ws.state + 8 * o;
+  const uint32_t rank[2] = {(uint32_t)(hw / 2 - 1), (uint32_t)(hw / 2)};
+  if (LEVEL == 1) {
+    const uint32_t* h = ws.hist1 + (size_t)o * kHist1;
+    for (int q = 0; q < 2; ++q) block_find_rank<kHist1, 256, false>(h, rank[q], &s_bin[q], &s_below[q], scratch);
+    if (threadIdx.x == 0) {
+      st[0] = (uint32_t)s_bin[0];
+      st[1] = (uint32_t)s_bin[1];
+      st[2] = s_below[0];
+      st[3] = s_below[1];
+    }
+  } else if (LEVEL == 2) {
+    const uint32_t* h = ws.hist2 + (size_t)o * 2 * kHist2;
+    for (int q = 0; q < 2; ++q)
+      block_find_rank<kHist2, 256, false>(h + q * kHist2, rank[q] - st[2 + q], &s_bin[q], &s_below[q], scratch);
+    if (threadIdx.x == 0) {
+      st[4] = (uint32_t)s_bin[0];
+      st[5] = (uint32_t)s_bin[1];
+      st[6] = s_below[0];
+      st[7] = s_below[1];
+    }
+  } else {
+    const uint32_t* h = ws.hist3 + (size_t)o * 2 * kHist3;
+    float vals[2];
+    for (int q = 0; q < 2; ++q) {
+      block_find_rank<kHist3, 256, false>(h + q * kHist3, rank[q] - st[2 + q] - st[6 + q], &s_bin[q], &s_below[q],
+                                          scratch);
+      vals[q] = __uint_as_float((((st[q] << 10) | st[4 + q]) << 9) | (uint32_t)s_bin[q]);
+    }
+    if (threadIdx.x == 0) {
+      const double med = 0.5 * ((double)vals[0] + (double)vals[1]);
+      const double tau = med / sqrt(log(4.0));
+      const double total = tau * (1.0 - pow(1.0 / nc.mult, (double)nc.n_scales)) / (1.0 - 1.0 / nc.mult);
+      const double pi = 3.14159265358979323846;
+      const double tt = total * sqrt(pi / 2.0) + nc.k * total * sqrt((4.0 - pi) / 2.0);
+      t_out[o] = (float)tt;
+      t_out64[o] = tt;
+    }
+  }
+}
 
 // Appends the taking lanes' values to this block's own list region; the
 // position comes from a block-local LDS counter (no global atomics).
@@ -239,28 +293,24 @@ __device__ __forceinline__ void block_append(bool take, uint32_t value, uint32_t
   if (take) region[base + __popcll(mask & ((1ull << lane) - 1ull))] = value;
 }
 
-// Level 2: every block finds the level-1 bins of both ranks, copies the
-// values of those bins into its own region of the candidate list (region b
-// = its chunk of A0, so it cannot overflow) and histograms their next 10 bits.
+// Level 2: every block copies the values of the two level-1 bins from its
+// chunk of A0 into its own region of the candidate list (region b = chunk
+// b, so it cannot overflow) and histograms their next 10 bits.
 __global__ void __launch_bounds__(256) k_noise_sel1(const float* __restrict__ a0, int hw, NoiseWs ws) {
-  __shared__ uint32_t scratch[256];
   __shared__ uint32_t h2[2][kHist2];
-  __shared__ int s_bin[2];
-  __shared__ uint32_t s_below[2];
   __shared__ uint32_t s_count;
   const int o = blockIdx.y;
   for (int i = threadIdx.x; i < 2 * kHist2; i += 256) (&h2[0][0])[i] = 0u;
   if (threadIdx.x == 0) s_count = 0u;
-  const uint32_t rank[2] = {(uint32_t)(hw / 2 - 1), (uint32_t)(hw / 2)};
-  const uint32_t* gh1 = ws.hist1 + (size_t)o * kHist1;
-  for (int q = 0; q < 2; ++q) block_find_rank<kHist1, 256, false>(gh1, rank[q], &s_bin[q], &s_below[q], scratch);
-  const uint32_t b0 = (uint32_t)s_bin[0], b1 = (uint32_t)s_bin[1];
+  const uint32_t* st = ws.state + 8 * o;
+  const uint32_t b0 = st[0], b1 = st[1];
+  __syncthreads();
   const float* src = a0 + (size_t)o * hw;
   const int per_block = (hw + gridDim.x - 1) / gridDim.x;
   const int beg = blockIdx.x * per_block;
   const int end = min(hw, beg + per_block);
   uint32_t* region = ws.cand + (size_t)o * hw + beg;
-  // chunk bounds are multiples of 4 (HW is a multiple of 256): 16-byte loads
+  // chunk bounds are multiples of 4 (both sides are multiples of 256, HW / regions is): 16-byte loads
   for (int i0 = beg; i0 < end; i0 += 1024) {
     const int i = i0 + 4 * threadIdx.x;
     const bool in = i < end;
@@ -286,50 +336,39 @@ __global__ void __launch_bounds__(256) k_noise_sel1(const float* __restrict__ a0
   }
 }
 
-// Level 3 over the candidate list, then the last block resolves both ranks
-// and evaluates the noise threshold in FP64.
-__global__ void __launch_bounds__(256) k_noise_sel2(int hw, NoiseWs ws, NoiseConsts nc, float* __restrict__ t_out,
-                                                    double* __restrict__ t_out64) {
-  __shared__ uint32_t scratch[256];
+// Level 3: one block per candidate region histograms the last 9 bits of the
+// candidates that share both upper levels of a rank.
+__global__ void __launch_bounds__(256) k_noise_sel2(int hw, NoiseWs ws) {
   __shared__ uint32_t h3[2][kHist3];
-  __shared__ int s_bin[2], s_bin2[2], s_bin3[2];
-  __shared__ uint32_t s_below[2], s_below2[2], s_below3[2];
-  __shared__ int s_last;
   const int o = blockIdx.y;
   for (int i = threadIdx.x; i < 2 * kHist3; i += 256) (&h3[0][0])[i] = 0u;
-  const uint32_t rank[2] = {(uint32_t)(hw / 2 - 1), (uint32_t)(hw / 2)};
-  const uint32_t* gh1 = ws.hist1 + (size_t)o * kHist1;
-  const uint32_t* gh2 = ws.hist2 + (size_t)o * 2 * kHist2;
-  for (int q = 0; q < 2; ++q) {
-    block_find_rank<kHist1, 256, false>(gh1, rank[q], &s_bin[q], &s_below[q], scratch);
-    block_find_rank<kHist2, 256, false>(gh2 + q * kHist2, rank[q] - s_below[q], &s_bin2[q], &s_below2[q], scratch);
-  }
-  const uint32_t p0 = ((uint32_t)s_bin[0] << 10) | (uint32_t)s_bin2[0];
-  const uint32_t p1 = ((uint32_t)s_bin[1] << 10) | (uint32_t)s_bin2[1];
+  const uint32_t* st = ws.state + 8 * o;
+  const uint32_t p0 = (st[0] << 10) | st[4];
+  const uint32_t p1 = (st[1] << 10) | st[5];
   const int per_region = (hw + ws.regions - 1) / ws.regions;
-  for (int rg = blockIdx.x; rg < ws.regions; rg += gridDim.x) {
-    const uint32_t n = ws.cnt[(size_t)o * ws.regions + rg];
-    const uint32_t* list = ws.cand + (size_t)o * hw + (size_t)rg * per_region;  // 16-byte aligned
-    for (uint32_t i = 4 * threadIdx.x; i < n; i += 1024) {
-      uint32_t qv[4];
-      if (i + 4 <= n) {
-        const uint4 q4 = *(const uint4*)(list + i);
-        qv[0] = q4.x;
-        qv[1] = q4.y;
-        qv[2] = q4.z;
-        qv[3] = q4.w;
-      } else {
+  const int rg = blockIdx.x;
+  const uint32_t n = ws.cnt[(size_t)o * ws.regions + rg];
+  const uint32_t* list = ws.cand + (size_t)o * hw + (size_t)rg * per_region;  // 16-byte aligned
+  __syncthreads();
+  for (uint32_t i = 4 * threadIdx.x; i < n; i += 1024) {
+    uint32_t qv[4];
+    if (i + 4 <= n) {
+      const uint4 q4 = *(const uint4*)(list + i);
+      qv[0] = q4.x;
+      qv[1] = q4.y;
+      qv[2] = q4.z;
+      qv[3] = q4.w;
+    } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) qv[e] = i + e < n ? list[i + e] : 0u;
-      }
+      for (int e = 0; e < 4; ++e) qv[e] = i + e < n ? list[i + e] : 0u;
+    }
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if (i + e >= n) break;
-        const uint32_t bits = qv[e];
-        const uint32_t pre = bits >> 9;
-        if (pre == p0) atomicAdd(&h3[0][bits & (kHist3 - 1)], 1u);
-        if (pre == p1) atomicAdd(&h3[1][bits & (kHist3 - 1)], 1u);
-      }
+    for (int e = 0; e < 4; ++e) {
+      if (i + e >= n) break;
+      const uint32_t bits = qv[e];
+      const uint32_t pre = bits >> 9;
+      if (pre == p0) atomicAdd(&h3[0][bits & (kHist3 - 1)], 1u);
+      if (pre == p1) atomicAdd(&h3[1][bits & (kHist3 - 1)], 1u);
     }
   }
   __syncthreads();
@@ -337,29 +376,6 @@ __global__ void __launch_bounds__(256) k_noise_sel2(int hw, NoiseWs ws, NoiseCon
   for (int i = threadIdx.x; i < 2 * kHist3; i += 256) {
     const uint32_t c = (&h3[0][0])[i];
     if (c) atomicAdd(&gh3[i], c);
-  }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) s_last = (atomicAdd(ws.done + o, 1u) == gridDim.x - 1);
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  for (int i = threadIdx.x; i < 2 * kHist3; i += 256) (&h3[0][0])[i] = __atomic_load_n(&gh3[i], __ATOMIC_RELAXED);
-  __syncthreads();
-  float vals[2];
-  for (int q = 0; q < 2; ++q) {
-    block_find_rank<kHist3, 256, false>(h3[q], rank[q] - s_below[q] - s_below2[q], &s_bin3[q], &s_below3[q],
-                                        scratch);
-    vals[q] = __uint_as_float((((uint32_t)s_bin[q] << 10 | (uint32_t)s_bin2[q]) << 9) | (uint32_t)s_bin3[q]);
-  }
-  if (threadIdx.x == 0) {
-    const double med = 0.5 * ((double)vals[0] + (double)vals[1]);
-    const double tau = med / sqrt(log(4.0));
-    const double total = tau * (1.0 - pow(1.0 / nc.mult, (double)nc.n_scales)) / (1.0 - 1.0 / nc.mult);
-    const double pi = 3.14159265358979323846;
-    const double tt = total * sqrt(pi / 2.0) + nc.k * total * sqrt((4.0 - pi) / 2.0);
-    t_out[o] = (float)tt;
-    t_out64[o] = tt;
   }
 }
 

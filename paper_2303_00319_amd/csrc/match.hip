@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "scan.hpp"
+
 namespace rift2 {
 
 constexpr int kTopK = 3;  // a keypoint owns <= 2 rows, so 3 rows hold j1 and j2
@@ -36,19 +38,37 @@ __device__ __forceinline__ uint16_t bf16_bits_of_count(uint32_t c) {
 }
 
 // Table layout: rows_pad x DP elements (BF16 bits as uint16, or float).
+// One work item = 8 consecutive elements of a row (D and DP are multiples of
+// 8), read as one 16-byte load and written as one (BF16) or two (FP32)
+// 16-byte stores.
 template <bool BF16>
 __global__ void __launch_bounds__(256) k_match_prep(const uint16_t* __restrict__ desc, const int32_t* __restrict__ n_dev,
                                                     int cap, int D, int DP, int rows_pad, void* __restrict__ table,
                                                     uint64_t* __restrict__ best, int n_best) {
   const int n = min(*n_dev, cap);
-  const size_t total = (size_t)rows_pad * DP;
-  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
-    const int r = (int)(idx / DP), k = (int)(idx % DP);
-    const uint32_t c = (r < n && k < D) ? desc[(size_t)r * D + k] : 0u;
-    if (BF16)
-      ((uint16_t*)table)[idx] = bf16_bits_of_count(c);
-    else
-      ((float*)table)[idx] = (float)c;
+  const int chunks = DP / 8;
+  const size_t total = (size_t)rows_pad * chunks;
+  for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < total; w += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)(w / chunks), k0 = 8 * (int)(w % chunks);
+    uint4 raw = make_uint4(0u, 0u, 0u, 0u);
+    if (r < n && k0 < D) raw = *(const uint4*)(desc + (size_t)r * D + k0);
+    const uint32_t word[4] = {raw.x, raw.y, raw.z, raw.w};
+    uint32_t c[8];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      c[2 * e] = word[e] & 0xffffu;
+      c[2 * e + 1] = word[e] >> 16;
+    }
+    if (BF16) {
+      uint32_t o[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) o[e] = (uint32_t)bf16_bits_of_count(c[2 * e]) | ((uint32_t)bf16_bits_of_count(c[2 * e + 1]) << 16);
+      *(uint4*)((uint16_t*)table + (size_t)r * DP + k0) = make_uint4(o[0], o[1], o[2], o[3]);
+    } else {
+      float* dst = (float*)table + (size_t)r * DP + k0;
+      *(float4*)dst = make_float4((float)c[0], (float)c[1], (float)c[2], (float)c[3]);
+      *(float4*)(dst + 4) = make_float4((float)c[4], (float)c[5], (float)c[6], (float)c[7]);
+    }
   }
   if (best) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_best; i += gridDim.x * blockDim.x) best[i] = ~0ull;
@@ -344,37 +364,28 @@ __global__ void __launch_bounds__(256) k_match_emit(const uint64_t* __restrict__
                                                     const int32_t* __restrict__ row_j1, const float* __restrict__ row_d1,
                                                     const int32_t* __restrict__ kp_b, MatchOut* __restrict__ out,
                                                     int32_t* __restrict__ n_out) {
-  __shared__ uint32_t red[256];
-  __shared__ uint32_t scan[256];
+  __shared__ uint32_t scratch[4];
+  __shared__ uint32_t sh_base;
   const int start = blockIdx.x * 256;
   uint32_t before = 0;
+#pragma unroll 4
   for (int k = threadIdx.x; k < start; k += 256) before += best[k] != ~0ull;
-  red[threadIdx.x] = before;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
-  }
-  const uint32_t base = red[0];
+  const uint32_t tot = block_inclusive_scan<256>(before, scratch);
+  if (threadIdx.x == 255) sh_base = tot;
   const int k = start + threadIdx.x;
-  const bool valid = k < cap_a && best[k] != ~0ull;
-  scan[threadIdx.x] = valid;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    const uint32_t v = threadIdx.x >= off ? scan[threadIdx.x - off] : 0u;
-    __syncthreads();
-    scan[threadIdx.x] += v;
-    __syncthreads();
-  }
+  const uint64_t bk = k < cap_a ? best[k] : ~0ull;
+  const bool valid = bk != ~0ull;
+  const uint32_t incl = block_inclusive_scan<256>(valid ? 1u : 0u, scratch);
+  const uint32_t base = sh_base;  // published before the second scan's barriers
   if (valid) {
-    const int row = (int)(best[k] & 0xffffffffu);
+    const int row = (int)(bk & 0xffffffffu);
     MatchOut m;
     m.kp_a = k;
     m.kp_b = kp_b[row_j1[row]];
     m.dist2 = row_d1[row];
-    out[base + scan[threadIdx.x] - 1] = m;
+    out[base + incl - 1] = m;
   }
-  if (start + 256 >= cap_a && threadIdx.x == 255) *n_out = (int32_t)(base + scan[255]);
+  if (start + 256 >= cap_a && threadIdx.x == 255) *n_out = (int32_t)(base + incl);
 }
 
 }  // namespace rift2
