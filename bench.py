@@ -8,7 +8,9 @@ most 5000 keypoints per image, 6x6x6 = 216-d dominant-index descriptors,
 exhaustive matching with the 0.9 ratio test.  One step = one pair through
 every stage: filter bank / MIM / moments (x2), FAST (x2), descriptors (x2),
 matching.  Inputs are resident in HBM before timing; each pair's step is a
-replayed HIP graph.
+replayed HIP graph.  With --slots S > 1, consecutive steps alternate between
+S buffer sets on S streams (S pairs in flight), so one pair's MFMA-bound
+matching can overlap the next pair's filter bank.
 
 Two forms are timed: plain FP32 (distance GEMM on FP32 MFMA) -- the
 reported `value` -- and mixed (BF16 MFMA on the exact integer counts, the
@@ -20,6 +22,7 @@ single GPU.
 from __future__ import annotations
 
 import argparse
+import faulthandler
 import json
 import math
 import os
@@ -62,6 +65,9 @@ def parse():
     ap.add_argument("--size", type=int, default=1024)
     ap.add_argument("--keypoints", type=int, default=5000)
     ap.add_argument("--no-graph", action="store_true", help="enqueue kernels directly instead of graph replay")
+    ap.add_argument("--slots", type=int, default=1,
+                    help="pairs in flight: consecutive steps use separate buffer sets and streams, so one pair's "
+                         "matching overlaps the next pair's filter bank (1 = every step on the current stream)")
     ap.add_argument("--serial", action="store_true",
                     help="run both images' stages on one stream (no overlap; per-kernel durations for rocprofv3)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -84,18 +90,31 @@ def time_form(r2, torch, imgs, args, precision):
     pc, det, dp, mp = r2.defaults()
     det.max_keypoints = args.keypoints
     mp.precision = precision
-    pipe = r2.PairPipeline(args.size, args.size, pc, det, dp, mp, serial=args.serial)
+    slots = max(1, args.slots)
+    if len(imgs) % slots:
+        raise SystemExit("--pairs must be a multiple of --slots")
+    pipes = [r2.PairPipeline(args.size, args.size, pc, det, dp, mp, serial=args.serial) for _ in range(slots)]
+    streams = [torch.cuda.Stream() for _ in range(slots)] if slots > 1 else []
     graphs = []
     if not args.no_graph:
-        for a, b in imgs:
-            graphs.append(pipe.capture(a, b))
+        for i, (a, b) in enumerate(imgs):
+            print(f"[bench] capture pair {i} on slot {i % slots}", file=sys.stderr, flush=True)
+            graphs.append(pipes[i % slots].capture(a, b))
+    print(f"[bench] warmup {args.warmup} + timed {args.steps} steps", file=sys.stderr, flush=True)
 
     def step(k):
-        if graphs:
-            graphs[k % len(graphs)].replay()
-        else:
-            a, b = imgs[k % len(imgs)]
-            pipe.run(a, b)
+        i = k % len(imgs)
+        if slots == 1:
+            if graphs:
+                graphs[i].replay()
+            else:
+                pipes[0].run(*imgs[i])
+            return
+        with torch.cuda.stream(streams[i % slots]):
+            if graphs:
+                graphs[i].replay()
+            else:
+                pipes[i % slots].run(*imgs[i], streams[i % slots])
 
     for k in range(args.warmup):
         step(k)
@@ -103,22 +122,24 @@ def time_form(r2, torch, imgs, args, precision):
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t0 = time.perf_counter()
     for k in range(args.steps):
-        ev[k][0].record()
+        st = streams[(k % len(imgs)) % slots] if slots > 1 else None
+        ev[k][0].record(st)
         step(k)
-        ev[k][1].record()
+        ev[k][1].record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     lat = [s.elapsed_time(e) for s, e in ev]
-    n_match = int(pipe.n_out.item())
-    n_kp = (int(pipe.a.nk.item()), int(pipe.b.nk.item()))
-    n_desc = (int(pipe.a.nd.item()), int(pipe.b.nd.item()))
+    last = pipes[((args.steps - 1) % len(imgs)) % slots]
+    n_match = int(last.n_out.item())
+    n_kp = (int(last.a.nk.item()), int(last.b.nk.item()))
+    n_desc = (int(last.a.nd.item()), int(last.b.nd.item()))
     return {
         "pairs_per_s": args.steps / wall,
         "ms_per_step": 1000.0 * wall / args.steps,
         "p50_ms": percentile(lat, 50),
         "p99_ms": percentile(lat, 99),
         "last_pair": {"keypoints": n_kp, "descriptor_rows": n_desc, "matches": n_match},
-        "pipe": pipe,
+        "pipe": pipes[0],
     }
 
 
@@ -196,6 +217,7 @@ def cpu_baseline(size, keypoints, n_pairs=3):
 
 
 def main():
+    faulthandler.enable()
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not part of this "
@@ -265,7 +287,8 @@ def main():
                         f"216-d descriptors, exhaustive NN + ratio 0.9",
             "pairs": args.pairs,
             "graph": not args.no_graph,
-            "streams": 1 if args.serial else 2,
+            "streams_per_pair": 1 if args.serial else 2,
+            "pairs_in_flight": max(1, args.slots),
             "last_pair": fp32["last_pair"],
         },
         "mixed": {

@@ -1,0 +1,105 @@
+"""Graph capture and replay of the whole pair step (the form bench.py times).
+
+A captured pair step is replayed several times, with eager work and host
+synchronisations between replays, and every replay's keypoints, descriptor
+rows and matches must equal those of the eager run.  Two pipelines (two
+pairs in flight on two streams) are also replayed concurrently.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from synth import make_pair  # noqa: E402
+
+
+def _translated_pair(index):
+    """Image A of the small case and a shifted, remapped copy (the descriptor grid is axis-aligned, so a
+    rotation-free pair has many correct matches)."""
+    import synth.gen as g
+
+    a, _, _ = make_pair(0, index)
+    b = g._warp_bilinear(a.astype(np.float64), 0.0, 7.0, 4.0)
+    b = np.rint(np.clip(255 * np.power(np.clip((255 - b) / 255, 0, 1), 0.5), 0, 255)).astype(np.uint8)
+    return a, b
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2303_00319_amd as r2
+
+    return r2, torch.device("cuda:0")
+
+
+def _snapshot(pipe):
+    torch.cuda.synchronize()
+    out = {}
+    for name, buf in (("a", pipe.a), ("b", pipe.b)):
+        nk = int(buf.nk.item())
+        nd = int(buf.nd.item())
+        out[name + "_kpts"] = buf.kpts[:nk].cpu().numpy().copy()
+        out[name + "_desc"] = buf.desc[:nd].cpu().numpy().copy()
+        out[name + "_dkp"] = buf.dkp[:nd].cpu().numpy().copy()
+    n = int(pipe.n_out.item())
+    out["matches"] = pipe.out[:n].cpu().numpy().copy()
+    return out
+
+
+def _same(x, y, tag):
+    assert x.keys() == y.keys()
+    for k in x:
+        assert x[k].shape == y[k].shape and np.array_equal(x[k], y[k]), f"{tag}: {k} differs"
+
+
+def _pipeline(r2, size, k, precision):
+    pc, det, dp, mp = r2.defaults()
+    det.max_keypoints = k
+    mp.precision = precision
+    return r2.PairPipeline(size, size, pc, det, dp, mp)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replay_equals_eager(precision):
+    r2, dev = _gpu()
+    print(f"[graph] 256x256 pair, 500 keypoints, precision {precision}", flush=True)
+    a, b = _translated_pair(1)
+    ta, tb = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+    pipe = _pipeline(r2, 256, 500, precision)
+    pipe.run(ta, tb)
+    ref = _snapshot(pipe)
+    assert len(ref["a_kpts"]) > 0 and len(ref["matches"]) > 0
+    g = pipe.capture(ta, tb)
+    side = torch.cuda.Stream()
+    for rep in range(3):
+        junk = torch.ones(1 << 20, device=dev) * rep  # eager work between replays
+        with torch.cuda.stream(side):
+            g.replay()
+        torch.cuda.current_stream().wait_stream(side)
+        _same(ref, _snapshot(pipe), f"replay {rep}")
+        del junk
+
+
+def test_two_pairs_in_flight():
+    r2, dev = _gpu()
+    print("[graph] two 256x256 pairs in flight on two streams", flush=True)
+    pairs = []
+    for i in (2, 3):
+        a, b = _translated_pair(i)
+        pairs.append((torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)))
+    pipes = [_pipeline(r2, 256, 500, 0) for _ in pairs]
+    refs = []
+    for pipe, (ta, tb) in zip(pipes, pairs):
+        pipe.run(ta, tb)
+        refs.append(_snapshot(pipe))
+    graphs = [pipe.capture(ta, tb) for pipe, (ta, tb) in zip(pipes, pairs)]
+    streams = [torch.cuda.Stream() for _ in pipes]
+    for rep in range(3):
+        for g, s in zip(graphs, streams):
+            with torch.cuda.stream(s):
+                g.replay()
+        torch.cuda.synchronize()
+        for i, pipe in enumerate(pipes):
+            _same(refs[i], _snapshot(pipe), f"pair {i} replay {rep}")
