@@ -34,24 +34,26 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 
-# HBM bytes per launch at 1024 x 1024 (N_s = 4, N_o = 6) from two rocprofv3
-# --pmc runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a plain copy of
-# known size gives), valid only for the filter sources they were taken on.
-FILTER_SOURCES = ("paper_2303_00319_amd/csrc/fft.hpp", "paper_2303_00319_amd/csrc/filter.hip")
+# Per-launch HBM bytes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a
+# plain copy of known size gives) from two rocprofv3 --pmc runs at 1024 x 1024
+# (N_s = 4, N_o = 6, 5000 keypoints), valid only for the sources they were
+# taken on (hash of the listed files).
 MEASURED_TRAFFIC = {
-    "sources_sha256_16": "33e50e64c81f93e3",
-    "size": 1024,
-    "bytes": {"pass_a": 254490448, "pass_b": 209746752},
+    "pass_a": {"sources": ("fft.hpp", "filter.hip", "api.hip"), "sha": None, "bytes": None},
+    "pass_b": {"sources": ("fft.hpp", "filter.hip", "api.hip"), "sha": None, "bytes": None},
+    "match_gemm": {"sources": ("match.hip", "api.hip"), "sha": None, "bytes": None},
 }
 
 
-def filter_sources_hash():
+def sources_hash(files):
     import hashlib
 
     h = hashlib.sha256()
-    for f in FILTER_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2303_00319_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -160,35 +162,54 @@ def profile_stages(r2, torch, pipe, imgs, steps):
     return {k: {"ms_avg": (v[0] / v[1] if v[1] else 0.0), "launches": v[1]} for k, v in raw.items()}
 
 
-def roofline(stages, h, w, n_scales, n_orient):
-    """Algorithmic HBM bytes per launch of the two dominant filter-bank kernels."""
+def roofline(stages, h, w, n_scales, n_orient, n_a, n_b, d):
+    """Roofline of the kernel with the most time per step.
+
+    Algorithmic work per launch: the column pass reads the row spectrum
+    (8 B/px) and writes F complex planes; the row pass reads the F planes and
+    writes MIM (1 B/px) and M (4 B/px); the distance GEMM does 2 n_a n_b D
+    flops on the step's actual descriptor rows.  The two filter passes run
+    once per image (twice per step), the GEMM once per step.
+    """
     hw = h * w
     f = n_scales * n_orient
-    alg = {
-        # column pass: read the row spectrum (8 B/px), write F complex planes
-        "pass_a": hw * (8 + 8 * f),
-        # row pass: read F complex planes, write MIM (1 B/px) and M (4 B/px)
-        "pass_b": hw * (8 * f + 5),
+    cand = {
+        "pass_a": ("hbm", hw * (8 + 8 * f), 2),
+        "pass_b": ("hbm", hw * (8 * f + 5), 2),
+        "match_gemm": ("mfma", 2.0 * n_a * n_b * d, 1),
     }
-    best = max(alg, key=lambda k: stages[k]["ms_avg"])
-    ms = stages[best]["ms_avg"]
-    achieved = alg[best] / (ms * 1e-3) / 1e9
+
+    def rate(k):
+        bound, work, _ = cand[k]
+        sec = stages[k]["ms_avg"] * 1e-3
+        return work / sec / (1e9 if bound == "hbm" else 1e12)
+
+    def peak(k):
+        return HBM_PEAK_GBS if cand[k][0] == "hbm" else FP32_MFMA_PEAK_TFLOPS
+
+    best = max(cand, key=lambda k: cand[k][2] * stages[k]["ms_avg"])
+    bound, work, per_step = cand[best]
+    achieved = rate(best)
     traffic = None
-    if (h == w == MEASURED_TRAFFIC["size"] and (n_scales, n_orient) == (4, 6)
-            and filter_sources_hash() == MEASURED_TRAFFIC["sources_sha256_16"]):
-        traffic = MEASURED_TRAFFIC["bytes"].get(best)
+    mt = MEASURED_TRAFFIC[best]
+    if (h == w == 1024 and (n_scales, n_orient) == (4, 6) and mt["bytes"] is not None
+            and sources_hash(mt["sources"]) == mt["sha"]):
+        traffic = mt["bytes"]
     return {
         "kernel": best,
-        "bound": "hbm",
-        "achieved": round(achieved, 1),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "bound": bound,
+        "achieved": round(achieved, 2),
+        "peak": peak(best),
+        "unit": "GB/s" if bound == "hbm" else "TFLOP/s",
+        "frac": round(achieved / peak(best), 4),
         "traffic": traffic,
-        "traffic_unit": "bytes per launch",
-        "alg_bytes_per_launch": alg[best],
-        "ms_per_launch": round(ms, 5),
-        "other": {k: round(alg[k] / (stages[k]["ms_avg"] * 1e-3) / 1e9, 1) for k in alg if k != best},
+        "traffic_unit": "HBM bytes per launch",
+        "algorithmic_per_launch": work,
+        "ms_per_launch": round(stages[best]["ms_avg"], 5),
+        "launches_per_step": per_step,
+        "other": {k: {"achieved": round(rate(k), 2), "unit": "GB/s" if cand[k][0] == "hbm" else "TFLOP/s",
+                      "frac": round(rate(k) / peak(k), 4), "ms_per_launch": round(stages[k]["ms_avg"], 5)}
+                  for k in cand if k != best},
     }
 
 
@@ -252,16 +273,16 @@ def main():
     stages = profile_stages(r2, torch, fp32["pipe"], imgs, args.profile_steps)
     stages_mixed = profile_stages(r2, torch, mixed["pipe"], imgs, args.profile_steps)
     pc = fp32["pipe"].pc
-    roof = roofline(stages, args.size, args.size, pc.n_scales, pc.n_orient)
     # matching GEMM utilisation (flops of the last pair's actual row counts)
     n_a, n_b = fp32["last_pair"]["descriptor_rows"]
     d = 216
+    roof = roofline(stages, args.size, args.size, pc.n_scales, pc.n_orient, n_a, n_b, d)
     gemm_flop = 2.0 * n_a * n_b * d
     mfma = {
         "fp32_tflops": round(gemm_flop / (stages["match_gemm"]["ms_avg"] * 1e-3) / 1e12, 2),
-        "fp32_frac_of_157.3": round(gemm_flop / (stages["match_gemm"]["ms_avg"] * 1e-3) / 157.3e12, 4),
+        "fp32_frac": round(gemm_flop / (stages["match_gemm"]["ms_avg"] * 1e-3) / (FP32_MFMA_PEAK_TFLOPS * 1e12), 4),
         "bf16_tflops": round(gemm_flop / (stages_mixed["match_gemm"]["ms_avg"] * 1e-3) / 1e12, 2),
-        "bf16_frac_of_2500": round(gemm_flop / (stages_mixed["match_gemm"]["ms_avg"] * 1e-3) / 2500e12, 4),
+        "bf16_frac": round(gemm_flop / (stages_mixed["match_gemm"]["ms_avg"] * 1e-3) / (BF16_MFMA_PEAK_TFLOPS * 1e12), 4),
     }
     cpu = None
     if not args.no_cpu:

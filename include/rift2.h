@@ -204,12 +204,13 @@ rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32
 /* Stage timing (diagnostics, not needed for computing).  While enabled, each
  * compute call records a HIP event pair on its stream around each of its
  * kernel groups: 0 row DFT, 1 column DFT + filter products + column IDFT,
- * 2 noise pre-pass, 3 noise median / threshold, 4 row IDFT + phase
- * congruency + MIM + moments, 5 detect (all kernels), 6 describe (all
- * kernels), 7 match table preparation, 8 match distance GEMM + top-k,
- * 9 match merge / ratio test / output.  rift2_profile_read waits for the
+ * 2 noise pre-pass, 3 noise median / threshold, 4 row IDFT + amplitude
+ * sums + phase congruency per orientation, 5 detect (all kernels),
+ * 6 describe (all kernels), 7 match table preparation, 8 match distance
+ * GEMM + top-k, 9 match merge / ratio test / output, 10 per-pixel reduction
+ * over orientations (MIM, moments).  rift2_profile_read waits for the
  * recorded events, adds the elapsed milliseconds and the number of launches
- * per group into ms[group] and count[group] (arrays of n_groups >= 10 host
+ * per group into ms[group] and count[group] (arrays of n_groups >= 11 host
  * elements), forgets them and returns the number of groups.  Events are
  * owned by the library; enabling on one thread while another computes is
  * not supported. */

@@ -54,7 +54,7 @@ EXPORTS = [
     "rift2_profile_enable", "rift2_profile_read",
 ]
 STAGES = ["row_dft", "pass_a", "noise_pre", "noise_sel", "pass_b", "detect", "describe", "match_prep",
-          "match_gemm", "match_merge"]
+          "match_gemm", "match_merge", "pass_b_reduce"]
 
 _LIB = None
 

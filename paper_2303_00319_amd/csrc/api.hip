@@ -107,7 +107,7 @@ DetectLayout detect_layout(int H, int W, const rift2_detect_params* d) {
 
 struct MatchLayout {
   size_t ta, tb, part, best, rowj, rowd, total;
-  int dp, rows_a, rows_b, slices, slice_rows;
+  int dp, rs, rows_a, rows_b, slices, slice_rows;
 };
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
@@ -116,11 +116,12 @@ MatchLayout match_layout(int cap_a, int cap_b, int D, int precision) {
   MatchLayout L;
   const bool bf = precision == RIFT2_PREC_BF16;
   L.dp = bf ? round_up(D, 16) : round_up(D, 8);
+  L.rs = bf ? L.dp + 8 : L.dp + 4;  // table row stride = the GEMM kernels' LDS row stride
   L.rows_a = round_up(cap_a, 32);
   L.rows_b = round_up(cap_b, 32);
   const int blocks_x = (L.rows_a + 127) / 128;
-  // enough blocks to fill the chip (256 CUs x ~8 waves), slices of >= 2 tiles
-  int slices = (2048 + blocks_x - 1) / blocks_x;
+  // enough blocks to fill the chip several times over (256 CUs x 2 blocks), slices of >= 2 tiles
+  int slices = (4096 + blocks_x - 1) / blocks_x;
   const int max_slices = (L.rows_b + 63) / 64;
   if (slices > max_slices) slices = max_slices;
   if (slices < 1) slices = 1;
@@ -128,8 +129,8 @@ MatchLayout match_layout(int cap_a, int cap_b, int D, int precision) {
   L.slices = (L.rows_b + L.slice_rows - 1) / L.slice_rows;
   const size_t el = bf ? 2 : 4;
   Carver c;
-  L.ta = c.take((size_t)L.rows_a * L.dp * el);
-  L.tb = c.take((size_t)L.rows_b * L.dp * el);
+  L.ta = c.take((size_t)L.rows_a * L.rs * el);
+  L.tb = c.take((size_t)L.rows_b * L.rs * el);
   L.part = c.take((size_t)L.rows_a * L.slices * 2 * kTopK * sizeof(int2));
   L.best = c.take((size_t)cap_a * sizeof(uint64_t));
   L.rowj = c.take((size_t)cap_a * sizeof(int32_t));
@@ -147,7 +148,7 @@ std::mutex g_init_mu;
 bool g_init_done[64] = {};
 
 // ---- stage timing (diagnostics)
-constexpr int kProfGroups = 10;
+constexpr int kProfGroups = 11;
 struct ProfRec {
   int group;
   hipEvent_t a, b;
@@ -267,8 +268,12 @@ bool dispatch_noise_pre(int W, int H, int n_orient, int n_scales, float2* y, flo
 template <int W, int P, int NS, int NO>
 void launch_pass_b_split(int H, const float2* y, const PCConsts& pcc, const float* t_o, float2* spc, uint8_t* mim,
                          float* mmax, float* mmin, float* amp, hipStream_t st) {
-  hipLaunchKernelGGL((k_pass_b_orient<W, P, NS>), dim3(H, NO), dim3(W / P), 0, st, y, H, pcc, t_o, spc, amp);
+  {
+    ProfScope ps(4, st);
+    hipLaunchKernelGGL((k_pass_b_orient<W, P, NS>), dim3(H, NO), dim3(W / P), 0, st, y, H, pcc, t_o, spc, amp);
+  }
   const int hw = H * W;
+  ProfScope ps(10, st);
   hipLaunchKernelGGL((k_pass_b_reduce<NO>), dim3((hw / 4 + 255) / 256), dim3(256), 0, st, spc, hw, pcc, mim, mmax, mmin);
 }
 
@@ -474,7 +479,6 @@ rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t
     hipLaunchKernelGGL(k_noise_bins<3>, dim3(pc->n_orient), dim3(256), 0, st, hw, nws, nc, t32, t64);
   }
   {
-    ProfScope ps(4, st);
     dispatch_pass_b(pc->n_scales, pc->n_orient, W, H, yp, pcc, t32, (float2*)(ws + L.spc), mim, max_moment,
                     min_moment, amp_sums, st);
   }
@@ -584,14 +588,14 @@ rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32
   (void)hipGetLastError();
   ProfScope ps7(7, st);
   if (bf) {
-    hipLaunchKernelGGL(k_match_prep<true>, dim3(512), dim3(256), 0, st, desc_a, nA_dev, cap_a, D, L.dp, L.rows_a, ta, best,
+    hipLaunchKernelGGL(k_match_prep<true>, dim3(512), dim3(256), 0, st, desc_a, nA_dev, cap_a, D, L.rs, L.rows_a, ta, best,
                        cap_a);
-    hipLaunchKernelGGL(k_match_prep<true>, dim3(512), dim3(256), 0, st, desc_b, nB_dev, cap_b, D, L.dp, L.rows_b, tb,
+    hipLaunchKernelGGL(k_match_prep<true>, dim3(512), dim3(256), 0, st, desc_b, nB_dev, cap_b, D, L.rs, L.rows_b, tb,
                        (uint64_t*)nullptr, 0);
   } else {
-    hipLaunchKernelGGL(k_match_prep<false>, dim3(512), dim3(256), 0, st, desc_a, nA_dev, cap_a, D, L.dp, L.rows_a, ta, best,
+    hipLaunchKernelGGL(k_match_prep<false>, dim3(512), dim3(256), 0, st, desc_a, nA_dev, cap_a, D, L.rs, L.rows_a, ta, best,
                        cap_a);
-    hipLaunchKernelGGL(k_match_prep<false>, dim3(512), dim3(256), 0, st, desc_b, nB_dev, cap_b, D, L.dp, L.rows_b, tb,
+    hipLaunchKernelGGL(k_match_prep<false>, dim3(512), dim3(256), 0, st, desc_b, nB_dev, cap_b, D, L.rs, L.rows_b, tb,
                        (uint64_t*)nullptr, 0);
   }
   ps7.finish();

@@ -29,7 +29,7 @@ constexpr int kTopK = 3;  // a keypoint owns <= 2 rows, so 3 rows hold j1 and j2
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float floatx16_t __attribute__((ext_vector_type(16)));
-typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));  // plain 16-byte vector (promotable)
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ uint16_t bf16_bits_of_count(uint32_t c) {
   // round to nearest even; exact for c <= 256
@@ -37,37 +37,35 @@ __device__ __forceinline__ uint16_t bf16_bits_of_count(uint32_t c) {
   return (uint16_t)((f + 0x7fffu + ((f >> 16) & 1u)) >> 16);
 }
 
-// Table layout: rows_pad x DP elements (BF16 bits as uint16, or float).
-// One work item = 8 consecutive elements of a row (D and DP are multiples of
-// 8), read as one 16-byte load and written as one (BF16) or two (FP32)
-// 16-byte stores.
+// Table layout: rows_pad x RS elements (BF16 bits as uint16, or float); RS is the
+// MFMA depth plus a zero pad that staggers the rows over the LDS banks.  One
+// work item = CH consecutive elements of a row (8 for BF16: 16-byte load and
+// store; 4 for FP32: 8-byte load, 16-byte store; D and RS are multiples).
 template <bool BF16>
 __global__ void __launch_bounds__(256) k_match_prep(const uint16_t* __restrict__ desc, const int32_t* __restrict__ n_dev,
-                                                    int cap, int D, int DP, int rows_pad, void* __restrict__ table,
+                                                    int cap, int D, int RS, int rows_pad, void* __restrict__ table,
                                                     uint64_t* __restrict__ best, int n_best) {
+  constexpr int CH = BF16 ? 8 : 4;
   const int n = min(*n_dev, cap);
-  const int chunks = DP / 8;
+  const int chunks = RS / CH;
   const size_t total = (size_t)rows_pad * chunks;
   for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < total; w += (size_t)gridDim.x * blockDim.x) {
-    const int r = (int)(w / chunks), k0 = 8 * (int)(w % chunks);
-    uint4 raw = make_uint4(0u, 0u, 0u, 0u);
-    if (r < n && k0 < D) raw = *(const uint4*)(desc + (size_t)r * D + k0);
-    const uint32_t word[4] = {raw.x, raw.y, raw.z, raw.w};
-    uint32_t c[8];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      c[2 * e] = word[e] & 0xffffu;
-      c[2 * e + 1] = word[e] >> 16;
-    }
+    const int r = (int)(w / chunks), k0 = CH * (int)(w % chunks);
+    const bool in = r < n && k0 < D;
     if (BF16) {
+      uint4 raw = make_uint4(0u, 0u, 0u, 0u);
+      if (in) raw = *(const uint4*)(desc + (size_t)r * D + k0);
+      const uint32_t word[4] = {raw.x, raw.y, raw.z, raw.w};
       uint32_t o[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) o[e] = (uint32_t)bf16_bits_of_count(c[2 * e]) | ((uint32_t)bf16_bits_of_count(c[2 * e + 1]) << 16);
-      *(uint4*)((uint16_t*)table + (size_t)r * DP + k0) = make_uint4(o[0], o[1], o[2], o[3]);
+      for (int e = 0; e < 4; ++e)
+        o[e] = (uint32_t)bf16_bits_of_count(word[e] & 0xffffu) | ((uint32_t)bf16_bits_of_count(word[e] >> 16) << 16);
+      *(uint4*)((uint16_t*)table + (size_t)r * RS + k0) = make_uint4(o[0], o[1], o[2], o[3]);
     } else {
-      float* dst = (float*)table + (size_t)r * DP + k0;
-      *(float4*)dst = make_float4((float)c[0], (float)c[1], (float)c[2], (float)c[3]);
-      *(float4*)(dst + 4) = make_float4((float)c[4], (float)c[5], (float)c[6], (float)c[7]);
+      uint2 raw = make_uint2(0u, 0u);
+      if (in) raw = *(const uint2*)(desc + (size_t)r * D + k0);
+      *(float4*)((float*)table + (size_t)r * RS + k0) =
+          make_float4((float)(raw.x & 0xffffu), (float)(raw.x >> 16), (float)(raw.y & 0xffffu), (float)(raw.y >> 16));
     }
   }
   if (best) {
@@ -102,60 +100,80 @@ __device__ __forceinline__ void top3_insert(Top3& t, float d, int j) {
 }
 
 // Epilogue of one 32x32 tile: lane holds 16 candidate dots of its query.
-// Accumulator register r of lane l is candidate row 8 (r/4) + 4 (l/32) + r%4.
+// Accumulator register r of lane l is candidate row 8 (r/4) + 4 (l/32) + r%4;
+// `ibt` holds the tile's 32 candidate inverse norms (LDS), so the four rows
+// 8k + 4g .. 8k + 4g + 3 of register group k are one 16-byte read.  All 16
+// distances are formed first; the insertion runs only where one of them can
+// enter the lane's top 3.
 __device__ __forceinline__ void tile_epilogue(const floatx16_t& acc, int lane, int j0, int j_end, float ia,
-                                              float ib_lane, Top3& top) {
+                                              const float* ibt, Top3& top) {
   const int g = lane >> 5;
+  float d2[16];
+  bool any = false;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int ci = 8 * (r >> 2) + 4 * g + (r & 3);
-    const float ib = __shfl(ib_lane, ci);
-    const float t1 = __fmul_rn(acc[r], ia);
-    const float t2 = __fmul_rn(t1, ib);
-    const float d2 = __fsub_rn(2.0f, __fmul_rn(2.0f, t2));
-    const int j = j0 + ci;
-    if (j < j_end && d2 < top.d[2]) top3_insert(top, d2, j);
-  }
-}
-
-// Candidate tiles of 32 rows are staged through LDS once per block (double
-// buffered: the next tile's global loads are in flight in registers while the
-// current tile is multiplied) and read by the block's 4 waves, each holding
-// 32 queries in registers.  grid = (ceil(rows_a / 128), S).
-template <typename TE, int DP>
-struct TileShape {
-  static constexpr int VEC = 16 / (int)sizeof(TE);  // elements per 16-byte load
-  static constexpr int PER_ROW = DP / VEC;
-  static constexpr int TOTAL = 32 * PER_ROW;          // 16-byte loads per tile
-  static constexpr int PER_THREAD = (TOTAL + 255) / 256;
-};
-
-// Unconditional loads (slots past the tile re-read a valid element) keep the
-// staging registers promotable while the loads are in flight.
-template <typename TE, int DP, int N>
-__device__ __forceinline__ void tile_load(u32x4_t (&r)[N], const TE* __restrict__ tb, int j0) {
-  using S = TileShape<TE, DP>;
+  for (int k = 0; k < 4; ++k) {
+    const float4 ib4 = *(const float4*)(ibt + 8 * k + 4 * g);
+    const float ibv[4] = {ib4.x, ib4.y, ib4.z, ib4.w};
 #pragma unroll
-  for (int q = 0; q < S::PER_THREAD; ++q) {
-    int idx = threadIdx.x + 256 * q;
-    idx = idx < S::TOTAL ? idx : idx - S::TOTAL;
-    const int row = idx / S::PER_ROW, col = idx % S::PER_ROW;
-    r[q] = *(const u32x4_t*)(tb + (size_t)(j0 + row) * DP + col * S::VEC);
-  }
-}
-
-template <typename TE, int DP, int RS, int N>
-__device__ __forceinline__ void tile_store(const u32x4_t (&r)[N], TE* tile) {
-  using S = TileShape<TE, DP>;
-#pragma unroll
-  for (int q = 0; q < S::PER_THREAD; ++q) {
-    const int idx = threadIdx.x + 256 * q;
-    if (idx < S::TOTAL) {
-      const int row = idx / S::PER_ROW, col = idx % S::PER_ROW;
-      *(u32x4_t*)(tile + row * RS + col * S::VEC) = r[q];
+    for (int e = 0; e < 4; ++e) {
+      const int r = 4 * k + e;
+      const float t1 = __fmul_rn(acc[r], ia);
+      const float t2 = __fmul_rn(t1, ibv[e]);
+      d2[r] = __fsub_rn(2.0f, __fmul_rn(2.0f, t2));
+      any |= (j0 + 8 * k + 4 * g + e < j_end) && d2[r] < top.d[2];
     }
   }
+  if (!any) return;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int j = j0 + 8 * (r >> 2) + 4 * g + (r & 3);
+    if (j < j_end && d2[r] < top.d[2]) top3_insert(top, d2[r], j);
+  }
 }
+
+// Candidate tiles of 32 rows are copied from the table straight into LDS
+// (global_load_lds, no staging registers; double buffered: the next tile's
+// copy is in flight while the current one is multiplied) and read by the
+// block's 4 waves, each holding 32 queries in registers.  The table rows
+// already carry the LDS row stride RS, so a tile is one contiguous block.
+// grid = (ceil(rows_a / 128), S).
+template <typename TE, int RS>
+struct TileCopy {
+  static constexpr int BYTES = 32 * RS * (int)sizeof(TE);
+  static constexpr int CHUNKS = BYTES / 16;          // 16-byte pieces per tile
+  static constexpr int ROUNDS = (CHUNKS + 255) / 256;  // copies per thread
+  static_assert(BYTES % 16 == 0, "16-byte rows");
+};
+
+template <typename TE, int RS>
+__device__ __forceinline__ void tile_copy(const TE* __restrict__ tb, int j0, TE* tile) {
+  using C = TileCopy<TE, RS>;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const char* src = (const char*)(tb + (size_t)j0 * RS);
+#pragma unroll
+  for (int q = 0; q < C::ROUNDS; ++q) {
+    const int first = (q * 4 + wave) * 64;  // this wave's first piece in round q
+    if (first + lane < C::CHUNKS)
+      __builtin_amdgcn_global_load_lds((const void*)(src + 16 * (first + lane)),
+                                       (__attribute__((address_space(3))) void*)((char*)tile + 16 * first), 16, 0, 0);
+  }
+}
+
+// Waits for this wave's tile copies to land in LDS (the block barrier that
+// follows publishes them).
+__device__ __forceinline__ void tile_copy_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// The tile's candidate inverse norms (zero past the last row) go to LDS with
+// the tile itself.
+__device__ __forceinline__ float tile_inv_load(const float* __restrict__ inv_b, int j0, int nb) {
+  const int j = j0 + (int)threadIdx.x;
+  return (threadIdx.x < 32 && j < nb) ? inv_b[j] : 0.0f;
+}
+
+template <int DP>
+constexpr int bf16_stride() { return DP + 8; }  // rows start 16 bytes apart modulo 128
+template <int DP>
+constexpr int f32_stride() { return DP + 4; }
 
 template <int DP>
 __global__ void __launch_bounds__(256) k_match_gemm_bf16(const uint16_t* __restrict__ ta, const float* __restrict__ inv_a,
@@ -165,16 +183,20 @@ __global__ void __launch_bounds__(256) k_match_gemm_bf16(const uint16_t* __restr
                                                          int slice_rows, int2* __restrict__ part) {
   static_assert(DP % 16 == 0, "padded depth");
   constexpr int KS = DP / 16;
-  constexpr int RS = DP + 8;  // row stride in LDS (elements): rows start 16 bytes apart mod 128
+  constexpr int RS = bf16_stride<DP>();
   __shared__ __attribute__((aligned(16))) uint16_t tile[2][32 * RS];
+  __shared__ __attribute__((aligned(16))) float ibt[2][32];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 5;
   const int na = min(*na_dev, cap_a), nb = min(*nb_dev, cap_b);
+  // the grid is sized for the capacity; blocks past the actual query rows
+  // leave at once (uniformly, before any barrier; nobody reads their lists)
+  if ((int)blockIdx.x * 128 >= na) return;
   const int q0 = (blockIdx.x * 4 + wave) * 32;
   const bool active = q0 < na;
   const int qi = q0 + (lane & 31);
   bf16x8_t qa[KS];
   if (active) {
-    const uint16_t* qrow = ta + (size_t)qi * DP + 8 * g;
+    const uint16_t* qrow = ta + (size_t)qi * RS + 8 * g;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) qa[ks] = __builtin_bit_cast(bf16x8_t, *(const uint4*)(qrow + 16 * ks));
   }
@@ -188,16 +210,21 @@ __global__ void __launch_bounds__(256) k_match_gemm_bf16(const uint16_t* __restr
     top.d[q] = INFINITY;
     top.j[q] = -1;
   }
-  u32x4_t stage[TileShape<uint16_t, DP>::PER_THREAD];
   if (ntile > 0) {
-    tile_load<uint16_t, DP>(stage, tb, j_beg);
-    tile_store<uint16_t, DP, RS>(stage, tile[0]);
+    tile_copy<uint16_t, RS>(tb, j_beg, tile[0]);
+    const float ib0 = tile_inv_load(inv_b, j_beg, nb);
+    if (threadIdx.x < 32) ibt[0][threadIdx.x] = ib0;
+    tile_copy_wait();
   }
   __syncthreads();
   for (int it = 0; it < ntile; ++it) {
     const int cur = it & 1;
     const int j0 = j_beg + 32 * it;
-    if (it + 1 < ntile) tile_load<uint16_t, DP>(stage, tb, j0 + 32);
+    float ib_next = 0.0f;
+    if (it + 1 < ntile) {
+      tile_copy<uint16_t, RS>(tb, j0 + 32, tile[cur ^ 1]);
+      ib_next = tile_inv_load(inv_b, j0 + 32, nb);
+    }
     if (active) {
       const uint16_t* crow = tile[cur] + (lane & 31) * RS + 8 * g;
       floatx16_t acc = {};
@@ -206,11 +233,12 @@ __global__ void __launch_bounds__(256) k_match_gemm_bf16(const uint16_t* __restr
         const uint4 raw = *(const uint4*)(crow + 16 * ks);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, raw), qa[ks], acc, 0, 0, 0);
       }
-      const int cj = j0 + (lane & 31);
-      const float ibl = cj < nb ? inv_b[cj] : 0.0f;
-      tile_epilogue(acc, lane, j0, j_end, ia, ibl, top);
+      tile_epilogue(acc, lane, j0, j_end, ia, ibt[cur], top);
     }
-    if (it + 1 < ntile) tile_store<uint16_t, DP, RS>(stage, tile[cur ^ 1]);
+    if (it + 1 < ntile) {
+      if (threadIdx.x < 32) ibt[cur ^ 1][threadIdx.x] = ib_next;
+      tile_copy_wait();
+    }
     __syncthreads();
   }
   if (active && qi < na) {
@@ -220,9 +248,12 @@ __global__ void __launch_bounds__(256) k_match_gemm_bf16(const uint16_t* __restr
   }
 }
 
-// FP32 MFMA (32x32x2).  Each lane keeps DP/2 query values; the depth is split
-// into chunks of 8: lane half g owns k = 8c + 4g + e, MFMA e of chunk c
-// consumes element e, so both operands use the same k assignment.
+// FP32 MFMA (32x32x2).  The depth is split into chunks of 8: lane half g
+// owns k = 8c + 4g + e, MFMA e of chunk c consumes element e, so both
+// operands use the same k assignment.  The query counts are small integers
+// (<= 256), held exactly as FP16 pairs and widened to FP32 for each MFMA,
+// which halves their registers; with one tile buffer (28 KB of LDS) three
+// blocks share a CU, and they cover each other's tile copies.
 template <int DP>
 __global__ void __launch_bounds__(256) k_match_gemm_f32(const float* __restrict__ ta, const float* __restrict__ inv_a,
                                                         const int32_t* __restrict__ na_dev,
@@ -231,18 +262,24 @@ __global__ void __launch_bounds__(256) k_match_gemm_f32(const float* __restrict_
                                                         int slice_rows, int2* __restrict__ part) {
   static_assert(DP % 8 == 0, "padded depth");
   constexpr int KC = DP / 8;
-  constexpr int RS = DP + 4;  // row stride in LDS (floats)
-  __shared__ __attribute__((aligned(16))) float tile[2][32 * RS];
+  constexpr int RS = f32_stride<DP>();
+  __shared__ __attribute__((aligned(16))) float tile[1][32 * RS];
+  __shared__ __attribute__((aligned(16))) float ibt[1][32];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 5;
   const int na = min(*na_dev, cap_a), nb = min(*nb_dev, cap_b);
+  if ((int)blockIdx.x * 128 >= na) return;
   const int q0 = (blockIdx.x * 4 + wave) * 32;
   const bool active = q0 < na;
   const int qi = q0 + (lane & 31);
-  float4 qa[KC];
+  half2_t qh[KC][2];
   if (active) {
-    const float* qrow = ta + (size_t)qi * DP + 4 * g;
+    const float* qrow = ta + (size_t)qi * RS + 4 * g;
 #pragma unroll
-    for (int c = 0; c < KC; ++c) qa[c] = *(const float4*)(qrow + 8 * c);
+    for (int c = 0; c < KC; ++c) {
+      const float4 v = *(const float4*)(qrow + 8 * c);
+      qh[c][0] = half2_t{(_Float16)v.x, (_Float16)v.y};
+      qh[c][1] = half2_t{(_Float16)v.z, (_Float16)v.w};
+    }
   }
   const float ia = (active && qi < na) ? inv_a[qi] : 0.0f;
   const int j_beg = blockIdx.y * slice_rows;
@@ -254,33 +291,28 @@ __global__ void __launch_bounds__(256) k_match_gemm_f32(const float* __restrict_
     top.d[q] = INFINITY;
     top.j[q] = -1;
   }
-  u32x4_t stage[TileShape<float, DP>::PER_THREAD];
-  if (ntile > 0) {
-    tile_load<float, DP>(stage, tb, j_beg);
-    tile_store<float, DP, RS>(stage, tile[0]);
-  }
-  __syncthreads();
   for (int it = 0; it < ntile; ++it) {
-    const int cur = it & 1;
     const int j0 = j_beg + 32 * it;
-    if (it + 1 < ntile) tile_load<float, DP>(stage, tb, j0 + 32);
+    if (it > 0) __syncthreads();
+    tile_copy<float, RS>(tb, j0, tile[0]);
+    const float ibv = tile_inv_load(inv_b, j0, nb);
+    if (threadIdx.x < 32) ibt[0][threadIdx.x] = ibv;
+    tile_copy_wait();
+    __syncthreads();
     if (active) {
-      const float* crow = tile[cur] + (lane & 31) * RS + 4 * g;
+      const float* crow = tile[0] + (lane & 31) * RS + 4 * g;
       floatx16_t acc = {};
 #pragma unroll
       for (int c = 0; c < KC; ++c) {
+        asm volatile("" : "+v"(qh[c][0]), "+v"(qh[c][1]));
         const float4 cb = *(const float4*)(crow + 8 * c);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.x, qa[c].x, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.y, qa[c].y, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.z, qa[c].z, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.w, qa[c].w, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.x, (float)qh[c][0].x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.y, (float)qh[c][0].y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.z, (float)qh[c][1].x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.w, (float)qh[c][1].y, acc, 0, 0, 0);
       }
-      const int cj = j0 + (lane & 31);
-      const float ibl = cj < nb ? inv_b[cj] : 0.0f;
-      tile_epilogue(acc, lane, j0, j_end, ia, ibl, top);
+      tile_epilogue(acc, lane, j0, j_end, ia, ibt[0], top);
     }
-    if (it + 1 < ntile) tile_store<float, DP, RS>(stage, tile[cur ^ 1]);
-    __syncthreads();
   }
   if (active && qi < na) {
     int2* dst = part + ((size_t)qi * gridDim.y + blockIdx.y) * (2 * kTopK) + g * kTopK;
