@@ -74,6 +74,15 @@ def parse():
                     help="run both images' stages on one stream (no overlap; per-kernel durations for rocprofv3)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--serve", action="store_true",
+                    help="serving form instead of the headline: a stream of mixed-size pair requests through the "
+                         "continuous-batching engine (prints its own JSON line)")
+    ap.add_argument("--requests", type=int, default=256, help="--serve: number of requests")
+    ap.add_argument("--rates", default="5,10,20,40,80,0",
+                    help="--serve: Poisson arrival rates in pairs/s to sweep (0 = all at once, saturation)")
+    ap.add_argument("--budget-gib", type=float, default=32.0, help="--serve: HBM arena for in-flight requests")
+    ap.add_argument("--inflight", type=int, default=8, help="--serve: requests running at once (two streams each)")
+    ap.add_argument("--pool", type=int, default=4, help="--serve: distinct resident pairs per size")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB read + 256 MiB write elementwise kernel first (HBM counter scale)")
     return ap.parse_args()
@@ -237,6 +246,84 @@ def cpu_baseline(size, keypoints, n_pairs=3):
             "matches": n_match}
 
 
+def serve(args, r2, torch):
+    """Serving form: mixed sizes, Poisson arrivals, continuous batching, BF16 matching."""
+    import numpy as np
+
+    from synth import make_pair
+    from synth.gen import serving_sizes
+
+    dev = torch.device("cuda:0")
+    sizes = serving_sizes()
+    pool = {}
+    for n in sizes:
+        for i in range(args.pool):
+            a, b, _ = make_pair(3, n * 100 + i, size=n)
+            pool[(n, i)] = (torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev))
+    torch.cuda.synchronize()
+    print(f"[serve] pool of {len(pool)} pairs resident", file=sys.stderr, flush=True)
+    rng = np.random.default_rng(1_000_003 * 3)
+    req_size = [int(x) for x in rng.choice(sizes, size=args.requests)]
+    pc, det, dp, mp = r2.defaults()
+    mp.precision = r2.PREC_BF16
+    results = []
+    for rate in [float(x) for x in args.rates.split(",")]:
+        gaps = rng.exponential(1.0 / rate, size=args.requests) if rate > 0 else np.zeros(args.requests)
+        arrive = np.cumsum(gaps) - gaps[0]
+        eng = r2.Engine(int(args.budget_gib * (1 << 30)), max_inflight=args.inflight, pc=pc, det=det, dp=dp, mp=mp)
+        # warm: one request of every size
+        for j, n in enumerate(sizes):
+            eng.submit(-1 - j, *pool[(n, 0)])
+        eng.drain()
+        torch.cuda.synchronize()
+        eng.close()
+        eng = r2.Engine(int(args.budget_gib * (1 << 30)), max_inflight=args.inflight, pc=pc, det=det, dp=dp, mp=mp)
+        t_epoch = time.perf_counter()
+        nxt = 0
+        done = []
+        arr_ms = {}
+        while len(done) < args.requests:
+            now = time.perf_counter() - t_epoch
+            while nxt < args.requests and arrive[nxt] <= now:
+                n = req_size[nxt]
+                a, b = pool[(n, nxt % args.pool)]
+                eng.submit(nxt, a, b)
+                arr_ms[nxt] = 1000.0 * arrive[nxt]
+                nxt += 1
+            got = eng.poll()
+            done += got
+            if not got and nxt < args.requests:
+                wait = arrive[nxt] - (time.perf_counter() - t_epoch)
+                if wait > 2e-4:
+                    time.sleep(min(wait, 1e-3))
+        bad = [d for d in done if d["status"] != 0]
+        lat = [d["done_ms"] - arr_ms[d["id"]] for d in done]
+        span_ms = max(d["done_ms"] for d in done) - min(arr_ms.values())
+        matches = sum(int(d["n_out"].item()) for d in done if d["n_out"] is not None)
+        res = {"rate": rate if rate > 0 else "saturation", "pairs_per_s": round(args.requests / (span_ms / 1000.0), 2),
+               "p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
+               "gpu_ms_p50": round(percentile([d["gpu_ms"] for d in done], 50), 3), "failed": len(bad),
+               "matches": matches}
+        print(f"[serve] {json.dumps(res)}", file=sys.stderr, flush=True)
+        results.append(res)
+        eng.close()
+    sat = [r for r in results if r["rate"] == "saturation"]
+    line = {
+        "metric": "serving: image pairs/s + p50/p99 latency, mixed sizes, continuous batching",
+        "value": sat[0]["pairs_per_s"] if sat else results[-1]["pairs_per_s"],
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f32 filter + bf16 matching (exact on counts)",
+        "data": "synthetic",
+        "config": {"workload": f"{args.requests} pair requests, sizes uniform over {list(sizes)}, keypoints 2e-3 HW, "
+                               f"Poisson arrivals", "budget_gib": args.budget_gib, "inflight": args.inflight,
+                   "distinct_pairs_per_size": args.pool},
+        "rates": results,
+    }
+    print(json.dumps(line))
+
+
 def main():
     faulthandler.enable()
     args = parse()
@@ -253,6 +340,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.serve:
+        return serve(args, r2, torch)
     dev = torch.device("cuda:0")
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)

@@ -201,6 +201,65 @@ rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32
                          int32_t cap_b, int32_t D, const rift2_match_params* mp, rift2_correspondence* out,
                          int32_t* n_out_dev, void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---------------------------------------------------------------- serving
+ * Continuous batching of image-pair requests of mixed sizes (the paper
+ * times one pair at a time; this serves a stream of them).  Requests wait in
+ * a host queue and are admitted in arrival order as soon as a stream pair is
+ * free and the request's buffers fit into the caller's HBM arena (the
+ * memory budget); admitted pairs run concurrently on their own streams.
+ * Every stage is the same call as above, so a request's result does not
+ * depend on what else is in flight.  One engine per host thread. */
+typedef struct rift2_engine rift2_engine;
+
+typedef struct {
+  int64_t id;                 /* caller's tag, returned with the completion */
+  const void* img_a;          /* device, H x W of `dtype`, row pitch W, resident until completion */
+  const void* img_b;
+  int32_t dtype, H, W;        /* both images of a pair share one size */
+  int32_t max_keypoints;      /* K per image; <= 0 selects floor(2e-3 * H * W) */
+  rift2_correspondence* out;  /* device, capacity 2 K entries (written by the match stage) */
+  int32_t* n_out;             /* device int32: number of matches */
+} rift2_request;
+
+typedef struct {
+  int64_t id;
+  int32_t status;   /* rift2_status of the request */
+  float gpu_ms;     /* admission to completion, on the GPU clock */
+  double admit_ms;  /* admission, ms after the engine's creation (GPU clock) */
+  double done_ms;   /* completion, ms after the engine's creation (GPU clock) */
+} rift2_completion;
+
+/* Arena bytes one request of this size needs (0 if unsupported); the
+ * detector, descriptor and matcher parameters are those given to create. */
+size_t rift2_engine_request_bytes(int32_t H, int32_t W, int32_t max_keypoints, const rift2_pc_params* pc,
+                                  const rift2_detect_params* det, const rift2_desc_params* dp,
+                                  const rift2_match_params* mp);
+
+/* arena: device memory of arena_bytes (256-byte aligned), owned by the
+ * caller and used only by the engine until rift2_engine_destroy returns.
+ * max_inflight (1..64): requests running at once (two streams each).  The
+ * parameter records are copied; det->max_keypoints is ignored (per
+ * request).  Calls rift2_init(device). */
+rift2_status rift2_engine_create(int device, void* arena, size_t arena_bytes, int32_t max_inflight,
+                                 const rift2_pc_params* pc, const rift2_detect_params* det,
+                                 const rift2_desc_params* dp, const rift2_match_params* mp,
+                                 rift2_engine** out);
+
+/* Queues a request (host only; nothing is launched until the next poll).
+ * Errors: RIFT2_ERR_INVALID_ARG, RIFT2_ERR_UNSUPPORTED (size). */
+rift2_status rift2_engine_submit(rift2_engine* e, const rift2_request* r);
+
+/* Reaps finished requests into done[0..max_done) and admits queued ones;
+ * returns the number of completions written, or minus a rift2_status.  A
+ * request that can never fit the arena completes with RIFT2_ERR_WORKSPACE. */
+int32_t rift2_engine_poll(rift2_engine* e, rift2_completion* done, int32_t max_done);
+
+/* Requests queued, running, or finished but not yet reported. */
+int32_t rift2_engine_pending(const rift2_engine* e);
+
+/* Waits for the running requests, then frees the engine's streams and events. */
+rift2_status rift2_engine_destroy(rift2_engine* e);
+
 /* Stage timing (diagnostics, not needed for computing).  While enabled, each
  * compute call records a HIP event pair on its stream around each of its
  * kernel groups: 0 row DFT, 1 column DFT + filter products + column IDFT,

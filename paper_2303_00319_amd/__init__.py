@@ -15,7 +15,7 @@ from ._lib import (PCParams, DetectParams, DescParams, MatchParams, PREC_FP32, P
 
 __all__ = [
     "defaults", "init", "filter_mim", "detect", "describe", "match", "Rift2Error", "PairPipeline",
-    "profile_enable", "profile_read", "PCParams", "DetectParams", "DescParams", "MatchParams",
+    "profile_enable", "profile_read", "PCParams", "DetectParams", "DescParams", "MatchParams", "Engine",
     "PREC_FP32", "PREC_BF16", "STAGES",
 ]
 
@@ -307,6 +307,95 @@ class PairPipeline:
         n = int(self.n_out.item())
         o = self.out[:n].cpu()
         return o
+
+
+# ----------------------------------------------------------------- serving engine
+
+class Engine:
+    """Continuous batching of image-pair requests (rift2_engine_* in include/rift2.h).
+
+    The arena (the HBM budget) is one device tensor; requests are admitted in
+    arrival order as their buffers fit into it and a stream pair is free.
+    Inputs must be complete on the device when submitted; the engine keeps a
+    reference to every tensor of a request until its completion is polled.
+    """
+
+    def __init__(self, arena_bytes, max_inflight=8, pc=None, det=None, dp=None, mp=None, device=0):
+        torch = _torch()
+        d_pc, d_det, d_dp, d_mp = defaults()
+        self.pc, self.det, self.dp, self.mp = pc or d_pc, det or d_det, dp or d_dp, mp or d_mp
+        self.dev = torch.device("cuda", device)
+        init(device)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.dev)
+        lib = _lib.load()
+        h = ctypes.c_void_p()
+        _lib.check(lib.rift2_engine_create(device, _ptr(self.arena), _nbytes(self.arena), max_inflight,
+                                           ctypes.byref(self.pc), ctypes.byref(self.det), ctypes.byref(self.dp),
+                                           ctypes.byref(self.mp), ctypes.byref(h)), "rift2_engine_create")
+        self._h = h
+        self._live = {}
+
+    def request_bytes(self, h, w, max_keypoints=0):
+        return _lib.load().rift2_engine_request_bytes(h, w, max_keypoints, ctypes.byref(self.pc),
+                                                      ctypes.byref(self.det), ctypes.byref(self.dp),
+                                                      ctypes.byref(self.mp))
+
+    @staticmethod
+    def keypoints(h, w, max_keypoints=0):
+        return max_keypoints if max_keypoints > 0 else int(2e-3 * h * w)
+
+    def submit(self, rid, img_a, img_b, max_keypoints=0, out=None, n_out=None):
+        """Queue one pair; returns the (out, n_out) device tensors the match stage writes."""
+        torch = _torch()
+        h, w = img_a.shape
+        k = self.keypoints(h, w, max_keypoints)
+        if out is None:
+            out = torch.empty((2 * k, 3), dtype=torch.int32, device=self.dev)
+        if n_out is None:
+            n_out = torch.zeros((1,), dtype=torch.int32, device=self.dev)
+        r = _lib.Request(int(rid), img_a.data_ptr(), img_b.data_ptr(), _image_dtype(img_a), h, w, max_keypoints,
+                         out.data_ptr(), n_out.data_ptr())
+        _lib.check(_lib.load().rift2_engine_submit(self._h, ctypes.byref(r)), "rift2_engine_submit")
+        self._live[int(rid)] = (img_a, img_b, out, n_out)
+        return out, n_out
+
+    def poll(self, max_done=256):
+        """Completed requests: [{id, status, gpu_ms, admit_ms, done_ms, out, n_out}]."""
+        buf = (_lib.Completion * max_done)()
+        n = _lib.load().rift2_engine_poll(self._h, buf, max_done)
+        if n < 0:
+            raise Rift2Error(-n, "rift2_engine_poll")
+        res = []
+        for c in buf[:n]:
+            live = self._live.pop(int(c.id), None)
+            res.append({"id": int(c.id), "status": int(c.status), "gpu_ms": float(c.gpu_ms),
+                        "admit_ms": float(c.admit_ms), "done_ms": float(c.done_ms),
+                        "out": live[2] if live else None, "n_out": live[3] if live else None})
+        return res
+
+    def pending(self):
+        return int(_lib.load().rift2_engine_pending(self._h))
+
+    def drain(self, sleep_s=0.0):
+        import time
+
+        done = []
+        while self.pending():
+            done += self.poll()
+            if sleep_s:
+                time.sleep(sleep_s)
+        return done
+
+    def close(self):
+        if self._h is not None:
+            _lib.load().rift2_engine_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ----------------------------------------------------------------- diagnostics

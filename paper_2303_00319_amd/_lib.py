@@ -47,11 +47,36 @@ class MatchParams(ctypes.Structure):
     _fields_ = [("ratio_sq", ctypes.c_float), ("precision", ctypes.c_int32)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [
+        ("id", ctypes.c_int64),
+        ("img_a", ctypes.c_void_p),
+        ("img_b", ctypes.c_void_p),
+        ("dtype", ctypes.c_int32),
+        ("H", ctypes.c_int32),
+        ("W", ctypes.c_int32),
+        ("max_keypoints", ctypes.c_int32),
+        ("out", ctypes.c_void_p),
+        ("n_out", ctypes.c_void_p),
+    ]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [
+        ("id", ctypes.c_int64),
+        ("status", ctypes.c_int32),
+        ("gpu_ms", ctypes.c_float),
+        ("admit_ms", ctypes.c_double),
+        ("done_ms", ctypes.c_double),
+    ]
+
+
 EXPORTS = [
     "rift2_default_params", "rift2_status_string", "rift2_init", "rift2_size_supported",
     "rift2_filter_workspace_size", "rift2_detect_workspace_size", "rift2_describe_workspace_size",
     "rift2_match_workspace_size", "rift2_filter_mim", "rift2_detect", "rift2_describe", "rift2_match",
-    "rift2_profile_enable", "rift2_profile_read",
+    "rift2_profile_enable", "rift2_profile_read", "rift2_engine_request_bytes", "rift2_engine_create",
+    "rift2_engine_submit", "rift2_engine_poll", "rift2_engine_pending", "rift2_engine_destroy",
 ]
 STAGES = ["row_dft", "pass_a", "noise_pre", "noise_sel", "pass_b", "detect", "describe", "match_prep",
           "match_gemm", "match_merge", "pass_b_reduce"]
@@ -103,6 +128,20 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rift2_profile_enable.restype = ctypes.c_int
     lib.rift2_profile_read.argtypes = [P(ctypes.c_double), P(ctypes.c_int64), ctypes.c_int]
     lib.rift2_profile_read.restype = ctypes.c_int
+    lib.rift2_engine_request_bytes.argtypes = [i32, i32, i32, P(PCParams), P(DetectParams), P(DescParams),
+                                               P(MatchParams)]
+    lib.rift2_engine_request_bytes.restype = sz
+    lib.rift2_engine_create.argtypes = [ctypes.c_int, vp, sz, i32, P(PCParams), P(DetectParams), P(DescParams),
+                                        P(MatchParams), P(vp)]
+    lib.rift2_engine_create.restype = ctypes.c_int
+    lib.rift2_engine_submit.argtypes = [vp, P(Request)]
+    lib.rift2_engine_submit.restype = ctypes.c_int
+    lib.rift2_engine_poll.argtypes = [vp, P(Completion), i32]
+    lib.rift2_engine_poll.restype = i32
+    lib.rift2_engine_pending.argtypes = [vp]
+    lib.rift2_engine_pending.restype = i32
+    lib.rift2_engine_destroy.argtypes = [vp]
+    lib.rift2_engine_destroy.restype = ctypes.c_int
     _LIB = lib
     return lib
 

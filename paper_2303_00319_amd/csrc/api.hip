@@ -15,6 +15,7 @@
 #include "fft.hpp"
 #include "filter.hip"
 #include "match.hip"
+#include "engine.hip"
 
 using namespace rift2;
 
@@ -623,6 +624,135 @@ rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32
   hipLaunchKernelGGL(k_match_emit, dim3((cap_a + 255) / 256), dim3(256), 0, st, best, cap_a, rowj, rowd, kp_b,
                      (MatchOut*)out, n_out_dev);
   return launch_status();
+}
+
+size_t rift2_engine_request_bytes(int32_t H, int32_t W, int32_t max_keypoints, const rift2_pc_params* pc,
+                                  const rift2_detect_params* det, const rift2_desc_params* dp,
+                                  const rift2_match_params* mp) {
+  if (!pc || !det || !dp || !mp) return 0;
+  rift2_request r{};
+  r.H = H;
+  r.W = W;
+  r.max_keypoints = max_keypoints;
+  ReqLayout L;
+  if (!req_layout(H, W, engine_keypoints(r), pc, det, dp, mp, &L)) return 0;
+  return L.total;
+}
+
+rift2_status rift2_engine_create(int device, void* arena, size_t arena_bytes, int32_t max_inflight,
+                                 const rift2_pc_params* pc, const rift2_detect_params* det,
+                                 const rift2_desc_params* dp, const rift2_match_params* mp, rift2_engine** out) {
+  if (!out || !arena || !arena_bytes || !pc || !det || !dp || !mp || max_inflight <= 0 || max_inflight > 64)
+    return RIFT2_ERR_INVALID_ARG;
+  if ((uintptr_t)arena & 255u) return RIFT2_ERR_INVALID_ARG;
+  *out = nullptr;
+  const rift2_status st = rift2_init(device);
+  if (st != RIFT2_OK) return st;
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(device) != hipSuccess) return RIFT2_ERR_DEVICE;
+  rift2_engine* e = new rift2_engine();
+  e->device = device;
+  e->arena = (char*)arena;
+  e->arena_bytes = arena_bytes;
+  e->pc = *pc;
+  e->det = *det;
+  e->dp = *dp;
+  e->mp = *mp;
+  e->alloc.reset(arena_bytes);
+  bool ok = hipEventCreate(&e->epoch) == hipSuccess;
+  e->slots.resize(max_inflight);
+  for (int i = 0; ok && i < max_inflight; ++i) {
+    EngineSlot& s = e->slots[i];
+    ok = hipStreamCreateWithFlags(&s.sa, hipStreamNonBlocking) == hipSuccess &&
+         hipStreamCreateWithFlags(&s.sb, hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreate(&s.b_done) == hipSuccess && hipEventCreate(&s.admit) == hipSuccess &&
+         hipEventCreate(&s.done) == hipSuccess;
+    e->free_slots.push_back(max_inflight - 1 - i);
+  }
+  if (ok) ok = hipEventRecord(e->epoch, e->slots[0].sa) == hipSuccess && hipEventSynchronize(e->epoch) == hipSuccess;
+  (void)hipSetDevice(prev);
+  if (!ok) {
+    rift2_engine_destroy(e);
+    return RIFT2_ERR_DEVICE;
+  }
+  *out = e;
+  return RIFT2_OK;
+}
+
+rift2_status rift2_engine_submit(rift2_engine* e, const rift2_request* r) {
+  if (!e || !r || !r->img_a || !r->img_b || !r->out || !r->n_out) return RIFT2_ERR_INVALID_ARG;
+  if (r->dtype != RIFT2_U8 && r->dtype != RIFT2_U16 && r->dtype != RIFT2_F32) return RIFT2_ERR_INVALID_ARG;
+  if (!size_ok(r->H) || !size_ok(r->W)) return RIFT2_ERR_UNSUPPORTED;
+  EngineReq q;
+  q.req = *r;
+  q.H = r->H;
+  q.W = r->W;
+  q.K = engine_keypoints(*r);
+  if (q.K <= 0) return RIFT2_ERR_INVALID_ARG;
+  e->pending.push_back(q);
+  return RIFT2_OK;
+}
+
+int32_t rift2_engine_poll(rift2_engine* e, rift2_completion* done, int32_t max_done) {
+  if (!e || (!done && max_done > 0) || max_done < 0) return -RIFT2_ERR_INVALID_ARG;
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(e->device) != hipSuccess) return -RIFT2_ERR_DEVICE;
+  int32_t n = 0;
+  while (n < max_done && !e->finished.empty()) {
+    done[n++] = e->finished.front();
+    e->finished.pop_front();
+  }
+  // reap finished requests (any order), then admit from the queue
+  for (auto it = e->inflight.begin(); it != e->inflight.end() && n < max_done;) {
+    const EngineSlot& s = e->slots[it->slot];
+    const hipError_t q = hipEventQuery(s.done);
+    if (q == hipErrorNotReady) {
+      ++it;
+      continue;
+    }
+    rift2_completion c{};
+    c.id = it->req.id;
+    c.status = q == hipSuccess ? it->status : RIFT2_ERR_DEVICE;
+    float t_admit = 0.0f, t_done = 0.0f;
+    if (q == hipSuccess && hipEventElapsedTime(&t_admit, e->epoch, s.admit) == hipSuccess &&
+        hipEventElapsedTime(&t_done, e->epoch, s.done) == hipSuccess) {
+      c.admit_ms = t_admit;
+      c.done_ms = t_done;
+      c.gpu_ms = t_done - t_admit;
+    }
+    done[n++] = c;
+    e->alloc.release(it->off, it->bytes);
+    e->free_slots.push_back(it->slot);
+    it = e->inflight.erase(it);
+  }
+  engine_pump(e);
+  (void)hipSetDevice(prev);
+  return n;
+}
+
+int32_t rift2_engine_pending(const rift2_engine* e) {
+  if (!e) return 0;
+  return (int32_t)(e->pending.size() + e->inflight.size() + e->finished.size());
+}
+
+rift2_status rift2_engine_destroy(rift2_engine* e) {
+  if (!e) return RIFT2_OK;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(e->device);
+  for (EngineSlot& s : e->slots) {
+    if (s.sa) (void)hipStreamSynchronize(s.sa);
+    if (s.sb) (void)hipStreamSynchronize(s.sb);
+    if (s.sa) (void)hipStreamDestroy(s.sa);
+    if (s.sb) (void)hipStreamDestroy(s.sb);
+    if (s.b_done) (void)hipEventDestroy(s.b_done);
+    if (s.admit) (void)hipEventDestroy(s.admit);
+    if (s.done) (void)hipEventDestroy(s.done);
+  }
+  if (e->epoch) (void)hipEventDestroy(e->epoch);
+  (void)hipSetDevice(prev);
+  delete e;
+  return RIFT2_OK;
 }
 
 rift2_status rift2_profile_enable(int on) {

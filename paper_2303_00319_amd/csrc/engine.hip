@@ -1,0 +1,238 @@
+// Serving engine: continuous batching of image-pair requests of mixed sizes.
+//
+// Requests queue on the host; the engine admits the head of the queue as soon
+// as (a) a stream pair is free and (b) its buffers fit into the caller's HBM
+// arena (first-fit over a free list with coalescing).  An admitted pair runs
+// the whole path -- both images' filter bank / detection / description on
+// two streams, then matching -- while later requests are admitted beside it,
+// so their kernels overlap on the device.  Completion is found by polling a
+// per-request event; the request's memory and streams go back to the pools
+// and the queue is pumped again.  Everything is host code over the C ABI
+// stages; the engine allocates no device memory.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <vector>
+
+#include "rift2.h"
+
+namespace rift2 {
+
+// Per-request device layout inside one arena region.
+struct ReqLayout {
+  struct Img {
+    size_t mim, mmax, kpts, nk, desc, inv, dkp, nd, ws_filter, ws_detect, ws_desc;
+  } img[2];
+  size_t ws_match, total;
+  size_t b_filter, b_detect, b_desc, b_match;
+  int32_t K, D;
+};
+
+inline size_t eng_align(size_t v) { return (v + 255) / 256 * 256; }
+
+inline bool req_layout(int H, int W, int K, const rift2_pc_params* pc, const rift2_detect_params* det_tpl,
+                       const rift2_desc_params* dp, const rift2_match_params* mp, ReqLayout* L) {
+  if (K <= 0) return false;
+  rift2_detect_params det = *det_tpl;
+  det.max_keypoints = K;
+  L->K = K;
+  L->D = dp->grid * dp->grid * dp->n_orient;
+  L->b_filter = rift2_filter_workspace_size(H, W, pc);
+  L->b_detect = rift2_detect_workspace_size(H, W, &det);
+  L->b_desc = rift2_describe_workspace_size(K);
+  L->b_match = rift2_match_workspace_size(2 * K, 2 * K, L->D, mp);
+  if (!L->b_filter || !L->b_detect || !L->b_desc || !L->b_match) return false;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = eng_align(off + bytes);
+    return o;
+  };
+  const size_t hw = (size_t)H * W;
+  for (int i = 0; i < 2; ++i) {
+    ReqLayout::Img& m = L->img[i];
+    m.mim = take(hw);
+    m.mmax = take(hw * sizeof(float));
+    m.kpts = take((size_t)K * sizeof(rift2_keypoint));
+    m.nk = take(sizeof(int32_t));
+    m.desc = take((size_t)2 * K * L->D * sizeof(uint16_t));
+    m.inv = take((size_t)2 * K * sizeof(float));
+    m.dkp = take((size_t)2 * K * sizeof(int32_t));
+    m.nd = take(sizeof(int32_t));
+    m.ws_filter = take(L->b_filter);
+    m.ws_detect = take(L->b_detect);
+    m.ws_desc = take(L->b_desc);
+  }
+  L->ws_match = take(L->b_match);
+  L->total = off;
+  return true;
+}
+
+// First-fit allocator over [0, size) with coalescing of freed ranges.
+class ArenaAlloc {
+ public:
+  void reset(size_t size) {
+    free_.clear();
+    if (size) free_[0] = size;
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes;
+        const size_t start = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[start] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    auto it = free_.emplace(off, bytes).first;
+    auto next = std::next(it);
+    if (next != free_.end() && it->first + it->second == next->first) {
+      it->second += next->second;
+      free_.erase(next);
+    }
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == it->first) {
+        prev->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+
+ private:
+  std::map<size_t, size_t> free_;
+};
+
+struct EngineSlot {
+  hipStream_t sa = nullptr, sb = nullptr;
+  hipEvent_t b_done = nullptr, admit = nullptr, done = nullptr;
+};
+
+struct EngineReq {
+  rift2_request req;
+  int H, W, K;
+  size_t off = 0, bytes = 0;
+  int slot = -1;
+  int32_t status = RIFT2_OK;
+};
+
+}  // namespace rift2
+
+struct rift2_engine {
+  int device = 0;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  rift2_pc_params pc;
+  rift2_detect_params det;
+  rift2_desc_params dp;
+  rift2_match_params mp;
+  rift2::ArenaAlloc alloc;
+  std::vector<rift2::EngineSlot> slots;
+  std::vector<int> free_slots;
+  std::deque<rift2::EngineReq> pending;
+  std::deque<rift2::EngineReq> inflight;
+  std::deque<rift2_completion> finished;  // failed at admission, reported by the next poll
+  hipEvent_t epoch = nullptr;
+};
+
+namespace rift2 {
+
+inline int engine_keypoints(const rift2_request& r) {
+  if (r.max_keypoints > 0) return r.max_keypoints;
+  return (int)std::floor(2e-3 * (double)r.H * (double)r.W);
+}
+
+// Enqueues one admitted request on its slot's streams.
+inline int32_t engine_launch(rift2_engine* e, EngineReq& q) {
+  const EngineSlot& s = e->slots[q.slot];
+  ReqLayout L;
+  req_layout(q.H, q.W, q.K, &e->pc, &e->det, &e->dp, &e->mp, &L);
+  char* base = e->arena + q.off;
+  rift2_detect_params det = e->det;
+  det.max_keypoints = q.K;
+  if (hipEventRecord(s.admit, s.sa) != hipSuccess) return RIFT2_ERR_DEVICE;
+  // image B's stages start after the admission mark too
+  if (hipStreamWaitEvent(s.sb, s.admit, 0) != hipSuccess) return RIFT2_ERR_DEVICE;
+  const void* imgs[2] = {q.req.img_a, q.req.img_b};
+  hipStream_t st[2] = {s.sa, s.sb};
+  for (int i = 0; i < 2; ++i) {
+    const ReqLayout::Img& m = L.img[i];
+    rift2_status r = rift2_filter_mim(imgs[i], q.req.dtype, q.H, q.W, q.W, &e->pc, (uint8_t*)(base + m.mim),
+                                      (float*)(base + m.mmax), nullptr, nullptr, base + m.ws_filter, L.b_filter,
+                                      st[i]);
+    if (r == RIFT2_OK)
+      r = rift2_detect((const float*)(base + m.mmax), q.H, q.W, &det, (rift2_keypoint*)(base + m.kpts),
+                       (int32_t*)(base + m.nk), base + m.ws_detect, L.b_detect, st[i]);
+    if (r == RIFT2_OK)
+      r = rift2_describe((const uint8_t*)(base + m.mim), q.H, q.W, (const rift2_keypoint*)(base + m.kpts),
+                         (const int32_t*)(base + m.nk), q.K, &e->dp, (uint16_t*)(base + m.desc),
+                         (float*)(base + m.inv), (int32_t*)(base + m.dkp), 2 * q.K, (int32_t*)(base + m.nd),
+                         base + m.ws_desc, L.b_desc, st[i]);
+    if (r != RIFT2_OK) return r;
+  }
+  if (hipEventRecord(s.b_done, s.sb) != hipSuccess) return RIFT2_ERR_DEVICE;
+  if (hipStreamWaitEvent(s.sa, s.b_done, 0) != hipSuccess) return RIFT2_ERR_DEVICE;
+  const ReqLayout::Img& a = L.img[0];
+  const ReqLayout::Img& b = L.img[1];
+  rift2_status r = rift2_match((const uint16_t*)(base + a.desc), (const float*)(base + a.inv),
+                               (const int32_t*)(base + a.dkp), (const int32_t*)(base + a.nd), 2 * q.K,
+                               (const uint16_t*)(base + b.desc), (const float*)(base + b.inv),
+                               (const int32_t*)(base + b.dkp), (const int32_t*)(base + b.nd), 2 * q.K, L.D, &e->mp,
+                               q.req.out, q.req.n_out, base + L.ws_match, L.b_match, s.sa);
+  if (r != RIFT2_OK) return r;
+  if (hipEventRecord(s.done, s.sa) != hipSuccess) return RIFT2_ERR_DEVICE;
+  return RIFT2_OK;
+}
+
+// Admits queued requests in arrival order while a slot and arena space are
+// free; a request larger than the whole arena fails at once.
+inline void engine_pump(rift2_engine* e) {
+  while (!e->pending.empty() && !e->free_slots.empty()) {
+    EngineReq& q = e->pending.front();
+    ReqLayout L;
+    if (!req_layout(q.H, q.W, q.K, &e->pc, &e->det, &e->dp, &e->mp, &L) || L.total > e->arena_bytes) {
+      rift2_completion c{};
+      c.id = q.req.id;
+      c.status = L.total > e->arena_bytes ? RIFT2_ERR_WORKSPACE : RIFT2_ERR_UNSUPPORTED;
+      e->finished.push_back(c);
+      e->pending.pop_front();
+      continue;
+    }
+    size_t off = 0;
+    if (!e->alloc.alloc(L.total, &off)) return;  // wait for memory to free up
+    q.off = off;
+    q.bytes = L.total;
+    q.slot = e->free_slots.back();
+    e->free_slots.pop_back();
+    q.status = engine_launch(e, q);
+    if (q.status != RIFT2_OK) {
+      // part of the request may be enqueued: let it drain before the memory
+      // and the streams are reused, then report the failure
+      const EngineSlot& s = e->slots[q.slot];
+      (void)hipStreamSynchronize(s.sa);
+      (void)hipStreamSynchronize(s.sb);
+      e->alloc.release(q.off, q.bytes);
+      e->free_slots.push_back(q.slot);
+      rift2_completion c{};
+      c.id = q.req.id;
+      c.status = q.status;
+      e->finished.push_back(c);
+      e->pending.pop_front();
+      continue;
+    }
+    e->inflight.push_back(q);
+    e->pending.pop_front();
+  }
+}
+
+}  // namespace rift2

@@ -1,0 +1,121 @@
+"""Serving engine: continuous batching of mixed-size pair requests.
+
+Each request's matches must be the same when it runs alone and when it runs
+in a mix of concurrent requests of other sizes; admission must respect the
+HBM arena (requests wait for memory, a request larger than the arena fails
+cleanly); and the engine's result must equal the direct stage calls.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from synth import make_pair  # noqa: E402
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2303_00319_amd as r2
+
+    return r2, torch.device("cuda:0")
+
+
+def _requests(dev):
+    """Mixed-size pool: (id, size, A, B) with the serving generator's pairs."""
+    sizes = [256, 512, 256, 768, 512, 256, 512, 768]
+    reqs = []
+    for i, n in enumerate(sizes):
+        a, b, _ = make_pair(3, i, size=n)
+        reqs.append((i, n, torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)))
+    torch.cuda.synchronize()
+    return reqs
+
+
+def _engine(r2, arena_bytes, inflight):
+    pc, det, dp, mp = r2.defaults()
+    mp.precision = r2.PREC_BF16
+    return r2.Engine(arena_bytes, max_inflight=inflight, pc=pc, det=det, dp=dp, mp=mp)
+
+
+def _result(done):
+    assert done["status"] == 0, done
+    n = int(done["n_out"].item())
+    return done["out"][:n].cpu().numpy().copy()
+
+
+def test_same_alone_and_in_the_mix():
+    r2, dev = _gpu()
+    reqs = _requests(dev)
+    print(f"[serving] {len(reqs)} requests, sizes {[n for _, n, _, _ in reqs]}", flush=True)
+    alone = {}
+    eng = _engine(r2, 2 << 30, 1)
+    for rid, n, a, b in reqs:
+        eng.submit(rid, a, b)
+        done = eng.drain()
+        assert len(done) == 1 and done[0]["id"] == rid
+        alone[rid] = _result(done[0])
+    eng.close()
+    assert sum(len(v) for v in alone.values()) > 0
+    eng = _engine(r2, 4 << 30, 6)
+    for rid, n, a, b in reqs:
+        eng.submit(rid, a, b)
+    done = eng.drain()
+    assert sorted(d["id"] for d in done) == [rid for rid, _, _, _ in reqs]
+    overlap = 0
+    for d in done:
+        got = _result(d)
+        assert np.array_equal(got, alone[d["id"]]), f"request {d['id']} differs in the mix"
+    # the mix really overlapped: some request was admitted before another finished
+    spans = sorted((d["admit_ms"], d["done_ms"]) for d in done)
+    overlap = sum(1 for (a0, d0), (a1, _) in zip(spans, spans[1:]) if a1 < d0)
+    print(f"[serving] overlapping admissions: {overlap}", flush=True)
+    assert overlap > 0
+
+
+def test_admission_waits_for_memory_and_rejects_oversize():
+    r2, dev = _gpu()
+    reqs = _requests(dev)[:5]
+    eng = _engine(r2, 1, 1)  # probe sizes only
+    need = max(eng.request_bytes(n, n) for _, n, _, _ in reqs)
+    eng.close()
+    # room for about two of the largest requests at once
+    eng = _engine(r2, int(2.2 * need), 8)
+    for rid, n, a, b in reqs:
+        eng.submit(rid, a, b)
+    done = eng.drain()
+    assert sorted(d["id"] for d in done) == [rid for rid, _, _, _ in reqs]
+    assert all(d["status"] == 0 for d in done)
+    # requests running at the same time never needed more than the arena
+    size_of = {rid: n for rid, n, _, _ in reqs}
+    events = sorted([(d["done_ms"], 0, d["id"]) for d in done] + [(d["admit_ms"], 1, d["id"]) for d in done])
+    live = peak = 0
+    for _, kind, rid in events:
+        live += (1 if kind else -1) * eng.request_bytes(size_of[rid], size_of[rid])
+        peak = max(peak, live)
+    assert peak <= int(2.2 * need)
+    eng.close()
+    # a request larger than the whole arena completes with RIFT2_ERR_WORKSPACE (3)
+    small = _engine(r2, need // 2, 2)
+    rid, n, a, b = max(reqs, key=lambda r: r[1])
+    small.submit(99, a, b)
+    d = small.drain()
+    assert len(d) == 1 and d[0]["id"] == 99 and d[0]["status"] == 3
+
+
+def test_engine_equals_direct_stage_calls():
+    r2, dev = _gpu()
+    rid, n, a, b = _requests(dev)[3]
+    pc, det, dp, mp = r2.defaults()
+    mp.precision = r2.PREC_BF16
+    det.max_keypoints = int(2e-3 * n * n)
+    pipe = r2.PairPipeline(n, n, pc, det, dp, mp)
+    pipe.run(a, b)
+    torch.cuda.synchronize()
+    want = pipe.out[:int(pipe.n_out.item())].cpu().numpy()
+    eng = _engine(r2, 1 << 30, 2)
+    eng.submit(rid, a, b)
+    got = _result(eng.drain()[0])
+    assert np.array_equal(got, want)
