@@ -55,7 +55,10 @@ typedef enum {
 
 typedef enum { RIFT2_U8 = 0, RIFT2_U16 = 1, RIFT2_F32 = 2 } rift2_dtype;
 
-typedef enum { RIFT2_PREC_FP32 = 0, RIFT2_PREC_BF16 = 1 } rift2_precision;
+/* Distance GEMM precision: FP32 and BF16 give the same exact dots on the
+ * integer counts; FP8 (E4M3, power-of-two scale per row) selects 8
+ * candidates per query approximately and re-ranks them with exact dots. */
+typedef enum { RIFT2_PREC_FP32 = 0, RIFT2_PREC_BF16 = 1, RIFT2_PREC_FP8 = 2 } rift2_precision;
 
 /* Log-Gabor bank and phase-congruency constants (Sections 2.1-2.2 name the
  * log-Gabor convolution sequence and one-dimensional phase congruency per

@@ -10,13 +10,13 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (PCParams, DetectParams, DescParams, MatchParams, PREC_FP32, PREC_BF16,  # noqa: F401
+from ._lib import (PCParams, DetectParams, DescParams, MatchParams, PREC_FP32, PREC_BF16, PREC_FP8,  # noqa: F401
                    Rift2Error, STAGES)
 
 __all__ = [
     "defaults", "init", "filter_mim", "detect", "describe", "match", "Rift2Error", "PairPipeline",
     "profile_enable", "profile_read", "PCParams", "DetectParams", "DescParams", "MatchParams", "Engine",
-    "PREC_FP32", "PREC_BF16", "STAGES",
+    "PREC_FP32", "PREC_BF16", "PREC_FP8", "STAGES",
 ]
 
 

@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(HERE, "librift2.so")
 
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_DEVICE = 0, 1, 2, 3, 4
 U8, U16, F32 = 0, 1, 2
-PREC_FP32, PREC_BF16 = 0, 1
+PREC_FP32, PREC_BF16, PREC_FP8 = 0, 1, 2
 
 
 class PCParams(ctypes.Structure):

@@ -15,6 +15,7 @@
 #include "fft.hpp"
 #include "filter.hip"
 #include "match.hip"
+#include "match_fp8.hip"
 #include "engine.hip"
 
 using namespace rift2;
@@ -107,8 +108,8 @@ DetectLayout detect_layout(int H, int W, const rift2_detect_params* d) {
 }
 
 struct MatchLayout {
-  size_t ta, tb, part, best, rowj, rowd, total;
-  int dp, rs, rows_a, rows_b, slices, slice_rows;
+  size_t ta, tb, wa, wb, part, best, rowj, rowd, total;
+  int dp, rs, rows_a, rows_b, slices, slice_rows, topk;
 };
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
@@ -116,8 +117,19 @@ int round_up(int v, int m) { return (v + m - 1) / m * m; }
 MatchLayout match_layout(int cap_a, int cap_b, int D, int precision) {
   MatchLayout L;
   const bool bf = precision == RIFT2_PREC_BF16;
-  L.dp = bf ? round_up(D, 16) : round_up(D, 8);
-  L.rs = bf ? L.dp + 8 : L.dp + 4;  // table row stride = the GEMM kernels' LDS row stride
+  const bool f8 = precision == RIFT2_PREC_FP8;
+  // table row stride = the GEMM kernels' LDS row stride (elements)
+  if (f8) {
+    L.dp = round_up(D, 64);
+    L.rs = L.dp + 16;
+  } else if (bf) {
+    L.dp = round_up(D, 16);
+    L.rs = L.dp + 8;
+  } else {
+    L.dp = round_up(D, 8);
+    L.rs = L.dp + 4;
+  }
+  L.topk = f8 ? kTopK8 : kTopK;
   L.rows_a = round_up(cap_a, 32);
   L.rows_b = round_up(cap_b, 32);
   const int blocks_x = (L.rows_a + 127) / 128;
@@ -128,11 +140,13 @@ MatchLayout match_layout(int cap_a, int cap_b, int D, int precision) {
   if (slices < 1) slices = 1;
   L.slice_rows = round_up((L.rows_b + slices - 1) / slices, 32);
   L.slices = (L.rows_b + L.slice_rows - 1) / L.slice_rows;
-  const size_t el = bf ? 2 : 4;
+  const size_t el = f8 ? 1 : (bf ? 2 : 4);
   Carver c;
   L.ta = c.take((size_t)L.rows_a * L.rs * el);
   L.tb = c.take((size_t)L.rows_b * L.rs * el);
-  L.part = c.take((size_t)L.rows_a * L.slices * 2 * kTopK * sizeof(int2));
+  L.wa = c.take((size_t)L.rows_a * sizeof(float));
+  L.wb = c.take((size_t)L.rows_b * sizeof(float));
+  L.part = c.take((size_t)L.rows_a * L.slices * 2 * L.topk * sizeof(int2));
   L.best = c.take((size_t)cap_a * sizeof(uint64_t));
   L.rowj = c.take((size_t)cap_a * sizeof(int32_t));
   L.rowd = c.take((size_t)cap_a * sizeof(float));
@@ -570,7 +584,8 @@ rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32
       !workspace)
     return RIFT2_ERR_INVALID_ARG;
   if (cap_a <= 0 || cap_b <= 0 || D <= 0) return RIFT2_ERR_INVALID_ARG;
-  if (!(mp->ratio_sq > 0.0f) || (mp->precision != RIFT2_PREC_FP32 && mp->precision != RIFT2_PREC_BF16))
+  if (!(mp->ratio_sq > 0.0f) ||
+      (mp->precision != RIFT2_PREC_FP32 && mp->precision != RIFT2_PREC_BF16 && mp->precision != RIFT2_PREC_FP8))
     return RIFT2_ERR_INVALID_ARG;
   if (D != 216 && D != 288) return RIFT2_ERR_UNSUPPORTED;
   // the table preparation reads descriptor rows as 16-byte vectors
@@ -587,6 +602,33 @@ rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32
   float* rowd = (float*)(ws + L.rowd);
   const bool bf = mp->precision == RIFT2_PREC_BF16;
   (void)hipGetLastError();
+  if (mp->precision == RIFT2_PREC_FP8) {
+    float* wa = (float*)(ws + L.wa);
+    float* wb = (float*)(ws + L.wb);
+    {
+      ProfScope ps7(7, st);
+      hipLaunchKernelGGL(k_match_prep_fp8, dim3(1024), dim3(256), 0, st, desc_a, inv_a, nA_dev, cap_a, D, L.rs,
+                         L.rows_a, (uint8_t*)ta, wa, best, cap_a);
+      hipLaunchKernelGGL(k_match_prep_fp8, dim3(1024), dim3(256), 0, st, desc_b, inv_b, nB_dev, cap_b, D, L.rs,
+                         L.rows_b, (uint8_t*)tb, wb, (uint64_t*)nullptr, 0);
+    }
+    {
+      ProfScope ps8(8, st);
+      const dim3 grid((L.rows_a + 127) / 128, L.slices);
+      if (L.dp == 256)
+        hipLaunchKernelGGL(k_match_gemm_fp8<256>, grid, dim3(256), 0, st, (const uint8_t*)ta, wa, nA_dev,
+                           (const uint8_t*)tb, wb, nB_dev, cap_a, cap_b, L.slice_rows, part);
+      else
+        hipLaunchKernelGGL(k_match_gemm_fp8<320>, grid, dim3(256), 0, st, (const uint8_t*)ta, wa, nA_dev,
+                           (const uint8_t*)tb, wb, nB_dev, cap_a, cap_b, L.slice_rows, part);
+    }
+    ProfScope ps9(9, st);
+    hipLaunchKernelGGL(k_match_merge8, dim3((cap_a + 3) / 4), dim3(256), 0, st, part, 2 * L.slices, nA_dev, desc_a, inv_a,
+                       kp_a, desc_b, inv_b, kp_b, D, mp->ratio_sq, cap_a, best, rowj, rowd);
+    hipLaunchKernelGGL(k_match_emit, dim3((cap_a + 255) / 256), dim3(256), 0, st, best, cap_a, rowj, rowd, kp_b,
+                       (MatchOut*)out, n_out_dev);
+    return launch_status();
+  }
   ProfScope ps7(7, st);
   if (bf) {
     hipLaunchKernelGGL(k_match_prep<true>, dim3(512), dim3(256), 0, st, desc_a, nA_dev, cap_a, D, L.rs, L.rows_a, ta, best,

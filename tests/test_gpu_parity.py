@@ -230,9 +230,35 @@ def test_match_exact_on_oracle_descriptors():
     for prec in (r2.PREC_FP32, r2.PREC_BF16):
         n = _check_match(r2, dev, fa["desc"], fa["desc_kp"], fb["desc"], fb["desc_kp"], prec, "c0 shifted")
         assert n > 100
+    # FP8: approximate candidate choice on the real counts (up to 256), exact re-rank
+    jac = _match_agreement(r2, dev, fa["desc"], fa["desc_kp"], fb["desc"], fb["desc_kp"], r2.PREC_FP8, "c0 shifted fp8")
+    assert jac >= 0.98
+
+
+def _match_agreement(r2, dev, ca, ka, cb, kb, precision, tag):
+    """Jaccard agreement of the match sets {(kp_a, kp_b)} with the oracle."""
+    mp = r2.defaults()[3]
+    mp.precision = precision
+    ref = match.match(ca, ka, cb, kb, dtype=np.float64)
+
+    def dev_set(c, k):
+        ct = torch.from_numpy(c.astype(np.int16)).to(dev)
+        inv = torch.from_numpy(match.inv_norms(c, np.float32)).to(dev)
+        kt = torch.from_numpy(k.astype(np.int32)).to(dev)
+        return ct, inv, kt, torch.tensor([len(c)], dtype=torch.int32, device=dev)
+
+    out, n = r2.match(*dev_set(ca, ka), *dev_set(cb, kb), mp)
+    n = int(n.item())
+    got = {(int(x), int(y)) for x, y in out[:n, :2].cpu().numpy()}
+    want = {(int(x), int(y)) for x, y in zip(ref[0], ref[1])}
+    jac = len(got & want) / max(1, len(got | want))
+    print(f"[match agreement] {tag}: gpu {len(got)}, oracle {len(want)}, Jaccard {jac:.4f}", flush=True)
+    return jac
 
 
 def test_match_random_sets_with_ties_and_ragged_sizes():
+    """Counts below 16 are exact in every precision (FP8 included: power-of-two row scales), so all
+    three forms must reproduce the oracle exactly, ties and ragged sizes included."""
     r2, dev = _gpu()
     rng = np.random.default_rng(9)
     for na, nb in ((1, 1), (3, 2), (33, 65), (700, 1111)):
@@ -241,12 +267,12 @@ def test_match_random_sets_with_ties_and_ragged_sizes():
         cb[: min(na, nb) // 2] = ca[: min(na, nb) // 2]
         ka = np.arange(na) // 2
         kb = np.arange(nb) // 2
-        for prec in (r2.PREC_FP32, r2.PREC_BF16):
+        for prec in (r2.PREC_FP32, r2.PREC_BF16, r2.PREC_FP8):
             _check_match(r2, dev, ca, ka, cb, kb, prec, f"random {na}x{nb}")
     # 288-d (N_o = 8) descriptors
     ca = rng.integers(0, 9, size=(300, 288)).astype(np.uint16)
     cb = np.concatenate([ca[:150], rng.integers(0, 9, size=(200, 288)).astype(np.uint16)])
-    for prec in (r2.PREC_FP32, r2.PREC_BF16):
+    for prec in (r2.PREC_FP32, r2.PREC_BF16, r2.PREC_FP8):
         _check_match(r2, dev, ca, np.arange(300), cb, np.arange(350), prec, "288-d")
 
 
