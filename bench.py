@@ -36,6 +36,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
+FP8_MFMA_PEAK_TFLOPS = 5000.0
 
 # Per-launch HBM bytes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a
 # plain copy of known size gives) from two rocprofv3 --pmc runs at 1024 x 1024
@@ -64,8 +65,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--pairs", type=int, default=4, help="distinct resident pairs cycled through")
-    ap.add_argument("--size", type=int, default=1024)
-    ap.add_argument("--keypoints", type=int, default=5000)
+    ap.add_argument("--config", type=int, default=1, choices=(1, 2, 4),
+                    help="workload: 1 = 1024^2 u8 pair, 5000 keypoints (the headline); 2 = 2048^2, 20000 keypoints; "
+                         "4 = 4096^2 12-bit u16, N_s=5 N_o=8, 50000 keypoints, 288-d")
+    ap.add_argument("--forms", default=None,
+                    help="matching precisions to time, first one is `value` (default fp32,bf16; config 4: fp8,bf16)")
+    ap.add_argument("--size", type=int, default=0, help="override the image side")
+    ap.add_argument("--keypoints", type=int, default=0, help="override the keypoints per image")
     ap.add_argument("--no-graph", action="store_true", help="enqueue kernels directly instead of graph replay")
     ap.add_argument("--slots", type=int, default=1,
                     help="pairs in flight: consecutive steps use separate buffer sets and streams, so one pair's "
@@ -99,6 +105,8 @@ def percentile(xs, q):
 
 def time_form(r2, torch, imgs, args, precision):
     pc, det, dp, mp = r2.defaults()
+    pc.n_scales, pc.n_orient = args.n_scales, args.n_orient
+    dp.n_orient = args.n_orient
     det.max_keypoints = args.keypoints
     mp.precision = precision
     slots = max(1, args.slots)
@@ -171,7 +179,7 @@ def profile_stages(r2, torch, pipe, imgs, steps):
     return {k: {"ms_avg": (v[0] / v[1] if v[1] else 0.0), "launches": v[1]} for k, v in raw.items()}
 
 
-def roofline(stages, h, w, n_scales, n_orient, n_a, n_b, d):
+def roofline(stages, h, w, n_scales, n_orient, n_a, n_b, d, gemm_peak=None):
     """Roofline of the kernel with the most time per step.
 
     Algorithmic work per launch: the column pass reads the row spectrum
@@ -194,7 +202,7 @@ def roofline(stages, h, w, n_scales, n_orient, n_a, n_b, d):
         return work / sec / (1e9 if bound == "hbm" else 1e12)
 
     def peak(k):
-        return HBM_PEAK_GBS if cand[k][0] == "hbm" else FP32_MFMA_PEAK_TFLOPS
+        return HBM_PEAK_GBS if cand[k][0] == "hbm" else (gemm_peak or FP32_MFMA_PEAK_TFLOPS)
 
     best = max(cand, key=lambda k: cand[k][2] * stages[k]["ms_avg"])
     bound, work, per_step = cand[best]
@@ -342,6 +350,15 @@ def main():
         sys.exit(1)
     if args.serve:
         return serve(args, r2, torch)
+    from synth.gen import CONFIGS
+
+    cfg = CONFIGS[args.config]
+    args.size = args.size or cfg.size
+    args.keypoints = args.keypoints or cfg.max_keypoints
+    args.n_scales, args.n_orient = cfg.n_scales, cfg.n_orient
+    forms = (args.forms or ("fp8,bf16" if args.config == 4 else "fp32,bf16")).split(",")
+    prec = {"fp32": r2.PREC_FP32, "bf16": r2.PREC_BF16, "fp8": r2.PREC_FP8}
+    peak = {"fp32": FP32_MFMA_PEAK_TFLOPS, "bf16": BF16_MFMA_PEAK_TFLOPS, "fp8": FP8_MFMA_PEAK_TFLOPS}
     dev = torch.device("cuda:0")
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
@@ -351,70 +368,78 @@ def main():
         del src, dst
     imgs = []
     for i in range(args.pairs):
-        a, b, _ = make_pair(1, i, size=args.size)
+        a, b, _ = make_pair(args.config, i, size=args.size)
         imgs.append((torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)))
     torch.cuda.synchronize()
-    print(f"[bench] {args.pairs} pairs {args.size}x{args.size} resident; timing fp32", file=sys.stderr, flush=True)
-    fp32 = time_form(r2, torch, imgs, args, r2.PREC_FP32)
-    print(f"[bench] fp32 {fp32['pairs_per_s']:.1f} pairs/s; timing mixed", file=sys.stderr, flush=True)
-    mixed = time_form(r2, torch, imgs, args, r2.PREC_BF16)
-    print(f"[bench] mixed {mixed['pairs_per_s']:.1f} pairs/s; profiling stages", file=sys.stderr, flush=True)
-    stages = profile_stages(r2, torch, fp32["pipe"], imgs, args.profile_steps)
-    stages_mixed = profile_stages(r2, torch, mixed["pipe"], imgs, args.profile_steps)
-    pc = fp32["pipe"].pc
+    in_type = "u16 (12-bit)" if imgs[0][0].dtype != torch.uint8 else "u8"
+    print(f"[bench] {args.pairs} pairs {args.size}x{args.size} {in_type} resident", file=sys.stderr, flush=True)
+    timed = {}
+    for f in forms:
+        print(f"[bench] timing {f}", file=sys.stderr, flush=True)
+        timed[f] = time_form(r2, torch, imgs, args, prec[f])
+        print(f"[bench] {f} {timed[f]['pairs_per_s']:.1f} pairs/s", file=sys.stderr, flush=True)
+    print("[bench] profiling stages", file=sys.stderr, flush=True)
+    stages = {f: profile_stages(r2, torch, timed[f]["pipe"], imgs, args.profile_steps) for f in forms}
+    main_form = forms[0]
+    d = args.n_orient * 36
     # matching GEMM utilisation (flops of the last pair's actual row counts)
-    n_a, n_b = fp32["last_pair"]["descriptor_rows"]
-    d = 216
-    roof = roofline(stages, args.size, args.size, pc.n_scales, pc.n_orient, n_a, n_b, d)
+    n_a, n_b = timed[main_form]["last_pair"]["descriptor_rows"]
     gemm_flop = 2.0 * n_a * n_b * d
-    mfma = {
-        "fp32_tflops": round(gemm_flop / (stages["match_gemm"]["ms_avg"] * 1e-3) / 1e12, 2),
-        "fp32_frac": round(gemm_flop / (stages["match_gemm"]["ms_avg"] * 1e-3) / (FP32_MFMA_PEAK_TFLOPS * 1e12), 4),
-        "bf16_tflops": round(gemm_flop / (stages_mixed["match_gemm"]["ms_avg"] * 1e-3) / 1e12, 2),
-        "bf16_frac": round(gemm_flop / (stages_mixed["match_gemm"]["ms_avg"] * 1e-3) / (BF16_MFMA_PEAK_TFLOPS * 1e12), 4),
-    }
+    roof = roofline(stages[main_form], args.size, args.size, args.n_scales, args.n_orient, n_a, n_b, d,
+                    peak[main_form])
+    mfma = {}
+    for f in forms:
+        t = stages[f]["match_gemm"]["ms_avg"] * 1e-3
+        mfma[f] = {"tflops": round(gemm_flop / t / 1e12, 2), "frac": round(gemm_flop / t / (peak[f] * 1e12), 4),
+                   "peak_tflops": peak[f]}
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and args.config == 1:
         print("[bench] cpu oracle baseline", file=sys.stderr, flush=True)
         cpu = cpu_baseline(args.size, args.keypoints)
+    head = timed[main_form]
+    metric = ("image pairs/s + p50/p99 latency (1024^2 pair, 5k kpts); mixed vs plain FP32" if args.config == 1 else
+              f"image pairs/s + p50/p99 latency ({args.size}^2 pair, {args.keypoints} kpts); " + " vs ".join(forms))
     line = {
-        "metric": "image pairs/s + p50/p99 latency (1024^2 pair, 5k kpts); mixed vs plain FP32",
-        "value": round(fp32["pairs_per_s"], 2),
+        "metric": metric,
+        "value": round(head["pairs_per_s"], 2),
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(fp32["ms_per_step"], 4),
-        "p50_ms": round(fp32["p50_ms"], 4),
-        "p99_ms": round(fp32["p99_ms"], 4),
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "p50_ms": round(head["p50_ms"], 4),
+        "p99_ms": round(head["p99_ms"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {"fp32": "f32", "bf16": "f32 filter + bf16 matching", "fp8": "f32 filter + fp8 matching"}[main_form],
         "data": "synthetic",
         "config": {
-            "workload": f"RIFT2 pair {args.size}x{args.size} u8, N_s=4 N_o=6, <= {args.keypoints} FAST kpts/image, "
-                        f"216-d descriptors, exhaustive NN + ratio 0.9",
+            "workload": f"RIFT2 pair {args.size}x{args.size} {in_type}, N_s={args.n_scales} N_o={args.n_orient}, "
+                        f"<= {args.keypoints} FAST kpts/image, {d}-d descriptors, exhaustive NN + ratio 0.9",
             "pairs": args.pairs,
             "graph": not args.no_graph,
             "streams_per_pair": 1 if args.serial else 2,
             "pairs_in_flight": max(1, args.slots),
-            "last_pair": fp32["last_pair"],
-        },
-        "mixed": {
-            "value": round(mixed["pairs_per_s"], 2),
-            "dtype": "f32 filter + bf16 matching (exact on counts)",
-            "ms_per_step": round(mixed["ms_per_step"], 4),
-            "p50_ms": round(mixed["p50_ms"], 4),
-            "p99_ms": round(mixed["p99_ms"], 4),
-            "speedup_vs_fp32": round(mixed["pairs_per_s"] / fp32["pairs_per_s"], 4),
+            "last_pair": head["last_pair"],
         },
         "roofline": roof,
         "mfma": mfma,
-        "stages_ms": {k: round(v["ms_avg"], 5) for k, v in stages.items()},
-        "stages_ms_mixed": {k: round(v["ms_avg"], 5) for k, v in stages_mixed.items()},
+        "stages_ms": {f: {k: round(v["ms_avg"], 5) for k, v in stages[f].items()} for f in forms},
         "cpu_baseline": cpu,
     }
+    for f in forms[1:]:
+        t = timed[f]
+        key = "mixed" if (args.config == 1 and f == "bf16") else f
+        line[key] = {
+            "value": round(t["pairs_per_s"], 2),
+            "dtype": {"fp32": "f32", "bf16": "f32 filter + bf16 matching (exact on counts)",
+                      "fp8": "f32 filter + fp8 candidates + exact re-rank"}[f],
+            "ms_per_step": round(t["ms_per_step"], 4),
+            "p50_ms": round(t["p50_ms"], 4),
+            "p99_ms": round(t["p99_ms"], 4),
+            f"speedup_vs_{main_form}": round(t["pairs_per_s"] / head["pairs_per_s"], 4),
+        }
     print(json.dumps(line))
 
 
