@@ -1,0 +1,229 @@
+"""Parity at the benchmark workloads' full sizes, in the configuration bench.py times.
+
+The whole pair runs as a replayed graph on resident buffers (PairPipeline,
+as in bench.py).  The oracle then checks what it can afford at that size:
+
+* 1024^2 / 5000 keypoints and 2048^2 / 20000 keypoints: the full FP64 filter
+  bank / MIM / moments; detection bit-exact on the GPU's own moment map;
+  descriptors bit-exact for a seeded sample of 400 keypoints on the GPU's own
+  MIM; FP32 and BF16 matches bit-exact for a seeded sample of 300 A keypoints
+  (every row of a sampled keypoint against every B row).
+* 4096^2 12-bit, N_s = 5, N_o = 8, 50000 keypoints: amplitude sums and MIM
+  at 8 sampled pixels (each response evaluated as its inverse-DFT sum at that
+  pixel), detection bit-exact, 400 sampled descriptors bit-exact, and the FP8
+  form's match agreement with the exact decision on 300 sampled keypoints.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from oracle import detect, describe, filterbank, match  # noqa: E402
+from synth import make_pair  # noqa: E402
+from synth.gen import CONFIGS  # noqa: E402
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2303_00319_amd as r2
+
+    return r2, torch.device("cuda:0")
+
+
+_pairs = {}
+
+
+def _pair(config):
+    """Image A of the workload and a shifted, intensity-inverted copy: the descriptor grid is
+    axis-aligned, so a rotation-free pair gives many matches to compare."""
+    if config not in _pairs:
+        import synth.gen as g
+
+        cfg = CONFIGS[config]
+        a, _, _ = make_pair(config, 0)
+        v = float(cfg.vmax)
+        b = g._warp_bilinear(a.astype(np.float64), 0.0, 7.0, 4.0)
+        b = np.rint(np.clip(v * np.power(np.clip((v - b) / v, 0, 1), 0.5), 0, v)).astype(a.dtype)
+        _pairs[config] = (a, b)
+    return _pairs[config]
+
+
+def _run_pipeline(r2, dev, config, precision, want_amp=False):
+    cfg = CONFIGS[config]
+    a, b = _pair(config)
+    pc, det, dp, mp = r2.defaults()
+    pc.n_scales, pc.n_orient = cfg.n_scales, cfg.n_orient
+    dp.n_orient = cfg.n_orient
+    det.max_keypoints = cfg.max_keypoints
+    mp.precision = precision
+    ta, tb = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+    pipe = r2.PairPipeline(cfg.size, cfg.size, pc, det, dp, mp)
+    g = pipe.capture(ta, tb)
+    g.replay()
+    torch.cuda.synchronize()
+    return a, b, pipe, (pc, det, dp, mp)
+
+
+def _image_outputs(buf):
+    nk = int(buf.nk.item())
+    nd = int(buf.nd.item())
+    return {
+        "M": buf.M.cpu().numpy(),
+        "mim": buf.mim.cpu().numpy(),
+        "kpts": buf.kpts[:nk].cpu().numpy(),
+        "desc": buf.desc[:nd].cpu().numpy().astype(np.uint16),
+        "inv": buf.inv[:nd].cpu().numpy(),
+        "dkp": buf.dkp[:nd].cpu().numpy(),
+    }
+
+
+def _check_detect(out, k):
+    kp_ref, sc_ref = detect.detect(out["M"], oracle.DetectParams(max_keypoints=k), dtype=np.float32)
+    got = out["kpts"]
+    assert len(got) == len(kp_ref), f"{len(got)} vs {len(kp_ref)} keypoints"
+    assert np.array_equal(got[:, :2], kp_ref), "keypoint positions / order differ"
+    assert np.array_equal(got[:, 2].view(np.float32), sc_ref.astype(np.float32)), "scores differ"
+
+
+def _rows_of(out, i, n):
+    """GPU rows of keypoint i: its primary row, then its secondary row if any."""
+    rows = [i]
+    sec = np.nonzero(out["dkp"][n:] == i)[0]
+    rows += [n + int(r) for r in sec]
+    return rows
+
+
+def _check_describe(out, n_orient, rng, samples=400):
+    n = len(out["kpts"])
+    pick = np.sort(rng.choice(n, size=min(samples, n), replace=False))
+    c_ref, k_ref, _ = describe.describe(out["mim"], out["kpts"][pick, :2], oracle.DescParams(n_orient=n_orient))
+    for r in range(len(c_ref)):
+        i = int(pick[k_ref[r]])
+        rows = _rows_of(out, i, n)
+        which = 0 if r < len(pick) else 1
+        assert len(rows) > which, f"keypoint {i}: missing secondary row"
+        assert np.array_equal(out["desc"][rows[which]], c_ref[r]), f"keypoint {i}: counts differ"
+    n_sec_ref = len(c_ref) - len(pick)
+    n_sec_gpu = sum(len(_rows_of(out, int(i), n)) - 1 for i in pick)
+    assert n_sec_ref == n_sec_gpu
+    inv_ref = match.inv_norms(c_ref, np.float32)
+    for r in range(len(pick)):
+        assert out["inv"][int(pick[r])] == inv_ref[r]
+
+
+def _sampled_match(oa, ob, rng, samples=300, dtype=np.float32):
+    """Oracle matches of a sample of A keypoints (all their rows) against every B row."""
+    n = len(oa["kpts"])
+    pick = np.sort(rng.choice(n, size=min(samples, n), replace=False))
+    rows = sorted(r for i in pick for r in _rows_of(oa, int(i), n))
+    ca = oa["desc"][rows]
+    ka = oa["dkp"][rows]
+    return set(int(i) for i in pick), match.match(ca, ka, ob["desc"], ob["dkp"], dtype=dtype)
+
+
+def _gpu_matches(pipe, keys):
+    n = int(pipe.n_out.item())
+    o = pipe.out[:n].cpu().numpy()
+    sel = [r for r in o if int(r[0]) in keys]
+    return {(int(r[0]), int(r[1])): int(r[2]) for r in sel}
+
+
+@pytest.mark.parametrize("config", [1, 2])
+def test_full_size_pair(config):
+    r2, dev = _gpu()
+    cfg = CONFIGS[config]
+    print(f"[full size] config {config}: {cfg.size}^2, K={cfg.max_keypoints}", flush=True)
+    a, b, pipe, (pc, det, dp, mp) = _run_pipeline(r2, dev, config, r2.PREC_FP32)
+    oa, ob = _image_outputs(pipe.a), _image_outputs(pipe.b)
+    # filter bank / MIM / moments against the full FP64 oracle
+    ref = filterbank.filter_mim(a, oracle.PCParams(), keep_amp=True)
+    ra = ref["amp"]
+    mim_agree = (oa["mim"] == ref["mim"]).mean()
+    srt = np.sort(ra, axis=0)
+    gap = (srt[-1] - srt[-2]) / np.maximum(srt[-1], np.sqrt(np.mean(ra * ra)))
+    diff = oa["mim"] != ref["mim"]
+    assert mim_agree >= 0.999, mim_agree
+    if diff.any():
+        assert gap[diff].max() < 1e-4
+    merr = np.abs(oa["M"].astype(np.float64) - ref["M"]).max() / ref["M"].max()
+    assert merr <= 2e-3, merr
+    print(f"  MIM agreement {mim_agree:.6f}, max moment rel err {merr:.2e}", flush=True)
+    for out in (oa, ob):
+        _check_detect(out, cfg.max_keypoints)
+    rng = np.random.default_rng(config)
+    _check_describe(oa, cfg.n_orient, rng)
+    keys, ref_m = _sampled_match(oa, ob, rng)
+    want = {(int(x), int(y)): int(np.float32(d).view(np.int32)) for x, y, d in zip(*ref_m)}
+    got = _gpu_matches(pipe, keys)
+    assert len(want) > 20, "too few sampled matches to compare"
+    assert got == want, f"FP32 matches differ on the sample ({len(got)} vs {len(want)})"
+    # the BF16 form on the same descriptors
+    _, _, pipe16, _ = _run_pipeline(r2, dev, config, r2.PREC_BF16)
+    assert _gpu_matches(pipe16, keys) == want, "BF16 matches differ on the sample"
+    print(f"  detect / describe / match exact; sampled matches {len(want)}", flush=True)
+
+
+def _responses_at(img, pixels, p):
+    """A_o (sum over scales of |EO_{s,o}|) at a few pixels, each EO as its inverse-DFT sum."""
+    h, w = img.shape
+    spec = filterbank.spectrum(img)
+    v, u, nyq = filterbank.frequency_grid(h, w)
+    r = np.sqrt(u * u + v * v)
+    theta = np.arctan2(-v, u)
+    low = filterbank.lowpass_factor(r, p)
+    ys = np.array([y for y, _ in pixels])
+    xs = np.array([x for _, x in pixels])
+    ey = np.exp(2j * np.pi * np.outer(np.arange(h), ys) / h)  # (H, n)
+    ex = np.exp(2j * np.pi * np.outer(np.arange(w), xs) / w)  # (W, n)
+    amp = np.zeros((p.n_orient, len(pixels)))
+    radial = [filterbank.radial_factor(r, s, p) for s in range(p.n_scales)]
+    for o in range(p.n_orient):
+        ang = filterbank.angular_factor(theta, o, p)
+        for s in range(p.n_scales):
+            g = radial[s] * low * ang
+            g[0, 0] = 0.0
+            g[nyq] = 0.0
+            sg = spec * g
+            eo = np.einsum("kn,kn->n", ey, sg @ ex) / (h * w)
+            amp[o] += np.abs(eo)
+    return amp
+
+
+def test_full_size_large_fp8():
+    r2, dev = _gpu()
+    cfg = CONFIGS[4]
+    print(f"[full size] config 4: {cfg.size}^2 12-bit, N_s={cfg.n_scales} N_o={cfg.n_orient}, K={cfg.max_keypoints}",
+          flush=True)
+    a, b, pipe, (pc, det, dp, mp) = _run_pipeline(r2, dev, 4, r2.PREC_FP8)
+    # amplitude sums at sampled pixels: one extra GPU call with A_o kept
+    fm = r2.filter_mim(torch.from_numpy(a).to(dev), pc, want_amp=True)
+    amp_gpu = fm["amp"].cpu().numpy()
+    rng = np.random.default_rng(4)
+    pixels = [(int(y), int(x)) for y, x in zip(rng.integers(0, cfg.size, 8), rng.integers(0, cfg.size, 8))]
+    p = oracle.PCParams(n_scales=cfg.n_scales, n_orient=cfg.n_orient)
+    amp_ref = _responses_at(a, pixels, p)
+    scale = math.sqrt(float(np.mean(amp_gpu.astype(np.float64) ** 2)))
+    for i, (y, x) in enumerate(pixels):
+        got = amp_gpu[:, y, x].astype(np.float64)
+        err = np.abs(got - amp_ref[:, i]) / np.maximum(amp_ref[:, i], scale)
+        assert err.max() <= 1e-4, (y, x, err.max())
+        srt = np.sort(amp_ref[:, i])
+        if (srt[-1] - srt[-2]) / max(srt[-1], scale) > 1e-4:
+            assert int(fm["mim"][y, x].item()) == int(np.argmax(amp_ref[:, i])), (y, x)
+    assert np.array_equal(fm["mim"].cpu().numpy(), pipe.a.mim.cpu().numpy())
+    oa, ob = _image_outputs(pipe.a), _image_outputs(pipe.b)
+    _check_detect(oa, cfg.max_keypoints)
+    _check_describe(oa, cfg.n_orient, rng)
+    keys, ref_m = _sampled_match(oa, ob, rng, dtype=np.float64)
+    want = {(int(x), int(y)) for x, y in zip(ref_m[0], ref_m[1])}
+    got = set(_gpu_matches(pipe, keys))
+    jac = len(got & want) / max(1, len(got | want))
+    print(f"  amplitudes / MIM / detect / describe exact; FP8 sampled matches gpu {len(got)} oracle {len(want)} "
+          f"Jaccard {jac:.4f}", flush=True)
+    assert len(want) > 20 and jac >= 0.95
