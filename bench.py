@@ -89,6 +89,9 @@ def parse():
     ap.add_argument("--budget-gib", type=float, default=32.0, help="--serve: HBM arena for in-flight requests")
     ap.add_argument("--inflight", type=int, default=8, help="--serve: requests running at once (two streams each)")
     ap.add_argument("--pool", type=int, default=4, help="--serve: distinct resident pairs per size")
+    ap.add_argument("--serve-sizes", default=None, help="--serve: comma-separated square sizes (default: the mix)")
+    ap.add_argument("--serve-keypoints", type=int, default=0, help="--serve: keypoints per image (0: 2e-3 HW)")
+    ap.add_argument("--serve-form", default="bf16", choices=("fp32", "bf16", "fp8"), help="--serve: matching form")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB read + 256 MiB write elementwise kernel first (HBM counter scale)")
     return ap.parse_args()
@@ -262,7 +265,7 @@ def serve(args, r2, torch):
     from synth.gen import serving_sizes
 
     dev = torch.device("cuda:0")
-    sizes = serving_sizes()
+    sizes = tuple(int(x) for x in args.serve_sizes.split(",")) if args.serve_sizes else serving_sizes()
     pool = {}
     for n in sizes:
         for i in range(args.pool):
@@ -273,7 +276,8 @@ def serve(args, r2, torch):
     rng = np.random.default_rng(1_000_003 * 3)
     req_size = [int(x) for x in rng.choice(sizes, size=args.requests)]
     pc, det, dp, mp = r2.defaults()
-    mp.precision = r2.PREC_BF16
+    mp.precision = {"fp32": r2.PREC_FP32, "bf16": r2.PREC_BF16, "fp8": r2.PREC_FP8}[args.serve_form]
+    kreq = args.serve_keypoints
     results = []
     for rate in [float(x) for x in args.rates.split(",")]:
         gaps = rng.exponential(1.0 / rate, size=args.requests) if rate > 0 else np.zeros(args.requests)
@@ -281,7 +285,7 @@ def serve(args, r2, torch):
         eng = r2.Engine(int(args.budget_gib * (1 << 30)), max_inflight=args.inflight, pc=pc, det=det, dp=dp, mp=mp)
         # warm: one request of every size
         for j, n in enumerate(sizes):
-            eng.submit(-1 - j, *pool[(n, 0)])
+            eng.submit(-1 - j, *pool[(n, 0)], max_keypoints=kreq)
         eng.drain()
         torch.cuda.synchronize()
         eng.close()
@@ -295,7 +299,7 @@ def serve(args, r2, torch):
             while nxt < args.requests and arrive[nxt] <= now:
                 n = req_size[nxt]
                 a, b = pool[(n, nxt % args.pool)]
-                eng.submit(nxt, a, b)
+                eng.submit(nxt, a, b, max_keypoints=kreq)
                 arr_ms[nxt] = 1000.0 * arrive[nxt]
                 nxt += 1
             got = eng.poll()
@@ -322,11 +326,11 @@ def serve(args, r2, torch):
         "unit": "pairs/s",
         "n_gpus": 1,
         "higher_is_better": True,
-        "dtype": "f32 filter + bf16 matching (exact on counts)",
+        "dtype": f"f32 filter + {args.serve_form} matching",
         "data": "synthetic",
-        "config": {"workload": f"{args.requests} pair requests, sizes uniform over {list(sizes)}, keypoints 2e-3 HW, "
-                               f"Poisson arrivals", "budget_gib": args.budget_gib, "inflight": args.inflight,
-                   "distinct_pairs_per_size": args.pool},
+        "config": {"workload": f"{args.requests} pair requests, sizes uniform over {list(sizes)}, keypoints "
+                               f"{kreq or '2e-3 HW'}, Poisson arrivals", "budget_gib": args.budget_gib,
+                   "inflight": args.inflight, "distinct_pairs_per_size": args.pool},
         "rates": results,
     }
     print(json.dumps(line))

@@ -166,6 +166,7 @@ rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t
  * score = largest passing threshold, corner iff score > fast_threshold, 3x3
  * non-maximum suppression (ties: lower raster index wins), patch-border
  * mask, then the max_keypoints strongest by (score desc, y*W+x asc).
+ *   moment      16-byte aligned
  *   kpts        capacity det->max_keypoints, sorted strongest first
  *   n_kpts_dev  device int32: number of keypoints written */
 rift2_status rift2_detect(const float* moment, int32_t H, int32_t W, const rift2_detect_params* det,

@@ -81,7 +81,7 @@ FilterLayout filter_layout(int H, int W, const rift2_pc_params* p) {
 }
 
 struct DetectLayout {
-  size_t hdr, hist, tile_cnt, cand, sel_cnt, sel, fin, part, total;
+  size_t hdr, mm, hist, tile_cnt, cand, sel_cnt, sel, fin, part, total;
   int n_tiles, n_part;
   uint32_t region;
 };
@@ -91,8 +91,9 @@ DetectLayout detect_layout(int H, int W, const rift2_detect_params* d) {
   Carver c;
   L.n_tiles = ((W + kTileX - 1) / kTileX) * ((H + kTileY - 1) / kTileY);
   const size_t slots = (size_t)L.n_tiles * kTileCap;
-  L.region = (uint32_t)((slots + kSelBlocks - 1) / kSelBlocks);
+  L.region = (uint32_t)(((L.n_tiles + kSelBlocks - 1) / kSelBlocks) * kTileCap);  // k_det_select1 tiles per block
   L.hdr = c.take(64);
+  L.mm = c.take(2 * kMinMaxBlocks * sizeof(uint32_t));
   L.hist = c.take(kDetHistBins * sizeof(uint32_t));
   L.tile_cnt = c.take((size_t)L.n_tiles * sizeof(uint32_t));
   L.cand = c.take(slots * sizeof(uint64_t));
@@ -504,6 +505,7 @@ rift2_status rift2_detect(const float* moment, int32_t H, int32_t W, const rift2
                           rift2_keypoint* kpts, int32_t* n_kpts_dev, void* workspace, size_t workspace_bytes,
                           void* stream) {
   if (!moment || !det || !kpts || !n_kpts_dev || !workspace) return RIFT2_ERR_INVALID_ARG;
+  if ((uintptr_t)moment & 15u) return RIFT2_ERR_INVALID_ARG;  // 16-byte loads
   if (H < 8 || W < 8 || (int64_t)H * W >= (1ll << 31)) return RIFT2_ERR_INVALID_ARG;
   if (!(det->fast_threshold >= 0.0f) || det->max_keypoints <= 0 || det->patch_size < 0 || (det->patch_size & 1))
     return RIFT2_ERR_INVALID_ARG;
@@ -512,6 +514,7 @@ rift2_status rift2_detect(const float* moment, int32_t H, int32_t W, const rift2
   hipStream_t st = (hipStream_t)stream;
   char* ws = (char*)workspace;
   uint32_t* hdr = (uint32_t*)(ws + L.hdr);
+  uint32_t* mm = (uint32_t*)(ws + L.mm);
   uint32_t* hist = (uint32_t*)(ws + L.hist);
   uint32_t* tile_cnt = (uint32_t*)(ws + L.tile_cnt);
   uint64_t* cand = (uint64_t*)(ws + L.cand);
@@ -521,14 +524,13 @@ rift2_status rift2_detect(const float* moment, int32_t H, int32_t W, const rift2
   uint32_t* part = (uint32_t*)(ws + L.part);
   (void)hipGetLastError();
   ProfScope ps(5, st);
-  hipLaunchKernelGGL(k_det_init, dim3(kDetHistBins / 256), dim3(256), 0, st, hdr, hist);
   const int n = H * W;
-  hipLaunchKernelGGL(k_det_minmax, dim3(std::min(256, (n + 255) / 256)), dim3(256), 0, st, moment, n, hdr);
+  hipLaunchKernelGGL(k_det_minmax, dim3(kMinMaxBlocks), dim3(256), 0, st, moment, n, mm, hist);
   hipLaunchKernelGGL(k_det_fast, dim3((W + kTileX - 1) / kTileX, (H + kTileY - 1) / kTileY), dim3(kTileX * kTileY), 0, st,
-                     moment, H, W, det->fast_threshold, det->patch_size / 2, hdr, hist, tile_cnt, cand);
+                     moment, H, W, det->fast_threshold, det->patch_size / 2, mm, hist, tile_cnt, cand);
   const uint32_t kmax = (uint32_t)det->max_keypoints;
-  hipLaunchKernelGGL(k_det_select1, dim3(kSelBlocks), dim3(256), 0, st, hdr, hist, tile_cnt, L.n_tiles, cand, sel,
-                     sel_cnt, kmax);
+  hipLaunchKernelGGL(k_det_bin, dim3(1), dim3(1024), 0, st, hdr, hist, kmax);
+  hipLaunchKernelGGL(k_det_select1, dim3(kSelBlocks), dim3(256), 0, st, hdr, tile_cnt, L.n_tiles, cand, sel, sel_cnt);
   hipLaunchKernelGGL(k_det_select2, dim3(1), dim3(1024), 0, st, hdr, sel, sel_cnt, L.region, fin, kmax);
   const int blocks = (int)((kmax + 255) / 256);
   hipLaunchKernelGGL(k_det_rank, dim3(blocks, L.n_part), dim3(256), 0, st, hdr, fin, part, kmax);

@@ -1,21 +1,21 @@
 // FAST keypoint kernels (Section 2.1 of the paper; Table 1 settings).
 //
-//   k_det_init    clear counters / histogram, min-max identities
-//   k_det_minmax  global min and max of the map (order-preserving uint keys)
-//   k_det_fast    per 32x8 tile: normalise (correctly rounded FP32 division),
-//                 FAST-9 score on the 16-pixel circle, 3x3 NMS with raster
-//                 tie-break, patch-border mask; survivors appended as 64-bit
-//                 keys (score bits << 32 | ~raster) plus a histogram of the
-//                 top 16 score bits
-//   k_det_select1 score bin of rank K (block-wide prefix search), candidates
-//                 of that bin and above gathered
-//   k_det_select2 one block: exact K-th key by a 4 x 12-bit radix selection
-//                 over the boundary bin (staged in LDS), winners compacted
+//   k_det_minmax  per-block min and max of the map (order-preserving uint keys,
+//                 16-byte loads) into partials; clears the score histogram
+//   k_det_fast    per 32x8 tile: global min / max from the partials,
+//                 normalise (correctly rounded FP32 division), FAST-9 score on
+//                 the 16-pixel circle, 3x3 NMS with raster tie-break,
+//                 patch-border mask; survivors appended as 64-bit keys (score
+//                 bits << 32 | ~raster) plus a histogram of the top 16 score bits
+//   k_det_bin     one block: candidate total, score bin of rank K and the count
+//                 above it (block-wide prefix search)
+//   k_det_select1 candidates of that bin and above gathered, one wave per tile
+//   k_det_select2 one block: exact K-th key inside the boundary bin (direct
+//                 ranking of a small boundary set, else a 4 x 12-bit radix
+//                 selection), winners compacted
 //   k_det_rank    rank of every winner = number of larger keys, counted over
 //                 key chunks in parallel
 //   k_det_emit    output record at its rank
-#pragma once
-
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -27,8 +27,9 @@ constexpr int kDetHistBins = 1 << 14;  // score bits >> 16 for scores in (0, 1]
 constexpr int kTileX = 32, kTileY = 8;
 constexpr int kHalo = 4;  // FAST radius 3 + NMS 1
 
-// Header words (zeroed per call): [0] candidates, [3] winners, [4] min key,
-// [5] max key, [8] boundary bin, [9] candidates above it.
+// Header words (written per call): [0] candidates, [3] winners, [8] boundary
+// bin, [9] candidates above it.
+constexpr int kMinMaxBlocks = 256;  // == k_det_fast's block size: one partial per thread
 
 __device__ __forceinline__ uint32_t float_order_key(float f) {
   const uint32_t b = __float_as_uint(f);
@@ -39,16 +40,22 @@ __device__ __forceinline__ float float_from_order_key(uint32_t k) {
   return __uint_as_float(b);
 }
 
-__global__ void k_det_init(uint32_t* __restrict__ hdr, uint32_t* __restrict__ hist) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < kDetHistBins) hist[i] = 0u;
-  if (i < 16) hdr[i] = (i == 4) ? 0xffffffffu : 0u;
-}
-
-__global__ void __launch_bounds__(256) k_det_minmax(const float* __restrict__ d, int n, uint32_t* __restrict__ hdr) {
+__global__ void __launch_bounds__(256) k_det_minmax(const float* __restrict__ d, int n, uint32_t* __restrict__ mm,
+                                                    uint32_t* __restrict__ hist) {
   __shared__ uint32_t red[2][4];
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < kDetHistBins; i += gridDim.x * 256) hist[i] = 0u;
   uint32_t lo = 0xffffffffu, hi = 0u;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+  const int n4 = n / 4;  // the map is 16-byte aligned (checked on the host)
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n4; i += gridDim.x * 256) {
+    const float4 v = ((const float4*)d)[i];
+    const uint32_t k[4] = {float_order_key(v.x), float_order_key(v.y), float_order_key(v.z), float_order_key(v.w)};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      lo = min(lo, k[e]);
+      hi = max(hi, k[e]);
+    }
+  }
+  for (int i = 4 * n4 + blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     const uint32_t k = float_order_key(d[i]);
     lo = min(lo, k);
     hi = max(hi, k);
@@ -67,8 +74,8 @@ __global__ void __launch_bounds__(256) k_det_minmax(const float* __restrict__ d,
       lo = min(lo, red[0][w]);
       hi = max(hi, red[1][w]);
     }
-    atomicMin(&hdr[4], lo);
-    atomicMax(&hdr[5], hi);
+    mm[2 * blockIdx.x] = lo;
+    mm[2 * blockIdx.x + 1] = hi;
   }
 }
 
@@ -103,8 +110,10 @@ __device__ __forceinline__ float fast_score(const float (&c)[16], float p) {
 // suppression are never 8-neighbours.
 constexpr int kTileCap = (kTileX / 2) * (kTileY / 2);
 
+static_assert(kTileX * kTileY == kMinMaxBlocks, "one min/max partial per k_det_fast thread");
+
 __global__ void __launch_bounds__(kTileX * kTileY) k_det_fast(const float* __restrict__ d, int H, int W, float thr,
-                                                              int half_patch, const uint32_t* __restrict__ hdr,
+                                                              int half_patch, const uint32_t* __restrict__ mm,
                                                               uint32_t* __restrict__ hist, uint32_t* __restrict__ tile_cnt,
                                                               uint64_t* __restrict__ cand) {
   constexpr int LX = kTileX + 2 * kHalo, LY = kTileY + 2 * kHalo;
@@ -112,9 +121,22 @@ __global__ void __launch_bounds__(kTileX * kTileY) k_det_fast(const float* __res
   __shared__ float sd[LY][LX];
   __shared__ float ss[SY][SX];
   __shared__ uint32_t s_count;
+  __shared__ uint32_t s_red[2][4];
   const int tile = blockIdx.y * gridDim.x + blockIdx.x;
-  const float lo = float_from_order_key(hdr[4]);
-  const float hi = float_from_order_key(hdr[5]);
+  uint32_t klo = mm[2 * threadIdx.x], khi = mm[2 * threadIdx.x + 1];
+  for (int off = 32; off > 0; off >>= 1) {
+    klo = min(klo, (uint32_t)__shfl_xor((int)klo, off));
+    khi = max(khi, (uint32_t)__shfl_xor((int)khi, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_red[0][threadIdx.x >> 6] = klo;
+    s_red[1][threadIdx.x >> 6] = khi;
+  }
+  __syncthreads();
+  klo = min(min(s_red[0][0], s_red[0][1]), min(s_red[0][2], s_red[0][3]));
+  khi = max(max(s_red[1][0], s_red[1][1]), max(s_red[1][2], s_red[1][3]));
+  const float lo = float_from_order_key(klo);
+  const float hi = float_from_order_key(khi);
   if (!(hi > lo)) {  // flat map: no keypoints (uniform across the grid)
     if (threadIdx.x == 0) tile_cnt[tile] = 0u;
     return;
@@ -187,58 +209,64 @@ __global__ void __launch_bounds__(kTileX * kTileY) k_det_fast(const float* __res
   if (threadIdx.x == 0) tile_cnt[tile] = s_count;
 }
 
-// Score bin holding the K-th best candidate; every candidate of that bin and
-// above is copied into this block's region of `sel` (region b covers the
-// candidate slots block b scans, so it cannot overflow).  Block 0 publishes
-// the candidate total, the bin and the count above it in hdr[0], [8], [9].
+// One block: candidate total n, the score bin holding the candidate of rank
+// min(K, n) - 1 from the top, and the number of candidates above that bin,
+// published in hdr[0], [8], [9] (bin 0 / above 0 when every candidate wins).
 constexpr int kSelBlocks = 64;
 
-__global__ void __launch_bounds__(256) k_det_select1(uint32_t* __restrict__ hdr, const uint32_t* __restrict__ hist,
-                                                     const uint32_t* __restrict__ tile_cnt, int n_tiles,
-                                                     const uint64_t* __restrict__ cand, uint64_t* __restrict__ sel,
-                                                     uint32_t* __restrict__ sel_cnt, uint32_t kmax) {
-  __shared__ uint32_t scratch[256];
+__global__ void __launch_bounds__(1024) k_det_bin(uint32_t* __restrict__ hdr, const uint32_t* __restrict__ hist,
+                                                  uint32_t kmax) {
+  __shared__ uint32_t scratch[16];
   __shared__ int sh_bin;
-  __shared__ uint32_t sh_above, sh_total, s_count;
-  constexpr int PER = kDetHistBins / 256;
+  __shared__ uint32_t sh_above, sh_total;
+  constexpr int PER = kDetHistBins / 1024;
   uint32_t sum = 0;
+#pragma unroll
   for (int i = 0; i < PER; ++i) sum += hist[threadIdx.x * PER + i];
-  const uint32_t incl = block_inclusive_scan<256>(sum, scratch);
-  if (threadIdx.x == 255) sh_total = incl;
+  const uint32_t incl = block_inclusive_scan<1024>(sum, scratch);
+  if (threadIdx.x == 1023) sh_total = incl;
   if (threadIdx.x == 0) {
     sh_bin = 0;
     sh_above = 0;
-    s_count = 0;
   }
   __syncthreads();
   const uint32_t n = sh_total;
   const uint32_t k = min(kmax, n);
-  if (k > 0 && k < n) block_find_rank<kDetHistBins, 256, true>(hist, k - 1, &sh_bin, &sh_above, scratch);
-  const uint32_t bin = (uint32_t)sh_bin;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (k > 0 && k < n) block_find_rank<kDetHistBins, 1024, true>(hist, k - 1, &sh_bin, &sh_above, scratch);
+  if (threadIdx.x == 0) {
     hdr[0] = n;
-    hdr[8] = bin;
+    hdr[8] = (uint32_t)sh_bin;
     hdr[9] = sh_above;
   }
-  const uint32_t slots = (uint32_t)n_tiles * kTileCap;
-  const uint32_t per = (slots + gridDim.x - 1) / gridDim.x;
-  const uint32_t beg = blockIdx.x * per;
-  const uint32_t end = min(slots, beg + per);
-  uint64_t* region = sel + beg;
-  for (uint32_t f0 = beg; f0 < end; f0 += 256) {
-    const uint32_t f = f0 + threadIdx.x;
+}
+
+// Every candidate of the boundary bin and above is copied into this block's
+// region of `sel` (region b holds the slots of the tiles block b scans, so it
+// cannot overflow); one wave reads one tile's compacted candidates.
+__global__ void __launch_bounds__(256) k_det_select1(const uint32_t* __restrict__ hdr,
+                                                     const uint32_t* __restrict__ tile_cnt, int n_tiles,
+                                                     const uint64_t* __restrict__ cand, uint64_t* __restrict__ sel,
+                                                     uint32_t* __restrict__ sel_cnt) {
+  __shared__ uint32_t s_count;
+  if (threadIdx.x == 0) s_count = 0u;
+  __syncthreads();
+  const uint32_t bin = hdr[8];
+  const int per = (n_tiles + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int t0 = blockIdx.x * per;
+  const int t1 = min(n_tiles, t0 + per);
+  uint64_t* region = sel + (size_t)t0 * kTileCap;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  static_assert(kTileCap == 64, "one lane per candidate slot of a tile");
+  for (int t = t0 + wave; t < t1; t += 4) {
+    const uint32_t cnt = tile_cnt[t];
     uint64_t key = 0;
     bool take = false;
-    if (f < end) {
-      const uint32_t t = f / kTileCap, i = f % kTileCap;
-      if (i < tile_cnt[t]) {
-        key = cand[f];
-        take = (uint32_t)(key >> 48) >= bin;
-      }
+    if ((uint32_t)lane < cnt) {
+      key = cand[(size_t)t * kTileCap + lane];
+      take = (uint32_t)(key >> 48) >= bin;
     }
     const uint64_t mask = __ballot(take);
     if (mask) {
-      const int lane = threadIdx.x & 63;
       const int leader = __ffsll((unsigned long long)mask) - 1;
       uint32_t base = 0;
       if (lane == leader) base = atomicAdd(&s_count, (uint32_t)__popcll(mask));
@@ -251,6 +279,7 @@ __global__ void __launch_bounds__(256) k_det_select1(uint32_t* __restrict__ hdr,
 }
 
 constexpr int kEdgeMax = 4096;
+constexpr uint32_t kEdgeDirect = 512;  // boundary sets up to this size are ranked directly
 
 // One block of 1024 threads: exact K-th key inside the boundary bin, then the
 // winners (keys >= K-th key) compacted into `fin` (exactly min(K, n) keys,
@@ -276,6 +305,7 @@ __global__ void __launch_bounds__(1024) k_det_select2(uint32_t* __restrict__ hdr
   __shared__ uint64_t edge[kEdgeMax];
   __shared__ uint32_t pre[kSelBlocks + 1];
   __shared__ uint32_t n_edge, s_final;
+  __shared__ uint64_t s_kth;
   __shared__ int sh_b;
   __shared__ uint32_t sh_before;
   const uint32_t n = hdr[0];
@@ -308,7 +338,19 @@ __global__ void __launch_bounds__(1024) k_det_select2(uint32_t* __restrict__ hdr
     uint32_t r = k - hdr[9] - 1;  // rank from the top inside the bin
     uint64_t prefix = bin;
     int known = 16;
-    for (int lv = 0; lv < 4; ++lv) {
+    if (ne <= kEdgeDirect) {
+      // small boundary set: every key's rank among the others (the keys are distinct)
+      if (threadIdx.x < ne) {
+        const uint64_t mine = edge[threadIdx.x];
+        uint32_t above = 0;
+        for (uint32_t j = 0; j < ne; ++j) above += edge[j] > mine ? 1u : 0u;
+        if (above == r) s_kth = mine;
+      }
+      __syncthreads();
+      prefix = s_kth;
+      known = 64;
+    }
+    for (int lv = 0; lv < 4 && known < 64; ++lv) {
       const int shift = 64 - known - 12;
       for (int i = threadIdx.x; i < 4096; i += 1024) lh[i] = 0u;
       __syncthreads();
