@@ -377,10 +377,13 @@ rift2_status rift2_init(int device) {
   int prev = 0;
   if (hipGetDevice(&prev) != hipSuccess) return RIFT2_ERR_DEVICE;
   if (hipSetDevice(device) != hipSuccess) return RIFT2_ERR_DEVICE;
-  static float2 host_tw[kTwN];
-  for (int k = 0; k < kTwN; ++k) {
-    const double a = -2.0 * M_PI * (double)k / (double)kTwN;
-    host_tw[k] = make_float2((float)std::cos(a), (float)std::sin(a));
+  static float2 host_tw[kTwTotal];
+  for (int len : kTwLengths) {
+    float2* tab = host_tw + tw_offset(len);
+    for (int m = 0; m < len; ++m) {
+      const double a = -2.0 * M_PI * (double)m / (double)len;
+      tab[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
   }
   const hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(g_twiddle), host_tw, sizeof(host_tw), 0, hipMemcpyHostToDevice);
   (void)hipSetDevice(prev);

@@ -17,9 +17,20 @@
 
 namespace rift2 {
 
-// Twiddle table: e^{-2 pi i k / kTwN}; kTwN is divisible by every supported N.
-constexpr int kTwN = 12288;
-__device__ float2 g_twiddle[kTwN];
+// Twiddle tables, one per supported line length, concatenated: entry
+// tw_offset(N) + m holds e^{-2 pi i m / N}.  A length's table is contiguous,
+// so the twiddles one stage reads share cache lines.
+constexpr int kTwLengths[] = {256, 512, 768, 1024, 1536, 2048, 4096};
+__host__ __device__ constexpr int tw_offset(int n) {
+  int off = 0;
+  for (int len : kTwLengths) {
+    if (len == n) return off;
+    off += len;
+  }
+  return -1;
+}
+constexpr int kTwTotal = 256 + 512 + 768 + 1024 + 1536 + 2048 + 4096;
+__device__ float2 g_twiddle[kTwTotal];
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -191,14 +202,24 @@ constexpr int lds_line() {
   return ((N + N / 16 + 31) / 32) * 32 + (L % 32);
 }
 
+// Buffer resource word 3 for raw (untyped) buffer access on gfx9.
+constexpr int kRawBufferWord3 = 0x00020000;
+
 // Twiddle e^{DIR 2 pi i m / N}, 0 <= m < N.
 template <int DIR, int N>
-__device__ __forceinline__ float2 twiddle(int m) {
-  int idx = m * (kTwN / N);
-  // Keep the table read inside the loop that uses it: hoisting every stage's
-  // twiddles out of the filter loops costs more registers than the reloads.
-  asm volatile("" : "+v"(idx));
-  float2 w = g_twiddle[idx];
+__device__ __forceinline__ float2 twiddle(uint32_t m) {
+  static_assert(tw_offset(N) >= 0, "no twiddle table for this length");
+  // A raw buffer load: the table's base and length sit in a scalar resource
+  // and each lane supplies a 32-bit byte offset, so a hoisted offset costs no
+  // per-use address arithmetic (reads past the table would return zero).
+  // The scalar offset is opaque so the load itself stays inside the loop
+  // that uses it: hoisting every stage's twiddles out of the filter loops
+  // costs more registers than the reloads.
+  const __amdgpu_buffer_rsrc_t rsrc =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(g_twiddle + tw_offset(N)), 0, N * (int)sizeof(float2), kRawBufferWord3);
+  int soff = 0;
+  asm volatile("" : "+s"(soff));
+  float2 w = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rsrc, m * (uint32_t)sizeof(float2), soff, 0));
   if (DIR > 0) w.y = -w.y;
   return w;
 }
@@ -212,8 +233,8 @@ __device__ __forceinline__ void fft_stage(float2 (&v)[P], int t) {
 #pragma unroll
     for (int r = 0; r < R; ++r) u[r] = v[b + r * NB];
     if constexpr (NS > 1) {
-      const int jm = (t + T * b) % NS;
-      constexpr int step = N / (NS * R);
+      const uint32_t jm = (uint32_t)(t + T * b) % NS;
+      constexpr uint32_t step = N / (NS * R);
 #pragma unroll
       for (int r = 1; r < R; ++r) u[r] = cmul(u[r], twiddle<DIR, N>(r * jm * step));
     }

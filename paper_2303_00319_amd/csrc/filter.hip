@@ -42,6 +42,13 @@ struct FilterConsts {
   float inv_hw;                // 1 / (H W), folded into the filter
 };
 
+// Hardware square root and reciprocal (v_sqrt_f32 / v_rcp_f32, about 1 ulp).
+// The filter path's results carry the FP32 FFT's rounding (~1e-6 relative),
+// so the correctly rounded library forms (a dozen instructions each) buy no
+// accuracy there.
+__device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 struct PCConsts {
   float eps, g, cutoff;
   float cos_o[kMaxOrient], sin_o[kMaxOrient];
@@ -99,7 +106,7 @@ __device__ __forceinline__ float ang_lowpass(float lr, float th, bool dead, int 
   float d = th - fc.theta_o[o];
   d = d > kPi ? d - 2.0f * kPi : (d < -kPi ? d + 2.0f * kPi : d);
   const float ang = __expf(-d * d * fc.inv_2sig_theta2);
-  const float lp = 1.0f / (1.0f + __expf(fc.two_n * (lr - fc.log_lp_cutoff)));
+  const float lp = hw_rcp(1.0f + __expf(fc.two_n * (lr - fc.log_lp_cutoff)));
   return dead ? 0.0f : ang * lp * fc.inv_hw;
 }
 
@@ -217,7 +224,7 @@ __global__ void __launch_bounds__(256) k_noise_pre(float2* __restrict__ y_in, in
 #pragma unroll
   for (int m = 0; m < P; ++m) {
     eo[t + T * m] = v[m];
-    const float a = sqrtf(v[m].x * v[m].x + v[m].y * v[m].y);
+    const float a = hw_sqrt(v[m].x * v[m].x + v[m].y * v[m].y);
     dst[t + T * m] = a;
     atomicAdd(&hist[min(__float_as_uint(a) >> (32 - kHistBits1 - 1), (uint32_t)(kHist1 - 1))], 1u);
   }
@@ -413,7 +420,7 @@ __global__ void __launch_bounds__(W / P) k_pass_b_orient(const float2* __restric
     if (s > 0) fft_line<+1, W, P>(zs[s], t, line);
 #pragma unroll
     for (int m = 0; m < P; ++m) {
-      const float a = sqrtf(zs[s][m].x * zs[s][m].x + zs[s][m].y * zs[s][m].y);
+      const float a = hw_sqrt(zs[s][m].x * zs[s][m].x + zs[s][m].y * zs[s][m].y);
       sa[m] += a;
       mx[m] = __uint_as_float(max(__float_as_uint(mx[m]), __float_as_uint(a)));
     }
@@ -429,13 +436,16 @@ __global__ void __launch_bounds__(W / P) k_pass_b_orient(const float2* __restric
 #pragma unroll
     for (int s = 0; s < NS; ++s) si += fabsf(zs[s][m].y * z.x - zs[s][m].x * z.y);
     const float z2 = z.x * z.x + z.y * z.y;
-    const float xe = sqrtf(z2) + pcc.eps;
-    const float en = (z2 - si) / xe;
-    const float spread = (sa[m] / (mx[m] + pcc.eps) - 1.0f) / (float)(NS - 1);
-    const float wgt = 1.0f / (1.0f + __expf(pcc.g * (pcc.cutoff - spread)));
-    const float pc = wgt * fmaxf(en - thr, 0.0f) / (sa[m] + pcc.eps);
+    const float xe = hw_sqrt(z2) + pcc.eps;
+    const float en = (z2 - si) * hw_rcp(xe);
+    const float spread = (sa[m] * hw_rcp(mx[m] + pcc.eps) - 1.0f) * (1.0f / (float)(NS - 1));
+    const float wgt = hw_rcp(1.0f + __expf(pcc.g * (pcc.cutoff - spread)));
+    const float pc = wgt * fmaxf(en - thr, 0.0f) * hw_rcp(sa[m] + pcc.eps);
     out[T * m] = make_float2(sa[m], pc);
-    if (amp) amp[(size_t)o * plane + rowo + t + T * m] = sa[m];
+  }
+  if (amp) {
+#pragma unroll
+    for (int m = 0; m < P; ++m) amp[(size_t)o * plane + rowo + t + T * m] = sa[m];
   }
 }
 
