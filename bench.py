@@ -8,9 +8,11 @@ most 5000 keypoints per image, 6x6x6 = 216-d dominant-index descriptors,
 exhaustive matching with the 0.9 ratio test.  One step = one pair through
 every stage: filter bank / MIM / moments (x2), FAST (x2), descriptors (x2),
 matching.  Inputs are resident in HBM before timing; each pair's step is a
-replayed HIP graph.  With --slots S > 1, consecutive steps alternate between
-S buffer sets on S streams (S pairs in flight), so one pair's MFMA-bound
-matching can overlap the next pair's filter bank.
+replayed HIP graph (the two images' stages on two streams, matching after
+both).  With --pipeline the software-pipelined form is timed as well and
+reported under "pipelined": step k runs pair k's image stages while pair
+k-1's matching runs on a third stream, on alternating buffer sets; its
+p50/p99 are per-pair latencies (a pair spans two consecutive steps).
 
 Two forms are timed: plain FP32 (distance GEMM on FP32 MFMA) -- the
 reported `value` -- and mixed (BF16 MFMA on the exact integer counts, the
@@ -73,11 +75,11 @@ def parse():
     ap.add_argument("--size", type=int, default=0, help="override the image side")
     ap.add_argument("--keypoints", type=int, default=0, help="override the keypoints per image")
     ap.add_argument("--no-graph", action="store_true", help="enqueue kernels directly instead of graph replay")
-    ap.add_argument("--slots", type=int, default=1,
-                    help="pairs in flight: consecutive steps use separate buffer sets and streams, so one pair's "
-                         "matching overlaps the next pair's filter bank (1 = every step on the current stream)")
+    ap.add_argument("--pipeline", action="store_true",
+                    help="also time the software-pipelined form (pair k's image stages beside pair k-1's matching)")
     ap.add_argument("--serial", action="store_true",
-                    help="run both images' stages on one stream (no overlap; per-kernel durations for rocprofv3)")
+                    help="run both images' stages on one stream, one pair per step (no overlap; per-kernel "
+                         "durations for rocprofv3)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--serve", action="store_true",
@@ -106,37 +108,37 @@ def percentile(xs, q):
     return s[lo] + (s[hi] - s[lo]) * (k - lo)
 
 
-def time_form(r2, torch, imgs, args, precision):
+def _form_params(r2, args, precision):
     pc, det, dp, mp = r2.defaults()
     pc.n_scales, pc.n_orient = args.n_scales, args.n_orient
     dp.n_orient = args.n_orient
     det.max_keypoints = args.keypoints
     mp.precision = precision
-    slots = max(1, args.slots)
-    if len(imgs) % slots:
-        raise SystemExit("--pairs must be a multiple of --slots")
-    pipes = [r2.PairPipeline(args.size, args.size, pc, det, dp, mp, serial=args.serial) for _ in range(slots)]
-    streams = [torch.cuda.Stream() for _ in range(slots)] if slots > 1 else []
+    return pc, det, dp, mp
+
+
+def _last_pair(pipe):
+    return {"keypoints": (int(pipe.a.nk.item()), int(pipe.b.nk.item())),
+            "descriptor_rows": (int(pipe.a.nd.item()), int(pipe.b.nd.item())),
+            "matches": int(pipe.n_out.item())}
+
+
+def time_single(r2, torch, imgs, args, precision):
+    """One pair per step, nothing overlapped: a replayed graph per resident pair."""
+    pc, det, dp, mp = _form_params(r2, args, precision)
+    pipe = r2.PairPipeline(args.size, args.size, pc, det, dp, mp, serial=args.serial)
     graphs = []
     if not args.no_graph:
         for i, (a, b) in enumerate(imgs):
-            print(f"[bench] capture pair {i} on slot {i % slots}", file=sys.stderr, flush=True)
-            graphs.append(pipes[i % slots].capture(a, b))
-    print(f"[bench] warmup {args.warmup} + timed {args.steps} steps", file=sys.stderr, flush=True)
+            print(f"[bench] capture single-pair step {i}", file=sys.stderr, flush=True)
+            graphs.append(pipe.capture(a, b))
 
     def step(k):
         i = k % len(imgs)
-        if slots == 1:
-            if graphs:
-                graphs[i].replay()
-            else:
-                pipes[0].run(*imgs[i])
-            return
-        with torch.cuda.stream(streams[i % slots]):
-            if graphs:
-                graphs[i].replay()
-            else:
-                pipes[i % slots].run(*imgs[i], streams[i % slots])
+        if graphs:
+            graphs[i].replay()
+        else:
+            pipe.run(*imgs[i])
 
     for k in range(args.warmup):
         step(k)
@@ -144,25 +146,78 @@ def time_form(r2, torch, imgs, args, precision):
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t0 = time.perf_counter()
     for k in range(args.steps):
-        st = streams[(k % len(imgs)) % slots] if slots > 1 else None
-        ev[k][0].record(st)
+        ev[k][0].record()
         step(k)
-        ev[k][1].record(st)
+        ev[k][1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     lat = [s.elapsed_time(e) for s, e in ev]
-    last = pipes[((args.steps - 1) % len(imgs)) % slots]
-    n_match = int(last.n_out.item())
-    n_kp = (int(last.a.nk.item()), int(last.b.nk.item()))
-    n_desc = (int(last.a.nd.item()), int(last.b.nd.item()))
     return {
         "pairs_per_s": args.steps / wall,
         "ms_per_step": 1000.0 * wall / args.steps,
         "p50_ms": percentile(lat, 50),
         "p99_ms": percentile(lat, 99),
-        "last_pair": {"keypoints": n_kp, "descriptor_rows": n_desc, "matches": n_match},
-        "pipe": pipes[0],
+        "last_pair": _last_pair(pipe),
+        "pipe": pipe,
     }
+
+
+def time_pipelined(r2, torch, imgs, args, precision):
+    """Step k = pair k's image stages beside pair k-1's matching (PipelinedPairs)."""
+    if len(imgs) % 2:
+        raise SystemExit("--pairs must be even for the pipelined form")
+    pc, det, dp, mp = _form_params(r2, args, precision)
+    pp = r2.PipelinedPairs(args.size, args.size, pc, det, dp, mp)
+    n = len(imgs)
+    pp.step(0, *imgs[0])  # fills one buffer set; matches nothing
+    graphs = {}
+    if not args.no_graph:
+        for k in range(1, n + 1):
+            print(f"[bench] capture pipelined step {k}", file=sys.stderr, flush=True)
+            graphs[k % n] = pp.capture(k, *imgs[k % n])
+    # steps continue from n + 1 so that every step's parity matches its graph's
+    k0 = n + 1
+
+    def step(k):
+        if graphs:
+            graphs[k % n].replay()
+        else:
+            pp.step(k, *imgs[k % n])
+
+    for k in range(k0, k0 + args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    first = k0 + args.warmup
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for q in range(args.steps):
+        ev[q][0].record()
+        step(first + q)
+        ev[q][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # pair first + q: image stages in step q, matching in step q + 1
+    lat = [ev[q][0].elapsed_time(ev[q + 1][1]) for q in range(args.steps - 1)]
+    steps_ms = [s.elapsed_time(e) for s, e in ev]
+    last = first + args.steps - 1
+    return {
+        "pairs_per_s": args.steps / wall,
+        "ms_per_step": 1000.0 * wall / args.steps,
+        "p50_ms": percentile(lat, 50),
+        "p99_ms": percentile(lat, 99),
+        "step_p50_ms": percentile(steps_ms, 50),
+        "last_pair": _last_pair(pp.matched_set(last)),
+        "pipe": pp.sets[0],
+    }
+
+
+def time_form(r2, torch, imgs, args, precision):
+    single = time_single(r2, torch, imgs, args, precision)
+    single["pipelined"] = None
+    if args.pipeline and not args.serial:
+        res = time_pipelined(r2, torch, imgs, args, precision)
+        single["pipelined"] = {k: round(res[k], 4) for k in ("pairs_per_s", "ms_per_step", "p50_ms", "p99_ms")}
+    return single
 
 
 def profile_stages(r2, torch, pipe, imgs, steps):
@@ -413,6 +468,7 @@ def main():
         "ms_per_step": round(head["ms_per_step"], 4),
         "p50_ms": round(head["p50_ms"], 4),
         "p99_ms": round(head["p99_ms"], 4),
+        "pipelined": head["pipelined"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -424,7 +480,6 @@ def main():
             "pairs": args.pairs,
             "graph": not args.no_graph,
             "streams_per_pair": 1 if args.serial else 2,
-            "pairs_in_flight": max(1, args.slots),
             "last_pair": head["last_pair"],
         },
         "roofline": roof,
@@ -442,6 +497,7 @@ def main():
             "ms_per_step": round(t["ms_per_step"], 4),
             "p50_ms": round(t["p50_ms"], 4),
             "p99_ms": round(t["p99_ms"], 4),
+            "pipelined": t["pipelined"],
             f"speedup_vs_{main_form}": round(t["pairs_per_s"] / head["pairs_per_s"], 4),
         }
     print(json.dumps(line))

@@ -14,7 +14,7 @@ from ._lib import (PCParams, DetectParams, DescParams, MatchParams, PREC_FP32, P
                    Rift2Error, STAGES)
 
 __all__ = [
-    "defaults", "init", "filter_mim", "detect", "describe", "match", "Rift2Error", "PairPipeline",
+    "defaults", "init", "filter_mim", "detect", "describe", "match", "Rift2Error", "PairPipeline", "PipelinedPairs",
     "profile_enable", "profile_read", "PCParams", "DetectParams", "DescParams", "MatchParams", "Engine",
     "PREC_FP32", "PREC_BF16", "PREC_FP8", "STAGES",
 ]
@@ -254,18 +254,27 @@ class PairPipeline:
         self._side = None
         self.serial = serial
 
-    def _image(self, img, buf, stream):
+    def _filter(self, img, buf, stream):
         filter_mim_into(img, self.pc, buf.mim, buf.M, None, None, buf.ws_filter, stream)
+
+    def _keypoints(self, buf, stream):
         detect_into(buf.M, self.det, buf.kpts, buf.nk, buf.ws_detect, stream)
         describe_into(buf.mim, buf.kpts, buf.nk, self.dp, buf.desc, buf.inv, buf.dkp, buf.nd, buf.ws_desc, stream)
+
+    def _image(self, img, buf, stream):
+        self._filter(img, buf, stream)
+        self._keypoints(buf, stream)
+
+    def _match(self, stream):
+        a, b = self.a, self.b
+        match_into(a.desc, a.inv, a.dkp, a.nd, b.desc, b.inv, b.dkp, b.nd, self.mp, self.out, self.n_out,
+                   self.ws_match, stream)
 
     def run_serial(self, img_a, img_b, stream=None):
         """Every stage on one stream, in order (used to time kernels one at a time)."""
         self._image(img_a, self.a, stream)
         self._image(img_b, self.b, stream)
-        a, b = self.a, self.b
-        match_into(a.desc, a.inv, a.dkp, a.nd, b.desc, b.inv, b.dkp, b.nd, self.mp, self.out, self.n_out,
-                   self.ws_match, stream)
+        self._match(stream)
 
     def run(self, img_a, img_b, stream=None):
         """Image B's stages run on a second stream, overlapping image A's; matching waits for both."""
@@ -280,9 +289,7 @@ class PairPipeline:
         self._image(img_a, self.a, main)
         self._image(img_b, self.b, side)
         main.wait_stream(side)
-        a, b = self.a, self.b
-        match_into(a.desc, a.inv, a.dkp, a.nd, b.desc, b.inv, b.dkp, b.nd, self.mp, self.out, self.n_out,
-                   self.ws_match, main)
+        self._match(main)
 
     def capture(self, img_a, img_b):
         """Capture run() on static input buffers into a graph; replay() re-runs it."""
@@ -307,6 +314,66 @@ class PairPipeline:
         n = int(self.n_out.item())
         o = self.out[:n].cpu()
         return o
+
+
+class PipelinedPairs:
+    """Consecutive pairs overlapped: step k runs pair k's filter bank,
+    detection and description (image A and image B on two streams) while
+    pair k-1's matching runs on a third stream.
+
+    Two PairPipeline buffer sets alternate: step k writes set k % 2 and
+    matches set (k - 1) % 2, so a step never touches what the other half of
+    the same step writes.  Steps must run in order; each step completes
+    before the next one starts (both are enqueued on one stream, or replayed
+    as graphs on one stream), so step k + 1 reuses the set that step k's
+    matching read only after it is done.  After step k, set (k - 1) % 2
+    holds pair k - 1's matches.
+    """
+
+    def __init__(self, h, w, pc=None, det=None, dp=None, mp=None, device=0):
+        self.sets = [PairPipeline(h, w, pc, det, dp, mp, device) for _ in range(2)]
+        self.dev = self.sets[0].dev
+        self._side = None
+        self._mstream = None
+        self.graphs = {}
+
+    def matched_set(self, k):
+        """The buffer set holding pair k - 1's matches once step k is done."""
+        return self.sets[(k + 1) % 2]
+
+    def step(self, k, img_a, img_b, stream=None):
+        """Enqueue step k (pair k's image stages, pair k - 1's matching); k = 0 matches nothing."""
+        torch = _torch()
+        main = stream if stream is not None else torch.cuda.current_stream(self.dev)
+        if self._side is None:
+            self._side = torch.cuda.Stream(device=self.dev)
+            self._mstream = torch.cuda.Stream(device=self.dev)
+        side, ms = self._side, self._mstream
+        cur, prev = self.sets[k % 2], self.sets[(k + 1) % 2]
+        side.wait_stream(main)
+        if k > 0:
+            ms.wait_stream(main)
+            prev._match(ms)
+        cur._image(img_a, cur.a, main)
+        cur._image(img_b, cur.b, side)
+        main.wait_stream(side)
+        if k > 0:
+            main.wait_stream(ms)
+
+    def capture(self, k, img_a, img_b):
+        """Graph of step k (k >= 1) on static inputs; steps with the same parity share buffer sets."""
+        torch = _torch()
+        s = torch.cuda.Stream(device=self.dev)
+        s.wait_stream(torch.cuda.current_stream(self.dev))
+        with torch.cuda.stream(s):
+            self.step(k, img_a, img_b, s)  # warm
+        torch.cuda.current_stream(self.dev).wait_stream(s)
+        torch.cuda.synchronize(self.dev)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            self.step(k, img_a, img_b, s)
+        self.graphs[k] = g
+        return g
 
 
 # ----------------------------------------------------------------- serving engine

@@ -302,10 +302,14 @@ __global__ void __launch_bounds__(256) k_match_gemm_f32(const float* __restrict_
     if (active) {
       const float* crow = tile[0] + (lane & 31) * RS + 4 * g;
       floatx16_t acc = {};
+      // the next chunk's candidate values are read before this chunk's
+      // products, so the LDS latency hides behind four MFMAs
+      float4 cb_next = *(const float4*)crow;
 #pragma unroll
       for (int c = 0; c < KC; ++c) {
+        const float4 cb = cb_next;
+        if (c + 1 < KC) cb_next = *(const float4*)(crow + 8 * (c + 1));
         asm volatile("" : "+v"(qh[c][0]), "+v"(qh[c][1]));
-        const float4 cb = *(const float4*)(crow + 8 * c);
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.x, (float)qh[c][0].x, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.y, (float)qh[c][0].y, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.z, (float)qh[c][1].x, acc, 0, 0, 0);
