@@ -212,7 +212,7 @@ __global__ void __launch_bounds__(kTileX * kTileY) k_det_fast(const float* __res
 // One block: candidate total n, the score bin holding the candidate of rank
 // min(K, n) - 1 from the top, and the number of candidates above that bin,
 // published in hdr[0], [8], [9] (bin 0 / above 0 when every candidate wins).
-constexpr int kSelBlocks = 64;
+constexpr int kSelBlocks = 256;
 
 __global__ void __launch_bounds__(1024) k_det_bin(uint32_t* __restrict__ hdr, const uint32_t* __restrict__ hist,
                                                   uint32_t kmax) {
@@ -311,15 +311,17 @@ __global__ void __launch_bounds__(1024) k_det_select2(uint32_t* __restrict__ hdr
   const uint32_t n = hdr[0];
   const uint32_t k = min(kmax, n);
   const uint64_t bin = hdr[8];
+  static_assert(kSelBlocks <= 1024, "one region count per thread");
   if (threadIdx.x == 0) {
     n_edge = 0;
     s_final = 0;
-    uint32_t acc = 0;
-    for (int r = 0; r < kSelBlocks; ++r) {
-      pre[r] = acc;
-      acc += sel_cnt[r];
-    }
-    pre[kSelBlocks] = acc;
+  }
+  {
+    // region offsets: exclusive prefix sums of the region counts
+    const uint32_t c = threadIdx.x < kSelBlocks ? sel_cnt[threadIdx.x] : 0u;
+    const uint32_t incl = block_inclusive_scan<1024>(c, scratch);
+    if (threadIdx.x < kSelBlocks) pre[threadIdx.x] = incl - c;
+    if (threadIdx.x == kSelBlocks - 1) pre[kSelBlocks] = incl;
   }
   __syncthreads();
   const uint32_t ns = pre[kSelBlocks];
@@ -424,8 +426,16 @@ __global__ void __launch_bounds__(256) k_det_emit(const uint32_t* __restrict__ h
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (blockIdx.x == 0 && threadIdx.x == 0) *n_out = (int32_t)n;
   if (i >= n) return;
-  uint32_t rank = 0;
-  for (int s = 0; s < n_part; ++s) rank += part[(size_t)s * kmax + i];
+  // eight independent partial sums: the loads are issued together instead of
+  // one latency after another
+  uint32_t acc[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+  int s = 0;
+  for (; s + 8 <= n_part; s += 8) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc[e] += part[(size_t)(s + e) * kmax + i];
+  }
+  for (; s < n_part; ++s) acc[0] += part[(size_t)s * kmax + i];
+  const uint32_t rank = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   const uint64_t key = fin[i];
   const uint32_t raster = ~(uint32_t)(key & 0xffffffffu);
   KeypointOut kp;
