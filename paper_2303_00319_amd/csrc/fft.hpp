@@ -293,6 +293,82 @@ __device__ __forceinline__ void fft_run(float2 (&v)[PL::P], int t, float2* line)
   }
 }
 
+// Two lines of one team transformed together: each stage's butterflies of
+// both lines (twiddles read once), then one exchange for both, so the lines
+// share every barrier and the wave has two independent chains to issue.
+template <int DIR, int N, int T, int P, int R, int NS>
+__device__ __forceinline__ void fft_stage2(float2 (&v0)[P], float2 (&v1)[P], int t) {
+  constexpr int NB = P / R;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    float2 u0[R], u1[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      u0[r] = v0[b + r * NB];
+      u1[r] = v1[b + r * NB];
+    }
+    if constexpr (NS > 1) {
+      const uint32_t jm = (uint32_t)(t + T * b) % NS;
+      constexpr uint32_t step = N / (NS * R);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const float2 w = twiddle<DIR, N>(r * jm * step);
+        u0[r] = cmul(u0[r], w);
+        u1[r] = cmul(u1[r], w);
+      }
+    }
+    dft<DIR, R>(u0);
+    dft<DIR, R>(u1);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      v0[b + r * NB] = u0[r];
+      v1[b + r * NB] = u1[r];
+    }
+  }
+}
+
+template <int N, int T, int P, int R, int NS, bool WAVE>
+__device__ __forceinline__ void fft_exchange2(float2 (&v0)[P], float2 (&v1)[P], int t, float2* l0, float2* l1) {
+  constexpr int NB = P / R;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = t + T * b;
+    const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      l0[lds_pad(base + r * NS)] = v0[b + r * NB];
+      l1[lds_pad(base + r * NS)] = v1[b + r * NB];
+    }
+  }
+  team_sync<WAVE>();
+#pragma unroll
+  for (int m = 0; m < P; ++m) {
+    v0[m] = l0[lds_pad(t + T * m)];
+    v1[m] = l1[lds_pad(t + T * m)];
+  }
+  team_sync<WAVE>();
+}
+
+template <int DIR, class PL, int S, int NS, bool WAVE>
+__device__ __forceinline__ void fft_run2(float2 (&v0)[PL::P], float2 (&v1)[PL::P], int t, float2* l0, float2* l1) {
+  if constexpr (S < PL::NR) {
+    constexpr int R = PL::rad(S);
+    fft_stage2<DIR, PL::N, PL::T, PL::P, R, NS>(v0, v1, t);
+    if constexpr (S + 1 < PL::NR) {
+      fft_exchange2<PL::N, PL::T, PL::P, R, NS, WAVE>(v0, v1, t, l0, l1);
+      fft_run2<DIR, PL, S + 1, NS * R, WAVE>(v0, v1, t, l0, l1);
+    }
+  }
+}
+
+// Two lines of one team (each with its own LDS line of lds_line<N>() points);
+// the same contract as fft_line otherwise.
+template <int DIR, int N, int P, bool WAVE = false>
+__device__ __forceinline__ void fft_line2(float2 (&v0)[P], float2 (&v1)[P], int t, float2* l0, float2* l1) {
+  static_assert(!WAVE || N / P == 64, "a wave team is 64 threads");
+  fft_run2<DIR, FftPlan<N, P>, 0, 1, WAVE>(v0, v1, t, l0, l1);
+}
+
 // Transform one line in the strided layout; `line` is this team's LDS line of
 // lds_line<N>() points.  With WAVE = false every thread of the block must
 // call this (it contains block barriers); with WAVE = true the team is one

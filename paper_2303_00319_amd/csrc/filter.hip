@@ -72,7 +72,8 @@ __global__ void __launch_bounds__(256) k_fwd_rows(const Tin* __restrict__ img, i
   float2 v[P];
 #pragma unroll
   for (int m = 0; m < P; ++m) v[m] = make_float2((float)row[t + T * m], 0.0f);
-  fft_line<-1, W, P>(v, t, lines[team]);
+  // a team that is exactly one wave exchanges with wave barriers only
+  fft_line<-1, W, P, T == 64>(v, t, lines[team]);
   float2* out = rrow + (size_t)y * W;
 #pragma unroll
   for (int m = 0; m < P; ++m) out[t + T * m] = v[m];
@@ -210,6 +211,7 @@ __global__ void __launch_bounds__(256) k_noise_pre(float2* __restrict__ y_in, in
   __shared__ uint32_t hist[kHist1];
   const int o = blockIdx.y;
   for (int i = threadIdx.x; i < kHist1; i += 256) hist[i] = 0u;
+  __syncthreads();  // the cleared histogram is visible before any wave adds to it
   const int team = threadIdx.x / T, t = threadIdx.x % T;
   const int y = blockIdx.x * LINES + team;
   const size_t plane = (size_t)H * W;
@@ -217,7 +219,7 @@ __global__ void __launch_bounds__(256) k_noise_pre(float2* __restrict__ y_in, in
   float2 v[P];
 #pragma unroll
   for (int m = 0; m < P; ++m) v[m] = src[t + T * m];
-  fft_line<+1, W, P>(v, t, lines[team]);  // contains barriers: hist init is visible after
+  fft_line<+1, W, P, T == 64>(v, t, lines[team]);  // one-wave teams: wave barriers only
   float* dst = a0 + (size_t)o * plane + (size_t)y * W;
   // the transformed row replaces its input: pass B takes EO_{0,o} as is
   float2* eo = src;
@@ -399,7 +401,10 @@ __global__ void __launch_bounds__(W / P) k_pass_b_orient(const float2* __restric
                                                          const float* __restrict__ t_o, float2* __restrict__ spc,
                                                          float* __restrict__ amp) {
   constexpr int T = W / P;
-  __shared__ float2 line[lds_line<W, T>()];
+  // scales past the first are transformed two at a time (shared exchanges)
+  // where the second LDS line leaves the occupancy alone
+  constexpr bool PAIR = W <= 2048;
+  __shared__ float2 line[PAIR ? 2 : 1][lds_line<W, T>()];
   const int t = threadIdx.x;
   const int y = blockIdx.x, o = blockIdx.y;
   const size_t plane = (size_t)H * W;
@@ -407,17 +412,25 @@ __global__ void __launch_bounds__(W / P) k_pass_b_orient(const float2* __restric
   const float2* base = y_in + (size_t)(o * NS) * plane + rowo + t;
   float2 zs[NS][P];
 #pragma unroll
-  for (int m = 0; m < P; ++m) zs[0][m] = base[T * m];
+  for (int s = 0; s < NS; ++s) {
+#pragma unroll
+    for (int m = 0; m < P; ++m) zs[s][m] = base[(size_t)s * plane + T * m];
+  }
+#pragma unroll
+  for (int s = 1; s < NS; s += PAIR ? 2 : 1) {
+    if constexpr (PAIR) {
+      if (s + 1 < NS) {
+        fft_line2<+1, W, P>(zs[s], zs[s + 1], t, line[0], line[PAIR ? 1 : 0]);
+        continue;
+      }
+    }
+    fft_line<+1, W, P>(zs[s], t, line[0]);
+  }
   float sa[P], mx[P];
 #pragma unroll
   for (int m = 0; m < P; ++m) sa[m] = mx[m] = 0.0f;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    if (s + 1 < NS) {
-#pragma unroll
-      for (int m = 0; m < P; ++m) zs[s + 1][m] = base[(size_t)(s + 1) * plane + T * m];
-    }
-    if (s > 0) fft_line<+1, W, P>(zs[s], t, line);
 #pragma unroll
     for (int m = 0; m < P; ++m) {
       const float a = hw_sqrt(zs[s][m].x * zs[s][m].x + zs[s][m].y * zs[s][m].y);
