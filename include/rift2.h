@@ -205,6 +205,74 @@ rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32
                          int32_t cap_b, int32_t D, const rift2_match_params* mp, rift2_correspondence* out,
                          int32_t* n_out_dev, void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---------------------------------------------------------------- outlier removal
+ * The putative matches are filtered by RANSAC (Section 1 and Fig. 1 name
+ * RANSAC, Fischler and Bolles 1981, as the step after matching), here over
+ * the similarity model u = a x - b y + tx, v = b x + a y + ty (the class of
+ * a rotation plus a translation, which the paper's image pairs differ by).
+ * Section 4 counts a match as correct when its residual under the
+ * ground-truth transform is below 3 pixels; rift2_consensus computes that
+ * count and the inliers' squared residuals for any given model.
+ *
+ * Matches are rift2_correspondence records (as rift2_match writes them)
+ * whose kp_a / kp_b index the keypoint tables kpts_a / kpts_b (as
+ * rift2_detect writes them); a descriptor row's keypoint index is what
+ * rift2_match reports.  Coordinates must lie in [0, 8192), keypoint indices
+ * in [0, kpt_cap); a list that breaks this is treated as empty and its
+ * result carries status RIFT2_ERR_INVALID_ARG.  Every floating-point step is
+ * one IEEE double operation in a fixed order, so counts, model and mask are
+ * reproducible bit for bit. */
+typedef struct {
+  double threshold; /* inlier iff squared residual < threshold^2 (pixels); Section 4 uses 3 */
+  int32_t refine;   /* least-squares refits of the chosen hypothesis, 0..16 */
+} rift2_ransac_params;
+
+typedef struct {
+  double a, b, tx, ty; /* final model (all 0 when best < 0) */
+  int32_t best;        /* chosen hypothesis, -1 when none has a model */
+  int32_t n_inliers;   /* consensus-set size of the final model */
+  int32_t n_matches;   /* number of matches used (0 for an invalid list) */
+  int32_t status;      /* RIFT2_OK or RIFT2_ERR_INVALID_ARG (see above) */
+} rift2_similarity;
+
+typedef struct {
+  int32_t n_inliers; /* matches with squared residual < threshold^2 */
+  int32_t status;    /* RIFT2_OK or RIFT2_ERR_INVALID_ARG */
+  double sum_sq;     /* sum of the inliers' squared residuals (RMSE = sqrt(sum_sq / n_inliers)) */
+} rift2_consensus_result;
+
+/* Workspace of rift2_ransac / rift2_consensus (0 if the arguments are out of range). */
+size_t rift2_ransac_workspace_size(int32_t match_cap, int32_t n_hyp);
+
+/* RANSAC over the first *n_matches_dev matches (at most match_cap <= 131072):
+ *  1. hypothesis h (0 <= h < n_hyp <= 2^20) samples matches
+ *     i = floor(u * N / 2^32) for its two uniform words u = words[2h],
+ *     words[2h + 1] (device uint32, drawn by the caller) and fits the
+ *     similarity to them exactly: (a + ib) = (w2 - w1) / (z2 - z1),
+ *     t = w1 - (a + ib) z1 with z = x + iy in A and w in B;
+ *  2. counts[h] = #{matches with squared residual < threshold^2}, or -1 when
+ *     z1 = z2 or N < 2;
+ *  3. the hypothesis with the largest count wins (lowest h on ties);
+ *  4. `refine` times: least-squares fit to the current consensus set, then
+ *     the set is recomputed (stops early when the set has no unique fit).
+ *   counts       device int32 [n_hyp], or NULL (kept in the workspace)
+ *   inlier_mask  device uint8 [match_cap]: 1 for the final consensus set
+ *   result       device rift2_similarity */
+rift2_status rift2_ransac(const rift2_correspondence* matches, const int32_t* n_matches_dev, int32_t match_cap,
+                          const rift2_keypoint* kpts_a, int32_t kpt_cap_a, const rift2_keypoint* kpts_b,
+                          int32_t kpt_cap_b, const uint32_t* words, int32_t n_hyp, const rift2_ransac_params* rp,
+                          int32_t* counts, uint8_t* inlier_mask, rift2_similarity* result, void* workspace,
+                          size_t workspace_bytes, void* stream);
+
+/* Consensus of the model (a, b, tx, ty) read from `model` (device, 4
+ * doubles; a rift2_similarity's first four fields qualify) over the first
+ * *n_matches_dev matches: mask (device uint8 [match_cap], may be NULL) and
+ * result (device).  sum_sq is accumulated in a fixed order. */
+rift2_status rift2_consensus(const double* model, const rift2_correspondence* matches, const int32_t* n_matches_dev,
+                             int32_t match_cap, const rift2_keypoint* kpts_a, int32_t kpt_cap_a,
+                             const rift2_keypoint* kpts_b, int32_t kpt_cap_b, double threshold, uint8_t* mask,
+                             rift2_consensus_result* result, void* workspace, size_t workspace_bytes, void* stream);
+
 /* ---------------------------------------------------------------- serving
  * Continuous batching of image-pair requests of mixed sizes (the paper
  * times one pair at a time; this serves a stream of them).  Requests wait in
@@ -271,9 +339,10 @@ rift2_status rift2_engine_destroy(rift2_engine* e);
  * sums + phase congruency per orientation, 5 detect (all kernels),
  * 6 describe (all kernels), 7 match table preparation, 8 match distance
  * GEMM + top-k, 9 match merge / ratio test / output, 10 per-pixel reduction
- * over orientations (MIM, moments).  rift2_profile_read waits for the
- * recorded events, adds the elapsed milliseconds and the number of launches
- * per group into ms[group] and count[group] (arrays of n_groups >= 11 host
+ * over orientations (MIM, moments), 11 outlier removal / consensus.
+ * rift2_profile_read waits for the recorded events, adds the elapsed
+ * milliseconds and the number of launches per group into ms[group] and
+ * count[group] (arrays of n_groups >= 12 host
  * elements), forgets them and returns the number of groups.  Events are
  * owned by the library; enabling on one thread while another computes is
  * not supported. */

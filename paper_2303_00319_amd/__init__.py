@@ -10,13 +10,14 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (PCParams, DetectParams, DescParams, MatchParams, PREC_FP32, PREC_BF16, PREC_FP8,  # noqa: F401
-                   Rift2Error, STAGES)
+from ._lib import (PCParams, DetectParams, DescParams, MatchParams, RansacParams, PREC_FP32, PREC_BF16,  # noqa: F401
+                   PREC_FP8, Rift2Error, STAGES)
 
 __all__ = [
     "defaults", "init", "filter_mim", "detect", "describe", "match", "Rift2Error", "PairPipeline", "PipelinedPairs",
     "profile_enable", "profile_read", "PCParams", "DetectParams", "DescParams", "MatchParams", "Engine",
-    "PREC_FP32", "PREC_BF16", "PREC_FP8", "STAGES",
+    "PREC_FP32", "PREC_BF16", "PREC_FP8", "STAGES", "RansacParams", "ransac", "consensus", "ransac_workspace_bytes",
+    "SIMILARITY_BYTES", "CONSENSUS_BYTES", "similarity_fields", "consensus_fields",
 ]
 
 
@@ -90,6 +91,13 @@ def match_workspace_bytes(cap_a, cap_b, d, mp):
     return n
 
 
+def ransac_workspace_bytes(match_cap, n_hyp):
+    n = _lib.load().rift2_ransac_workspace_size(match_cap, n_hyp)
+    if n == 0:
+        raise Rift2Error(_lib.ERR_UNSUPPORTED, "rift2_ransac_workspace_size")
+    return n
+
+
 # ----------------------------------------------------------------- calls on caller buffers
 
 def filter_mim_into(img, pc, mim, mmax, mmin, amp, ws, stream=None):
@@ -124,6 +132,25 @@ def match_into(desc_a, inv_a, kp_a, n_a, desc_b, inv_b, kp_b, n_b, mp, out, n_ou
                          _ptr(kp_b), _ptr(n_b), desc_b.shape[0], d, ctypes.byref(mp), _ptr(out), _ptr(n_out),
                          _ptr(ws), _nbytes(ws), _stream(stream))
     _lib.check(st, "rift2_match")
+
+
+def ransac_into(matches, n_matches, kpts_a, kpts_b, words, rp, counts, mask, result, ws, stream=None):
+    """RANSAC on device buffers: matches int32 [cap, 3] (kp_a, kp_b, d2 bits), keypoints int32 [cap_k, 3],
+    words uint32/int32 [n_hyp, 2]; counts int32 [n_hyp] or None, mask uint8 [cap], result uint8 [48]."""
+    lib = _lib.load()
+    st = lib.rift2_ransac(_ptr(matches), _ptr(n_matches), matches.shape[0], _ptr(kpts_a), kpts_a.shape[0],
+                          _ptr(kpts_b), kpts_b.shape[0], _ptr(words), words.shape[0], ctypes.byref(rp),
+                          _ptr(counts), _ptr(mask), _ptr(result), _ptr(ws), _nbytes(ws), _stream(stream))
+    _lib.check(st, "rift2_ransac")
+
+
+def consensus_into(model, matches, n_matches, kpts_a, kpts_b, threshold, mask, result, ws, stream=None):
+    """Consensus of a device model (float64 [4] = a, b, tx, ty); result uint8 [16]."""
+    lib = _lib.load()
+    st = lib.rift2_consensus(_ptr(model), _ptr(matches), _ptr(n_matches), matches.shape[0], _ptr(kpts_a),
+                             kpts_a.shape[0], _ptr(kpts_b), kpts_b.shape[0], float(threshold), _ptr(mask),
+                             _ptr(result), _ptr(ws), _nbytes(ws), _stream(stream))
+    _lib.check(st, "rift2_consensus")
 
 
 # ----------------------------------------------------------------- allocating convenience calls
@@ -204,6 +231,55 @@ def match(desc_a, inv_a, kp_a, n_a, desc_b, inv_b, kp_b, n_b, mp: MatchParams | 
                                                              dtype=torch.uint8, device=dev)
     match_into(desc_a, inv_a, kp_a, n_a, desc_b, inv_b, kp_b, n_b, mp, out, n, ws, stream)
     return out, n
+
+
+SIMILARITY_BYTES = 48  # rift2_similarity
+CONSENSUS_BYTES = 16  # rift2_consensus_result
+
+
+def similarity_fields(result):
+    """Host dict of a rift2_similarity held in a uint8 [48] tensor."""
+    raw = result.cpu()
+    d = raw[:32].view(_torch().float64).tolist()
+    i = raw[32:48].view(_torch().int32).tolist()
+    return {"model": tuple(d), "best": i[0], "n_inliers": i[1], "n_matches": i[2], "status": i[3]}
+
+
+def consensus_fields(result):
+    """Host dict of a rift2_consensus_result held in a uint8 [16] tensor."""
+    raw = result.cpu()
+    i = raw[:8].view(_torch().int32).tolist()
+    return {"n_inliers": i[0], "status": i[1], "sum_sq": raw[8:16].view(_torch().float64).item()}
+
+
+def ransac(matches, n_matches, kpts_a, kpts_b, words, threshold=3.0, refine=2, stream=None):
+    """RANSAC over a similarity on device matches: (result uint8 [48], mask uint8 [cap], counts int32 [n_hyp]).
+
+    words: uint32 (as int32) [n_hyp, 2] uniform sample words on the device."""
+    torch = _torch()
+    dev = matches.device
+    init(dev.index or 0)
+    cap, n_hyp = matches.shape[0], words.shape[0]
+    rp = RansacParams(float(threshold), int(refine))
+    counts = torch.empty((n_hyp,), dtype=torch.int32, device=dev)
+    mask = torch.empty((cap,), dtype=torch.uint8, device=dev)
+    result = torch.empty((SIMILARITY_BYTES,), dtype=torch.uint8, device=dev)
+    ws = torch.empty(ransac_workspace_bytes(cap, n_hyp), dtype=torch.uint8, device=dev)
+    ransac_into(matches, n_matches, kpts_a, kpts_b, words, rp, counts, mask, result, ws, stream)
+    return result, mask, counts
+
+
+def consensus(model, matches, n_matches, kpts_a, kpts_b, threshold=3.0, stream=None):
+    """Consensus of a model (device float64 [4]) over device matches: (result uint8 [16], mask uint8 [cap])."""
+    torch = _torch()
+    dev = matches.device
+    init(dev.index or 0)
+    cap = matches.shape[0]
+    mask = torch.empty((cap,), dtype=torch.uint8, device=dev)
+    result = torch.empty((CONSENSUS_BYTES,), dtype=torch.uint8, device=dev)
+    ws = torch.empty(ransac_workspace_bytes(cap, 0), dtype=torch.uint8, device=dev)
+    consensus_into(model, matches, n_matches, kpts_a, kpts_b, threshold, mask, result, ws, stream)
+    return result, mask
 
 
 # ----------------------------------------------------------------- whole pair with resident buffers

@@ -47,6 +47,10 @@ class MatchParams(ctypes.Structure):
     _fields_ = [("ratio_sq", ctypes.c_float), ("precision", ctypes.c_int32)]
 
 
+class RansacParams(ctypes.Structure):
+    _fields_ = [("threshold", ctypes.c_double), ("refine", ctypes.c_int32)]
+
+
 class Request(ctypes.Structure):
     _fields_ = [
         ("id", ctypes.c_int64),
@@ -77,9 +81,10 @@ EXPORTS = [
     "rift2_match_workspace_size", "rift2_filter_mim", "rift2_detect", "rift2_describe", "rift2_match",
     "rift2_profile_enable", "rift2_profile_read", "rift2_engine_request_bytes", "rift2_engine_create",
     "rift2_engine_submit", "rift2_engine_poll", "rift2_engine_pending", "rift2_engine_destroy",
+    "rift2_ransac_workspace_size", "rift2_ransac", "rift2_consensus",
 ]
 STAGES = ["row_dft", "pass_a", "noise_pre", "noise_sel", "pass_b", "detect", "describe", "match_prep",
-          "match_gemm", "match_merge", "pass_b_reduce"]
+          "match_gemm", "match_merge", "pass_b_reduce", "ransac"]
 
 _LIB = None
 
@@ -124,6 +129,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rift2_describe.restype = ctypes.c_int
     lib.rift2_match.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, i32, i32, P(MatchParams), vp, vp, vp, sz, vp]
     lib.rift2_match.restype = ctypes.c_int
+    lib.rift2_ransac_workspace_size.argtypes = [i32, i32]
+    lib.rift2_ransac_workspace_size.restype = sz
+    lib.rift2_ransac.argtypes = [vp, vp, i32, vp, i32, vp, i32, vp, i32, P(RansacParams), vp, vp, vp, vp, sz, vp]
+    lib.rift2_ransac.restype = ctypes.c_int
+    lib.rift2_consensus.argtypes = [vp, vp, vp, i32, vp, i32, vp, i32, ctypes.c_double, vp, vp, vp, sz, vp]
+    lib.rift2_consensus.restype = ctypes.c_int
     lib.rift2_profile_enable.argtypes = [ctypes.c_int]
     lib.rift2_profile_enable.restype = ctypes.c_int
     lib.rift2_profile_read.argtypes = [P(ctypes.c_double), P(ctypes.c_int64), ctypes.c_int]

@@ -16,6 +16,7 @@
 #include "filter.hip"
 #include "match.hip"
 #include "match_fp8.hip"
+#include "ransac.hip"
 #include "engine.hip"
 
 using namespace rift2;
@@ -155,6 +156,22 @@ MatchLayout match_layout(int cap_a, int cap_b, int D, int precision) {
   return L;
 }
 
+struct RansacLayout {
+  size_t xy, flags, counts, total;
+  int n_flags;
+};
+
+bool ransac_layout(int match_cap, int n_hyp, RansacLayout* L) {
+  if (match_cap < 1 || match_cap > kRansacMaxMatches || n_hyp < 0 || n_hyp > kRansacMaxHyp) return false;
+  Carver c;
+  L->n_flags = (match_cap + 255) / 256;
+  L->xy = c.take((size_t)match_cap * sizeof(int4));
+  L->flags = c.take((size_t)L->n_flags * sizeof(int32_t));
+  L->counts = c.take((size_t)n_hyp * sizeof(int32_t));
+  L->total = c.off;
+  return true;
+}
+
 rift2_status launch_status() {
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? RIFT2_OK : RIFT2_ERR_DEVICE;
@@ -164,7 +181,7 @@ std::mutex g_init_mu;
 bool g_init_done[64] = {};
 
 // ---- stage timing (diagnostics)
-constexpr int kProfGroups = 11;
+constexpr int kProfGroups = 12;
 struct ProfRec {
   int group;
   hipEvent_t a, b;
@@ -670,6 +687,69 @@ rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32
                      mp->ratio_sq, cap_a, best, rowj, rowd);
   hipLaunchKernelGGL(k_match_emit, dim3((cap_a + 255) / 256), dim3(256), 0, st, best, cap_a, rowj, rowd, kp_b,
                      (MatchOut*)out, n_out_dev);
+  return launch_status();
+}
+
+size_t rift2_ransac_workspace_size(int32_t match_cap, int32_t n_hyp) {
+  RansacLayout L;
+  return ransac_layout(match_cap, n_hyp, &L) ? L.total : 0;
+}
+
+rift2_status rift2_ransac(const rift2_correspondence* matches, const int32_t* n_matches_dev, int32_t match_cap,
+                          const rift2_keypoint* kpts_a, int32_t kpt_cap_a, const rift2_keypoint* kpts_b,
+                          int32_t kpt_cap_b, const uint32_t* words, int32_t n_hyp, const rift2_ransac_params* rp,
+                          int32_t* counts, uint8_t* inlier_mask, rift2_similarity* result, void* workspace,
+                          size_t workspace_bytes, void* stream) {
+  if (!matches || !n_matches_dev || !kpts_a || !kpts_b || !words || !rp || !inlier_mask || !result || !workspace)
+    return RIFT2_ERR_INVALID_ARG;
+  if (kpt_cap_a < 1 || kpt_cap_b < 1 || n_hyp < 1 || rp->refine < 0 || rp->refine > 16 ||
+      !std::isfinite(rp->threshold) || !(rp->threshold > 0.0))
+    return RIFT2_ERR_INVALID_ARG;
+  if ((uintptr_t)words & 7u || (uintptr_t)result & 7u || (uintptr_t)workspace & 15u) return RIFT2_ERR_INVALID_ARG;
+  RansacLayout L;
+  if (!ransac_layout(match_cap, n_hyp, &L)) return RIFT2_ERR_UNSUPPORTED;
+  if (workspace_bytes < L.total) return RIFT2_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  int4* xy = (int4*)(ws + L.xy);
+  int32_t* flags = (int32_t*)(ws + L.flags);
+  int32_t* cnt = counts ? counts : (int32_t*)(ws + L.counts);
+  const double tau2 = rp->threshold * rp->threshold;
+  (void)hipGetLastError();
+  ProfScope ps(11, st);
+  hipLaunchKernelGGL(k_ransac_gather, dim3(L.n_flags), dim3(256), 0, st, (const RansacMatch*)matches, n_matches_dev,
+                     match_cap, (const RansacKp*)kpts_a, kpt_cap_a, (const RansacKp*)kpts_b, kpt_cap_b, xy, flags);
+  const int hyp_per_block = 4 * kRansacHypPerWave;
+  hipLaunchKernelGGL(k_ransac_score, dim3((n_hyp + hyp_per_block - 1) / hyp_per_block), dim3(256), 0, st,
+                     (const int4*)xy, n_matches_dev, match_cap, (const int32_t*)flags, L.n_flags,
+                     (const uint2*)words, n_hyp, tau2, cnt);
+  hipLaunchKernelGGL(k_ransac_refine, dim3(1), dim3(1024), 0, st, (const int4*)xy, n_matches_dev, match_cap,
+                     (const uint2*)words, (const int32_t*)cnt, n_hyp, tau2, (int)rp->refine, (const int32_t*)flags,
+                     L.n_flags, inlier_mask, (RansacResult*)result);
+  return launch_status();
+}
+
+rift2_status rift2_consensus(const double* model, const rift2_correspondence* matches, const int32_t* n_matches_dev,
+                             int32_t match_cap, const rift2_keypoint* kpts_a, int32_t kpt_cap_a,
+                             const rift2_keypoint* kpts_b, int32_t kpt_cap_b, double threshold, uint8_t* mask,
+                             rift2_consensus_result* result, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!model || !matches || !n_matches_dev || !kpts_a || !kpts_b || !result || !workspace)
+    return RIFT2_ERR_INVALID_ARG;
+  if (kpt_cap_a < 1 || kpt_cap_b < 1 || !std::isfinite(threshold) || !(threshold > 0.0)) return RIFT2_ERR_INVALID_ARG;
+  if ((uintptr_t)model & 7u || (uintptr_t)result & 7u || (uintptr_t)workspace & 15u) return RIFT2_ERR_INVALID_ARG;
+  RansacLayout L;
+  if (!ransac_layout(match_cap, 0, &L)) return RIFT2_ERR_UNSUPPORTED;
+  if (workspace_bytes < L.total) return RIFT2_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  int4* xy = (int4*)(ws + L.xy);
+  int32_t* flags = (int32_t*)(ws + L.flags);
+  (void)hipGetLastError();
+  ProfScope ps(11, st);
+  hipLaunchKernelGGL(k_ransac_gather, dim3(L.n_flags), dim3(256), 0, st, (const RansacMatch*)matches, n_matches_dev,
+                     match_cap, (const RansacKp*)kpts_a, kpt_cap_a, (const RansacKp*)kpts_b, kpt_cap_b, xy, flags);
+  hipLaunchKernelGGL(k_consensus, dim3(1), dim3(1024), 0, st, (const int4*)xy, n_matches_dev, match_cap,
+                     (const int32_t*)flags, L.n_flags, model, threshold * threshold, mask, (ConsensusOut*)result);
   return launch_status();
 }
 

@@ -1,0 +1,383 @@
+// Outlier removal of the putative matches (Section 1 and Fig. 1: the matches
+// are filtered by RANSAC, Fischler and Bolles 1981) and the consensus of a
+// given transform, which also yields the correct-match count and RMSE of
+// Section 4 when the transform is the ground truth.
+//
+// Model: the similarity u = a x - b y + tx, v = b x + a y + ty, i.e.
+// w = (a + ib) z + t for z = x + iy, w = u + iv.
+//
+//   k_ransac_gather  match list + keypoint tables -> int4 (xa, ya, xb, yb),
+//                    range check of every coordinate
+//   k_ransac_score   one wave per group of hypotheses: the exact fit to the
+//                    hypothesis' two sampled matches, then its consensus
+//                    count over all matches (ballot + popcount per 64)
+//   k_ransac_refine  one block: the hypothesis with the largest count (lowest
+//                    index on ties), then least-squares refits to the
+//                    consensus set from exact integer sums, the final
+//                    inlier mask and count
+//   k_consensus      one block: residuals of a given model, mask, count and
+//                    the sum of the inliers' squared residuals
+//
+// Every floating-point step is one IEEE double operation in the order
+// written (contraction into FMA is switched off in each function), so the
+// consensus decisions are reproducible by any implementation that follows
+// the same formulas.  Coordinates are integers below 2^13 and there are at
+// most 2^17 matches, so every least-squares sum is an exact int64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rift2 {
+
+constexpr int kRansacMaxMatches = 1 << 17;
+constexpr int kRansacCoordLimit = 1 << 13;
+constexpr int kRansacMaxHyp = 1 << 20;
+constexpr int kRansacHypPerWave = 4;
+
+struct RansacKp {  // layout of rift2_keypoint
+  int x, y;
+  float score;
+};
+
+struct RansacMatch {  // layout of rift2_correspondence
+  int kp_a, kp_b;
+  float dist2;
+};
+
+struct RansacResult {  // layout of rift2_similarity
+  double a, b, tx, ty;
+  int32_t best;
+  int32_t n_inliers;
+  int32_t n_matches;
+  int32_t status;
+};
+
+struct Sim {
+  double a, b, tx, ty;
+};
+
+// Exact fit to the minimal sample p -> (p.z, p.w), q -> (q.z, q.w): with
+// d = q - p in A and e likewise in B, (a + ib) = e / d = e conj(d) / |d|^2,
+// t = w_p - (a + ib) z_p.  False when the two A points coincide.
+__device__ __forceinline__ bool sim_fit_pair(int4 p, int4 q, Sim& m) {
+#pragma clang fp contract(off)
+  const long long dx = (long long)q.x - p.x, dy = (long long)q.y - p.y;
+  const long long du = (long long)q.z - p.z, dv = (long long)q.w - p.w;
+  const long long den = dx * dx + dy * dy;
+  if (den == 0) return false;
+  const double fden = (double)den;
+  m.a = (double)(dx * du + dy * dv) / fden;
+  m.b = (double)(dx * dv - dy * du) / fden;
+  const double x1 = (double)p.x, y1 = (double)p.y;
+  m.tx = (double)p.z - (m.a * x1 - m.b * y1);
+  m.ty = (double)p.w - (m.b * x1 + m.a * y1);
+  return true;
+}
+
+// Squared distance between the model's image of (x, y) and (u, v).
+__device__ __forceinline__ double sim_residual_sq(const Sim& m, double x, double y, double u, double v) {
+#pragma clang fp contract(off)
+  const double ex = ((m.a * x - m.b * y) + m.tx) - u;
+  const double ey = ((m.b * x + m.a * y) + m.ty) - v;
+  return ex * ex + ey * ey;
+}
+
+// Sums of the least-squares normal equations over a set of correspondences.
+struct LsqSums {
+  long long n, sx, sy, su, sv, sxx_yy, sxu_yv, sxv_yu;
+};
+
+__device__ __forceinline__ void lsq_add(LsqSums& s, int4 p) {
+  const long long x = p.x, y = p.y, u = p.z, v = p.w;
+  s.n += 1;
+  s.sx += x;
+  s.sy += y;
+  s.su += u;
+  s.sv += v;
+  s.sxx_yy += x * x + y * y;
+  s.sxu_yv += x * u + y * v;
+  s.sxv_yu += x * v - y * u;
+}
+
+// Least squares: minimising sum |(a + ib) z + t - w|^2 gives
+// (a + ib) = sum conj(z - zbar)(w - wbar) / sum |z - zbar|^2 and
+// t = wbar - (a + ib) zbar, here from the n-scaled integer sums.
+__device__ __forceinline__ bool sim_fit_lsq(const LsqSums& s, Sim& m) {
+#pragma clang fp contract(off)
+  if (s.n < 2) return false;
+  const long long den = s.n * s.sxx_yy - (s.sx * s.sx + s.sy * s.sy);
+  if (den == 0) return false;
+  const long long num_a = s.n * s.sxu_yv - (s.sx * s.su + s.sy * s.sv);
+  const long long num_b = s.n * s.sxv_yu - (s.sx * s.sv - s.sy * s.su);
+  const double fden = (double)den;
+  m.a = (double)num_a / fden;
+  m.b = (double)num_b / fden;
+  const double fx = (double)s.sx, fy = (double)s.sy, fn = (double)s.n;
+  m.tx = ((double)s.su - (m.a * fx - m.b * fy)) / fn;
+  m.ty = ((double)s.sv - (m.b * fx + m.a * fy)) / fn;
+  return true;
+}
+
+// Sample index of a uniform 32-bit word: floor(u * n / 2^32).
+__device__ __forceinline__ int sample_index(uint32_t u, int n) {
+  return (int)(((uint64_t)u * (uint64_t)(uint32_t)n) >> 32);
+}
+
+// grid = ceil(cap / 256).  Block z writes flags[z] = 1 when one of its
+// matches refers to a keypoint index outside [0, cap_k) or to a coordinate
+// outside [0, kRansacCoordLimit), else 0 (every block writes its flag, so
+// nothing needs clearing between calls).
+__global__ void __launch_bounds__(256) k_ransac_gather(const RansacMatch* __restrict__ m, const int32_t* __restrict__ n_dev,
+                                                       int cap, const RansacKp* __restrict__ ka, int cap_ka,
+                                                       const RansacKp* __restrict__ kb, int cap_kb,
+                                                       int4* __restrict__ xy, int32_t* __restrict__ flags) {
+  const int n = min(*n_dev, cap);
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  bool bad = false;
+  if (i < n) {
+    const RansacMatch c = m[i];
+    int4 p = make_int4(0, 0, 0, 0);
+    bool ok = c.kp_a >= 0 && c.kp_a < cap_ka && c.kp_b >= 0 && c.kp_b < cap_kb;
+    if (ok) {
+      const RansacKp a = ka[c.kp_a], b = kb[c.kp_b];
+      p = make_int4(a.x, a.y, b.x, b.y);
+      ok = (unsigned)p.x < (unsigned)kRansacCoordLimit && (unsigned)p.y < (unsigned)kRansacCoordLimit &&
+           (unsigned)p.z < (unsigned)kRansacCoordLimit && (unsigned)p.w < (unsigned)kRansacCoordLimit;
+    }
+    if (!ok) p = make_int4(0, 0, 0, 0);
+    bad = !ok;
+    xy[i] = p;
+  }
+  const int any = __syncthreads_or(bad ? 1 : 0);
+  if (threadIdx.x == 0) flags[blockIdx.x] = any ? 1 : 0;
+}
+
+// True in every lane of the calling wave when one of flags[0..nf) is set.
+__device__ __forceinline__ bool wave_any_flag(const int32_t* __restrict__ flags, int nf) {
+  bool any = false;
+  for (int base = 0; base < nf; base += 64) {
+    const int i = base + (threadIdx.x & 63);
+    any = any || __ballot(i < nf && flags[i] != 0) != 0ull;
+  }
+  return any;
+}
+
+// grid = ceil(n_hyp / (4 * kRansacHypPerWave)), block 256: wave w scores
+// hypotheses [w G, w G + G).  counts[h] = consensus size, or -1 when the
+// sample is degenerate, there are fewer than two matches or a gather flag
+// (n_flags of them) is set.
+__global__ void __launch_bounds__(256) k_ransac_score(const int4* __restrict__ xy, const int32_t* __restrict__ n_dev,
+                                                      int cap, const int32_t* __restrict__ flags, int n_flags,
+                                                      const uint2* __restrict__ words, int n_hyp, double tau2,
+                                                      int32_t* __restrict__ counts) {
+#pragma clang fp contract(off)
+  constexpr int G = kRansacHypPerWave;
+  const int lane = threadIdx.x & 63;
+  const int h0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * G;
+  if (h0 >= n_hyp) return;
+  // an invalid match list counts as empty: every hypothesis gets -1
+  const int n = wave_any_flag(flags, n_flags) ? 0 : min(*n_dev, cap);
+  Sim m[G];
+  bool ok[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int h = h0 + g;
+    ok[g] = false;
+    m[g] = Sim{0.0, 0.0, 0.0, 0.0};
+    if (h < n_hyp && n >= 2) {
+      const uint2 w = words[h];
+      ok[g] = sim_fit_pair(xy[sample_index(w.x, n)], xy[sample_index(w.y, n)], m[g]);
+    }
+  }
+  int cnt[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) cnt[g] = 0;
+  const int n_eff = n >= 2 ? n : 0;
+  for (int base = 0; base < n_eff; base += 64) {
+    const int i = base + lane;
+    const bool live = i < n_eff;
+    const int4 p = live ? xy[i] : make_int4(0, 0, 0, 0);
+    const double x = (double)p.x, y = (double)p.y, u = (double)p.z, v = (double)p.w;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const bool in = live && sim_residual_sq(m[g], x, y, u, v) < tau2;
+      cnt[g] += __popcll(__ballot(in));
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (h0 + g < n_hyp) counts[h0 + g] = ok[g] ? cnt[g] : -1;
+  }
+}
+
+// Block-wide int64 sums of the eight least-squares accumulators (1024 threads).
+__device__ __forceinline__ LsqSums block_sum_lsq(LsqSums s, long long* sh /* 16 x 8 */) {
+  long long v[8] = {s.n, s.sx, s.sy, s.su, s.sv, s.sxx_yy, s.sxu_yv, s.sxv_yu};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sh[w * 8 + k] = v[k];
+  }
+  __syncthreads();
+  long long t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) t[k] += sh[q * 8 + k];
+  }
+  return LsqSums{t[0], t[1], t[2], t[3], t[4], t[5], t[6], t[7]};
+}
+
+__device__ __forceinline__ int block_sum_int(int v, int* sh /* 16 */) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int t = 0;
+  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += sh[q];
+  return t;
+}
+
+// One block of 1024 threads.  Chooses the best hypothesis, refines it
+// `refine` times by least squares on its consensus set (stopping early when
+// the set has no unique fit), then writes the final mask over [0, cap) and
+// the result record.
+__global__ void __launch_bounds__(1024) k_ransac_refine(const int4* __restrict__ xy, const int32_t* __restrict__ n_dev,
+                                                        int cap, const uint2* __restrict__ words,
+                                                        const int32_t* __restrict__ counts, int n_hyp, double tau2,
+                                                        int refine, const int32_t* __restrict__ flags, int n_flags,
+                                                        uint8_t* __restrict__ mask, RansacResult* __restrict__ out) {
+#pragma clang fp contract(off)
+  __shared__ unsigned long long sh_key[16];
+  __shared__ long long sh_sum[16 * 8];
+  __shared__ int sh_cnt[16];
+  const int tid = threadIdx.x;
+  const bool invalid = wave_any_flag(flags, n_flags);
+  const int n = invalid ? 0 : min(*n_dev, cap);
+
+  // best hypothesis: key = count << 32 | ~h, so the largest key has the
+  // largest count and, among equal counts, the lowest index
+  unsigned long long key = 0;
+  if (!invalid) {
+    for (int h = tid; h < n_hyp; h += 1024) {
+      const int c = counts[h];
+      if (c >= 0) {
+        const unsigned long long k = ((unsigned long long)(unsigned)c << 32) | (unsigned long long)(~(uint32_t)h);
+        key = k > key ? k : key;
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const unsigned long long o = __shfl_xor(key, off, 64);
+    key = o > key ? o : key;
+  }
+  if ((tid & 63) == 0) sh_key[tid >> 6] = key;
+  __syncthreads();
+  key = 0;
+  for (int q = 0; q < 16; ++q) key = sh_key[q] > key ? sh_key[q] : key;
+
+  Sim m{0.0, 0.0, 0.0, 0.0};
+  int best = -1;
+  if (key != 0 && n >= 2) {
+    best = (int)(~(uint32_t)(key & 0xffffffffull));
+    const uint2 w = words[best];
+    if (!sim_fit_pair(xy[sample_index(w.x, n)], xy[sample_index(w.y, n)], m)) best = -1;  // cannot happen: counted
+  }
+  if (best >= 0) {
+    for (int it = 0; it < refine; ++it) {
+      LsqSums s{0, 0, 0, 0, 0, 0, 0, 0};
+      for (int i = tid; i < n; i += 1024) {
+        const int4 p = xy[i];
+        if (sim_residual_sq(m, (double)p.x, (double)p.y, (double)p.z, (double)p.w) < tau2) lsq_add(s, p);
+      }
+      const LsqSums t = block_sum_lsq(s, sh_sum);
+      Sim f;
+      if (!sim_fit_lsq(t, f)) break;
+      m = f;
+    }
+  }
+  int local = 0;
+  for (int i = tid; i < cap; i += 1024) {
+    uint8_t in = 0;
+    if (best >= 0 && i < n) {
+      const int4 p = xy[i];
+      in = sim_residual_sq(m, (double)p.x, (double)p.y, (double)p.z, (double)p.w) < tau2 ? 1 : 0;
+    }
+    mask[i] = in;
+    local += in;
+  }
+  const int total = block_sum_int(local, sh_cnt);
+  if (tid == 0) {
+    RansacResult r;
+    r.a = m.a;
+    r.b = m.b;
+    r.tx = m.tx;
+    r.ty = m.ty;
+    r.best = best;
+    r.n_inliers = total;
+    r.n_matches = n;
+    r.status = invalid ? 1 : 0;
+    *out = r;
+  }
+}
+
+struct ConsensusOut {  // layout of rift2_consensus_result
+  int32_t n_inliers;
+  int32_t status;
+  double sum_sq;
+};
+
+// One block of 1024 threads: consensus of the model (a, b, tx, ty) read from
+// `model` (device).  Writes mask[0..cap) (if not null) and the inlier count
+// and sum of the inliers' squared residuals, added in a fixed order: per
+// thread over its strided matches, then a fixed tree over the block.
+__global__ void __launch_bounds__(1024) k_consensus(const int4* __restrict__ xy, const int32_t* __restrict__ n_dev,
+                                                    int cap, const int32_t* __restrict__ flags, int n_flags,
+                                                    const double* __restrict__ model, double tau2,
+                                                    uint8_t* __restrict__ mask, ConsensusOut* __restrict__ out) {
+#pragma clang fp contract(off)
+  __shared__ double sh_d[16];
+  __shared__ int sh_cnt[16];
+  const bool invalid = wave_any_flag(flags, n_flags);
+  const int n = invalid ? 0 : min(*n_dev, cap);
+  const Sim m{model[0], model[1], model[2], model[3]};
+  int local = 0;
+  double ssq = 0.0;
+  for (int i = threadIdx.x; i < cap; i += 1024) {
+    uint8_t in = 0;
+    if (i < n) {
+      const int4 p = xy[i];
+      const double r2 = sim_residual_sq(m, (double)p.x, (double)p.y, (double)p.z, (double)p.w);
+      if (r2 < tau2) {
+        in = 1;
+        ssq = ssq + r2;
+      }
+    }
+    if (mask) mask[i] = in;
+    local += in;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) ssq = ssq + __shfl_xor(ssq, off, 64);
+  if ((threadIdx.x & 63) == 0) sh_d[threadIdx.x >> 6] = ssq;
+  const int total = block_sum_int(local, sh_cnt);  // its barriers also publish sh_d
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < 16; ++q) t = t + sh_d[q];
+    ConsensusOut r;
+    r.n_inliers = total;
+    r.status = invalid ? 1 : 0;
+    r.sum_sq = t;
+    *out = r;
+  }
+}
+
+}  // namespace rift2

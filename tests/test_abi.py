@@ -122,6 +122,37 @@ def test_argument_errors_return_before_any_launch():
     assert lib.rift2_status_string(_l.ERR_WORKSPACE) == b"workspace too small"
 
 
+def test_ransac_validation_and_workspace():
+    _l, lib = _lib()
+    fake = ctypes.c_void_p(0x1000)
+    null = ctypes.c_void_p(0)
+    rp = _l.RansacParams(3.0, 2)
+    assert lib.rift2_ransac_workspace_size(5000, 4096) >= 5000 * 16 + 4096 * 4
+    assert lib.rift2_ransac_workspace_size(0, 10) == 0
+    assert lib.rift2_ransac_workspace_size((1 << 17) + 1, 10) == 0
+    assert lib.rift2_ransac_workspace_size(10, (1 << 20) + 1) == 0
+
+    def call(matches=fake, cap=100, words=fake, n_hyp=64, params=rp, ws_bytes=1 << 20, mask=fake):
+        return lib.rift2_ransac(matches, fake, cap, fake, 10, fake, 10, words, n_hyp, ctypes.byref(params), null,
+                                mask, fake, fake, ws_bytes, null)
+
+    assert call(matches=null) == _l.ERR_INVALID_ARG
+    assert call(mask=null) == _l.ERR_INVALID_ARG
+    assert call(n_hyp=0) == _l.ERR_INVALID_ARG
+    assert call(params=_l.RansacParams(0.0, 2)) == _l.ERR_INVALID_ARG
+    assert call(params=_l.RansacParams(float("nan"), 2)) == _l.ERR_INVALID_ARG
+    assert call(params=_l.RansacParams(3.0, 17)) == _l.ERR_INVALID_ARG
+    assert call(words=ctypes.c_void_p(0x1004)) == _l.ERR_INVALID_ARG  # misaligned word pairs
+    assert call(cap=(1 << 17) + 1) == _l.ERR_UNSUPPORTED
+    assert call(ws_bytes=64) == _l.ERR_WORKSPACE
+    assert lib.rift2_consensus(fake, fake, fake, 100, fake, 10, fake, 10, -1.0, null, fake, fake, 1 << 20,
+                               null) == _l.ERR_INVALID_ARG
+    assert lib.rift2_consensus(null, fake, fake, 100, fake, 10, fake, 10, 3.0, null, fake, fake, 1 << 20,
+                               null) == _l.ERR_INVALID_ARG
+    assert lib.rift2_consensus(fake, fake, fake, 100, fake, 10, fake, 10, 3.0, null, fake, fake, 16,
+                               null) == _l.ERR_WORKSPACE
+
+
 def test_binding_fails_loudly_without_the_library(tmp_path):
     from paper_2303_00319_amd import _lib as l
 
