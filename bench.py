@@ -39,6 +39,7 @@ HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 FP8_MFMA_PEAK_TFLOPS = 5000.0
+FP64_PEAK_TFLOPS = 78.6  # vector FP64, FMA counted as two flops
 
 # Per-launch HBM bytes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a
 # plain copy of known size gives) from two rocprofv3 --pmc runs at 1024 x 1024
@@ -94,6 +95,10 @@ def parse():
     ap.add_argument("--serve-sizes", default=None, help="--serve: comma-separated square sizes (default: the mix)")
     ap.add_argument("--serve-keypoints", type=int, default=0, help="--serve: keypoints per image (0: 2e-3 HW)")
     ap.add_argument("--serve-form", default="bf16", choices=("fp32", "bf16", "fp8"), help="--serve: matching form")
+    ap.add_argument("--ransac", type=int, default=0,
+                    help="hypotheses of an outlier-removal stage appended to every pair step (0: none)")
+    ap.add_argument("--ransac-matches", type=int, default=5000,
+                    help="matches of the planted set the standalone outlier-removal timing runs on")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB read + 256 MiB write elementwise kernel first (HBM counter scale)")
     return ap.parse_args()
@@ -123,10 +128,17 @@ def _last_pair(pipe):
             "matches": int(pipe.n_out.item())}
 
 
+def _ransac_words(torch, n_hyp, seed=0):
+    from synth.matches import sample_words
+
+    return torch.from_numpy(sample_words(seed, n_hyp).view("int32").copy()).to(torch.device("cuda:0"))
+
+
 def time_single(r2, torch, imgs, args, precision):
     """One pair per step, nothing overlapped: a replayed graph per resident pair."""
     pc, det, dp, mp = _form_params(r2, args, precision)
-    pipe = r2.PairPipeline(args.size, args.size, pc, det, dp, mp, serial=args.serial)
+    words = _ransac_words(torch, args.ransac) if args.ransac > 0 else None
+    pipe = r2.PairPipeline(args.size, args.size, pc, det, dp, mp, serial=args.serial, ransac_words=words)
     graphs = []
     if not args.no_graph:
         for i, (a, b) in enumerate(imgs):
@@ -286,6 +298,46 @@ def roofline(stages, h, w, n_scales, n_orient, n_a, n_b, d, gemm_peak=None):
                       "frac": round(rate(k) / peak(k), 4), "ms_per_launch": round(stages[k]["ms_avg"], 5)}
                   for k in cand if k != best},
     }
+
+
+def time_outliers(r2, torch, args, n_hyp=4096, reps=50):
+    """rift2_ransac alone on a planted match set of the headline shape (10 % correct, 4096 hypotheses).
+
+    Work: one FP64 residual test per (hypothesis, match), 6 multiplies and 7
+    adds with no fused operations, against the FP64 vector peak; the chip's
+    FP64 rate counts an FMA as two flops, so plain multiplies and adds reach
+    half of it at most.
+    """
+    from synth.matches import planted_matches
+
+    dev = torch.device("cuda:0")
+    n = args.ransac_matches
+    ka, kb, m, _, _ = planted_matches(0, n // 10, n - n // 10, size=args.size)
+    mt = torch.from_numpy(m).to(dev)
+    nt = torch.tensor([n], dtype=torch.int32, device=dev)
+    kat, kbt = torch.from_numpy(ka).to(dev), torch.from_numpy(kb).to(dev)
+    words = _ransac_words(torch, n_hyp, seed=1)
+    res, mask, counts = r2.ransac(mt, nt, kat, kbt, words)
+    ws = torch.empty(r2.ransac_workspace_bytes(n, n_hyp), dtype=torch.uint8, device=dev)
+    rp = r2.RansacParams(3.0, 2)
+    for _ in range(5):
+        r2.ransac_into(mt, nt, kat, kbt, words, rp, counts, mask, res, ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        r2.ransac_into(mt, nt, kat, kbt, words, rp, counts, mask, res, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    f = r2.similarity_fields(res)
+    flops = 13.0 * n_hyp * n
+    return {"workload": f"{n} matches ({n // 10} planted correct), {n_hyp} hypotheses, similarity model, "
+                        f"threshold 3 px, 2 least-squares refits", "ms_per_call": round(ms, 5),
+            "tests_per_s": round(n_hyp * n / (ms * 1e-3), 1),
+            "fp64": {"bound": "alu", "achieved_tflops": round(flops / (ms * 1e-3) / 1e12, 3),
+                     "peak_tflops": FP64_PEAK_TFLOPS, "frac": round(flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)},
+            "inliers": f["n_inliers"], "best": f["best"]}
 
 
 def cpu_baseline(size, keypoints, n_pairs=3):
@@ -451,6 +503,8 @@ def main():
         t = stages[f]["match_gemm"]["ms_avg"] * 1e-3
         mfma[f] = {"tflops": round(gemm_flop / t / 1e12, 2), "frac": round(gemm_flop / t / (peak[f] * 1e12), 4),
                    "peak_tflops": peak[f]}
+    print("[bench] outlier removal", file=sys.stderr, flush=True)
+    outliers = time_outliers(r2, torch, args)
     cpu = None
     if not args.no_cpu and args.config == 1:
         print("[bench] cpu oracle baseline", file=sys.stderr, flush=True)
@@ -486,7 +540,10 @@ def main():
         "mfma": mfma,
         "stages_ms": {f: {k: round(v["ms_avg"], 5) for k, v in stages[f].items()} for f in forms},
         "cpu_baseline": cpu,
+        "outliers": outliers,
     }
+    if args.ransac > 0:
+        line["config"]["ransac_hypotheses_in_step"] = args.ransac
     for f in forms[1:]:
         t = timed[f]
         key = "mixed" if (args.config == 1 and f == "bf16") else f

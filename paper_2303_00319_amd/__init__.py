@@ -309,7 +309,11 @@ class PairPipeline:
     allocation), so it can be captured into a HIP graph and replayed.
     """
 
-    def __init__(self, h, w, pc=None, det=None, dp=None, mp=None, device=0, serial=False):
+    def __init__(self, h, w, pc=None, det=None, dp=None, mp=None, device=0, serial=False, ransac_words=None,
+                 ransac_params=None):
+        """ransac_words: optional device int32 [n_hyp, 2] uniform sample words; when given, every run ends
+        with rift2_ransac on the pair's matches (threshold 3 px, 2 refits unless ransac_params says
+        otherwise), results in ransac_result / ransac_mask."""
         torch = _torch()
         d_pc, d_det, d_dp, d_mp = defaults()
         self.pc = pc or d_pc
@@ -326,6 +330,13 @@ class PairPipeline:
         self.out = torch.empty((cap, 3), dtype=torch.int32, device=self.dev)
         self.n_out = torch.zeros((1,), dtype=torch.int32, device=self.dev)
         self.ws_match = torch.empty(match_workspace_bytes(cap, cap, d, self.mp), dtype=torch.uint8, device=self.dev)
+        self.ransac_words = ransac_words
+        if ransac_words is not None:
+            self.ransac_params = ransac_params or RansacParams(3.0, 2)
+            self.ransac_result = torch.zeros((SIMILARITY_BYTES,), dtype=torch.uint8, device=self.dev)
+            self.ransac_mask = torch.zeros((cap,), dtype=torch.uint8, device=self.dev)
+            self.ws_ransac = torch.empty(ransac_workspace_bytes(cap, ransac_words.shape[0]), dtype=torch.uint8,
+                                         device=self.dev)
         self.graph = None
         self._side = None
         self.serial = serial
@@ -345,6 +356,9 @@ class PairPipeline:
         a, b = self.a, self.b
         match_into(a.desc, a.inv, a.dkp, a.nd, b.desc, b.inv, b.dkp, b.nd, self.mp, self.out, self.n_out,
                    self.ws_match, stream)
+        if self.ransac_words is not None:
+            ransac_into(self.out, self.n_out, a.kpts, b.kpts, self.ransac_words, self.ransac_params, None,
+                        self.ransac_mask, self.ransac_result, self.ws_ransac, stream)
 
     def run_serial(self, img_a, img_b, stream=None):
         """Every stage on one stream, in order (used to time kernels one at a time)."""

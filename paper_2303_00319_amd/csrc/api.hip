@@ -157,7 +157,7 @@ MatchLayout match_layout(int cap_a, int cap_b, int D, int precision) {
 }
 
 struct RansacLayout {
-  size_t xy, flags, counts, total;
+  size_t xy, flags, key, counts, total;
   int n_flags;
 };
 
@@ -167,6 +167,7 @@ bool ransac_layout(int match_cap, int n_hyp, RansacLayout* L) {
   L->n_flags = (match_cap + 255) / 256;
   L->xy = c.take((size_t)match_cap * sizeof(int4));
   L->flags = c.take((size_t)L->n_flags * sizeof(int32_t));
+  L->key = c.take(sizeof(unsigned long long));
   L->counts = c.take((size_t)n_hyp * sizeof(int32_t));
   L->total = c.off;
   return true;
@@ -714,18 +715,19 @@ rift2_status rift2_ransac(const rift2_correspondence* matches, const int32_t* n_
   int4* xy = (int4*)(ws + L.xy);
   int32_t* flags = (int32_t*)(ws + L.flags);
   int32_t* cnt = counts ? counts : (int32_t*)(ws + L.counts);
+  unsigned long long* key = (unsigned long long*)(ws + L.key);
   const double tau2 = rp->threshold * rp->threshold;
   (void)hipGetLastError();
   ProfScope ps(11, st);
   hipLaunchKernelGGL(k_ransac_gather, dim3(L.n_flags), dim3(256), 0, st, (const RansacMatch*)matches, n_matches_dev,
-                     match_cap, (const RansacKp*)kpts_a, kpt_cap_a, (const RansacKp*)kpts_b, kpt_cap_b, xy, flags);
-  const int hyp_per_block = 4 * kRansacHypPerWave;
-  hipLaunchKernelGGL(k_ransac_score, dim3((n_hyp + hyp_per_block - 1) / hyp_per_block), dim3(256), 0, st,
+                     match_cap, (const RansacKp*)kpts_a, kpt_cap_a, (const RansacKp*)kpts_b, kpt_cap_b, xy, flags,
+                     key);
+  hipLaunchKernelGGL(k_ransac_score, dim3((n_hyp + kRansacHypPerBlock - 1) / kRansacHypPerBlock), dim3(256), 0, st,
                      (const int4*)xy, n_matches_dev, match_cap, (const int32_t*)flags, L.n_flags,
-                     (const uint2*)words, n_hyp, tau2, cnt);
+                     (const uint2*)words, n_hyp, tau2, cnt, key);
   hipLaunchKernelGGL(k_ransac_refine, dim3(1), dim3(1024), 0, st, (const int4*)xy, n_matches_dev, match_cap,
-                     (const uint2*)words, (const int32_t*)cnt, n_hyp, tau2, (int)rp->refine, (const int32_t*)flags,
-                     L.n_flags, inlier_mask, (RansacResult*)result);
+                     (const uint2*)words, (const unsigned long long*)key, tau2, (int)rp->refine,
+                     (const int32_t*)flags, L.n_flags, inlier_mask, (RansacResult*)result);
   return launch_status();
 }
 
@@ -747,7 +749,8 @@ rift2_status rift2_consensus(const double* model, const rift2_correspondence* ma
   (void)hipGetLastError();
   ProfScope ps(11, st);
   hipLaunchKernelGGL(k_ransac_gather, dim3(L.n_flags), dim3(256), 0, st, (const RansacMatch*)matches, n_matches_dev,
-                     match_cap, (const RansacKp*)kpts_a, kpt_cap_a, (const RansacKp*)kpts_b, kpt_cap_b, xy, flags);
+                     match_cap, (const RansacKp*)kpts_a, kpt_cap_a, (const RansacKp*)kpts_b, kpt_cap_b, xy, flags,
+                     (unsigned long long*)nullptr);
   hipLaunchKernelGGL(k_consensus, dim3(1), dim3(1024), 0, st, (const int4*)xy, n_matches_dev, match_cap,
                      (const int32_t*)flags, L.n_flags, model, threshold * threshold, mask, (ConsensusOut*)result);
   return launch_status();

@@ -8,11 +8,12 @@
 //
 //   k_ransac_gather  match list + keypoint tables -> int4 (xa, ya, xb, yb),
 //                    range check of every coordinate
-//   k_ransac_score   one wave per group of hypotheses: the exact fit to the
+//   k_ransac_score   one block per group of hypotheses: the exact fit to the
 //                    hypothesis' two sampled matches, then its consensus
 //                    count over all matches (ballot + popcount per 64)
 //   k_ransac_refine  one block: the hypothesis with the largest count (lowest
-//                    index on ties), then least-squares refits to the
+//                    index on ties, an atomic maximum of the scoring kernel),
+//                    then least-squares refits to the
 //                    consensus set from exact integer sums, the final
 //                    inlier mask and count
 //   k_consensus      one block: residuals of a given model, mask, count and
@@ -33,7 +34,7 @@ namespace rift2 {
 constexpr int kRansacMaxMatches = 1 << 17;
 constexpr int kRansacCoordLimit = 1 << 13;
 constexpr int kRansacMaxHyp = 1 << 20;
-constexpr int kRansacHypPerWave = 4;
+constexpr int kRansacHypPerBlock = 4;
 
 struct RansacKp {  // layout of rift2_keypoint
   int x, y;
@@ -127,13 +128,15 @@ __device__ __forceinline__ int sample_index(uint32_t u, int n) {
 // grid = ceil(cap / 256).  Block z writes flags[z] = 1 when one of its
 // matches refers to a keypoint index outside [0, cap_k) or to a coordinate
 // outside [0, kRansacCoordLimit), else 0 (every block writes its flag, so
-// nothing needs clearing between calls).
+// nothing needs clearing between calls).  Also clears *best_key (if given).
 __global__ void __launch_bounds__(256) k_ransac_gather(const RansacMatch* __restrict__ m, const int32_t* __restrict__ n_dev,
                                                        int cap, const RansacKp* __restrict__ ka, int cap_ka,
                                                        const RansacKp* __restrict__ kb, int cap_kb,
-                                                       int4* __restrict__ xy, int32_t* __restrict__ flags) {
+                                                       int4* __restrict__ xy, int32_t* __restrict__ flags,
+                                                       unsigned long long* __restrict__ best_key) {
   const int n = min(*n_dev, cap);
   const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i == 0 && best_key) *best_key = 0ull;  // the scoring kernel that follows takes maxima into it
   bool bad = false;
   if (i < n) {
     const RansacMatch c = m[i];
@@ -163,19 +166,23 @@ __device__ __forceinline__ bool wave_any_flag(const int32_t* __restrict__ flags,
   return any;
 }
 
-// grid = ceil(n_hyp / (4 * kRansacHypPerWave)), block 256: wave w scores
-// hypotheses [w G, w G + G).  counts[h] = consensus size, or -1 when the
-// sample is degenerate, there are fewer than two matches or a gather flag
-// (n_flags of them) is set.
+// grid = ceil(n_hyp / kRansacHypPerBlock), block 256: block z scores
+// hypotheses [z G, z G + G); its four waves take interleaved 64-match chunks
+// and their counts are added through LDS.  counts[h] = consensus size, or -1
+// when the sample is degenerate, there are fewer than two matches or a
+// gather flag (n_flags of them) is set; every counted hypothesis also takes
+// the maximum of (count << 32 | ~h) into *best_key (cleared by the gather).
 __global__ void __launch_bounds__(256) k_ransac_score(const int4* __restrict__ xy, const int32_t* __restrict__ n_dev,
                                                       int cap, const int32_t* __restrict__ flags, int n_flags,
                                                       const uint2* __restrict__ words, int n_hyp, double tau2,
-                                                      int32_t* __restrict__ counts) {
+                                                      int32_t* __restrict__ counts,
+                                                      unsigned long long* __restrict__ best_key) {
 #pragma clang fp contract(off)
-  constexpr int G = kRansacHypPerWave;
+  constexpr int G = kRansacHypPerBlock;
+  __shared__ int sh_cnt[4][G];
   const int lane = threadIdx.x & 63;
-  const int h0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * G;
-  if (h0 >= n_hyp) return;
+  const int wave = threadIdx.x >> 6;
+  const int h0 = blockIdx.x * G;
   // an invalid match list counts as empty: every hypothesis gets -1
   const int n = wave_any_flag(flags, n_flags) ? 0 : min(*n_dev, cap);
   Sim m[G];
@@ -194,26 +201,42 @@ __global__ void __launch_bounds__(256) k_ransac_score(const int4* __restrict__ x
 #pragma unroll
   for (int g = 0; g < G; ++g) cnt[g] = 0;
   const int n_eff = n >= 2 ? n : 0;
-  for (int base = 0; base < n_eff; base += 64) {
-    const int i = base + lane;
-    const bool live = i < n_eff;
-    const int4 p = live ? xy[i] : make_int4(0, 0, 0, 0);
+  const int4 zero = make_int4(0, 0, 0, 0);
+  int base = wave * 64;
+  int4 p = base + lane < n_eff ? xy[base + lane] : zero;
+  for (; base < n_eff; base += 256) {
+    const int nxt = base + 256 + lane;
+    const int4 pn = nxt < n_eff ? xy[nxt] : zero;  // next chunk in flight during this one
+    const bool live = base + lane < n_eff;
     const double x = (double)p.x, y = (double)p.y, u = (double)p.z, v = (double)p.w;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const bool in = live && sim_residual_sq(m[g], x, y, u, v) < tau2;
       cnt[g] += __popcll(__ballot(in));
     }
+    p = pn;
   }
   if (lane == 0) {
 #pragma unroll
-    for (int g = 0; g < G; ++g)
-      if (h0 + g < n_hyp) counts[h0 + g] = ok[g] ? cnt[g] : -1;
+    for (int g = 0; g < G; ++g) sh_cnt[wave][g] = cnt[g];
+  }
+  __syncthreads();
+  if (threadIdx.x < G) {
+    const int g = threadIdx.x;
+    const int h = h0 + g;
+    if (h < n_hyp) {
+      const int c = sh_cnt[0][g] + sh_cnt[1][g] + sh_cnt[2][g] + sh_cnt[3][g];
+      counts[h] = ok[g] ? c : -1;
+      // count << 32 | ~h: the maximum has the largest count, then the lowest index
+      if (ok[g]) atomicMax(best_key, ((unsigned long long)(unsigned)c << 32) | (unsigned long long)(~(uint32_t)h));
+    }
   }
 }
 
-// Block-wide int64 sums of the eight least-squares accumulators (1024 threads).
-__device__ __forceinline__ LsqSums block_sum_lsq(LsqSums s, long long* sh /* 16 x 8 */) {
+// Block-wide int64 sums of the eight least-squares accumulators (1024
+// threads): a shuffle tree per wave, then eight threads add the 16 wave
+// totals.  Integer sums, so the order does not matter.
+__device__ __forceinline__ LsqSums block_sum_lsq(LsqSums s, long long* sh /* 16 x 8 + 8 */) {
   long long v[8] = {s.n, s.sx, s.sy, s.su, s.sv, s.sxx_yy, s.sxu_yv, s.sxv_yu};
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
@@ -221,18 +244,19 @@ __device__ __forceinline__ LsqSums block_sum_lsq(LsqSums s, long long* sh /* 16 
     for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
   }
   const int w = threadIdx.x >> 6;
-  __syncthreads();
+  __syncthreads();  // sh may still be read by a previous call
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) sh[w * 8 + k] = v[k];
   }
   __syncthreads();
-  long long t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) t[k] += sh[q * 8 + k];
+  if (threadIdx.x < 8) {
+    long long t = 0;
+    for (int q = 0; q < 16; ++q) t += sh[q * 8 + threadIdx.x];
+    sh[128 + threadIdx.x] = t;
   }
-  return LsqSums{t[0], t[1], t[2], t[3], t[4], t[5], t[6], t[7]};
+  __syncthreads();
+  return LsqSums{sh[128], sh[129], sh[130], sh[131], sh[132], sh[133], sh[134], sh[135]};
 }
 
 __device__ __forceinline__ int block_sum_int(int v, int* sh /* 16 */) {
@@ -246,44 +270,25 @@ __device__ __forceinline__ int block_sum_int(int v, int* sh /* 16 */) {
   return t;
 }
 
-// One block of 1024 threads.  Chooses the best hypothesis, refines it
-// `refine` times by least squares on its consensus set (stopping early when
-// the set has no unique fit), then writes the final mask over [0, cap) and
-// the result record.
+constexpr int kRefineBatch = 8;  // matches per thread whose loads are issued together
+
+// One block of 1024 threads.  Takes the best hypothesis from *best_key
+// (count << 32 | ~h, the maximum over all hypotheses, so the largest count
+// and among equal counts the lowest index), refines it `refine` times by
+// least squares on its consensus set (stopping early when the set has no
+// unique fit), then writes the final mask over [0, cap) and the result.
 __global__ void __launch_bounds__(1024) k_ransac_refine(const int4* __restrict__ xy, const int32_t* __restrict__ n_dev,
                                                         int cap, const uint2* __restrict__ words,
-                                                        const int32_t* __restrict__ counts, int n_hyp, double tau2,
+                                                        const unsigned long long* __restrict__ best_key, double tau2,
                                                         int refine, const int32_t* __restrict__ flags, int n_flags,
                                                         uint8_t* __restrict__ mask, RansacResult* __restrict__ out) {
 #pragma clang fp contract(off)
-  __shared__ unsigned long long sh_key[16];
-  __shared__ long long sh_sum[16 * 8];
+  __shared__ long long sh_sum[16 * 8 + 8];
   __shared__ int sh_cnt[16];
   const int tid = threadIdx.x;
   const bool invalid = wave_any_flag(flags, n_flags);
   const int n = invalid ? 0 : min(*n_dev, cap);
-
-  // best hypothesis: key = count << 32 | ~h, so the largest key has the
-  // largest count and, among equal counts, the lowest index
-  unsigned long long key = 0;
-  if (!invalid) {
-    for (int h = tid; h < n_hyp; h += 1024) {
-      const int c = counts[h];
-      if (c >= 0) {
-        const unsigned long long k = ((unsigned long long)(unsigned)c << 32) | (unsigned long long)(~(uint32_t)h);
-        key = k > key ? k : key;
-      }
-    }
-  }
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const unsigned long long o = __shfl_xor(key, off, 64);
-    key = o > key ? o : key;
-  }
-  if ((tid & 63) == 0) sh_key[tid >> 6] = key;
-  __syncthreads();
-  key = 0;
-  for (int q = 0; q < 16; ++q) key = sh_key[q] > key ? sh_key[q] : key;
+  const unsigned long long key = invalid ? 0ull : *best_key;
 
   Sim m{0.0, 0.0, 0.0, 0.0};
   int best = -1;
@@ -292,12 +297,23 @@ __global__ void __launch_bounds__(1024) k_ransac_refine(const int4* __restrict__
     const uint2 w = words[best];
     if (!sim_fit_pair(xy[sample_index(w.x, n)], xy[sample_index(w.y, n)], m)) best = -1;  // cannot happen: counted
   }
+  const int4 zero = make_int4(0, 0, 0, 0);
   if (best >= 0) {
     for (int it = 0; it < refine; ++it) {
       LsqSums s{0, 0, 0, 0, 0, 0, 0, 0};
-      for (int i = tid; i < n; i += 1024) {
-        const int4 p = xy[i];
-        if (sim_residual_sq(m, (double)p.x, (double)p.y, (double)p.z, (double)p.w) < tau2) lsq_add(s, p);
+      for (int b0 = 0; b0 < n; b0 += 1024 * kRefineBatch) {
+        int4 p[kRefineBatch];
+#pragma unroll
+        for (int r = 0; r < kRefineBatch; ++r) {
+          const int i = b0 + r * 1024 + tid;
+          p[r] = i < n ? xy[i] : zero;
+        }
+#pragma unroll
+        for (int r = 0; r < kRefineBatch; ++r) {
+          const int i = b0 + r * 1024 + tid;
+          if (i < n && sim_residual_sq(m, (double)p[r].x, (double)p[r].y, (double)p[r].z, (double)p[r].w) < tau2)
+            lsq_add(s, p[r]);
+        }
       }
       const LsqSums t = block_sum_lsq(s, sh_sum);
       Sim f;
@@ -306,14 +322,24 @@ __global__ void __launch_bounds__(1024) k_ransac_refine(const int4* __restrict__
     }
   }
   int local = 0;
-  for (int i = tid; i < cap; i += 1024) {
-    uint8_t in = 0;
-    if (best >= 0 && i < n) {
-      const int4 p = xy[i];
-      in = sim_residual_sq(m, (double)p.x, (double)p.y, (double)p.z, (double)p.w) < tau2 ? 1 : 0;
+  for (int b0 = 0; b0 < cap; b0 += 1024 * kRefineBatch) {
+    int4 p[kRefineBatch];
+#pragma unroll
+    for (int r = 0; r < kRefineBatch; ++r) {
+      const int i = b0 + r * 1024 + tid;
+      p[r] = (best >= 0 && i < n) ? xy[i] : zero;
     }
-    mask[i] = in;
-    local += in;
+#pragma unroll
+    for (int r = 0; r < kRefineBatch; ++r) {
+      const int i = b0 + r * 1024 + tid;
+      if (i < cap) {
+        const uint8_t in = (best >= 0 && i < n &&
+                            sim_residual_sq(m, (double)p[r].x, (double)p[r].y, (double)p[r].z, (double)p[r].w) < tau2)
+                               ? 1 : 0;
+        mask[i] = in;
+        local += in;
+      }
+    }
   }
   const int total = block_sum_int(local, sh_cnt);
   if (tid == 0) {

@@ -45,6 +45,9 @@ def _snapshot(pipe):
         out[name + "_dkp"] = buf.dkp[:nd].cpu().numpy().copy()
     n = int(pipe.n_out.item())
     out["matches"] = pipe.out[:n].cpu().numpy().copy()
+    if getattr(pipe, "ransac_words", None) is not None:
+        out["ransac"] = pipe.ransac_result.cpu().numpy().copy()
+        out["ransac_mask"] = pipe.ransac_mask.cpu().numpy().copy()
     return out
 
 
@@ -54,11 +57,11 @@ def _same(x, y, tag):
         assert x[k].shape == y[k].shape and np.array_equal(x[k], y[k]), f"{tag}: {k} differs"
 
 
-def _pipeline(r2, size, k, precision):
+def _pipeline(r2, size, k, precision, words=None):
     pc, det, dp, mp = r2.defaults()
     det.max_keypoints = k
     mp.precision = precision
-    return r2.PairPipeline(size, size, pc, det, dp, mp)
+    return r2.PairPipeline(size, size, pc, det, dp, mp, ransac_words=words)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -78,6 +81,34 @@ def test_graph_replay_equals_eager(precision):
         with torch.cuda.stream(side):
             g.replay()
         torch.cuda.current_stream().wait_stream(side)
+        _same(ref, _snapshot(pipe), f"replay {rep}")
+        del junk
+
+
+def test_graph_replay_with_outlier_removal():
+    """The pair step with rift2_ransac appended: every replay equals the eager run, and the
+    model moves the image centre by the pair's (7, 4) shift."""
+    r2, dev = _gpu()
+    from synth.matches import sample_words
+
+    print("[graph] 256x256 pair + RANSAC (512 hypotheses)", flush=True)
+    a, b = _translated_pair(8)
+    ta, tb = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+    words = torch.from_numpy(sample_words(8, 512).view(np.int32).copy()).to(dev)
+    pipe = _pipeline(r2, 256, 500, 1, words)
+    pipe.run(ta, tb)
+    ref = _snapshot(pipe)
+    f = r2.similarity_fields(pipe.ransac_result)
+    assert f["status"] == 0 and f["n_inliers"] > 50
+    a_, b_, tx, ty = f["model"]
+    assert abs(a_ - 1) < 1e-2 and abs(b_) < 1e-2
+    c = 127.5  # the image centre moves by the shift
+    assert abs(a_ * c - b_ * c + tx - (c + 7)) < 1.0 and abs(b_ * c + a_ * c + ty - (c + 4)) < 1.0
+    g = pipe.capture(ta, tb)
+    for rep in range(3):
+        junk = torch.ones(1 << 20, device=dev) * rep
+        pipe.ransac_mask.zero_()
+        g.replay()
         _same(ref, _snapshot(pipe), f"replay {rep}")
         del junk
 
