@@ -19,6 +19,14 @@ For each keypoint (x, y):
 Descriptor values are integer counts; distances use the L2-normalised vector.
 Row order: all primary rows in keypoint order, then all secondary rows in
 keypoint order.
+
+RIFT's convolution-sequence ring (Section 2.3), the method RIFT2 replaces, is
+here as the baseline variant: the template image gets one plain descriptor
+per keypoint (the MIM as computed, initial layer 1), the reference image gets
+N_o descriptors per keypoint, one per choice of initial layer omega of the
+ring.  Taking layer omega as the first relabels every MIM value v as
+(v - omega) mod N_o (Section 3's analysis of the ring), so bin b of ring row
+omega counts the pixels whose original value is (b + omega) mod N_o.
 """
 from __future__ import annotations
 
@@ -26,7 +34,8 @@ import numpy as np
 
 from .params import DescParams
 
-__all__ = ["cell_histograms", "dominant", "recode_histogram", "recode_mim", "describe"]
+__all__ = ["cell_histograms", "dominant", "recode_histogram", "recode_mim", "describe", "ring_histogram",
+           "describe_plain", "describe_ring"]
 
 
 def cell_histograms(mim: np.ndarray, x: int, y: int, p: DescParams) -> np.ndarray:
@@ -88,3 +97,43 @@ def describe(mim: np.ndarray, kpts: np.ndarray, p: DescParams = DescParams()):
     kp = np.array([r[0] for r in rows], dtype=np.int32)
     sh = np.array([r[1] for r in rows], dtype=np.int32)
     return counts, kp, sh
+
+
+def ring_histogram(h: np.ndarray, omega: int) -> np.ndarray:
+    """Cell histograms of the MIM rebuilt with layer omega (0-based) as the ring's initial layer.
+
+    Every MIM value v becomes (v - omega) mod N_o (Section 3: starting the ring
+    one layer later lowers every index by one, cyclically), so new bin b counts
+    the pixels whose value was (b + omega) mod N_o.
+    """
+    n = h.shape[-1]
+    out = np.zeros_like(h)
+    for v in range(n):
+        out[..., (v - omega) % n] += h[..., v]
+    return out
+
+
+def _rows(mim, kpts, p, shifts):
+    rows, kp, sh = [], [], []
+    for i, (x, y) in enumerate(np.asarray(kpts, dtype=np.int64)):
+        h = cell_histograms(mim, int(x), int(y), p)
+        for omega in shifts:
+            rows.append(ring_histogram(h, omega).ravel())
+            kp.append(i)
+            sh.append(omega)
+    d = p.grid * p.grid * p.n_orient
+    if not rows:
+        return np.zeros((0, d), np.uint16), np.zeros((0,), np.int32), np.zeros((0,), np.int32)
+    return np.stack(rows).astype(np.uint16), np.array(kp, np.int32), np.array(sh, np.int32)
+
+
+def describe_plain(mim: np.ndarray, kpts: np.ndarray, p: DescParams = DescParams()):
+    """RIFT's template descriptors (Sections 2.2-2.3): one row per keypoint, the cell histograms of the
+    MIM as computed, no dominant-index normalisation.  Returns (counts, kp_index, shift = 0)."""
+    return _rows(mim, kpts, p, [0])
+
+
+def describe_ring(mim: np.ndarray, kpts: np.ndarray, p: DescParams = DescParams()):
+    """RIFT's reference descriptors (Section 2.3): N_o rows per keypoint, row k N_o + omega built from
+    the MIM with layer omega as the ring's initial layer.  Returns (counts, kp_index, omega)."""
+    return _rows(mim, kpts, p, list(range(p.n_orient)))

@@ -188,6 +188,70 @@ def test_descriptor_rot90_grid_law():
     assert checked >= 3
 
 
+def test_ring_rows_reproduce_the_paper_example():
+    """Section 3's example: the ring's second MIM (initial layer 2) has the
+    histogram printed in the paper, and RIFT2's recoded histogram is the ring
+    member whose initial layer is the dominant index."""
+    g = json.load(open(os.path.join(GOLDEN, "paper_histogram_example.json")))
+    p = DescParams(patch_size=36, grid=6, n_orient=6)
+    rng = np.random.default_rng(16)
+    vals = np.repeat(np.arange(6), g["hist_initial_layer_1"])
+    rng.shuffle(vals)
+    mim = np.zeros((60, 60), dtype=np.uint8)
+    mim[12:48, 12:48] = vals.reshape(36, 36)
+    kp = np.array([[30, 30]])
+    ring, kpi, om = ds.describe_ring(mim, kp, p)
+    assert ring.shape == (6, 216) and list(kpi) == [0] * 6 and list(om) == list(range(6))
+    hists = ring.reshape(6, 36, 6).astype(int).sum(axis=1)
+    assert list(hists[0]) == g["hist_initial_layer_1"]
+    assert list(hists[1]) == g["hist_initial_layer_2"]
+    # relabelling the MIM directly (layer 2 first: value v -> v - 1 mod 6) gives ring row 1
+    plain2, _, _ = ds.describe_plain(((mim.astype(int) - 1) % 6).astype(np.uint8), kp, p)
+    assert np.array_equal(plain2[0], ring[1])
+    rift2, _, sh = ds.describe(mim, kp, p)
+    assert sh[0] == g["dominant_index_one_based_layer_1"] - 1
+    assert np.array_equal(rift2[0], ring[sh[0]])
+    assert list(hists[sh[0]]) == g["recoded_hist"]
+
+
+def test_ring_contains_every_rift2_row_and_sums_to_the_patch():
+    rng = np.random.default_rng(17)
+    mim = rng.integers(0, 6, size=(200, 210)).astype(np.uint8)
+    kp = np.array([[60, 70], [100, 150], [48, 48], [162, 152]])
+    ring, kpi, om = ds.describe_ring(mim, kp, DescParams())
+    plain, pk, _ = ds.describe_plain(mim, kp, DescParams())
+    rift2, rk, sh = ds.describe(mim, kp, DescParams())
+    assert ring.shape == (24, 216) and list(kpi) == [k for k in range(4) for _ in range(6)]
+    assert np.array_equal(plain, ring[0::6]) and list(pk) == [0, 1, 2, 3]
+    assert np.all(ring.astype(int).sum(axis=1) == 96 * 96)
+    for row, k, s in zip(rift2, rk, sh):
+        assert np.array_equal(row, ring[6 * k + s])
+    # each ring row is a per-cell cyclic permutation of the plain row
+    for k in range(4):
+        cells = plain[k].reshape(36, 6).astype(int)
+        for w in range(6):
+            assert np.array_equal(ring[6 * k + w].reshape(36, 6), np.roll(cells, -w, axis=1))
+
+
+def test_ring_rows_follow_a_rot90_rotation():
+    """Under an exact 90-degree rotation the MIM values shift by N_o/2, so the
+    rotated image's plain descriptor is the original ring row N_o/2 with the
+    cell grid rotated (the ring absorbs the value shift, not the grid)."""
+    rng = np.random.default_rng(18)
+    n = 160
+    mim = rng.integers(0, 6, size=(n, n)).astype(np.uint8)
+    rmim = ((np.rot90(mim).astype(int) + 3) % 6).astype(np.uint8)
+    p = DescParams()
+    for (x, y) in [(60, 70), (80, 80), (100, 64)]:
+        ring, _, _ = ds.describe_ring(mim, np.array([[x, y]]), p)
+        pr, _, _ = ds.describe_plain(rmim, np.array([[y, n - x]]), p)
+        a = ring[3].reshape(6, 6, 6)
+        b = pr[0].reshape(6, 6, 6)
+        for ci in range(6):
+            for cj in range(6):
+                assert np.array_equal(b[ci, cj], a[cj, 5 - ci])
+
+
 # ---------------------------------------------------------------- matching
 
 def _random_descriptors(rng, n_kp, d=216, dup=0.3):
@@ -230,3 +294,23 @@ def test_exact_dots_are_exact():
     d64 = c.astype(np.float64) @ c.astype(np.float64).T
     d_int = c.astype(np.int64) @ c.astype(np.int64).T
     assert np.array_equal(d64.astype(np.int64), d_int)
+
+
+def test_ring_matching_equals_bruteforce_and_recovers_rotated_values():
+    """Template rows against reference ring rows: the matcher equals pure-Python
+    brute force, and a template whose MIM values are shifted by omega (a
+    rotation by omega pi / N_o in the value sense) finds its reference keypoint
+    through ring row omega."""
+    rng = np.random.default_rng(19)
+    n_kp, cells, no = 20, 4, 6
+    base = rng.integers(0, 30, size=(n_kp, cells, no))
+    ring = np.stack([np.roll(base[k], -w, axis=1).ravel() for k in range(n_kp) for w in range(no)]).astype(np.uint16)
+    kr = np.repeat(np.arange(n_kp), no).astype(np.int32)
+    shift = rng.integers(0, no, size=n_kp)
+    tmpl = np.stack([np.roll(base[k], -shift[k], axis=1).ravel() for k in range(n_kp)])
+    tmpl = (tmpl + rng.integers(0, 2, size=tmpl.shape)).astype(np.uint16)
+    kt = np.arange(n_kp, dtype=np.int32)
+    got = mt.match(tmpl, kt, ring, kr, MatchParams())
+    ref = mt.match_bruteforce(tmpl, kt, ring, kr, MatchParams())
+    assert list(got[0]) == ref[0] and list(got[1]) == ref[1]
+    assert len(ref[0]) >= 15 and all(a == b for a, b in zip(ref[0], ref[1]))
