@@ -92,6 +92,14 @@ typedef struct {
   int32_t patch_size;
 } rift2_detect_params;
 
+/* Row forms of rift2_describe.  RIFT2_DESC_DOMINANT is the paper's method
+ * (Section 3).  The other two serve RIFT's convolution-sequence ring
+ * (Section 2.3), the baseline RIFT2 replaces: RIFT2_DESC_PLAIN is one row of
+ * the cell histograms as computed (the ring's first member), RIFT2_DESC_RING
+ * is n_orient rows per keypoint, row k n_orient + w built from the MIM with
+ * layer w as the ring's first (bin b counts MIM value (b + w) mod n_orient). */
+typedef enum { RIFT2_DESC_DOMINANT = 0, RIFT2_DESC_PLAIN = 1, RIFT2_DESC_RING = 2 } rift2_desc_mode;
+
 /* Descriptor (Section 2.2: 6x6 grid of N_o-bin MIM histograms; Section 3:
  * dominant index and second MIM when the second peak reaches the dominant
  * ratio, Table 1: 0.8).  The ratio is the exact fraction num/den. */
@@ -101,13 +109,23 @@ typedef struct {
   int32_t n_orient;
   int32_t dominant_num;
   int32_t dominant_den;
+  int32_t mode; /* rift2_desc_mode */
 } rift2_desc_params;
 
 /* Matching (Section 4: brute force, nearest feature distance) with a
- * second-neighbour ratio test d1^2 < ratio_sq * d2^2. */
+ * second-neighbour ratio test d1^2 < ratio_sq * d2^2.
+ * ring = 0: the rows of A and B are matched as they are.
+ * ring = R (2..8, FP32 or BF16): RIFT's ring matching (Section 2.3).  A holds
+ * R rows per keypoint in RIFT2_DESC_RING form and B one RIFT2_DESC_PLAIN row
+ * per keypoint.  The result is that of matching each A keypoint's plain row
+ * against all R ring rows of every B keypoint (candidate order: B keypoint
+ * r's ring row w is candidate r R + w); A row g R + w paired with B row r
+ * gives the same dot product as A's plain row with ring row (R - w) mod R of
+ * B keypoint r, so A carries the R-fold rows and the cost. */
 typedef struct {
   float ratio_sq;
   int32_t precision; /* rift2_precision of the distance GEMM */
+  int32_t ring;      /* 0, or rows per A keypoint of a ring matching */
 } rift2_match_params;
 
 typedef struct {
@@ -125,7 +143,8 @@ typedef struct {
 /* Defaults: n_scales 4, n_orient 6, min_wavelength 3, mult 2.1, sigma_onf
  * 0.55, dtheta_on_sigma 1.2, lp 0.45/15, k 2, cutoff 0.5, g 10, eps 1e-4;
  * FAST 0.001, 5000 keypoints, patch 96; grid 6, ratio 4/5; ratio_sq 0.81,
- * FP32.  Any argument may be NULL. */
+ * FP32, no ring; descriptor form RIFT2_DESC_DOMINANT.  Any argument may be
+ * NULL. */
 void rift2_default_params(rift2_pc_params* pc, rift2_detect_params* det, rift2_desc_params* desc,
                           rift2_match_params* match);
 
@@ -179,7 +198,9 @@ rift2_status rift2_detect(const float* moment, int32_t H, int32_t W, const rift2
  * MIM value is (b + s) mod n_orient}; primary rows (s = dominant index) for
  * keypoints 0..n-1 come first, then the secondary rows (s = second peak)
  * in keypoint order.  inv_norm[row] = fl(1 / fl(sqrt(sum counts^2))),
- * desc_kp[row] = keypoint index.  desc_cap must be >= 2 * kpt_cap.
+ * desc_kp[row] = keypoint index.  desc_cap must be >= 2 * kpt_cap
+ * (RIFT2_DESC_DOMINANT), kpt_cap (RIFT2_DESC_PLAIN) or n_orient * kpt_cap
+ * (RIFT2_DESC_RING, rows k n_orient + w).
  *   n_desc_dev  device int32: number of rows written */
 rift2_status rift2_describe(const uint8_t* mim, int32_t H, int32_t W, const rift2_keypoint* kpts,
                             const int32_t* n_kpts_dev, int32_t kpt_cap, const rift2_desc_params* dp,

@@ -6,7 +6,7 @@ import numpy as np
 from .params import PCParams, DetectParams, DescParams, MatchParams
 from . import filterbank, detect, describe, match
 
-__all__ = ["image_features", "match_pair"]
+__all__ = ["image_features", "match_pair", "ring_match_pair"]
 
 
 def image_features(img, pc=PCParams(), det=DetectParams(), desc=None, dtype=np.float64, keep_amp=False):
@@ -24,3 +24,19 @@ def match_pair(img_a, img_b, pc=PCParams(), det=DetectParams(), mp=MatchParams()
     fb = image_features(img_b, pc, det, dtype=dtype)
     m = match.match(fa["desc"], fa["desc_kp"], fb["desc"], fb["desc_kp"], mp, dtype=dtype)
     return fa, fb, m
+
+
+def ring_match_pair(img_t, img_r, pc=PCParams(), det=DetectParams(), mp=MatchParams(), dtype=np.float64):
+    """RIFT's ring form of one pair (Section 2.3), the baseline RIFT2 replaces: the template's plain
+    descriptors are matched against the N_o ring descriptors of every reference keypoint.
+    Returns (template features, reference features, matches (kp_t, kp_r, d2))."""
+    desc = DescParams(patch_size=det.patch_size, n_orient=pc.n_orient)
+    feats = []
+    for img, form in ((img_t, describe.describe_plain), (img_r, describe.describe_ring)):
+        fm = filterbank.filter_mim(img, pc)
+        kpts, scores = detect.detect(fm["M"], det, dtype=dtype)
+        counts, kp, shift = form(fm["mim"], kpts, desc)
+        feats.append({"fm": fm, "kpts": kpts, "scores": scores, "desc": counts, "desc_kp": kp, "shift": shift})
+    ft, fr = feats
+    m = match.match(ft["desc"], ft["desc_kp"], fr["desc"], fr["desc_kp"], mp, dtype=dtype)
+    return ft, fr, m

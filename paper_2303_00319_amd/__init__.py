@@ -11,13 +11,14 @@ import ctypes
 
 from . import _lib
 from ._lib import (PCParams, DetectParams, DescParams, MatchParams, RansacParams, PREC_FP32, PREC_BF16,  # noqa: F401
-                   PREC_FP8, Rift2Error, STAGES)
+                   PREC_FP8, DESC_DOMINANT, DESC_PLAIN, DESC_RING, Rift2Error, STAGES)
 
 __all__ = [
     "defaults", "init", "filter_mim", "detect", "describe", "match", "Rift2Error", "PairPipeline", "PipelinedPairs",
     "profile_enable", "profile_read", "PCParams", "DetectParams", "DescParams", "MatchParams", "Engine",
     "PREC_FP32", "PREC_BF16", "PREC_FP8", "STAGES", "RansacParams", "ransac", "consensus", "ransac_workspace_bytes",
-    "SIMILARITY_BYTES", "CONSENSUS_BYTES", "similarity_fields", "consensus_fields",
+    "SIMILARITY_BYTES", "CONSENSUS_BYTES", "similarity_fields", "consensus_fields", "DESC_DOMINANT", "DESC_PLAIN",
+    "DESC_RING", "rows_per_keypoint",
 ]
 
 
@@ -197,8 +198,14 @@ def detect(moment, det: DetectParams | None = None, workspace=None, stream=None)
     return kpts, n
 
 
+def rows_per_keypoint(dp):
+    """Descriptor rows a keypoint may produce in the form dp.mode."""
+    return {_lib.DESC_DOMINANT: 2, _lib.DESC_PLAIN: 1, _lib.DESC_RING: dp.n_orient}[dp.mode]
+
+
 def describe(mim, kpts, n_kpts, dp: DescParams | None = None, workspace=None, stream=None):
-    """(desc int16 [2K, D] holding uint16 counts, inv_norm f32 [2K], desc_kp int32 [2K], n_desc int32 [1])."""
+    """(desc int16 [R K, D] holding uint16 counts, inv_norm f32 [R K], desc_kp int32 [R K], n_desc int32 [1]),
+    R = rows_per_keypoint(dp)."""
     torch = _torch()
     if dp is None:
         dp = defaults()[2]
@@ -206,9 +213,10 @@ def describe(mim, kpts, n_kpts, dp: DescParams | None = None, workspace=None, st
     dev = mim.device
     cap = kpts.shape[0]
     d = dp.grid * dp.grid * dp.n_orient
-    desc = torch.empty((2 * cap, d), dtype=torch.int16, device=dev)
-    inv = torch.empty((2 * cap,), dtype=torch.float32, device=dev)
-    dkp = torch.empty((2 * cap,), dtype=torch.int32, device=dev)
+    rows = rows_per_keypoint(dp) * cap
+    desc = torch.empty((rows, d), dtype=torch.int16, device=dev)
+    inv = torch.empty((rows,), dtype=torch.float32, device=dev)
+    dkp = torch.empty((rows,), dtype=torch.int32, device=dev)
     nd = torch.zeros((1,), dtype=torch.int32, device=dev)
     ws = workspace if workspace is not None else torch.empty(describe_workspace_bytes(cap), dtype=torch.uint8,
                                                              device=dev)
@@ -293,9 +301,11 @@ class _ImageBuffers:
         self.M = torch.empty((h, w), dtype=torch.float32, device=dev)
         self.kpts = torch.empty((cap, 3), dtype=torch.int32, device=dev)
         self.nk = torch.zeros((1,), dtype=torch.int32, device=dev)
-        self.desc = torch.empty((2 * cap, d), dtype=torch.int16, device=dev)
-        self.inv = torch.empty((2 * cap,), dtype=torch.float32, device=dev)
-        self.dkp = torch.empty((2 * cap,), dtype=torch.int32, device=dev)
+        self.dp = dp
+        self.rows = rows_per_keypoint(dp) * cap
+        self.desc = torch.empty((self.rows, d), dtype=torch.int16, device=dev)
+        self.inv = torch.empty((self.rows,), dtype=torch.float32, device=dev)
+        self.dkp = torch.empty((self.rows,), dtype=torch.int32, device=dev)
         self.nd = torch.zeros((1,), dtype=torch.int32, device=dev)
         self.ws_filter = torch.empty(filter_workspace_bytes(h, w, pc), dtype=torch.uint8, device=dev)
         self.ws_detect = torch.empty(detect_workspace_bytes(h, w, det), dtype=torch.uint8, device=dev)
@@ -310,10 +320,15 @@ class PairPipeline:
     """
 
     def __init__(self, h, w, pc=None, det=None, dp=None, mp=None, device=0, serial=False, ransac_words=None,
-                 ransac_params=None):
+                 ransac_params=None, ring=False):
         """ransac_words: optional device int32 [n_hyp, 2] uniform sample words; when given, every run ends
         with rift2_ransac on the pair's matches (threshold 3 px, 2 refits unless ransac_params says
-        otherwise), results in ransac_result / ransac_mask."""
+        otherwise), results in ransac_result / ransac_mask.
+
+        ring=True runs RIFT's convolution-sequence ring instead of RIFT2's dominant index (the baseline
+        the paper compares against): image A is the template, described with n_orient ring rows per
+        keypoint (the ring's cost sits on A's side, see rift2_match_params), image B the reference with
+        one plain row per keypoint, and the matching is the ring matching."""
         torch = _torch()
         d_pc, d_det, d_dp, d_mp = defaults()
         self.pc = pc or d_pc
@@ -323,13 +338,21 @@ class PairPipeline:
         self.dev = torch.device("cuda", device)
         init(device)
         self.h, self.w = h, w
-        self.a = _ImageBuffers(h, w, self.pc, self.det, self.dp, self.dev)
-        self.b = _ImageBuffers(h, w, self.pc, self.det, self.dp, self.dev)
+        self.ring = ring
+        dp_a, dp_b = self.dp, self.dp
+        if ring:
+            dp_a, dp_b = DescParams.from_buffer_copy(self.dp), DescParams.from_buffer_copy(self.dp)
+            dp_a.mode, dp_b.mode = DESC_RING, DESC_PLAIN
+            self.mp = MatchParams.from_buffer_copy(self.mp)
+            self.mp.ring = self.dp.n_orient
+        self.a = _ImageBuffers(h, w, self.pc, self.det, dp_a, self.dev)
+        self.b = _ImageBuffers(h, w, self.pc, self.det, dp_b, self.dev)
         cap = 2 * self.det.max_keypoints
         d = self.dp.grid * self.dp.grid * self.dp.n_orient
         self.out = torch.empty((cap, 3), dtype=torch.int32, device=self.dev)
         self.n_out = torch.zeros((1,), dtype=torch.int32, device=self.dev)
-        self.ws_match = torch.empty(match_workspace_bytes(cap, cap, d, self.mp), dtype=torch.uint8, device=self.dev)
+        self.ws_match = torch.empty(match_workspace_bytes(self.a.rows, self.b.rows, d, self.mp), dtype=torch.uint8,
+                                    device=self.dev)
         self.ransac_words = ransac_words
         if ransac_words is not None:
             self.ransac_params = ransac_params or RansacParams(3.0, 2)
@@ -346,7 +369,7 @@ class PairPipeline:
 
     def _keypoints(self, buf, stream):
         detect_into(buf.M, self.det, buf.kpts, buf.nk, buf.ws_detect, stream)
-        describe_into(buf.mim, buf.kpts, buf.nk, self.dp, buf.desc, buf.inv, buf.dkp, buf.nd, buf.ws_desc, stream)
+        describe_into(buf.mim, buf.kpts, buf.nk, buf.dp, buf.desc, buf.inv, buf.dkp, buf.nd, buf.ws_desc, stream)
 
     def _image(self, img, buf, stream):
         self._filter(img, buf, stream)

@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "librift2.so")
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_DEVICE = 0, 1, 2, 3, 4
 U8, U16, F32 = 0, 1, 2
 PREC_FP32, PREC_BF16, PREC_FP8 = 0, 1, 2
+DESC_DOMINANT, DESC_PLAIN, DESC_RING = 0, 1, 2
 
 
 class PCParams(ctypes.Structure):
@@ -40,11 +41,12 @@ class DescParams(ctypes.Structure):
         ("n_orient", ctypes.c_int32),
         ("dominant_num", ctypes.c_int32),
         ("dominant_den", ctypes.c_int32),
+        ("mode", ctypes.c_int32),
     ]
 
 
 class MatchParams(ctypes.Structure):
-    _fields_ = [("ratio_sq", ctypes.c_float), ("precision", ctypes.c_int32)]
+    _fields_ = [("ratio_sq", ctypes.c_float), ("precision", ctypes.c_int32), ("ring", ctypes.c_int32)]
 
 
 class RansacParams(ctypes.Structure):

@@ -368,10 +368,12 @@ void rift2_default_params(rift2_pc_params* pc, rift2_detect_params* det, rift2_d
     desc->n_orient = 6;
     desc->dominant_num = 4;
     desc->dominant_den = 5;
+    desc->mode = RIFT2_DESC_DOMINANT;
   }
   if (match) {
     match->ratio_sq = 0.81f;
     match->precision = RIFT2_PREC_FP32;
+    match->ring = 0;
   }
 }
 
@@ -566,7 +568,11 @@ rift2_status rift2_describe(const uint8_t* mim, int32_t H, int32_t W, const rift
                             size_t workspace_bytes, void* stream) {
   if (!mim || !kpts || !n_kpts_dev || !dp || !desc || !inv_norm || !desc_kp || !n_desc_dev || !workspace)
     return RIFT2_ERR_INVALID_ARG;
-  if (H <= 0 || W <= 0 || kpt_cap <= 0 || desc_cap < 2 * kpt_cap) return RIFT2_ERR_INVALID_ARG;
+  if (H <= 0 || W <= 0 || kpt_cap <= 0) return RIFT2_ERR_INVALID_ARG;
+  if (dp->mode != RIFT2_DESC_DOMINANT && dp->mode != RIFT2_DESC_PLAIN && dp->mode != RIFT2_DESC_RING)
+    return RIFT2_ERR_INVALID_ARG;
+  const int rows_per_kp = dp->mode == RIFT2_DESC_RING ? dp->n_orient : (dp->mode == RIFT2_DESC_PLAIN ? 1 : 2);
+  if ((int64_t)desc_cap < (int64_t)rows_per_kp * kpt_cap) return RIFT2_ERR_INVALID_ARG;
   if (dp->dominant_num < 0 || dp->dominant_den <= 0) return RIFT2_ERR_INVALID_ARG;
   if (workspace_bytes < rift2_describe_workspace_size(kpt_cap)) return RIFT2_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
@@ -574,25 +580,32 @@ rift2_status rift2_describe(const uint8_t* mim, int32_t H, int32_t W, const rift
   const int* kp = (const int*)kpts;
   (void)hipGetLastError();
   const int blocks2 = (kpt_cap + kDesc2Kpts - 1) / kDesc2Kpts;
+  const bool second = dp->mode == RIFT2_DESC_DOMINANT;  // only RIFT2's form has secondary rows
   ProfScope ps(6, st);
   if (dp->patch_size == 96 && dp->grid == 6 && dp->n_orient == 6) {
     constexpr int KPB = desc_kpb<96>();
     hipLaunchKernelGGL((k_describe<96, 6, 6>), dim3((kpt_cap + KPB - 1) / KPB), dim3(96 * KPB), 0, st, mim, H, W, kp,
-                       n_kpts_dev, kpt_cap, dp->dominant_num, dp->dominant_den, desc, inv_norm, desc_kp, info);
-    hipLaunchKernelGGL((k_describe2<6, 6>), dim3(blocks2), dim3(256), 0, st, n_kpts_dev, kpt_cap, info, desc, inv_norm,
-                       desc_kp, n_desc_dev);
+                       n_kpts_dev, kpt_cap, dp->dominant_num, dp->dominant_den, dp->mode, desc, inv_norm, desc_kp,
+                       info, n_desc_dev);
+    if (second)
+      hipLaunchKernelGGL((k_describe2<6, 6>), dim3(blocks2), dim3(256), 0, st, n_kpts_dev, kpt_cap, info, desc,
+                         inv_norm, desc_kp, n_desc_dev);
   } else if (dp->patch_size == 96 && dp->grid == 6 && dp->n_orient == 8) {
     constexpr int KPB = desc_kpb<96>();
     hipLaunchKernelGGL((k_describe<96, 6, 8>), dim3((kpt_cap + KPB - 1) / KPB), dim3(96 * KPB), 0, st, mim, H, W, kp,
-                       n_kpts_dev, kpt_cap, dp->dominant_num, dp->dominant_den, desc, inv_norm, desc_kp, info);
-    hipLaunchKernelGGL((k_describe2<6, 8>), dim3(blocks2), dim3(256), 0, st, n_kpts_dev, kpt_cap, info, desc, inv_norm,
-                       desc_kp, n_desc_dev);
+                       n_kpts_dev, kpt_cap, dp->dominant_num, dp->dominant_den, dp->mode, desc, inv_norm, desc_kp,
+                       info, n_desc_dev);
+    if (second)
+      hipLaunchKernelGGL((k_describe2<6, 8>), dim3(blocks2), dim3(256), 0, st, n_kpts_dev, kpt_cap, info, desc,
+                         inv_norm, desc_kp, n_desc_dev);
   } else if (dp->patch_size == 64 && dp->grid == 4 && dp->n_orient == 6) {
     constexpr int KPB = desc_kpb<64>();
     hipLaunchKernelGGL((k_describe<64, 4, 6>), dim3((kpt_cap + KPB - 1) / KPB), dim3(64 * KPB), 0, st, mim, H, W, kp,
-                       n_kpts_dev, kpt_cap, dp->dominant_num, dp->dominant_den, desc, inv_norm, desc_kp, info);
-    hipLaunchKernelGGL((k_describe2<4, 6>), dim3(blocks2), dim3(256), 0, st, n_kpts_dev, kpt_cap, info, desc, inv_norm,
-                       desc_kp, n_desc_dev);
+                       n_kpts_dev, kpt_cap, dp->dominant_num, dp->dominant_den, dp->mode, desc, inv_norm, desc_kp,
+                       info, n_desc_dev);
+    if (second)
+      hipLaunchKernelGGL((k_describe2<4, 6>), dim3(blocks2), dim3(256), 0, st, n_kpts_dev, kpt_cap, info, desc,
+                         inv_norm, desc_kp, n_desc_dev);
   } else {
     return RIFT2_ERR_UNSUPPORTED;
   }
@@ -611,6 +624,8 @@ rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32
       (mp->precision != RIFT2_PREC_FP32 && mp->precision != RIFT2_PREC_BF16 && mp->precision != RIFT2_PREC_FP8))
     return RIFT2_ERR_INVALID_ARG;
   if (D != 216 && D != 288) return RIFT2_ERR_UNSUPPORTED;
+  if (mp->ring < 0 || mp->ring == 1 || mp->ring > kMaxOrient) return RIFT2_ERR_INVALID_ARG;
+  if (mp->ring && mp->precision == RIFT2_PREC_FP8) return RIFT2_ERR_UNSUPPORTED;
   // the table preparation reads descriptor rows as 16-byte vectors
   if (((uintptr_t)desc_a & 15u) || ((uintptr_t)desc_b & 15u)) return RIFT2_ERR_INVALID_ARG;
   const MatchLayout L = match_layout(cap_a, cap_b, D, mp->precision);
@@ -684,8 +699,12 @@ rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32
   }
   ps8.finish();
   ProfScope ps9(9, st);
-  hipLaunchKernelGGL(k_match_merge, dim3((cap_a + 3) / 4), dim3(256), 0, st, part, 2 * L.slices, nA_dev, kp_a, kp_b,
-                     mp->ratio_sq, cap_a, best, rowj, rowd);
+  if (mp->ring)
+    hipLaunchKernelGGL(k_match_merge_ring, dim3((cap_a / mp->ring + 3) / 4), dim3(256), 0, st, part, 2 * L.slices,
+                       (int)mp->ring, nA_dev, kp_a, kp_b, mp->ratio_sq, cap_a, best, rowj, rowd);
+  else
+    hipLaunchKernelGGL(k_match_merge, dim3((cap_a + 3) / 4), dim3(256), 0, st, part, 2 * L.slices, nA_dev, kp_a, kp_b,
+                       mp->ratio_sq, cap_a, best, rowj, rowd);
   hipLaunchKernelGGL(k_match_emit, dim3((cap_a + 255) / 256), dim3(256), 0, st, best, cap_a, rowj, rowd, kp_b,
                      (MatchOut*)out, n_out_dev);
   return launch_status();
@@ -774,6 +793,7 @@ rift2_status rift2_engine_create(int device, void* arena, size_t arena_bytes, in
                                  const rift2_desc_params* dp, const rift2_match_params* mp, rift2_engine** out) {
   if (!out || !arena || !arena_bytes || !pc || !det || !dp || !mp || max_inflight <= 0 || max_inflight > 64)
     return RIFT2_ERR_INVALID_ARG;
+  if (dp->mode != RIFT2_DESC_DOMINANT || mp->ring != 0) return RIFT2_ERR_UNSUPPORTED;  // the engine serves RIFT2
   if ((uintptr_t)arena & 255u) return RIFT2_ERR_INVALID_ARG;
   *out = nullptr;
   const rift2_status st = rift2_init(device);

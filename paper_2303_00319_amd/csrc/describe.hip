@@ -11,6 +11,12 @@
 //   k_describe2   secondary rows (shift s2) for keypoints whose second peak
 //                 reaches num/den of the first, placed after all primary rows
 //                 in keypoint order.
+//
+// Two more row forms serve RIFT's convolution-sequence ring (Section 2.3),
+// the baseline RIFT2 replaces: kDescPlain writes the cell histograms as they
+// are (no normalisation, one row per keypoint) and kDescRing writes N_o rows
+// per keypoint, row i N_o + w being the histograms of the MIM rebuilt with
+// layer w as the ring's first (bin b counts value (b + w) mod N_o).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -49,6 +55,8 @@ __device__ __forceinline__ float inv_sqrt_rn(uint32_t n) {
   return q;
 }
 
+constexpr int kDescDominant = 0, kDescPlain = 1, kDescRing = 2;
+
 template <int P>
 constexpr int desc_kpb() { return (P % 64 == 0) ? 1 : (P % 32 == 0 ? 2 : 4); }
 
@@ -56,9 +64,10 @@ template <int P, int G, int NO>
 __global__ void __launch_bounds__(P * desc_kpb<P>()) k_describe(const uint8_t* __restrict__ mim, int H, int W,
                                                                 const int* __restrict__ kpts /* x, y, score */,
                                                                 const int32_t* __restrict__ n_kpts, int kpt_cap,
-                                                                int dom_num, int dom_den, uint16_t* __restrict__ desc,
+                                                                int dom_num, int dom_den, int mode,
+                                                                uint16_t* __restrict__ desc,
                                                                 float* __restrict__ inv_norm, int32_t* __restrict__ desc_kp,
-                                                                uint32_t* __restrict__ info) {
+                                                                uint32_t* __restrict__ info, int32_t* __restrict__ n_desc) {
   constexpr int KPB = desc_kpb<P>();
   constexpr int CS = P / G;  // cell side, a power of two dividing 64
   constexpr int D = G * G * NO;
@@ -72,6 +81,8 @@ __global__ void __launch_bounds__(P * desc_kpb<P>()) k_describe(const uint8_t* _
   const int n = min(*n_kpts, kpt_cap);
   const int i = blockIdx.x * KPB + local;
   const bool active = i < n;
+  // plain and ring forms have no secondary rows, so the row count is known here
+  if (mode != kDescDominant && blockIdx.x == 0 && threadIdx.x == 0) *n_desc = (mode == kDescRing ? NO : 1) * n;
   int kx = 0, ky = 0;
   if (active) {
     kx = kpts[3 * i];
@@ -122,8 +133,9 @@ __global__ void __launch_bounds__(P * desc_kpb<P>()) k_describe(const uint8_t* _
     int s2 = (s == 0) ? 1 : 0;
     for (int b = 0; b < NO; ++b)
       if (b != s && hist[local][b] > hist[local][s2]) s2 = b;
-    const bool two = sh_ok[local] &&
+    const bool two = mode == kDescDominant && sh_ok[local] &&
                      (uint64_t)dom_den * hist[local][s2] >= (uint64_t)dom_num * hist[local][s];
+    if (mode != kDescDominant) s = 0;
     sh_s[local] = s;
     sh_delta[local] = (s2 - s + NO) % NO;
     sh_two[local] = two;
@@ -131,8 +143,9 @@ __global__ void __launch_bounds__(P * desc_kpb<P>()) k_describe(const uint8_t* _
   __syncthreads();
   const int s = sh_s[local];
   uint32_t n2 = 0;
+  const int rows_per_kp = mode == kDescRing ? NO : 1;
   if (active) {
-    uint16_t* row = desc + (size_t)i * D;
+    uint16_t* row = desc + (size_t)i * rows_per_kp * D;  // ring: row i NO + 0 (s = 0)
     for (int e = x; e < D; e += P) {
       const int c = e / NO, b = e % NO;
       int bb = b + s;
@@ -143,11 +156,30 @@ __global__ void __launch_bounds__(P * desc_kpb<P>()) k_describe(const uint8_t* _
     }
   }
   atomicAdd(&sh_n2[local], n2);
+  if (mode == kDescRing && active) {
+    // rows i NO + w for w >= 1; the norm is shared (each row permutes the same counts)
+    uint16_t* rows = desc + (size_t)i * NO * D;
+    for (int e = D + x; e < NO * D; e += P) {
+      const int w = e / D, r = e - w * D;
+      const int c = r / NO, b = r - c * NO;
+      int bb = b + w;
+      if (bb >= NO) bb -= NO;
+      rows[e] = (uint16_t)h[local][c][bb];
+    }
+  }
   __syncthreads();
   if (active && x == 0) {
     const uint32_t nn = sh_n2[local];
-    inv_norm[i] = nn ? inv_sqrt_rn(nn) : 0.0f;
-    desc_kp[i] = i;
+    const float inv = nn ? inv_sqrt_rn(nn) : 0.0f;
+    if (mode == kDescRing) {
+      for (int w = 0; w < NO; ++w) {
+        inv_norm[i * NO + w] = inv;
+        desc_kp[i * NO + w] = i;
+      }
+    } else {
+      inv_norm[i] = inv;
+      desc_kp[i] = i;
+    }
     info[i] = sh_two[local] ? (0x100u | (uint32_t)sh_delta[local]) : 0u;
   }
 }

@@ -390,6 +390,73 @@ __global__ void __launch_bounds__(256) k_match_merge(const int2* __restrict__ pa
   atomicMin((unsigned long long*)&best[ka], (unsigned long long)key);
 }
 
+// Ring form (RIFT's convolution-sequence ring, the baseline variant): A holds
+// R consecutive rows per keypoint, row g R + w being keypoint g's counts
+// shifted by w, and B one plain row per keypoint.  The dot product of A row
+// g R + w with B row r equals that of g's plain row with B keypoint r's ring
+// row (R - w) mod R, so candidate (w, r) stands for reference ring row
+// r R + (R - w) mod R, and the nearest / second-nearest choice runs over all R
+// lists of the keypoint with that index order.  Each B row is a different
+// keypoint, so every per-query top-3 list holds the best candidate of a
+// keypoint other than j1's.  One wave per A keypoint; the decision goes
+// straight into best[kp] with g standing for the row.
+__global__ void __launch_bounds__(256) k_match_merge_ring(const int2* __restrict__ part, int lists, int R,
+                                                          const int32_t* __restrict__ na_dev,
+                                                          const int32_t* __restrict__ kp_a,
+                                                          const int32_t* __restrict__ kp_b, float ratio_sq, int cap_a,
+                                                          uint64_t* __restrict__ best, int32_t* __restrict__ row_j1,
+                                                          float* __restrict__ row_d1) {
+  const int lane = threadIdx.x & 63;
+  const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int na = min(*na_dev, cap_a);
+  if (g >= na / R) return;
+  const int per = lists * kTopK;
+  const int total = R * per;
+  const int2* src = part + (size_t)g * R * per;  // the R query rows' lists are contiguous
+  float d1 = INFINITY;
+  int j1 = -1;
+  for (int q = lane; q < total; q += 64) {
+    const int2 e = src[q];
+    if (e.y < 0) continue;
+    const int w = q / per;
+    const int jr = e.y * R + (w == 0 ? 0 : R - w);
+    const float d = __int_as_float(e.x);
+    if (j1 < 0 || better(d, jr, d1, j1)) {
+      d1 = d;
+      j1 = jr;
+    }
+  }
+  wave_argmin(d1, j1);
+  if (j1 < 0) return;
+  const int r1 = j1 / R;
+  const int k1 = kp_b[r1];
+  float d2 = INFINITY;
+  int j2 = -1;
+  for (int q = lane; q < total; q += 64) {
+    const int2 e = src[q];
+    if (e.y < 0 || kp_b[e.y] == k1) continue;
+    const int w = q / per;
+    const int jr = e.y * R + (w == 0 ? 0 : R - w);
+    const float d = __int_as_float(e.x);
+    if (j2 < 0 || better(d, jr, d2, j2)) {
+      d2 = d;
+      j2 = jr;
+    }
+  }
+  wave_argmin(d2, j2);
+  if (lane != 0) return;
+  row_j1[g] = r1;
+  row_d1[g] = d1;
+  if (j2 < 0) return;
+  if (!(d1 < __fmul_rn(ratio_sq, d2))) return;
+  const int ka = kp_a[g * R];
+  if (ka < 0 || ka >= cap_a) return;
+  const uint32_t b = __float_as_uint(d1);
+  const uint32_t ok = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+  const uint64_t key = ((uint64_t)ok << 32) | (uint32_t)g;
+  atomicMin((unsigned long long*)&best[ka], (unsigned long long)key);
+}
+
 struct MatchOut {
   int kp_a, kp_b;
   float dist2;
