@@ -18,6 +18,11 @@ Two forms are timed: plain FP32 (distance GEMM on FP32 MFMA) -- the
 reported `value` -- and mixed (BF16 MFMA on the exact integer counts, the
 same distances bit for bit), reported under "mixed".
 
+The paper's comparison is timed beside them under "rift_ring": the same
+pairs through RIFT's convolution-sequence ring (N_o descriptors per template
+keypoint, N_o-fold matching, no dominant index), with the same detector and
+matching precision, and RIFT2's speed-up over it.
+
 Prints one JSON line.  `--gpus` above 1 is rejected: this build runs on a
 single GPU.
 """
@@ -73,6 +78,9 @@ def parse():
                          "4 = 4096^2 12-bit u16, N_s=5 N_o=8, 50000 keypoints, 288-d")
     ap.add_argument("--forms", default=None,
                     help="matching precisions to time, first one is `value` (default fp32,bf16; config 4: fp8,bf16)")
+    ap.add_argument("--ring-forms", default=None,
+                    help="matching precisions of RIFT's ring form to time beside RIFT2 (default fp32,bf16; "
+                         "config 4: bf16; '' for none)")
     ap.add_argument("--size", type=int, default=0, help="override the image side")
     ap.add_argument("--keypoints", type=int, default=0, help="override the keypoints per image")
     ap.add_argument("--no-graph", action="store_true", help="enqueue kernels directly instead of graph replay")
@@ -134,11 +142,11 @@ def _ransac_words(torch, n_hyp, seed=0):
     return torch.from_numpy(sample_words(seed, n_hyp).view("int32").copy()).to(torch.device("cuda:0"))
 
 
-def time_single(r2, torch, imgs, args, precision):
+def time_single(r2, torch, imgs, args, precision, ring=False):
     """One pair per step, nothing overlapped: a replayed graph per resident pair."""
     pc, det, dp, mp = _form_params(r2, args, precision)
     words = _ransac_words(torch, args.ransac) if args.ransac > 0 else None
-    pipe = r2.PairPipeline(args.size, args.size, pc, det, dp, mp, serial=args.serial, ransac_words=words)
+    pipe = r2.PairPipeline(args.size, args.size, pc, det, dp, mp, serial=args.serial, ransac_words=words, ring=ring)
     graphs = []
     if not args.no_graph:
         for i, (a, b) in enumerate(imgs):
@@ -489,8 +497,16 @@ def main():
         print(f"[bench] timing {f}", file=sys.stderr, flush=True)
         timed[f] = time_form(r2, torch, imgs, args, prec[f])
         print(f"[bench] {f} {timed[f]['pairs_per_s']:.1f} pairs/s", file=sys.stderr, flush=True)
+    ring_forms = [f for f in (args.ring_forms if args.ring_forms is not None else
+                              ("bf16" if args.config == 4 else "fp32,bf16")).split(",") if f]
+    ring = {}
+    for f in ring_forms:
+        print(f"[bench] timing RIFT ring {f}", file=sys.stderr, flush=True)
+        ring[f] = time_single(r2, torch, imgs, args, prec[f], ring=True)
+        print(f"[bench] ring {f} {ring[f]['pairs_per_s']:.1f} pairs/s", file=sys.stderr, flush=True)
     print("[bench] profiling stages", file=sys.stderr, flush=True)
     stages = {f: profile_stages(r2, torch, timed[f]["pipe"], imgs, args.profile_steps) for f in forms}
+    ring_stages = {f: profile_stages(r2, torch, ring[f]["pipe"], imgs, args.profile_steps) for f in ring_forms}
     main_form = forms[0]
     d = args.n_orient * 36
     # matching GEMM utilisation (flops of the last pair's actual row counts)
@@ -541,7 +557,25 @@ def main():
         "stages_ms": {f: {k: round(v["ms_avg"], 5) for k, v in stages[f].items()} for f in forms},
         "cpu_baseline": cpu,
         "outliers": outliers,
+        "rift_ring": None,
     }
+    if ring:
+        line["rift_ring"] = {
+            "workload": "same pairs, detector and precision; template described with all N_o ring members, "
+                        "reference with one plain row per keypoint, N_o-fold matching (RIFT, Section 2.3)",
+            "paper_ratio_cpu": {"sar_optical": round(29.24 / 10.93, 3), "ir_optical": round(35.82 / 13.24, 3),
+                                "note": "RIFT (MATLAB) / RIFT2 (C++) running time per pair, Table 2"},
+        }
+        for f in ring_forms:
+            t = ring[f]
+            base = timed.get(f)
+            line["rift_ring"][f] = {
+                "pairs_per_s": round(t["pairs_per_s"], 2), "ms_per_step": round(t["ms_per_step"], 4),
+                "p50_ms": round(t["p50_ms"], 4), "p99_ms": round(t["p99_ms"], 4),
+                "descriptor_rows": t["last_pair"]["descriptor_rows"], "matches": t["last_pair"]["matches"],
+                "stages_ms": {k: round(v["ms_avg"], 5) for k, v in ring_stages[f].items()},
+                "rift2_speedup": round(base["pairs_per_s"] / t["pairs_per_s"], 3) if base else None,
+            }
     if args.ransac > 0:
         line["config"]["ransac_hypotheses_in_step"] = args.ransac
     for f in forms[1:]:
