@@ -192,6 +192,18 @@ rift2_status rift2_detect(const float* moment, int32_t H, int32_t W, const rift2
                           rift2_keypoint* kpts, int32_t* n_kpts_dev, void* workspace,
                           size_t workspace_bytes, void* stream);
 
+/* RIFT's full detector (Section 2.1): FAST points on the maximum-moment map
+ * (edge features) and on the minimum-moment map (corners), each map with its
+ * own min-max normalisation, scores, 3x3 suppression and border mask as in
+ * rift2_detect, then their union: a pixel kept on both maps appears once with
+ * the larger of its two scores, and the max_keypoints strongest of the union
+ * are taken by (score desc, y*W+x asc).  Both maps 16-byte aligned; the
+ * workspace comes from rift2_detect_union_workspace_size. */
+size_t rift2_detect_union_workspace_size(int H, int W, const rift2_detect_params* det);
+rift2_status rift2_detect_union(const float* max_moment, const float* min_moment, int32_t H, int32_t W,
+                                const rift2_detect_params* det, rift2_keypoint* kpts, int32_t* n_kpts_dev,
+                                void* workspace, size_t workspace_bytes, void* stream);
+
 /* Dominant-index descriptors (Section 3, Eqs. 1-2) of the first *n_kpts_dev
  * keypoints (at most kpt_cap) on a 0-based MIM.  Row layout: uint16 counts
  * desc[row][(cy*grid + cx)*n_orient + b] = #{pixels of cell (cy, cx) whose

@@ -22,7 +22,7 @@ import numpy as np
 from .params import DetectParams
 
 __all__ = ["CIRCLE", "normalise", "fast_scores", "nms", "border_mask", "top_k", "detect",
-           "fast_score_bruteforce"]
+           "fast_score_bruteforce", "detect_union"]
 
 # (dx, dy) around the circle, clockwise starting straight above the centre.
 CIRCLE = [(0, -3), (1, -3), (2, -2), (3, -1), (3, 0), (3, 1), (2, 2), (1, 3),
@@ -128,3 +128,22 @@ def detect(d: np.ndarray, p: DetectParams = DetectParams(), dtype=np.float64):
     sc = fast_scores(dn)
     keep = nms(sc, p.fast_threshold) & border_mask(*dn.shape, p.patch_size)
     return top_k(sc, keep, p.max_keypoints)
+
+
+def detect_union(d_edge: np.ndarray, d_corner: np.ndarray, p: DetectParams = DetectParams(), dtype=np.float64):
+    """RIFT's detector (Section 2.1): FAST on the maximum-moment map (edge features) and on the
+    minimum-moment map (corners), steps 1-4 on each map separately, then the union of the two point
+    sets -- a pixel found on both keeps the larger score -- and step 5 on the union."""
+    h, w = np.shape(d_edge)
+    score = np.zeros((h, w), dtype=dtype)
+    keep = np.zeros((h, w), dtype=bool)
+    border = border_mask(h, w, p.patch_size)
+    for d in (d_edge, d_corner):
+        dn = normalise(d, dtype)
+        if dn is None:
+            continue
+        sc = fast_scores(dn)
+        k = nms(sc, p.fast_threshold) & border
+        score = np.where(k & keep, np.maximum(score, sc), np.where(k, sc, score)).astype(dtype)
+        keep |= k
+    return top_k(score, keep, p.max_keypoints)

@@ -18,7 +18,7 @@ __all__ = [
     "profile_enable", "profile_read", "PCParams", "DetectParams", "DescParams", "MatchParams", "Engine",
     "PREC_FP32", "PREC_BF16", "PREC_FP8", "STAGES", "RansacParams", "ransac", "consensus", "ransac_workspace_bytes",
     "SIMILARITY_BYTES", "CONSENSUS_BYTES", "similarity_fields", "consensus_fields", "DESC_DOMINANT", "DESC_PLAIN",
-    "DESC_RING", "rows_per_keypoint",
+    "DESC_RING", "rows_per_keypoint", "detect_union",
 ]
 
 
@@ -81,6 +81,10 @@ def detect_workspace_bytes(h, w, det):
     return _lib.load().rift2_detect_workspace_size(h, w, ctypes.byref(det))
 
 
+def detect_union_workspace_bytes(h, w, det):
+    return _lib.load().rift2_detect_union_workspace_size(h, w, ctypes.byref(det))
+
+
 def describe_workspace_bytes(cap):
     return _lib.load().rift2_describe_workspace_size(cap)
 
@@ -115,6 +119,14 @@ def detect_into(moment, det, kpts, n, ws, stream=None):
     st = lib.rift2_detect(_ptr(moment), h, w, ctypes.byref(det), _ptr(kpts), _ptr(n), _ptr(ws), _nbytes(ws),
                           _stream(stream))
     _lib.check(st, "rift2_detect")
+
+
+def detect_union_into(max_moment, min_moment, det, kpts, n, ws, stream=None):
+    lib = _lib.load()
+    h, w = max_moment.shape
+    st = lib.rift2_detect_union(_ptr(max_moment), _ptr(min_moment), h, w, ctypes.byref(det), _ptr(kpts), _ptr(n),
+                                _ptr(ws), _nbytes(ws), _stream(stream))
+    _lib.check(st, "rift2_detect_union")
 
 
 def describe_into(mim, kpts, n_kpts, dp, desc, inv, dkp, nd, ws, stream=None):
@@ -201,6 +213,22 @@ def detect(moment, det: DetectParams | None = None, workspace=None, stream=None)
 def rows_per_keypoint(dp):
     """Descriptor rows a keypoint may produce in the form dp.mode."""
     return {_lib.DESC_DOMINANT: 2, _lib.DESC_PLAIN: 1, _lib.DESC_RING: dp.n_orient}[dp.mode]
+
+
+def detect_union(max_moment, min_moment, det: DetectParams | None = None, workspace=None, stream=None):
+    """RIFT's corner + edge union: (keypoints int32 [K, 3] = x, y, score bits; n int32 [1])."""
+    torch = _torch()
+    if det is None:
+        det = defaults()[1]
+    init(max_moment.device.index or 0)
+    h, w = max_moment.shape
+    dev = max_moment.device
+    kpts = torch.empty((det.max_keypoints, 3), dtype=torch.int32, device=dev)
+    n = torch.zeros((1,), dtype=torch.int32, device=dev)
+    ws = workspace if workspace is not None else torch.empty(detect_union_workspace_bytes(h, w, det),
+                                                             dtype=torch.uint8, device=dev)
+    detect_union_into(max_moment, min_moment, det, kpts, n, ws, stream)
+    return kpts, n
 
 
 def describe(mim, kpts, n_kpts, dp: DescParams | None = None, workspace=None, stream=None):
@@ -293,8 +321,10 @@ def consensus(model, matches, n_matches, kpts_a, kpts_b, threshold=3.0, stream=N
 # ----------------------------------------------------------------- whole pair with resident buffers
 
 class _ImageBuffers:
-    def __init__(self, h, w, pc, det, dp, dev):
+    def __init__(self, h, w, pc, det, dp, dev, union=False):
         torch = _torch()
+        self.union = union
+        self.m = torch.empty((h, w), dtype=torch.float32, device=dev) if union else None
         cap = det.max_keypoints
         d = dp.grid * dp.grid * dp.n_orient
         self.mim = torch.empty((h, w), dtype=torch.uint8, device=dev)
@@ -308,7 +338,8 @@ class _ImageBuffers:
         self.dkp = torch.empty((self.rows,), dtype=torch.int32, device=dev)
         self.nd = torch.zeros((1,), dtype=torch.int32, device=dev)
         self.ws_filter = torch.empty(filter_workspace_bytes(h, w, pc), dtype=torch.uint8, device=dev)
-        self.ws_detect = torch.empty(detect_workspace_bytes(h, w, det), dtype=torch.uint8, device=dev)
+        ws_det = detect_union_workspace_bytes(h, w, det) if union else detect_workspace_bytes(h, w, det)
+        self.ws_detect = torch.empty(ws_det, dtype=torch.uint8, device=dev)
         self.ws_desc = torch.empty(describe_workspace_bytes(cap), dtype=torch.uint8, device=dev)
 
 
@@ -320,7 +351,7 @@ class PairPipeline:
     """
 
     def __init__(self, h, w, pc=None, det=None, dp=None, mp=None, device=0, serial=False, ransac_words=None,
-                 ransac_params=None, ring=False):
+                 ransac_params=None, ring=False, union=False):
         """ransac_words: optional device int32 [n_hyp, 2] uniform sample words; when given, every run ends
         with rift2_ransac on the pair's matches (threshold 3 px, 2 refits unless ransac_params says
         otherwise), results in ransac_result / ransac_mask.
@@ -328,7 +359,10 @@ class PairPipeline:
         ring=True runs RIFT's convolution-sequence ring instead of RIFT2's dominant index (the baseline
         the paper compares against): image A is the template, described with n_orient ring rows per
         keypoint (the ring's cost sits on A's side, see rift2_match_params), image B the reference with
-        one plain row per keypoint, and the matching is the ring matching."""
+        one plain row per keypoint, and the matching is the ring matching.
+
+        union=True detects with RIFT's corner + edge union (FAST on the minimum- and the maximum-moment
+        maps) instead of the maximum-moment map alone."""
         torch = _torch()
         d_pc, d_det, d_dp, d_mp = defaults()
         self.pc = pc or d_pc
@@ -345,8 +379,8 @@ class PairPipeline:
             dp_a.mode, dp_b.mode = DESC_RING, DESC_PLAIN
             self.mp = MatchParams.from_buffer_copy(self.mp)
             self.mp.ring = self.dp.n_orient
-        self.a = _ImageBuffers(h, w, self.pc, self.det, dp_a, self.dev)
-        self.b = _ImageBuffers(h, w, self.pc, self.det, dp_b, self.dev)
+        self.a = _ImageBuffers(h, w, self.pc, self.det, dp_a, self.dev, union)
+        self.b = _ImageBuffers(h, w, self.pc, self.det, dp_b, self.dev, union)
         cap = 2 * self.det.max_keypoints
         d = self.dp.grid * self.dp.grid * self.dp.n_orient
         self.out = torch.empty((cap, 3), dtype=torch.int32, device=self.dev)
@@ -365,10 +399,13 @@ class PairPipeline:
         self.serial = serial
 
     def _filter(self, img, buf, stream):
-        filter_mim_into(img, self.pc, buf.mim, buf.M, None, None, buf.ws_filter, stream)
+        filter_mim_into(img, self.pc, buf.mim, buf.M, buf.m, None, buf.ws_filter, stream)
 
     def _keypoints(self, buf, stream):
-        detect_into(buf.M, self.det, buf.kpts, buf.nk, buf.ws_detect, stream)
+        if buf.union:
+            detect_union_into(buf.M, buf.m, self.det, buf.kpts, buf.nk, buf.ws_detect, stream)
+        else:
+            detect_into(buf.M, self.det, buf.kpts, buf.nk, buf.ws_detect, stream)
         describe_into(buf.mim, buf.kpts, buf.nk, buf.dp, buf.desc, buf.inv, buf.dkp, buf.nd, buf.ws_desc, stream)
 
     def _image(self, img, buf, stream):

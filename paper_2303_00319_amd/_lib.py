@@ -83,7 +83,8 @@ EXPORTS = [
     "rift2_match_workspace_size", "rift2_filter_mim", "rift2_detect", "rift2_describe", "rift2_match",
     "rift2_profile_enable", "rift2_profile_read", "rift2_engine_request_bytes", "rift2_engine_create",
     "rift2_engine_submit", "rift2_engine_poll", "rift2_engine_pending", "rift2_engine_destroy",
-    "rift2_ransac_workspace_size", "rift2_ransac", "rift2_consensus",
+    "rift2_ransac_workspace_size", "rift2_ransac", "rift2_consensus", "rift2_detect_union_workspace_size",
+    "rift2_detect_union",
 ]
 STAGES = ["row_dft", "pass_a", "noise_pre", "noise_sel", "pass_b", "detect", "describe", "match_prep",
           "match_gemm", "match_merge", "pass_b_reduce", "ransac"]
@@ -131,6 +132,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rift2_describe.restype = ctypes.c_int
     lib.rift2_match.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, i32, i32, P(MatchParams), vp, vp, vp, sz, vp]
     lib.rift2_match.restype = ctypes.c_int
+    lib.rift2_detect_union_workspace_size.argtypes = [ctypes.c_int, ctypes.c_int, P(DetectParams)]
+    lib.rift2_detect_union_workspace_size.restype = sz
+    lib.rift2_detect_union.argtypes = [vp, vp, i32, i32, P(DetectParams), vp, vp, vp, sz, vp]
+    lib.rift2_detect_union.restype = ctypes.c_int
     lib.rift2_ransac_workspace_size.argtypes = [i32, i32]
     lib.rift2_ransac_workspace_size.restype = sz
     lib.rift2_ransac.argtypes = [vp, vp, i32, vp, i32, vp, i32, vp, i32, P(RansacParams), vp, vp, vp, vp, sz, vp]

@@ -87,14 +87,15 @@ struct DetectLayout {
   uint32_t region;
 };
 
-DetectLayout detect_layout(int H, int W, const rift2_detect_params* d) {
+// maps = 2: the corner + edge union, whose candidate lists are twice the tiles.
+DetectLayout detect_layout(int H, int W, const rift2_detect_params* d, int maps = 1) {
   DetectLayout L;
   Carver c;
-  L.n_tiles = ((W + kTileX - 1) / kTileX) * ((H + kTileY - 1) / kTileY);
+  L.n_tiles = maps * ((W + kTileX - 1) / kTileX) * ((H + kTileY - 1) / kTileY);
   const size_t slots = (size_t)L.n_tiles * kTileCap;
   L.region = (uint32_t)(((L.n_tiles + kSelBlocks - 1) / kSelBlocks) * kTileCap);  // k_det_select1 tiles per block
   L.hdr = c.take(64);
-  L.mm = c.take(2 * kMinMaxBlocks * sizeof(uint32_t));
+  L.mm = c.take(2 * maps * kMinMaxBlocks * sizeof(uint32_t));
   L.hist = c.take(kDetHistBins * sizeof(uint32_t));
   L.tile_cnt = c.take((size_t)L.n_tiles * sizeof(uint32_t));
   L.cand = c.take(slots * sizeof(uint64_t));
@@ -422,6 +423,11 @@ size_t rift2_detect_workspace_size(int H, int W, const rift2_detect_params* det)
   return detect_layout(H, W, det).total;
 }
 
+size_t rift2_detect_union_workspace_size(int H, int W, const rift2_detect_params* det) {
+  if (H <= 0 || W <= 0 || !det || det->max_keypoints <= 0) return 0;
+  return detect_layout(H, W, det, 2).total;
+}
+
 size_t rift2_describe_workspace_size(int32_t kpt_cap) {
   if (kpt_cap <= 0) return 0;
   return align_up((size_t)kpt_cap * sizeof(uint32_t));
@@ -524,15 +530,16 @@ rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t
   return launch_status();
 }
 
-rift2_status rift2_detect(const float* moment, int32_t H, int32_t W, const rift2_detect_params* det,
-                          rift2_keypoint* kpts, int32_t* n_kpts_dev, void* workspace, size_t workspace_bytes,
-                          void* stream) {
-  if (!moment || !det || !kpts || !n_kpts_dev || !workspace) return RIFT2_ERR_INVALID_ARG;
-  if ((uintptr_t)moment & 15u) return RIFT2_ERR_INVALID_ARG;  // 16-byte loads
+static rift2_status detect_launch(const float* edge, const float* corner, int32_t H, int32_t W,
+                                  const rift2_detect_params* det, rift2_keypoint* kpts, int32_t* n_kpts_dev,
+                                  void* workspace, size_t workspace_bytes, void* stream) {
+  if (!edge || !det || !kpts || !n_kpts_dev || !workspace) return RIFT2_ERR_INVALID_ARG;
+  if (((uintptr_t)edge & 15u) || ((uintptr_t)corner & 15u)) return RIFT2_ERR_INVALID_ARG;  // 16-byte loads
   if (H < 8 || W < 8 || (int64_t)H * W >= (1ll << 31)) return RIFT2_ERR_INVALID_ARG;
   if (!(det->fast_threshold >= 0.0f) || det->max_keypoints <= 0 || det->patch_size < 0 || (det->patch_size & 1))
     return RIFT2_ERR_INVALID_ARG;
-  const DetectLayout L = detect_layout(H, W, det);
+  const int maps = corner ? 2 : 1;
+  const DetectLayout L = detect_layout(H, W, det, maps);
   if (workspace_bytes < L.total) return RIFT2_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   char* ws = (char*)workspace;
@@ -548,9 +555,17 @@ rift2_status rift2_detect(const float* moment, int32_t H, int32_t W, const rift2
   (void)hipGetLastError();
   ProfScope ps(5, st);
   const int n = H * W;
-  hipLaunchKernelGGL(k_det_minmax, dim3(kMinMaxBlocks), dim3(256), 0, st, moment, n, mm, hist);
-  hipLaunchKernelGGL(k_det_fast, dim3((W + kTileX - 1) / kTileX, (H + kTileY - 1) / kTileY), dim3(kTileX * kTileY), 0, st,
-                     moment, H, W, det->fast_threshold, det->patch_size / 2, mm, hist, tile_cnt, cand);
+  const dim3 tiles((W + kTileX - 1) / kTileX, (H + kTileY - 1) / kTileY);
+  hipLaunchKernelGGL(k_det_minmax, dim3(kMinMaxBlocks), dim3(256), 0, st, edge, n, mm, hist);
+  if (corner) {
+    uint32_t* mm2 = mm + 2 * kMinMaxBlocks;
+    hipLaunchKernelGGL(k_det_minmax, dim3(kMinMaxBlocks), dim3(256), 0, st, corner, n, mm2, hist);
+    hipLaunchKernelGGL(k_det_fast_union, tiles, dim3(kTileX * kTileY), 0, st, edge, corner, H, W, det->fast_threshold,
+                       det->patch_size / 2, (const uint32_t*)mm, (const uint32_t*)mm2, hist, tile_cnt, cand);
+  } else {
+    hipLaunchKernelGGL(k_det_fast, tiles, dim3(kTileX * kTileY), 0, st, edge, H, W, det->fast_threshold,
+                       det->patch_size / 2, mm, hist, tile_cnt, cand);
+  }
   const uint32_t kmax = (uint32_t)det->max_keypoints;
   hipLaunchKernelGGL(k_det_bin, dim3(1), dim3(1024), 0, st, hdr, hist, kmax);
   hipLaunchKernelGGL(k_det_select1, dim3(kSelBlocks), dim3(256), 0, st, hdr, tile_cnt, L.n_tiles, cand, sel, sel_cnt);
@@ -560,6 +575,19 @@ rift2_status rift2_detect(const float* moment, int32_t H, int32_t W, const rift2
   hipLaunchKernelGGL(k_det_emit, dim3(blocks), dim3(256), 0, st, hdr, fin, part, L.n_part, kmax, W,
                      (KeypointOut*)kpts, n_kpts_dev);
   return launch_status();
+}
+
+rift2_status rift2_detect(const float* moment, int32_t H, int32_t W, const rift2_detect_params* det,
+                          rift2_keypoint* kpts, int32_t* n_kpts_dev, void* workspace, size_t workspace_bytes,
+                          void* stream) {
+  return detect_launch(moment, nullptr, H, W, det, kpts, n_kpts_dev, workspace, workspace_bytes, stream);
+}
+
+rift2_status rift2_detect_union(const float* max_moment, const float* min_moment, int32_t H, int32_t W,
+                                const rift2_detect_params* det, rift2_keypoint* kpts, int32_t* n_kpts_dev,
+                                void* workspace, size_t workspace_bytes, void* stream) {
+  if (!min_moment) return RIFT2_ERR_INVALID_ARG;
+  return detect_launch(max_moment, min_moment, H, W, det, kpts, n_kpts_dev, workspace, workspace_bytes, stream);
 }
 
 rift2_status rift2_describe(const uint8_t* mim, int32_t H, int32_t W, const rift2_keypoint* kpts,

@@ -112,22 +112,24 @@ constexpr int kTileCap = (kTileX / 2) * (kTileY / 2);
 
 static_assert(kTileX * kTileY == kMinMaxBlocks, "one min/max partial per k_det_fast thread");
 
-__global__ void __launch_bounds__(kTileX * kTileY) k_det_fast(const float* __restrict__ d, int H, int W, float thr,
-                                                              int half_patch, const uint32_t* __restrict__ mm,
-                                                              uint32_t* __restrict__ hist, uint32_t* __restrict__ tile_cnt,
-                                                              uint64_t* __restrict__ cand) {
-  constexpr int LX = kTileX + 2 * kHalo, LY = kTileY + 2 * kHalo;
-  constexpr int SX = kTileX + 2, SY = kTileY + 2;
-  __shared__ float sd[LY][LX];
-  __shared__ float ss[SY][SX];
-  __shared__ uint32_t s_count;
-  __shared__ uint32_t s_red[2][4];
-  const int tile = blockIdx.y * gridDim.x + blockIdx.x;
+constexpr int kLX = kTileX + 2 * kHalo, kLY = kTileY + 2 * kHalo;
+constexpr int kSX = kTileX + 2, kSY = kTileY + 2;
+
+// One map's FAST stage for this block's tile: global min / max from the
+// kMinMaxBlocks partials `mm`, the normalised tile plus halo in `sd`, scores
+// of the tile plus a one-pixel ring in `ss`, then 3x3 suppression and the
+// patch-border mask.  Returns whether this thread's pixel survives, with its
+// score in `sc`.  A flat map (max == min) has no keypoints.  Every thread of
+// the block must call it (it holds barriers).
+__device__ __forceinline__ bool tile_fast(const float* __restrict__ d, int H, int W, float thr, int half_patch,
+                                          const uint32_t* __restrict__ mm, float (&sd)[kLY][kLX],
+                                          float (&ss)[kSY][kSX], uint32_t (&s_red)[2][4], float& sc) {
   uint32_t klo = mm[2 * threadIdx.x], khi = mm[2 * threadIdx.x + 1];
   for (int off = 32; off > 0; off >>= 1) {
     klo = min(klo, (uint32_t)__shfl_xor((int)klo, off));
     khi = max(khi, (uint32_t)__shfl_xor((int)khi, off));
   }
+  __syncthreads();  // s_red may still be read by a previous call
   if ((threadIdx.x & 63) == 0) {
     s_red[0][threadIdx.x >> 6] = klo;
     s_red[1][threadIdx.x >> 6] = khi;
@@ -137,15 +139,12 @@ __global__ void __launch_bounds__(kTileX * kTileY) k_det_fast(const float* __res
   khi = max(max(s_red[1][0], s_red[1][1]), max(s_red[1][2], s_red[1][3]));
   const float lo = float_from_order_key(klo);
   const float hi = float_from_order_key(khi);
-  if (!(hi > lo)) {  // flat map: no keypoints (uniform across the grid)
-    if (threadIdx.x == 0) tile_cnt[tile] = 0u;
-    return;
-  }
-  if (threadIdx.x == 0) s_count = 0u;
+  sc = 0.0f;
+  if (!(hi > lo)) return false;  // uniform across the grid
   const float rng = __fsub_rn(hi, lo);
   const int x0 = blockIdx.x * kTileX - kHalo, y0 = blockIdx.y * kTileY - kHalo;
-  for (int i = threadIdx.x; i < LX * LY; i += blockDim.x) {
-    const int ly = i / LX, lx = i % LX;
+  for (int i = threadIdx.x; i < kLX * kLY; i += blockDim.x) {
+    const int ly = i / kLX, lx = i % kLX;
     const int gy = y0 + ly, gx = x0 + lx;
     float v = 0.0f;
     if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = __fdiv_rn(__fsub_rn(d[(size_t)gy * W + gx], lo), rng);
@@ -153,25 +152,24 @@ __global__ void __launch_bounds__(kTileX * kTileY) k_det_fast(const float* __res
   }
   __syncthreads();
   // scores of the tile plus a one-pixel ring
-  for (int i = threadIdx.x; i < SX * SY; i += blockDim.x) {
-    const int sy = i / SX, sx = i % SX;
+  for (int i = threadIdx.x; i < kSX * kSY; i += blockDim.x) {
+    const int sy = i / kSX, sx = i % kSX;
     const int gy = y0 + kHalo - 1 + sy, gx = x0 + kHalo - 1 + sx;
-    float sc = 0.0f;
+    float v = 0.0f;
     if (gy >= 3 && gy <= H - 4 && gx >= 3 && gx <= W - 4) {
       const int cy = sy + kHalo - 1, cx = sx + kHalo - 1;
       const float c[16] = {sd[cy - 3][cx], sd[cy - 3][cx + 1], sd[cy - 2][cx + 2], sd[cy - 1][cx + 3],
                            sd[cy][cx + 3],     sd[cy + 1][cx + 3], sd[cy + 2][cx + 2], sd[cy + 3][cx + 1],
                            sd[cy + 3][cx],     sd[cy + 3][cx - 1], sd[cy + 2][cx - 2], sd[cy + 1][cx - 3],
                            sd[cy][cx - 3],     sd[cy - 1][cx - 3], sd[cy - 2][cx - 2], sd[cy - 3][cx - 1]};
-      sc = fast_score(c, sd[cy][cx]);
+      v = fast_score(c, sd[cy][cx]);
     }
-    ss[sy][sx] = sc;
+    ss[sy][sx] = v;
   }
   __syncthreads();
   const int tx = threadIdx.x % kTileX, ty = threadIdx.x / kTileX;
   const int gx = blockIdx.x * kTileX + tx, gy = blockIdx.y * kTileY + ty;
   bool keep = false;
-  float sc = 0.0f;
   if (gx < W && gy < H) {
     sc = ss[ty + 1][tx + 1];
     keep = sc > thr;
@@ -190,23 +188,83 @@ __global__ void __launch_bounds__(kTileX * kTileY) k_det_fast(const float* __res
     }
     keep = keep && gy >= half_patch && gy <= H - half_patch && gx >= half_patch && gx <= W - half_patch;
   }
+  return keep;
+}
+
+// Appends the block's surviving pixels (score sc) to the slots of list
+// `tile`, counted in s_count, plus the score histogram.
+__device__ __forceinline__ void tile_append(bool keep, float sc, int W, int tile, uint32_t* s_count,
+                                            uint32_t* __restrict__ hist, uint64_t* __restrict__ cand) {
   const uint64_t mask = __ballot(keep);
-  if (mask) {
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((unsigned long long)mask) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&s_count, (uint32_t)__popcll(mask));
-    base = __shfl(base, leader);
-    if (keep) {
-      const uint32_t raster = (uint32_t)gy * (uint32_t)W + (uint32_t)gx;
-      const uint32_t sb = __float_as_uint(sc);
-      cand[(size_t)tile * kTileCap + base + __popcll(mask & ((1ull << lane) - 1ull))] =
-          ((uint64_t)sb << 32) | (uint64_t)(~raster);
-      atomicAdd(&hist[min(sb >> 16, (uint32_t)(kDetHistBins - 1))], 1u);
-    }
+  if (!mask) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(s_count, (uint32_t)__popcll(mask));
+  base = __shfl(base, leader);
+  if (keep) {
+    const int gx = blockIdx.x * kTileX + (int)(threadIdx.x % kTileX);
+    const int gy = blockIdx.y * kTileY + (int)(threadIdx.x / kTileX);
+    const uint32_t raster = (uint32_t)gy * (uint32_t)W + (uint32_t)gx;
+    const uint32_t sb = __float_as_uint(sc);
+    cand[(size_t)tile * kTileCap + base + __popcll(mask & ((1ull << lane) - 1ull))] =
+        ((uint64_t)sb << 32) | (uint64_t)(~raster);
+    atomicAdd(&hist[min(sb >> 16, (uint32_t)(kDetHistBins - 1))], 1u);
   }
+}
+
+__global__ void __launch_bounds__(kTileX * kTileY) k_det_fast(const float* __restrict__ d, int H, int W, float thr,
+                                                              int half_patch, const uint32_t* __restrict__ mm,
+                                                              uint32_t* __restrict__ hist, uint32_t* __restrict__ tile_cnt,
+                                                              uint64_t* __restrict__ cand) {
+  __shared__ float sd[kLY][kLX];
+  __shared__ float ss[kSY][kSX];
+  __shared__ uint32_t s_count;
+  __shared__ uint32_t s_red[2][4];
+  const int tile = blockIdx.y * gridDim.x + blockIdx.x;
+  if (threadIdx.x == 0) s_count = 0u;
+  float sc;
+  const bool keep = tile_fast(d, H, W, thr, half_patch, mm, sd, ss, s_red, sc);
+  tile_append(keep, sc, W, tile, &s_count, hist, cand);
   __syncthreads();
   if (threadIdx.x == 0) tile_cnt[tile] = s_count;
+}
+
+// RIFT's detector (Section 2.1): FAST points on the maximum-moment map
+// (edges) and on the minimum-moment map (corners), each map with its own
+// normalisation, scores and suppression, then their union.  A pixel kept on
+// both maps appears once, in the first map's list, with the larger score;
+// the second map's other survivors go to list n_tiles + tile.  Each list is
+// one map's suppression survivors, so kTileCap bounds both.
+__global__ void __launch_bounds__(kTileX * kTileY) k_det_fast_union(const float* __restrict__ d_edge,
+                                                                    const float* __restrict__ d_corner, int H, int W,
+                                                                    float thr, int half_patch,
+                                                                    const uint32_t* __restrict__ mm_edge,
+                                                                    const uint32_t* __restrict__ mm_corner,
+                                                                    uint32_t* __restrict__ hist,
+                                                                    uint32_t* __restrict__ tile_cnt,
+                                                                    uint64_t* __restrict__ cand) {
+  __shared__ float sd[kLY][kLX];
+  __shared__ float ss[kSY][kSX];
+  __shared__ uint32_t s_count[2];
+  __shared__ uint32_t s_red[2][4];
+  const int tile = blockIdx.y * gridDim.x + blockIdx.x;
+  const int n_tiles = gridDim.x * gridDim.y;
+  if (threadIdx.x == 0) {
+    s_count[0] = 0u;
+    s_count[1] = 0u;
+  }
+  float sc_e, sc_c;
+  const bool keep_e = tile_fast(d_edge, H, W, thr, half_patch, mm_edge, sd, ss, s_red, sc_e);
+  const bool keep_c = tile_fast(d_corner, H, W, thr, half_patch, mm_corner, sd, ss, s_red, sc_c);
+  const float sc_first = keep_c ? fmaxf(sc_e, sc_c) : sc_e;
+  tile_append(keep_e, sc_first, W, tile, &s_count[0], hist, cand);
+  tile_append(keep_c && !keep_e, sc_c, W, n_tiles + tile, &s_count[1], hist, cand);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    tile_cnt[tile] = s_count[0];
+    tile_cnt[n_tiles + tile] = s_count[1];
+  }
 }
 
 // One block: candidate total n, the score bin holding the candidate of rank

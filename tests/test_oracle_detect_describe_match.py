@@ -102,6 +102,55 @@ def test_flat_map_has_no_keypoints():
 
 # ---------------------------------------------------------------- description
 
+def _union_by_sets(d_edge, d_corner, p, dtype):
+    """The union from two separate single-map detections (every survivor, K unbounded): a dict
+    keyed by pixel keeps the larger score, then one sort by (score desc, raster asc)."""
+    big = DetectParams(fast_threshold=p.fast_threshold, max_keypoints=10 ** 9, patch_size=p.patch_size)
+    best = {}
+    for d in (d_edge, d_corner):
+        pts, sc = dt.detect(d, big, dtype=dtype)
+        for (x, y), s in zip(pts.tolist(), sc.tolist()):
+            best[(x, y)] = max(best.get((x, y), -1.0), s)
+    w = np.shape(d_edge)[1]
+    order = sorted(best, key=lambda q: (-best[q], q[1] * w + q[0]))[: p.max_keypoints]
+    return order, [best[q] for q in order]
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_union_detector_equals_merged_single_map_detections(dtype):
+    rng = np.random.default_rng(21)
+    for k in (7, 60, 10 ** 6):
+        e = np.round(rng.uniform(0, 1, size=(120, 140)) * 16)  # coarse values: tied scores everywhere
+        c = np.round(rng.uniform(0, 1, size=(120, 140)) * 16)
+        c[40:80, 50:90] = e[40:80, 50:90]  # both maps agree here: shared pixels
+        p = DetectParams(max_keypoints=k, patch_size=20)
+        pts, sc = dt.detect_union(e, c, p, dtype=dtype)
+        ref_pts, ref_sc = _union_by_sets(e, c, p, dtype)
+        assert [tuple(q) for q in pts.tolist()] == ref_pts
+        assert np.array_equal(np.asarray(sc, dtype), np.asarray(ref_sc, dtype))
+        shared = set(map(tuple, dt.detect(e, p, dtype)[0].tolist())) & set(map(tuple, dt.detect(c, p, dtype)[0].tolist()))
+        assert len(pts) == min(k, len(set(ref_pts)))
+    assert shared  # the agreeing region yields pixels kept on both maps
+
+
+def test_union_detector_special_cases():
+    rng = np.random.default_rng(22)
+    e = rng.uniform(0, 1, size=(100, 100))
+    c = rng.uniform(0, 1, size=(100, 100))
+    p = DetectParams(max_keypoints=300, patch_size=20)
+    # a flat corner map adds nothing
+    pe, se = dt.detect(e, p)
+    pu, su = dt.detect_union(e, np.full_like(e, 3.0), p)
+    assert np.array_equal(pe, pu) and np.array_equal(se, su)
+    # the union does not depend on which map is which
+    a = dt.detect_union(e, c, p)
+    b = dt.detect_union(c, e, p)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    # a map with itself is the single-map detection
+    pu, su = dt.detect_union(e, e, p)
+    assert np.array_equal(pe, pu) and np.array_equal(se, su)
+
+
 def test_paper_worked_histogram_example():
     g = json.load(open(os.path.join(GOLDEN, "paper_histogram_example.json")))
     p = DescParams(patch_size=36, grid=6, n_orient=g["n_orient"])
