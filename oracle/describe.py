@@ -35,7 +35,8 @@ import numpy as np
 from .params import DescParams
 
 __all__ = ["cell_histograms", "dominant", "recode_histogram", "recode_mim", "describe", "ring_histogram",
-           "describe_plain", "describe_ring"]
+           "describe_plain", "describe_ring", "rotation_table", "disc_histogram", "rotated_cell_histograms",
+           "describe_rotated"]
 
 
 def cell_histograms(mim: np.ndarray, x: int, y: int, p: DescParams) -> np.ndarray:
@@ -137,3 +138,89 @@ def describe_ring(mim: np.ndarray, kpts: np.ndarray, p: DescParams = DescParams(
     """RIFT's reference descriptors (Section 2.3): N_o rows per keypoint, row k N_o + omega built from
     the MIM with layer omega as the ring's initial layer.  Returns (counts, kp_index, omega)."""
     return _rows(mim, kpts, p, list(range(p.n_orient)))
+
+
+# ---------------------------------------------------------------- sampling grid turned by the dominant index
+#
+# Section 3 takes the dominant index as SIFT takes its dominant orientation.
+# SIFT also turns its sampling grid by that orientation; this variant does the
+# same, since index s stands for the filter direction s pi / N_o:
+#   * the dominant index comes from the MIM values inside the disc of diameter
+#     P around the keypoint (a support that a rotation maps onto itself);
+#   * sample (i, j) of the P x P grid (column i, row j) sits at offset
+#     (u, v) = (i - P/2 + 1/2, j - P/2 + 1/2) from the corner point
+#     (x - 1/2, y - 1/2) shared by the keypoint pixel and its upper-left
+#     neighbours, so that with no turn the grid is exactly the axis-aligned
+#     patch of `cell_histograms`;
+#   * the offset is turned counter-clockwise on screen (y grows downwards) by
+#     theta = s pi / N_o: (u cos + v sin, -u sin + v cos), and the nearest
+#     pixel is read.  The turn uses 16-bit fixed-point cos / sin values, so
+#     the pixel choice is exact integer arithmetic:
+#       X = x + floor((c U + s V) / 2^17),  Y = y + floor((-s U + c V) / 2^17)
+#     with U = 2i - P + 1, V = 2j - P + 1 and (c, s) the table entry;
+#   * samples that fall outside the image are not counted;
+#   * the sampled values are recoded by s (Eq. 2) and counted per cell;
+#   * the second peak (80 % rule) gives a second row with its own turn.
+# Angles are only known modulo pi (an index is a direction, not a heading),
+# so a pair rotated by more than a half turn relative to the grid sees its
+# descriptors with the cell grid turned by pi.
+
+
+def rotation_table(n_orient: int):
+    """[(cos_q, sin_q)] for theta = k pi / N_o, k = 0..N_o-1, as round(2^16 cos), round(2^16 sin)."""
+    import math
+
+    return [(int(round(math.cos(k * math.pi / n_orient) * 65536.0)),
+             int(round(math.sin(k * math.pi / n_orient) * 65536.0))) for k in range(n_orient)]
+
+
+def disc_histogram(mim: np.ndarray, x: int, y: int, p: DescParams) -> np.ndarray:
+    """Counts of the MIM values of the pixels x + i - P/2, y + j - P/2 whose sample offsets (U, V) =
+    (2i - P + 1, 2j - P + 1) satisfy U^2 + V^2 <= P^2 (the disc of diameter P), inside the image."""
+    h, w = mim.shape
+    P = p.patch_size
+    idx = np.arange(P)
+    U = 2 * idx - P + 1
+    inside = (U[None, :] ** 2 + U[:, None] ** 2) <= P * P
+    ys = y + idx - P // 2
+    xs = x + idx - P // 2
+    ok = inside & ((ys >= 0) & (ys < h))[:, None] & ((xs >= 0) & (xs < w))[None, :]
+    vals = mim[np.clip(ys, 0, h - 1)[:, None], np.clip(xs, 0, w - 1)[None, :]].astype(np.int64)
+    return np.bincount(vals[ok], minlength=p.n_orient)[: p.n_orient]
+
+
+def rotated_cell_histograms(mim: np.ndarray, x: int, y: int, s: int, p: DescParams) -> np.ndarray:
+    """h[cy, cx, b]: samples of the grid turned by s pi / N_o whose MIM value recodes (Eq. 2) to b."""
+    h, w = mim.shape
+    P, G, n = p.patch_size, p.grid, p.n_orient
+    c, sn = rotation_table(n)[s]
+    idx = np.arange(P)
+    U = (2 * idx - P + 1)[None, :]  # column i
+    V = (2 * idx - P + 1)[:, None]  # row j
+    X = x + ((c * U + sn * V) >> 17)
+    Y = y + ((-sn * U + c * V) >> 17)
+    ok = (X >= 0) & (X < w) & (Y >= 0) & (Y < h)
+    vals = mim[np.clip(Y, 0, h - 1), np.clip(X, 0, w - 1)].astype(np.int64)
+    b = (vals - s) % n
+    cell = (idx[:, None] * G // P) * G + (idx[None, :] * G // P)
+    flat = (cell * n + b)[ok]
+    return np.bincount(flat, minlength=G * G * n).reshape(G, G, n)
+
+
+def describe_rotated(mim: np.ndarray, kpts: np.ndarray, p: DescParams = DescParams()):
+    """Dominant-index descriptors on a grid turned by the dominant index (see above).
+
+    Same row order and outputs as `describe`: (counts, kp_index, shift)."""
+    prim, sec = [], []
+    for i, (x, y) in enumerate(np.asarray(kpts, dtype=np.int64)):
+        hist = disc_histogram(mim, int(x), int(y), p)
+        s, s2, has2 = dominant(hist, p)
+        prim.append((i, s, rotated_cell_histograms(mim, int(x), int(y), s, p).ravel()))
+        if has2:
+            sec.append((i, s2, rotated_cell_histograms(mim, int(x), int(y), s2, p).ravel()))
+    rows = prim + sec
+    d = p.grid * p.grid * p.n_orient
+    if not rows:
+        return np.zeros((0, d), np.uint16), np.zeros((0,), np.int32), np.zeros((0,), np.int32)
+    counts = np.stack([r[2] for r in rows]).astype(np.uint16)
+    return counts, np.array([r[0] for r in rows], np.int32), np.array([r[1] for r in rows], np.int32)

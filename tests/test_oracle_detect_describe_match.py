@@ -363,3 +363,70 @@ def test_ring_matching_equals_bruteforce_and_recovers_rotated_values():
     ref = mt.match_bruteforce(tmpl, kt, ring, kr, MatchParams())
     assert list(got[0]) == ref[0] and list(got[1]) == ref[1]
     assert len(ref[0]) >= 15 and all(a == b for a, b in zip(ref[0], ref[1]))
+
+
+# ---------------------------------------------------------------- grid turned by the dominant index
+
+def test_turned_grid_without_turn_is_the_axis_aligned_descriptor():
+    """When every dominant index is 0 the grid is not turned, and each row equals the axis-aligned
+    descriptor's row."""
+    rng = np.random.default_rng(23)
+    mim = rng.integers(0, 6, size=(220, 240))
+    mim[rng.uniform(size=mim.shape) < 0.6] = 0  # value 0 dominates every patch, no second peak
+    mim = mim.astype(np.uint8)
+    kp = np.array([[60, 70], [120, 110], [48, 48], [192, 172], [100, 150]])
+    c, k, sh = ds.describe_rotated(mim, kp, DescParams())
+    c0, k0, sh0 = ds.describe(mim, kp, DescParams())
+    assert list(sh) == [0] * 5 and list(sh0) == [0] * 5
+    assert np.array_equal(c, c0) and np.array_equal(k, k0)
+
+
+def test_turned_grid_follows_rot90_up_to_a_half_turn():
+    """rot90 turns the image a quarter turn counter-clockwise and raises MIM values by N_o/2; the
+    keypoint (x, y) moves to (y, W - x) (the grid's centre is the pixel corner).  Its rows are then
+    identical, or -- when s + N_o/2 wraps past N_o, the direction being known only modulo pi -- the
+    same with the cell grid turned by pi."""
+    rng = np.random.default_rng(24)
+    n, no = 260, 6
+    mim = rng.integers(0, 6, size=(n, n))
+    mim[mim == 5] = 2
+    mim[(mim == 4) & (rng.uniform(size=mim.shape) < 0.5)] = 1  # uneven histograms: untied peaks
+    corner = mim[140:, 140:]
+    corner[rng.uniform(size=corner.shape) < 0.3] = 4  # a region whose dominant index wraps
+    mim = mim.astype(np.uint8)
+    rmim = ((np.rot90(mim).astype(int) + no // 2) % no).astype(np.uint8)
+    p = DescParams()
+    seen = {False: 0, True: 0}
+    for x, y in [(100, 110), (130, 100), (150, 100), (110, 125), (200, 200), (190, 210), (215, 185)]:
+        hist = ds.disc_histogram(mim, x, y, p)
+        top = np.sort(hist)[::-1]
+        if top[0] == top[1] or top[1] == top[2]:
+            continue
+        c, k, sh = ds.describe_rotated(mim, np.array([[x, y]]), p)
+        cr, kr, shr = ds.describe_rotated(rmim, np.array([[y, n - x]]), p)
+        assert len(c) == len(cr) and list(shr) == [(s + no // 2) % no for s in sh]
+        for row, rrow, s in zip(c, cr, sh):
+            wrap = s + no // 2 >= no
+            a = row.reshape(6, 6, no)
+            b = rrow.reshape(6, 6, no)
+            assert np.array_equal(b, a[::-1, ::-1] if wrap else a)
+            seen[wrap] += 1
+    assert seen[False] >= 1 and seen[True] >= 1
+
+
+def test_turned_grid_counts_and_rotation_table():
+    rng = np.random.default_rng(25)
+    mim = rng.integers(0, 6, size=(300, 280)).astype(np.uint8)
+    kp = np.array([[140, 150], [100, 200], [50, 50], [260, 250]])
+    c, k, sh = ds.describe_rotated(mim, kp, DescParams())
+    sums = c.astype(int).sum(axis=1)
+    for row, kk in enumerate(k):
+        x, y = kp[kk]
+        interior = min(x, y, 280 - 1 - x, 300 - 1 - y) >= 68  # the turned square reaches P / sqrt(2)
+        assert sums[row] == 96 * 96 if interior else sums[row] <= 96 * 96
+    assert sums.min() < 96 * 96  # a corner keypoint loses samples outside the image
+    for no in (6, 8):
+        t = ds.rotation_table(no)
+        assert t[0] == (65536, 0) and t[no // 2] == (0, 65536)
+        for cq, sq in t:
+            assert abs(cq * cq + sq * sq - 65536 ** 2) < 2 * 65536
