@@ -97,8 +97,17 @@ typedef struct {
  * (Section 2.3), the baseline RIFT2 replaces: RIFT2_DESC_PLAIN is one row of
  * the cell histograms as computed (the ring's first member), RIFT2_DESC_RING
  * is n_orient rows per keypoint, row k n_orient + w built from the MIM with
- * layer w as the ring's first (bin b counts MIM value (b + w) mod n_orient). */
-typedef enum { RIFT2_DESC_DOMINANT = 0, RIFT2_DESC_PLAIN = 1, RIFT2_DESC_RING = 2 } rift2_desc_mode;
+ * layer w as the ring's first (bin b counts MIM value (b + w) mod n_orient).
+ * RIFT2_DESC_TURNED is RIFT2's descriptor with the sampling grid also turned
+ * by the dominant index, as SIFT turns its grid by its dominant orientation
+ * (Section 3 takes SIFT as its model): s and s2 come from the MIM values in
+ * the disc of diameter patch_size around the keypoint; sample (i, j) of the
+ * patch_size^2 grid reads the pixel (x + ((c U + s V) >> 17),
+ * y + ((-s U + c V) >> 17)) with U = 2i - patch_size + 1,
+ * V = 2j - patch_size + 1 and (c, s) = round(2^16 (cos, sin)(k pi / n_orient))
+ * for the row's index k; samples outside the image are not counted; rows
+ * as in RIFT2_DESC_DOMINANT (second row on its own turned grid). */
+typedef enum { RIFT2_DESC_DOMINANT = 0, RIFT2_DESC_PLAIN = 1, RIFT2_DESC_RING = 2, RIFT2_DESC_TURNED = 3 } rift2_desc_mode;
 
 /* Descriptor (Section 2.2: 6x6 grid of N_o-bin MIM histograms; Section 3:
  * dominant index and second MIM when the second peak reaches the dominant
@@ -211,8 +220,8 @@ rift2_status rift2_detect_union(const float* max_moment, const float* min_moment
  * keypoints 0..n-1 come first, then the secondary rows (s = second peak)
  * in keypoint order.  inv_norm[row] = fl(1 / fl(sqrt(sum counts^2))),
  * desc_kp[row] = keypoint index.  desc_cap must be >= 2 * kpt_cap
- * (RIFT2_DESC_DOMINANT), kpt_cap (RIFT2_DESC_PLAIN) or n_orient * kpt_cap
- * (RIFT2_DESC_RING, rows k n_orient + w).
+ * (RIFT2_DESC_DOMINANT, RIFT2_DESC_TURNED), kpt_cap (RIFT2_DESC_PLAIN) or
+ * n_orient * kpt_cap (RIFT2_DESC_RING, rows k n_orient + w).
  *   n_desc_dev  device int32: number of rows written */
 rift2_status rift2_describe(const uint8_t* mim, int32_t H, int32_t W, const rift2_keypoint* kpts,
                             const int32_t* n_kpts_dev, int32_t kpt_cap, const rift2_desc_params* dp,

@@ -9,19 +9,21 @@ from . import filterbank, detect, describe, match
 __all__ = ["image_features", "match_pair", "ring_match_pair"]
 
 
-def image_features(img, pc=PCParams(), det=DetectParams(), desc=None, dtype=np.float64, keep_amp=False):
-    """Filter/MIM, keypoints on the max moment map and descriptors of one image."""
+def image_features(img, pc=PCParams(), det=DetectParams(), desc=None, dtype=np.float64, keep_amp=False,
+                   turned=False):
+    """Filter/MIM, keypoints on the max moment map and descriptors of one image (turned=True: the
+    sampling grid turned by the dominant index, describe.describe_rotated)."""
     if desc is None:
         desc = DescParams(patch_size=det.patch_size, n_orient=pc.n_orient)
     fm = filterbank.filter_mim(img, pc, keep_amp=keep_amp)
     kpts, scores = detect.detect(fm["M"], det, dtype=dtype)
-    counts, kp, shift = describe.describe(fm["mim"], kpts, desc)
+    counts, kp, shift = (describe.describe_rotated if turned else describe.describe)(fm["mim"], kpts, desc)
     return {"fm": fm, "kpts": kpts, "scores": scores, "desc": counts, "desc_kp": kp, "shift": shift}
 
 
-def match_pair(img_a, img_b, pc=PCParams(), det=DetectParams(), mp=MatchParams(), dtype=np.float64):
-    fa = image_features(img_a, pc, det, dtype=dtype)
-    fb = image_features(img_b, pc, det, dtype=dtype)
+def match_pair(img_a, img_b, pc=PCParams(), det=DetectParams(), mp=MatchParams(), dtype=np.float64, turned=False):
+    fa = image_features(img_a, pc, det, dtype=dtype, turned=turned)
+    fb = image_features(img_b, pc, det, dtype=dtype, turned=turned)
     m = match.match(fa["desc"], fa["desc_kp"], fb["desc"], fb["desc_kp"], mp, dtype=dtype)
     return fa, fb, m
 

@@ -11,14 +11,14 @@ import ctypes
 
 from . import _lib
 from ._lib import (PCParams, DetectParams, DescParams, MatchParams, RansacParams, PREC_FP32, PREC_BF16,  # noqa: F401
-                   PREC_FP8, DESC_DOMINANT, DESC_PLAIN, DESC_RING, Rift2Error, STAGES)
+                   PREC_FP8, DESC_DOMINANT, DESC_PLAIN, DESC_RING, DESC_TURNED, Rift2Error, STAGES)
 
 __all__ = [
     "defaults", "init", "filter_mim", "detect", "describe", "match", "Rift2Error", "PairPipeline", "PipelinedPairs",
     "profile_enable", "profile_read", "PCParams", "DetectParams", "DescParams", "MatchParams", "Engine",
     "PREC_FP32", "PREC_BF16", "PREC_FP8", "STAGES", "RansacParams", "ransac", "consensus", "ransac_workspace_bytes",
     "SIMILARITY_BYTES", "CONSENSUS_BYTES", "similarity_fields", "consensus_fields", "DESC_DOMINANT", "DESC_PLAIN",
-    "DESC_RING", "rows_per_keypoint", "detect_union",
+    "DESC_RING", "DESC_TURNED", "rows_per_keypoint", "detect_union",
 ]
 
 
@@ -212,7 +212,7 @@ def detect(moment, det: DetectParams | None = None, workspace=None, stream=None)
 
 def rows_per_keypoint(dp):
     """Descriptor rows a keypoint may produce in the form dp.mode."""
-    return {_lib.DESC_DOMINANT: 2, _lib.DESC_PLAIN: 1, _lib.DESC_RING: dp.n_orient}[dp.mode]
+    return {_lib.DESC_DOMINANT: 2, _lib.DESC_PLAIN: 1, _lib.DESC_RING: dp.n_orient, _lib.DESC_TURNED: 2}[dp.mode]
 
 
 def detect_union(max_moment, min_moment, det: DetectParams | None = None, workspace=None, stream=None):

@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(HERE, "librift2.so")
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_DEVICE = 0, 1, 2, 3, 4
 U8, U16, F32 = 0, 1, 2
 PREC_FP32, PREC_BF16, PREC_FP8 = 0, 1, 2
-DESC_DOMINANT, DESC_PLAIN, DESC_RING = 0, 1, 2
+DESC_DOMINANT, DESC_PLAIN, DESC_RING, DESC_TURNED = 0, 1, 2, 3
 
 
 class PCParams(ctypes.Structure):

@@ -428,9 +428,26 @@ size_t rift2_detect_union_workspace_size(int H, int W, const rift2_detect_params
   return detect_layout(H, W, det, 2).total;
 }
 
+// info word per keypoint, then the turned-grid form's staged second rows
+// (largest descriptor, 6 x 6 x 8) and their inverse norms.
+struct DescLayout {
+  size_t info, stage, stage_inv, total;
+};
+constexpr int kDescMaxD = 6 * 6 * 8;
+
+DescLayout desc_layout(int kpt_cap) {
+  DescLayout L;
+  Carver c;
+  L.info = c.take((size_t)kpt_cap * sizeof(uint32_t));
+  L.stage = c.take((size_t)kpt_cap * kDescMaxD * sizeof(uint16_t));
+  L.stage_inv = c.take((size_t)kpt_cap * sizeof(float));
+  L.total = c.off;
+  return L;
+}
+
 size_t rift2_describe_workspace_size(int32_t kpt_cap) {
   if (kpt_cap <= 0) return 0;
-  return align_up((size_t)kpt_cap * sizeof(uint32_t));
+  return desc_layout(kpt_cap).total;
 }
 
 size_t rift2_match_workspace_size(int32_t cap_a, int32_t cap_b, int32_t D, const rift2_match_params* mp) {
@@ -597,47 +614,53 @@ rift2_status rift2_describe(const uint8_t* mim, int32_t H, int32_t W, const rift
   if (!mim || !kpts || !n_kpts_dev || !dp || !desc || !inv_norm || !desc_kp || !n_desc_dev || !workspace)
     return RIFT2_ERR_INVALID_ARG;
   if (H <= 0 || W <= 0 || kpt_cap <= 0) return RIFT2_ERR_INVALID_ARG;
-  if (dp->mode != RIFT2_DESC_DOMINANT && dp->mode != RIFT2_DESC_PLAIN && dp->mode != RIFT2_DESC_RING)
+  if (dp->mode != RIFT2_DESC_DOMINANT && dp->mode != RIFT2_DESC_PLAIN && dp->mode != RIFT2_DESC_RING &&
+      dp->mode != RIFT2_DESC_TURNED)
     return RIFT2_ERR_INVALID_ARG;
   const int rows_per_kp = dp->mode == RIFT2_DESC_RING ? dp->n_orient : (dp->mode == RIFT2_DESC_PLAIN ? 1 : 2);
   if ((int64_t)desc_cap < (int64_t)rows_per_kp * kpt_cap) return RIFT2_ERR_INVALID_ARG;
   if (dp->dominant_num < 0 || dp->dominant_den <= 0) return RIFT2_ERR_INVALID_ARG;
   if (workspace_bytes < rift2_describe_workspace_size(kpt_cap)) return RIFT2_ERR_WORKSPACE;
+  const DescLayout DL = desc_layout(kpt_cap);
   hipStream_t st = (hipStream_t)stream;
-  uint32_t* info = (uint32_t*)workspace;
+  char* wsb = (char*)workspace;
+  uint32_t* info = (uint32_t*)(wsb + DL.info);
+  uint16_t* stage = (uint16_t*)(wsb + DL.stage);
+  float* stage_inv = (float*)(wsb + DL.stage_inv);
   const int* kp = (const int*)kpts;
   (void)hipGetLastError();
   const int blocks2 = (kpt_cap + kDesc2Kpts - 1) / kDesc2Kpts;
-  const bool second = dp->mode == RIFT2_DESC_DOMINANT;  // only RIFT2's form has secondary rows
-  ProfScope ps(6, st);
-  if (dp->patch_size == 96 && dp->grid == 6 && dp->n_orient == 6) {
-    constexpr int KPB = desc_kpb<96>();
-    hipLaunchKernelGGL((k_describe<96, 6, 6>), dim3((kpt_cap + KPB - 1) / KPB), dim3(96 * KPB), 0, st, mim, H, W, kp,
-                       n_kpts_dev, kpt_cap, dp->dominant_num, dp->dominant_den, dp->mode, desc, inv_norm, desc_kp,
-                       info, n_desc_dev);
-    if (second)
-      hipLaunchKernelGGL((k_describe2<6, 6>), dim3(blocks2), dim3(256), 0, st, n_kpts_dev, kpt_cap, info, desc,
-                         inv_norm, desc_kp, n_desc_dev);
-  } else if (dp->patch_size == 96 && dp->grid == 6 && dp->n_orient == 8) {
-    constexpr int KPB = desc_kpb<96>();
-    hipLaunchKernelGGL((k_describe<96, 6, 8>), dim3((kpt_cap + KPB - 1) / KPB), dim3(96 * KPB), 0, st, mim, H, W, kp,
-                       n_kpts_dev, kpt_cap, dp->dominant_num, dp->dominant_den, dp->mode, desc, inv_norm, desc_kp,
-                       info, n_desc_dev);
-    if (second)
-      hipLaunchKernelGGL((k_describe2<6, 8>), dim3(blocks2), dim3(256), 0, st, n_kpts_dev, kpt_cap, info, desc,
-                         inv_norm, desc_kp, n_desc_dev);
-  } else if (dp->patch_size == 64 && dp->grid == 4 && dp->n_orient == 6) {
-    constexpr int KPB = desc_kpb<64>();
-    hipLaunchKernelGGL((k_describe<64, 4, 6>), dim3((kpt_cap + KPB - 1) / KPB), dim3(64 * KPB), 0, st, mim, H, W, kp,
-                       n_kpts_dev, kpt_cap, dp->dominant_num, dp->dominant_den, dp->mode, desc, inv_norm, desc_kp,
-                       info, n_desc_dev);
-    if (second)
-      hipLaunchKernelGGL((k_describe2<4, 6>), dim3(blocks2), dim3(256), 0, st, n_kpts_dev, kpt_cap, info, desc,
-                         inv_norm, desc_kp, n_desc_dev);
-  } else {
-    return RIFT2_ERR_UNSUPPORTED;
+  const bool turned = dp->mode == RIFT2_DESC_TURNED;
+  const bool second = dp->mode == RIFT2_DESC_DOMINANT || turned;  // forms with second rows
+  TurnTable tt{};
+  for (int k = 0; k < dp->n_orient && k < 8; ++k) {
+    tt.c[k] = (int)std::lround(std::cos(k * M_PI / dp->n_orient) * 65536.0);
+    tt.s[k] = (int)std::lround(std::sin(k * M_PI / dp->n_orient) * 65536.0);
   }
-  return launch_status();
+  const uint16_t* src_rows = turned ? stage : desc;
+  const float* src_inv = turned ? stage_inv : inv_norm;
+  ProfScope ps(6, st);
+#define RIFT2_DESCRIBE_CASE(P_, G_, NO_)                                                                              \
+  if (dp->patch_size == P_ && dp->grid == G_ && dp->n_orient == NO_) {                                               \
+    constexpr int KPB = desc_kpb<P_>();                                                                               \
+    const dim3 grid((kpt_cap + KPB - 1) / KPB);                                                                       \
+    if (turned)                                                                                                        \
+      hipLaunchKernelGGL((k_describe_turn<P_, G_, NO_>), grid, dim3(P_ * KPB), 0, st, mim, H, W, kp, n_kpts_dev,       \
+                         kpt_cap, dp->dominant_num, dp->dominant_den, tt, desc, inv_norm, desc_kp, info, stage,      \
+                         stage_inv);                                                                                   \
+    else                                                                                                               \
+      hipLaunchKernelGGL((k_describe<P_, G_, NO_>), grid, dim3(P_ * KPB), 0, st, mim, H, W, kp, n_kpts_dev, kpt_cap,   \
+                         dp->dominant_num, dp->dominant_den, dp->mode, desc, inv_norm, desc_kp, info, n_desc_dev);   \
+    if (second)                                                                                                        \
+      hipLaunchKernelGGL((k_describe2<G_, NO_>), dim3(blocks2), dim3(256), 0, st, n_kpts_dev, kpt_cap, info, src_rows, \
+                         src_inv, desc, inv_norm, desc_kp, n_desc_dev);                                               \
+    return launch_status();                                                                                           \
+  }
+  RIFT2_DESCRIBE_CASE(96, 6, 6)
+  RIFT2_DESCRIBE_CASE(96, 6, 8)
+  RIFT2_DESCRIBE_CASE(64, 4, 6)
+#undef RIFT2_DESCRIBE_CASE
+  return RIFT2_ERR_UNSUPPORTED;
 }
 
 rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32_t* kp_a, const int32_t* nA_dev,

@@ -55,7 +55,7 @@ __device__ __forceinline__ float inv_sqrt_rn(uint32_t n) {
   return q;
 }
 
-constexpr int kDescDominant = 0, kDescPlain = 1, kDescRing = 2;
+constexpr int kDescDominant = 0, kDescPlain = 1, kDescRing = 2, kDescTurned = 3;
 
 template <int P>
 constexpr int desc_kpb() { return (P % 64 == 0) ? 1 : (P % 32 == 0 ? 2 : 4); }
@@ -184,6 +184,153 @@ __global__ void __launch_bounds__(P * desc_kpb<P>()) k_describe(const uint8_t* _
   }
 }
 
+// ---------------------------------------------------------------- grid turned by the dominant index
+//
+// SIFT-style variant of the descriptor: the dominant index s stands for the
+// filter direction s pi / N_o, so the sampling grid is turned by that angle
+// (counter-clockwise on screen, y down) before the cells are counted.
+//   * s and s2 come from the MIM values inside the disc of diameter P;
+//   * sample (i, j) sits at offset ((2i - P + 1) / 2, (2j - P + 1) / 2) from
+//     the keypoint pixel's upper-left corner, turned with 16-bit fixed-point
+//     cos / sin, nearest pixel X = x + ((c U + s V) >> 17),
+//     Y = y + ((-s U + c V) >> 17), U = 2i - P + 1, V = 2j - P + 1;
+//   * samples outside the image are not counted; values recode by the row's
+//     own index (Eq. 2).
+// The primary row goes to row i; a second row (80 % rule) is built on its own
+// turned grid into the staging rows and placed after the primary rows by
+// k_describe2.
+struct TurnTable {
+  int c[8], s[8];  // round(2^16 cos(k pi / N_o)), round(2^16 sin(k pi / N_o))
+};
+
+template <int P, int G, int NO>
+__global__ void __launch_bounds__(P * desc_kpb<P>()) k_describe_turn(const uint8_t* __restrict__ mim, int H, int W,
+                                                                     const int* __restrict__ kpts,
+                                                                     const int32_t* __restrict__ n_kpts, int kpt_cap,
+                                                                     int dom_num, int dom_den, TurnTable tt,
+                                                                     uint16_t* __restrict__ desc,
+                                                                     float* __restrict__ inv_norm,
+                                                                     int32_t* __restrict__ desc_kp,
+                                                                     uint32_t* __restrict__ info,
+                                                                     uint16_t* __restrict__ stage,
+                                                                     float* __restrict__ stage_inv) {
+  constexpr int KPB = desc_kpb<P>();
+  constexpr int CS = P / G;
+  constexpr int D = G * G * NO;
+  static_assert(CS == 8 || CS == 16 || CS == 32, "cell side");
+  static_assert(NO >= 2 && NO <= 8, "orientations");
+  __shared__ uint32_t h[KPB][G * G][NO];
+  __shared__ uint32_t hist[KPB][NO];
+  __shared__ int sh_s[KPB], sh_s2[KPB], sh_two[KPB];
+  __shared__ uint32_t sh_n2[KPB][2];
+  const int local = threadIdx.x / P, x = threadIdx.x % P;
+  const int n = min(*n_kpts, kpt_cap);
+  const int i = blockIdx.x * KPB + local;
+  const bool active = i < n;
+  int kx = 0, ky = 0;
+  if (active) {
+    kx = kpts[3 * i];
+    ky = kpts[3 * i + 1];
+  }
+  if (x < NO) hist[local][x] = 0u;
+  if (x < 2) sh_n2[local][x] = 0u;
+  __syncthreads();
+  // disc histogram: this thread's column, offsets U = 2x - P + 1
+  {
+    const int U = 2 * x - P + 1;
+    const int gx = kx + x - P / 2;
+    uint64_t cnt = 0;  // 8-bit field per value; a column holds at most P < 256 pixels
+    if (active && gx >= 0 && gx < W) {
+      for (int j = 0; j < P; ++j) {
+        const int V = 2 * j - P + 1;
+        const int gy = ky + j - P / 2;
+        if (U * U + V * V <= P * P && gy >= 0 && gy < H) cnt += 1ull << (8 * (mim[(size_t)gy * W + gx] & 7));
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < NO; ++b) {
+      const uint32_t v = (uint32_t)(cnt >> (8 * b)) & 0xffu;
+      if (v) atomicAdd(&hist[local][b], v);
+    }
+  }
+  __syncthreads();
+  if (x == 0) {
+    int s = 0;
+    for (int b = 1; b < NO; ++b)
+      if (hist[local][b] > hist[local][s]) s = b;
+    int s2 = (s == 0) ? 1 : 0;
+    for (int b = 0; b < NO; ++b)
+      if (b != s && hist[local][b] > hist[local][s2]) s2 = b;
+    sh_s[local] = s;
+    sh_s2[local] = s2;
+    sh_two[local] = active && (uint64_t)dom_den * hist[local][s2] >= (uint64_t)dom_num * hist[local][s];
+  }
+  __syncthreads();
+  const int rows = sh_two[local] ? 2 : 1;  // uniform over the keypoint's threads
+  int rows_blk = 1;                         // uniform over the block (the loop below holds barriers)
+  for (int q = 0; q < KPB; ++q) rows_blk = max(rows_blk, sh_two[q] ? 2 : 1);
+  for (int form = 0; form < rows_blk; ++form) {
+    const int r = form == 0 ? sh_s[local] : sh_s2[local];
+    const int cq = tt.c[r], sq = tt.s[r];
+    const int U = 2 * x - P + 1;
+    const bool live = active && form < rows;
+    for (int cy = 0; cy < G; ++cy) {
+      uint64_t cnt = 0;
+      if (live) {
+        for (int rr = 0; rr < CS; ++rr) {
+          const int V = 2 * (cy * CS + rr) - P + 1;
+          const int X = kx + ((cq * U + sq * V) >> 17);
+          const int Y = ky + ((-sq * U + cq * V) >> 17);
+          if (X >= 0 && X < W && Y >= 0 && Y < H) {
+            int b = (int)(mim[(size_t)Y * W + X] & 7) - r;
+            if (b < 0) b += NO;
+            cnt += 1ull << (8 * b);
+          }
+        }
+      }
+      const uint32_t lo = (uint32_t)cnt, hi = (uint32_t)(cnt >> 32);
+      uint32_t w[4];
+      w[0] = (lo & 0xffu) | ((lo << 8) & 0xff0000u);
+      w[1] = ((lo >> 16) & 0xffu) | ((lo >> 8) & 0xff0000u);
+      w[2] = (hi & 0xffu) | ((hi << 8) & 0xff0000u);
+      w[3] = ((hi >> 16) & 0xffu) | ((hi >> 8) & 0xff0000u);
+      constexpr int NW = (NO + 1) / 2;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) {
+#pragma unroll
+        for (int off = 1; off < CS; off <<= 1) w[q] += (uint32_t)__shfl_xor((int)w[q], off);
+      }
+      if ((x % CS) == 0) {
+        const int cx = x / CS;
+#pragma unroll
+        for (int b = 0; b < NO; ++b) h[local][cy * G + cx][b] = (w[b >> 1] >> (16 * (b & 1))) & 0xffffu;
+      }
+    }
+    __syncthreads();
+    uint32_t n2 = 0;
+    if (live) {
+      uint16_t* row = (form == 0 ? desc : stage) + (size_t)i * D;
+      for (int e = x; e < D; e += P) {
+        const uint32_t v = h[local][e / NO][e % NO];
+        row[e] = (uint16_t)v;
+        n2 += v * v;
+      }
+      atomicAdd(&sh_n2[local][form], n2);
+    }
+    __syncthreads();  // h is rewritten by the next form
+  }
+  if (active && x == 0) {
+    const uint32_t nn = sh_n2[local][0];
+    inv_norm[i] = nn ? inv_sqrt_rn(nn) : 0.0f;
+    desc_kp[i] = i;
+    if (rows == 2) {
+      const uint32_t n2 = sh_n2[local][1];
+      stage_inv[i] = n2 ? inv_sqrt_rn(n2) : 0.0f;
+    }
+    info[i] = rows == 2 ? 0x100u : 0u;  // second row staged, no further rotation
+  }
+}
+
 // Secondary rows: row n + (number of flagged keypoints before i).  A block
 // covers kDesc2Kpts keypoints; its flagged keypoints are compacted by one
 // wave ballot, and every (flagged keypoint, cell) pair is one work item that
@@ -193,11 +340,14 @@ __global__ void __launch_bounds__(P * desc_kpb<P>()) k_describe(const uint8_t* _
 // packed (index | rotation << 24) word would address far outside the rows.
 constexpr int kDesc2Kpts = 64;
 
+// src_rows / src_inv: where keypoint k's second row is built from -- the
+// primary rows and their norms (rotated by the stored delta), or a staging
+// area that already holds finished second rows (delta 0).
 template <int G, int NO>
 __global__ void __launch_bounds__(256) k_describe2(const int32_t* __restrict__ n_kpts, int kpt_cap,
-                                                   const uint32_t* __restrict__ info, uint16_t* __restrict__ desc,
-                                                   float* __restrict__ inv_norm, int32_t* __restrict__ desc_kp,
-                                                   int32_t* __restrict__ n_desc) {
+                                                   const uint32_t* __restrict__ info, const uint16_t* src_rows,
+                                                   const float* src_inv, uint16_t* desc, float* inv_norm,
+                                                   int32_t* __restrict__ desc_kp, int32_t* __restrict__ n_desc) {
   constexpr int CELLS = G * G;
   constexpr int D = CELLS * NO;
   __shared__ uint32_t scratch[4];
@@ -232,7 +382,7 @@ __global__ void __launch_bounds__(256) k_describe2(const int32_t* __restrict__ n
   for (int w = threadIdx.x; w < nflag * CELLS; w += 256) {
     const int fi = w / CELLS, c = w - fi * CELLS;
     const int src_kp = flagged_kp[fi], delta = flagged_delta[fi];
-    const uint16_t* src = desc + (size_t)src_kp * D + c * NO;
+    const uint16_t* src = src_rows + (size_t)src_kp * D + c * NO;
     uint16_t* dst = desc + (size_t)(n + base + fi) * D + c * NO;
 #pragma unroll
     for (int b = 0; b < NO; ++b) {
@@ -244,7 +394,7 @@ __global__ void __launch_bounds__(256) k_describe2(const int32_t* __restrict__ n
   for (int fi = threadIdx.x; fi < nflag; fi += 256) {
     const int row = n + base + fi;
     const int src_kp = flagged_kp[fi];
-    inv_norm[row] = inv_norm[src_kp];
+    inv_norm[row] = src_inv[src_kp];
     desc_kp[row] = src_kp;
   }
 }
