@@ -81,6 +81,9 @@ def parse():
     ap.add_argument("--ring-forms", default=None,
                     help="matching precisions of RIFT's ring form to time beside RIFT2 (default fp32,bf16; "
                          "config 4: bf16; '' for none)")
+    ap.add_argument("--variants", default="turned,union",
+                    help="other forms of the path to time (FP32 matching): turned = descriptor grid turned by the "
+                         "dominant index, union = RIFT's corner + edge detector; '' for none")
     ap.add_argument("--size", type=int, default=0, help="override the image side")
     ap.add_argument("--keypoints", type=int, default=0, help="override the keypoints per image")
     ap.add_argument("--no-graph", action="store_true", help="enqueue kernels directly instead of graph replay")
@@ -142,11 +145,14 @@ def _ransac_words(torch, n_hyp, seed=0):
     return torch.from_numpy(sample_words(seed, n_hyp).view("int32").copy()).to(torch.device("cuda:0"))
 
 
-def time_single(r2, torch, imgs, args, precision, ring=False):
+def time_single(r2, torch, imgs, args, precision, ring=False, variant=None):
     """One pair per step, nothing overlapped: a replayed graph per resident pair."""
     pc, det, dp, mp = _form_params(r2, args, precision)
+    if variant == "turned":
+        dp.mode = r2.DESC_TURNED
     words = _ransac_words(torch, args.ransac) if args.ransac > 0 else None
-    pipe = r2.PairPipeline(args.size, args.size, pc, det, dp, mp, serial=args.serial, ransac_words=words, ring=ring)
+    pipe = r2.PairPipeline(args.size, args.size, pc, det, dp, mp, serial=args.serial, ransac_words=words, ring=ring,
+                           union=variant == "union")
     graphs = []
     if not args.no_graph:
         for i, (a, b) in enumerate(imgs):
@@ -348,6 +354,27 @@ def time_outliers(r2, torch, args, n_hyp=4096, reps=50):
             "inliers": f["n_inliers"], "best": f["best"]}
 
 
+def section4_metrics(r2, torch, pipe, imgs, gts):
+    """Section 4's evaluation on the resident pairs: matches whose residual under the pair's ground
+    truth is below 3 px are correct (rift2_consensus), the RMSE is over them (20 px for a failed pair)
+    and a pair succeeds with at least 10 correct matches."""
+    from synth.gen import gt_similarity
+
+    per = []
+    for (a, b), gt in zip(imgs, gts):
+        pipe.run(a, b)
+        model = torch.tensor(gt_similarity(gt), dtype=torch.float64, device=a.device)
+        res, _ = r2.consensus(model, pipe.out, pipe.n_out, pipe.a.kpts, pipe.b.kpts, threshold=3.0)
+        f = r2.consensus_fields(res)
+        n = f["n_inliers"]
+        per.append({"matches": int(pipe.n_out.item()), "correct": n,
+                    "rmse": round(math.sqrt(f["sum_sq"] / n), 3) if n >= 10 else 20.0,
+                    "angle_deg": round(math.degrees(gt["phi"]), 1)})
+    ok = [p for p in per if p["correct"] >= 10]
+    return {"pairs": per, "success_rate": round(len(ok) / len(per), 3),
+            "mean_rmse": round(sum(p["rmse"] for p in per) / len(per), 3)}
+
+
 def cpu_baseline(size, keypoints, n_pairs=3):
     """The FP64 oracle on `n_pairs` full pairs of the same workload, single-threaded."""
     import numpy as np
@@ -485,10 +512,11 @@ def main():
         torch.add(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    imgs = []
+    imgs, gts = [], []
     for i in range(args.pairs):
-        a, b, _ = make_pair(args.config, i, size=args.size)
+        a, b, gt = make_pair(args.config, i, size=args.size)
         imgs.append((torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)))
+        gts.append(gt)
     torch.cuda.synchronize()
     in_type = "u16 (12-bit)" if imgs[0][0].dtype != torch.uint8 else "u8"
     print(f"[bench] {args.pairs} pairs {args.size}x{args.size} {in_type} resident", file=sys.stderr, flush=True)
@@ -504,8 +532,14 @@ def main():
         print(f"[bench] timing RIFT ring {f}", file=sys.stderr, flush=True)
         ring[f] = time_single(r2, torch, imgs, args, prec[f], ring=True)
         print(f"[bench] ring {f} {ring[f]['pairs_per_s']:.1f} pairs/s", file=sys.stderr, flush=True)
+    variants = {}
+    for v in [v for v in args.variants.split(",") if v]:
+        print(f"[bench] timing variant {v}", file=sys.stderr, flush=True)
+        variants[v] = time_single(r2, torch, imgs, args, prec["fp32"], variant=v)
+        print(f"[bench] {v} {variants[v]['pairs_per_s']:.1f} pairs/s", file=sys.stderr, flush=True)
     print("[bench] profiling stages", file=sys.stderr, flush=True)
     stages = {f: profile_stages(r2, torch, timed[f]["pipe"], imgs, args.profile_steps) for f in forms}
+    var_stages = {v: profile_stages(r2, torch, variants[v]["pipe"], imgs, args.profile_steps) for v in variants}
     ring_stages = {f: profile_stages(r2, torch, ring[f]["pipe"], imgs, args.profile_steps) for f in ring_forms}
     main_form = forms[0]
     d = args.n_orient * 36
@@ -519,6 +553,10 @@ def main():
         t = stages[f]["match_gemm"]["ms_avg"] * 1e-3
         mfma[f] = {"tflops": round(gemm_flop / t / 1e12, 2), "frac": round(gemm_flop / t / (peak[f] * 1e12), 4),
                    "peak_tflops": peak[f]}
+    print("[bench] section 4 metrics", file=sys.stderr, flush=True)
+    accuracy = {main_form: section4_metrics(r2, torch, timed[main_form]["pipe"], imgs, gts)}
+    for v in variants:
+        accuracy[v] = section4_metrics(r2, torch, variants[v]["pipe"], imgs, gts)
     print("[bench] outlier removal", file=sys.stderr, flush=True)
     outliers = time_outliers(r2, torch, args)
     cpu = None
@@ -557,7 +595,15 @@ def main():
         "stages_ms": {f: {k: round(v["ms_avg"], 5) for k, v in stages[f].items()} for f in forms},
         "cpu_baseline": cpu,
         "outliers": outliers,
+        "accuracy": accuracy,
         "rift_ring": None,
+        "variants": {v: {"what": {"turned": "descriptor grid turned by the dominant index",
+                                  "union": "RIFT's corner + edge detector union"}[v],
+                         "pairs_per_s": round(t["pairs_per_s"], 2), "ms_per_step": round(t["ms_per_step"], 4),
+                         "p50_ms": round(t["p50_ms"], 4), "last_pair": t["last_pair"],
+                         "detect_ms": round(var_stages[v]["detect"]["ms_avg"], 5),
+                         "describe_ms": round(var_stages[v]["describe"]["ms_avg"], 5)}
+                     for v, t in variants.items()},
     }
     if ring:
         line["rift_ring"] = {

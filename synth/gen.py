@@ -23,7 +23,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-__all__ = ["CONFIGS", "PairConfig", "make_pair", "make_scene", "serving_sizes", "keypoint_cap"]
+__all__ = ["CONFIGS", "PairConfig", "make_pair", "make_scene", "serving_sizes", "keypoint_cap", "gt_similarity"]
 
 
 @dataclass(frozen=True)
@@ -210,3 +210,12 @@ def make_pair(config: int, index: int, size: int | None = None):
     b = np.rint(np.clip(b, 0, cfg.vmax))
     gt = {"phi": phi, "t": (tx, ty), "size": (n, n)}
     return a.astype(cfg.dtype), b.astype(cfg.dtype), gt
+
+
+def gt_similarity(gt) -> tuple:
+    """The pair's warp p_B = R(phi)(p_A - c) + c + t as (a, b, tx, ty) with u = a x - b y + tx,
+    v = b x + a y + ty (c the image centre)."""
+    h, w = gt["size"]
+    cx, cy = (w - 1) / 2.0, (h - 1) / 2.0
+    a, b = math.cos(gt["phi"]), math.sin(gt["phi"])
+    return (a, b, cx + gt["t"][0] - (a * cx - b * cy), cy + gt["t"][1] - (b * cx + a * cy))

@@ -29,3 +29,13 @@ def test_large_config_is_12_bit():
 
 def test_serving_keypoint_cap():
     assert [keypoint_cap(s, s) for s in (512, 768, 1024, 1536, 2048)] == [524, 1179, 2097, 4718, 8388]
+
+
+def test_gt_similarity_equals_the_oracle_ground_truth_model():
+    from oracle import outliers
+    from synth.gen import gt_similarity
+
+    for cfg, idx in ((0, 0), (1, 3), (4, 1)):
+        _, _, gt = make_pair(cfg, idx, size=256)
+        want = outliers.gt_model(gt["phi"], gt["t"], gt["size"])
+        assert np.allclose(gt_similarity(gt), want, rtol=0, atol=1e-9)
