@@ -163,3 +163,38 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
             l.load(str(tmp_path / "missing.so"))
         finally:
             l._LIB = saved
+
+
+def test_variant_forms_are_validated_on_the_host():
+    _l, lib = _lib()
+    fake = ctypes.c_void_p(0x1000)
+    null = ctypes.c_void_p(0)
+    pc, det, desc, mp = _l.PCParams(), _l.DetectParams(), _l.DescParams(), _l.MatchParams()
+    lib.rift2_default_params(ctypes.byref(pc), ctypes.byref(det), ctypes.byref(desc), ctypes.byref(mp))
+    assert desc.mode == _l.DESC_DOMINANT and mp.ring == 0
+    # describe: unknown form; ring rows need n_orient x kpt_cap rows; plain needs kpt_cap
+    for mode, cap, want in ((7, 1000, _l.ERR_INVALID_ARG), (_l.DESC_RING, 599, _l.ERR_INVALID_ARG),
+                            (_l.DESC_PLAIN, 99, _l.ERR_INVALID_ARG), (_l.DESC_TURNED, 199, _l.ERR_INVALID_ARG)):
+        d = _l.DescParams.from_buffer_copy(desc)
+        d.mode = mode
+        assert lib.rift2_describe(fake, 256, 256, fake, fake, 100, ctypes.byref(d), fake, fake, fake, cap, fake, fake,
+                                  1 << 30, null) == want, mode
+    assert lib.rift2_describe_workspace_size(100) >= 100 * (4 + 288 * 2 + 4)
+    # match: ring of 1 row, ring beyond 8, ring with FP8 candidates
+    for ring, prec, want in ((1, 0, _l.ERR_INVALID_ARG), (9, 0, _l.ERR_INVALID_ARG), (6, _l.PREC_FP8, _l.ERR_UNSUPPORTED)):
+        m = _l.MatchParams(0.81, prec, ring)
+        assert lib.rift2_match(fake, fake, fake, fake, 60, fake, fake, fake, fake, 10, 216, ctypes.byref(m), fake, fake,
+                               fake, 1 << 30, null) == want, (ring, prec)
+    # corner + edge union: the second map is required and 16-byte aligned; its workspace is larger
+    assert lib.rift2_detect_union(fake, null, 256, 256, ctypes.byref(det), fake, fake, fake, 1 << 30,
+                                  null) == _l.ERR_INVALID_ARG
+    assert lib.rift2_detect_union(fake, ctypes.c_void_p(0x1004), 256, 256, ctypes.byref(det), fake, fake, fake,
+                                  1 << 30, null) == _l.ERR_INVALID_ARG
+    assert (lib.rift2_detect_union_workspace_size(1024, 1024, ctypes.byref(det)) >
+            lib.rift2_detect_workspace_size(1024, 1024, ctypes.byref(det)))
+    # the serving engine serves RIFT2's form only
+    ring_dp = _l.DescParams.from_buffer_copy(desc)
+    ring_dp.mode = _l.DESC_RING
+    handle = ctypes.c_void_p(0)
+    assert lib.rift2_engine_create(0, ctypes.c_void_p(0x10000), 1 << 30, 4, ctypes.byref(pc), ctypes.byref(det),
+                                   ctypes.byref(ring_dp), ctypes.byref(mp), ctypes.byref(handle)) == _l.ERR_UNSUPPORTED
