@@ -227,3 +227,69 @@ def test_full_size_large_fp8():
     print(f"  amplitudes / MIM / detect / describe exact; FP8 sampled matches gpu {len(got)} oracle {len(want)} "
           f"Jaccard {jac:.4f}", flush=True)
     assert len(want) > 20 and jac >= 0.95
+
+
+def _run_variant(r2, dev, config, **kw):
+    cfg = CONFIGS[config]
+    a, b = _pair(config)
+    pc, det, dp, mp = r2.defaults()
+    det.max_keypoints = cfg.max_keypoints
+    if kw.pop("turned", False):
+        dp.mode = r2.DESC_TURNED
+    pipe = r2.PairPipeline(cfg.size, cfg.size, pc, det, dp, mp, **kw)
+    g = pipe.capture(torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev))
+    g.replay()
+    torch.cuda.synchronize()
+    return pipe
+
+
+def test_full_size_variants_1024():
+    """The corner + edge union, the turned grid and RIFT's ring at 1024^2 / 5000 keypoints, graph
+    replayed as bench.py times them: detection bit-exact on the GPU's own moment maps, sampled
+    descriptors bit-exact on its own MIM, sampled FP32 matches bit-exact."""
+    r2, dev = _gpu()
+    cfg = CONFIGS[1]
+    rng = np.random.default_rng(11)
+    print("[full size] variants at 1024^2: union", flush=True)
+    pipe = _run_variant(r2, dev, 1, union=True)
+    for buf in (pipe.a, pipe.b):
+        nk = int(buf.nk.item())
+        ref_pts, ref_sc = detect.detect_union(buf.M.cpu().numpy(), buf.m.cpu().numpy(),
+                                              oracle.DetectParams(max_keypoints=cfg.max_keypoints), dtype=np.float32)
+        got = buf.kpts[:nk].cpu().numpy()
+        assert nk == len(ref_pts) and np.array_equal(got[:, :2], ref_pts)
+        assert np.array_equal(got[:, 2].view(np.float32), np.asarray(ref_sc, np.float32))
+
+    print("[full size] variants at 1024^2: turned grid", flush=True)
+    pipe = _run_variant(r2, dev, 1, turned=True)
+    oa, ob = _image_outputs(pipe.a), _image_outputs(pipe.b)
+    n = len(oa["kpts"])
+    pick = np.sort(rng.choice(n, size=400, replace=False))
+    c_ref, k_ref, _ = describe.describe_rotated(oa["mim"], oa["kpts"][pick, :2], oracle.DescParams())
+    for r in range(len(c_ref)):
+        i = int(pick[k_ref[r]])
+        rows = _rows_of(oa, i, n)
+        which = 0 if r < len(pick) else 1
+        assert len(rows) > which and np.array_equal(oa["desc"][rows[which]], c_ref[r]), f"keypoint {i}"
+    keys, ref_m = _sampled_match(oa, ob, rng)
+    want = {(int(x), int(y)): int(np.float32(d).view(np.int32)) for x, y, d in zip(*ref_m)}
+    assert _gpu_matches(pipe, keys) == want and len(want) > 20
+
+    print("[full size] variants at 1024^2: RIFT ring", flush=True)
+    pipe = _run_variant(r2, dev, 1, ring=True)
+    ta = {"mim": pipe.a.mim.cpu().numpy(), "kpts": pipe.a.kpts[:int(pipe.a.nk.item())].cpu().numpy()}
+    tb = {"mim": pipe.b.mim.cpu().numpy(), "kpts": pipe.b.kpts[:int(pipe.b.nk.item())].cpu().numpy()}
+    nd_a = int(pipe.a.nd.item())
+    ring_a = pipe.a.desc[:nd_a].cpu().numpy().astype(np.uint16)
+    assert nd_a == 6 * len(ta["kpts"])
+    pick = np.sort(rng.choice(len(ta["kpts"]), size=300, replace=False))
+    ring_ref, _, _ = describe.describe_ring(ta["mim"], ta["kpts"][pick, :2], oracle.DescParams())
+    assert np.array_equal(ring_a.reshape(-1, 6, 216)[pick].reshape(-1, 216), ring_ref)
+    # the oracle's ring matching: sampled template keypoints (plain rows) against every reference ring row
+    plain_t, _, _ = describe.describe_plain(ta["mim"], ta["kpts"][pick, :2], oracle.DescParams())
+    ring_r, kring_r, _ = describe.describe_ring(tb["mim"], tb["kpts"][:, :2], oracle.DescParams())
+    ref_m = match.match(plain_t, pick.astype(np.int32), ring_r, kring_r, dtype=np.float32)
+    want = {(int(x), int(y)): int(np.float32(d).view(np.int32)) for x, y, d in zip(*ref_m)}
+    got = _gpu_matches(pipe, set(int(i) for i in pick))
+    print(f"  union, turned and ring exact; sampled ring matches {len(want)}", flush=True)
+    assert got == want and len(want) > 20
