@@ -756,7 +756,9 @@ rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32
   else
     hipLaunchKernelGGL(k_match_merge, dim3((cap_a + 3) / 4), dim3(256), 0, st, part, 2 * L.slices, nA_dev, kp_a, kp_b,
                        mp->ratio_sq, cap_a, best, rowj, rowd);
-  hipLaunchKernelGGL(k_match_emit, dim3((cap_a + 255) / 256), dim3(256), 0, st, best, cap_a, rowj, rowd, kp_b,
+  // ring rows come R per keypoint, so keypoint indices stay below cap_a / R
+  const int kp_range = mp->ring ? cap_a / mp->ring : cap_a;
+  hipLaunchKernelGGL(k_match_emit, dim3((kp_range + 255) / 256), dim3(256), 0, st, best, kp_range, rowj, rowd, kp_b,
                      (MatchOut*)out, n_out_dev);
   return launch_status();
 }

@@ -185,17 +185,22 @@ __global__ void __launch_bounds__(256) k_ransac_score(const int4* __restrict__ x
   const int h0 = blockIdx.x * G;
   // an invalid match list counts as empty: every hypothesis gets -1
   const int n = wave_any_flag(flags, n_flags) ? 0 : min(*n_dev, cap);
+  // lane g fits hypothesis h0 + g; every lane then reads the G models
+  Sim mine{0.0, 0.0, 0.0, 0.0};
+  bool mine_ok = false;
+  if (lane < G && h0 + lane < n_hyp && n >= 2) {
+    const uint2 w = words[h0 + lane];
+    mine_ok = sim_fit_pair(xy[sample_index(w.x, n)], xy[sample_index(w.y, n)], mine);
+  }
   Sim m[G];
   bool ok[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) {
-    const int h = h0 + g;
-    ok[g] = false;
-    m[g] = Sim{0.0, 0.0, 0.0, 0.0};
-    if (h < n_hyp && n >= 2) {
-      const uint2 w = words[h];
-      ok[g] = sim_fit_pair(xy[sample_index(w.x, n)], xy[sample_index(w.y, n)], m[g]);
-    }
+    m[g].a = __shfl(mine.a, g, 64);
+    m[g].b = __shfl(mine.b, g, 64);
+    m[g].tx = __shfl(mine.tx, g, 64);
+    m[g].ty = __shfl(mine.ty, g, 64);
+    ok[g] = __shfl((int)mine_ok, g, 64) != 0;
   }
   int cnt[G];
 #pragma unroll
