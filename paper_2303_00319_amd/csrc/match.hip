@@ -109,7 +109,6 @@ __device__ __forceinline__ void tile_epilogue(const floatx16_t& acc, int lane, i
                                               const float* ibt, Top3& top) {
   const int g = lane >> 5;
   float d2[16];
-  bool any = false;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const float4 ib4 = *(const float4*)(ibt + 8 * k + 4 * g);
@@ -117,11 +116,21 @@ __device__ __forceinline__ void tile_epilogue(const floatx16_t& acc, int lane, i
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int r = 4 * k + e;
-      const float t1 = __fmul_rn(acc[r], ia);
-      const float t2 = __fmul_rn(t1, ibv[e]);
-      d2[r] = __fsub_rn(2.0f, __fmul_rn(2.0f, t2));
-      any |= (j0 + 8 * k + 4 * g + e < j_end) && d2[r] < top.d[2];
+      const float t2 = __fmul_rn(__fmul_rn(acc[r], ia), ibv[e]);
+      // 2 t2 is exact, so one fused rounding equals fl(2 - fl(2 t2))
+      d2[r] = __fmaf_rn(-2.0f, t2, 2.0f);
     }
+  }
+  const bool full = j0 + 32 <= j_end;  // uniform: only a slice's last tile is partial
+  bool any = false;
+  if (full) {
+    float mn = d2[0];
+#pragma unroll
+    for (int r = 1; r < 16; ++r) mn = fminf(mn, d2[r]);
+    any = mn < top.d[2];
+  } else {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) any |= (j0 + 8 * (r >> 2) + 4 * g + (r & 3) < j_end) && d2[r] < top.d[2];
   }
   if (!any) return;
 #pragma unroll
