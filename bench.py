@@ -375,6 +375,33 @@ def section4_metrics(r2, torch, pipe, imgs, gts):
             "mean_rmse": round(sum(p["rmse"] for p in per) / len(per), 3)}
 
 
+def form_agreement(r2, torch, args, forms, prec):
+    """Match sets of every matching form on one pair that keeps matches: the workload's scene and a
+    translated, inverted copy without rotation or speckle (the workload's own pairs leave no row
+    through the ratio test).  Each form's Jaccard is taken against the first form's set; the FP64
+    oracle's agreement at this size is checked by the full-size GPU tests."""
+    from synth import make_shifted_pair
+
+    a, b, _ = make_shifted_pair(args.config, 0, size=args.size)
+    dev = torch.device("cuda:0")
+    ta, tb = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+    sets = {}
+    for f in forms:
+        pc, det, dp, mp = _form_params(r2, args, prec[f])
+        pipe = r2.PairPipeline(args.size, args.size, pc, det, dp, mp)
+        pipe.run(ta, tb)
+        torch.cuda.synchronize()
+        n = int(pipe.n_out.item())
+        sets[f] = {(int(x), int(y)) for x, y in pipe.out[:n, :2].cpu().tolist()}
+        del pipe
+    ref = sets[forms[0]]
+    return {"workload": f"scene of pair 0, B = A shifted by (5, -3) px, inverted + gamma 0.5, no rotation or speckle, "
+                        f"{args.keypoints} kpts",
+            "reference_form": forms[0],
+            **{f: {"matches": len(sets[f]), "jaccard": round(len(sets[f] & ref) / max(1, len(sets[f] | ref)), 6)}
+               for f in forms}}
+
+
 def cpu_baseline(size, keypoints, n_pairs=3):
     """The FP64 oracle on `n_pairs` full pairs of the same workload, single-threaded."""
     import numpy as np
@@ -557,6 +584,8 @@ def main():
     accuracy = {main_form: section4_metrics(r2, torch, timed[main_form]["pipe"], imgs, gts)}
     for v in variants:
         accuracy[v] = section4_metrics(r2, torch, variants[v]["pipe"], imgs, gts)
+    print("[bench] match-set agreement of the forms", file=sys.stderr, flush=True)
+    agreement = form_agreement(r2, torch, args, forms, prec)
     print("[bench] outlier removal", file=sys.stderr, flush=True)
     outliers = time_outliers(r2, torch, args)
     cpu = None
@@ -596,6 +625,7 @@ def main():
         "cpu_baseline": cpu,
         "outliers": outliers,
         "accuracy": accuracy,
+        "agreement": agreement,
         "rift_ring": None,
         "variants": {v: {"what": {"turned": "descriptor grid turned by the dominant index",
                                   "union": "RIFT's corner + edge detector union"}[v],

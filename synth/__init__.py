@@ -5,4 +5,4 @@ scenes, warps them by a known similarity transform and applies a nonlinear
 intensity remap plus multiplicative speckle.  Both the CPU oracle tests and
 the GPU path take their inputs from here.
 """
-from .gen import CONFIGS, make_pair, make_scene, serving_sizes, keypoint_cap  # noqa: F401
+from .gen import CONFIGS, make_pair, make_shifted_pair, make_scene, serving_sizes, keypoint_cap  # noqa: F401

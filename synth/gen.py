@@ -23,7 +23,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-__all__ = ["CONFIGS", "PairConfig", "make_pair", "make_scene", "serving_sizes", "keypoint_cap", "gt_similarity"]
+__all__ = ["CONFIGS", "PairConfig", "make_pair", "make_shifted_pair", "make_scene", "serving_sizes", "keypoint_cap",
+           "gt_similarity"]
 
 
 @dataclass(frozen=True)
@@ -209,6 +210,26 @@ def make_pair(config: int, index: int, size: int | None = None):
     b = b * noise_rng.gamma(shape=cfg.looks, scale=1.0 / cfg.looks, size=b.shape)
     b = np.rint(np.clip(b, 0, cfg.vmax))
     gt = {"phi": phi, "t": (tx, ty), "size": (n, n)}
+    return a.astype(cfg.dtype), b.astype(cfg.dtype), gt
+
+
+def make_shifted_pair(config: int, index: int, size: int | None = None, shift=(5.0, -3.0)):
+    """Return (A, B, gt): A is pair `index`'s scene of workload `config`; B is A translated by `shift`
+    (bilinear, zero outside), inverted and gamma-0.5 remapped, with no rotation and no speckle.
+
+    The workloads' own pairs (arbitrary rotations, 1- or 4-look speckle) leave almost no descriptor
+    rows through the ratio test, so a match-set comparison on them is empty; this pair keeps
+    thousands of matches at the same size and keypoint count."""
+    cfg = CONFIGS[config]
+    n = cfg.size if size is None else int(size)
+    scale = (n * n) / float(cfg.size * cfg.size)
+    n_blob = max(10, int(round(cfg.n_blob * scale)))
+    n_shape = max(4, int(round(cfg.n_shape * scale)))
+    scene_rng, _, noise_rng = _streams(SEED_STRIDE * config + index)
+    a = make_scene(n, n_blob, n_shape, cfg.vmax, scene_rng)
+    b = _warp_bilinear(a, 0.0, float(shift[0]), float(shift[1]))
+    b = np.rint(np.clip(_remap(b, "invert_gamma", cfg.vmax, noise_rng), 0, cfg.vmax))
+    gt = {"phi": 0.0, "t": (float(shift[0]), float(shift[1])), "size": (n, n)}
     return a.astype(cfg.dtype), b.astype(cfg.dtype), gt
 
 

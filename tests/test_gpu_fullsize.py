@@ -24,7 +24,7 @@ pytestmark = pytest.mark.gpu
 
 import oracle  # noqa: E402
 from oracle import detect, describe, filterbank, match  # noqa: E402
-from synth import make_pair  # noqa: E402
+from synth import make_pair, make_shifted_pair  # noqa: E402
 from synth.gen import CONFIGS  # noqa: E402
 
 
@@ -43,13 +43,7 @@ def _pair(config):
     """Image A of the workload and a shifted, intensity-inverted copy: the descriptor grid is
     axis-aligned, so a rotation-free pair gives many matches to compare."""
     if config not in _pairs:
-        import synth.gen as g
-
-        cfg = CONFIGS[config]
-        a, _, _ = make_pair(config, 0)
-        v = float(cfg.vmax)
-        b = g._warp_bilinear(a.astype(np.float64), 0.0, 7.0, 4.0)
-        b = np.rint(np.clip(v * np.power(np.clip((v - b) / v, 0, 1), 0.5), 0, v)).astype(a.dtype)
+        a, b, _ = make_shifted_pair(config, 0, shift=(7.0, 4.0))
         _pairs[config] = (a, b)
     return _pairs[config]
 
@@ -167,6 +161,40 @@ def test_full_size_pair(config):
     _, _, pipe16, _ = _run_pipeline(r2, dev, config, r2.PREC_BF16)
     assert _gpu_matches(pipe16, keys) == want, "BF16 matches differ on the sample"
     print(f"  detect / describe / match exact; sampled matches {len(want)}", flush=True)
+
+
+def test_match_set_agreement_1024():
+    """Match-set agreement with the FP64 oracle at the headline size (1024^2, 5000 keypoints), every
+    descriptor row: (i) stage-isolated, the oracle matching the GPU's own descriptor tables (the pure
+    precision effect of each matching form; FP32 and BF16 >= 99.5 %, FP8 >= 98 %), and (ii) end to end,
+    the oracle's FP64 pipeline against the GPU pipeline, matches identified by their coordinates."""
+    r2, dev = _gpu()
+    cfg = CONFIGS[1]
+    forms = (("fp32", r2.PREC_FP32, 0.995), ("bf16", r2.PREC_BF16, 0.995), ("fp8", r2.PREC_FP8, 0.98))
+    sets = {}
+    for name, prec, bar in forms:
+        print(f"[agreement] 1024^2 shifted pair, {name} form", flush=True)
+        a, b, pipe, _ = _run_pipeline(r2, dev, 1, prec)
+        oa, ob = _image_outputs(pipe.a), _image_outputs(pipe.b)
+        ref = match.match(oa["desc"], oa["dkp"], ob["desc"], ob["dkp"], dtype=np.float64)
+        want = {(int(x), int(y)) for x, y in zip(ref[0], ref[1])}
+        n = int(pipe.n_out.item())
+        o = pipe.out[:n].cpu().numpy()
+        got = {(int(r[0]), int(r[1])) for r in o}
+        jac = len(got & want) / max(1, len(got | want))
+        print(f"  stage-isolated {name}: rows {len(oa['desc'])} x {len(ob['desc'])}, gpu {len(got)}, "
+              f"oracle {len(want)}, Jaccard {jac:.5f}", flush=True)
+        assert len(want) > 1000, "too few matches for a meaningful comparison"
+        assert jac >= bar, f"{name}: Jaccard {jac}"
+        sets[name] = {(tuple(oa["kpts"][i, :2]), tuple(ob["kpts"][j, :2])) for i, j in got}
+    assert sets["bf16"] == sets["fp32"], "BF16 and FP32 forms differ on identical descriptors"
+    a, b = _pair(1)
+    fa, fb, mref = oracle.pipeline.match_pair(a, b, det=oracle.DetectParams(max_keypoints=cfg.max_keypoints))
+    want = {(tuple(fa["kpts"][i]), tuple(fb["kpts"][j])) for i, j in zip(mref[0], mref[1])}
+    for name in sets:
+        jac = len(sets[name] & want) / max(1, len(sets[name] | want))
+        print(f"  end-to-end {name}: gpu {len(sets[name])}, oracle {len(want)}, Jaccard {jac:.5f}", flush=True)
+        assert jac >= 0.9, f"{name}: end-to-end Jaccard {jac}"
 
 
 def _responses_at(img, pixels, p):
