@@ -732,14 +732,16 @@ rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32
   }
   ps7.finish();
   const dim3 grid((L.rows_a + 127) / 128, L.slices);
+  // the BF16 GEMM deals its cells to the XCDs itself (gemm_cell): 1-D grid
+  const dim3 grid_xcd(8 * ((grid.x + 1) / 2) * ((L.slices + 3) / 4));
   ProfScope ps8(8, st);
   if (bf) {
     if (L.dp == 224)
-      hipLaunchKernelGGL(k_match_gemm_bf16<224>, grid, dim3(256), 0, st, (const uint16_t*)ta, inv_a, nA_dev,
-                         (const uint16_t*)tb, inv_b, nB_dev, cap_a, cap_b, L.slice_rows, part);
+      hipLaunchKernelGGL(k_match_gemm_bf16<224>, grid_xcd, dim3(256), 0, st, (const uint16_t*)ta, inv_a, nA_dev,
+                         (const uint16_t*)tb, inv_b, nB_dev, cap_a, cap_b, L.slice_rows, L.slices, part);
     else
-      hipLaunchKernelGGL(k_match_gemm_bf16<288>, grid, dim3(256), 0, st, (const uint16_t*)ta, inv_a, nA_dev,
-                         (const uint16_t*)tb, inv_b, nB_dev, cap_a, cap_b, L.slice_rows, part);
+      hipLaunchKernelGGL(k_match_gemm_bf16<288>, grid_xcd, dim3(256), 0, st, (const uint16_t*)ta, inv_a, nA_dev,
+                         (const uint16_t*)tb, inv_b, nB_dev, cap_a, cap_b, L.slice_rows, L.slices, part);
   } else {
     if (L.dp == 216)
       hipLaunchKernelGGL(k_match_gemm_f32<216>, grid, dim3(256), 0, st, (const float*)ta, inv_a, nA_dev,

@@ -184,23 +184,78 @@ constexpr int bf16_stride() { return DP + 8; }  // rows start 16 bytes apart mod
 template <int DP>
 constexpr int f32_stride() { return DP + 4; }
 
+// Products of one 32-candidate tile with the wave's 32 queries.  Each
+// candidate fragment is read from LDS PF MFMAs ahead of its use, so the LDS
+// latency overlaps the dependent MFMA chain instead of preceding every MFMA.
+template <int KS, int RS>
+__device__ __forceinline__ floatx16_t bf16_tile_products(const uint16_t* tile, int lane, const bf16x8_t* qa) {
+  constexpr int PF = KS < 4 ? KS : 4;
+  const uint16_t* crow = tile + (lane & 31) * RS + 8 * (lane >> 5);
+  uint4 fr[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p) fr[p] = *(const uint4*)(crow + 16 * p);
+  floatx16_t acc = {};
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const uint4 cur = fr[ks % PF];
+    if (ks + PF < KS) fr[ks % PF] = *(const uint4*)(crow + 16 * (ks + PF));
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, cur), qa[ks], acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// The two tile buffers are separate LDS objects and the loop body is written
+// out once per buffer, so every read names a buffer that the copy in flight
+// does not write: the compiler then lets the next tile's copy run under the
+// current tile's products instead of waiting for it before the first read.
+// Which (query block, slice) a block of the GEMM grid computes.  Blocks are
+// dealt to the 8 XCDs round robin by their linear id, and each XCD has its
+// own L2; so XCD x works only on half x / 4 of the actual query blocks
+// against quarter x % 4 of the actual candidate slices (about 1.4 + 1.1 MB of
+// BF16 tables at 1024^2 / 5000 keypoints), which its L2 holds, instead of
+// streaming all of B past every L2.  The halves and quarters are cut from
+// the device-side row counts, so every XCD gets the same share whatever the
+// capacities; blocks beyond their XCD's share leave at once.  The grid is
+// 8 * ceil(query blocks of the capacity / 2) * ceil(slices / 4).
+struct GemmCell {
+  int qb, slice, n_slices_act;
+  bool ok;
+};
+
+__device__ __forceinline__ GemmCell gemm_cell(int na, int nb, int slice_rows, int slices) {
+  GemmCell c;
+  const int nqb = (na + 127) / 128;
+  // a candidate count of zero still has one (empty) slice, which writes the lists
+  c.n_slices_act = max(1, min(slices, (nb + slice_rows - 1) / slice_rows));
+  const int xcd = (int)(blockIdx.x & 7u), w = (int)(blockIdx.x >> 3);
+  const int ha = xcd >> 2, hb = xcd & 3;
+  const int q_lo = ha * nqb / 2, q_n = (ha + 1) * nqb / 2 - q_lo;
+  const int s_lo = hb * c.n_slices_act / 4, s_n = (hb + 1) * c.n_slices_act / 4 - s_lo;
+  c.ok = q_n > 0 && w < q_n * s_n;
+  c.qb = c.ok ? q_lo + w % q_n : 0;
+  c.slice = c.ok ? s_lo + w / q_n : 0;
+  return c;
+}
+
 template <int DP>
-__global__ void __launch_bounds__(256) k_match_gemm_bf16(const uint16_t* __restrict__ ta, const float* __restrict__ inv_a,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_match_gemm_bf16(const uint16_t* __restrict__ ta, const float* __restrict__ inv_a,
                                                          const int32_t* __restrict__ na_dev,
                                                          const uint16_t* __restrict__ tb, const float* __restrict__ inv_b,
                                                          const int32_t* __restrict__ nb_dev, int cap_a, int cap_b,
-                                                         int slice_rows, int2* __restrict__ part) {
+                                                         int slice_rows, int slices, int2* __restrict__ part) {
   static_assert(DP % 16 == 0, "padded depth");
   constexpr int KS = DP / 16;
   constexpr int RS = bf16_stride<DP>();
-  __shared__ __attribute__((aligned(16))) uint16_t tile[2][32 * RS];
-  __shared__ __attribute__((aligned(16))) float ibt[2][32];
+  __shared__ __attribute__((aligned(16))) uint16_t tile0[32 * RS];
+  __shared__ __attribute__((aligned(16))) uint16_t tile1[32 * RS];
+  __shared__ __attribute__((aligned(16))) float ibt0[32];
+  __shared__ __attribute__((aligned(16))) float ibt1[32];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 5;
   const int na = min(*na_dev, cap_a), nb = min(*nb_dev, cap_b);
-  // the grid is sized for the capacity; blocks past the actual query rows
-  // leave at once (uniformly, before any barrier; nobody reads their lists)
-  if ((int)blockIdx.x * 128 >= na) return;
-  const int q0 = (blockIdx.x * 4 + wave) * 32;
+  // blocks without a cell leave at once (uniformly, before any barrier)
+  const GemmCell cell = gemm_cell(na, nb, slice_rows, slices);
+  if (!cell.ok) return;
+  const int q0 = (cell.qb * 4 + wave) * 32;
   const bool active = q0 < na;
   const int qi = q0 + (lane & 31);
   bf16x8_t qa[KS];
@@ -210,7 +265,7 @@ __global__ void __launch_bounds__(256) k_match_gemm_bf16(const uint16_t* __restr
     for (int ks = 0; ks < KS; ++ks) qa[ks] = __builtin_bit_cast(bf16x8_t, *(const uint4*)(qrow + 16 * ks));
   }
   const float ia = (active && qi < na) ? inv_a[qi] : 0.0f;
-  const int j_beg = blockIdx.y * slice_rows;
+  const int j_beg = cell.slice * slice_rows;
   const int j_end = min(nb, j_beg + slice_rows);
   const int ntile = j_end > j_beg ? (j_end - j_beg + 31) / 32 : 0;
   Top3 top;
@@ -220,40 +275,42 @@ __global__ void __launch_bounds__(256) k_match_gemm_bf16(const uint16_t* __restr
     top.j[q] = -1;
   }
   if (ntile > 0) {
-    tile_copy<uint16_t, RS>(tb, j_beg, tile[0]);
+    tile_copy<uint16_t, RS>(tb, j_beg, tile0);
     const float ib0 = tile_inv_load(inv_b, j_beg, nb);
-    if (threadIdx.x < 32) ibt[0][threadIdx.x] = ib0;
+    if (threadIdx.x < 32) ibt0[threadIdx.x] = ib0;
     tile_copy_wait();
   }
   __syncthreads();
-  for (int it = 0; it < ntile; ++it) {
-    const int cur = it & 1;
+  // tile `it` is in (tc, ic); tile it + 1 goes to (tn, in) meanwhile
+  auto step = [&](int it, const uint16_t* tc, uint16_t* tn, const float* ic, float* in) {
     const int j0 = j_beg + 32 * it;
+    const bool more = it + 1 < ntile;
     float ib_next = 0.0f;
-    if (it + 1 < ntile) {
-      tile_copy<uint16_t, RS>(tb, j0 + 32, tile[cur ^ 1]);
+    if (more) {
+      tile_copy<uint16_t, RS>(tb, j0 + 32, tn);
       ib_next = tile_inv_load(inv_b, j0 + 32, nb);
     }
-    if (active) {
-      const uint16_t* crow = tile[cur] + (lane & 31) * RS + 8 * g;
-      floatx16_t acc = {};
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const uint4 raw = *(const uint4*)(crow + 16 * ks);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, raw), qa[ks], acc, 0, 0, 0);
-      }
-      tile_epilogue(acc, lane, j0, j_end, ia, ibt[cur], top);
-    }
-    if (it + 1 < ntile) {
-      if (threadIdx.x < 32) ibt[cur ^ 1][threadIdx.x] = ib_next;
+    if (active) tile_epilogue(bf16_tile_products<KS, RS>(tc, lane, qa), lane, j0, j_end, ia, ic, top);
+    if (more) {
+      if (threadIdx.x < 32) in[threadIdx.x] = ib_next;
       tile_copy_wait();
     }
     __syncthreads();
+  };
+  for (int it = 0; it < ntile; it += 2) {
+    step(it, tile0, tile1, ibt0, ibt1);
+    if (it + 1 < ntile) step(it + 1, tile1, tile0, ibt1, ibt0);
   }
   if (active && qi < na) {
-    int2* dst = part + ((size_t)qi * gridDim.y + blockIdx.y) * (2 * kTopK) + g * kTopK;
+    int2* row = part + (size_t)qi * slices * (2 * kTopK) + g * kTopK;
+    int2* dst = row + (size_t)cell.slice * (2 * kTopK);
 #pragma unroll
     for (int q = 0; q < kTopK; ++q) dst[q] = make_int2(__float_as_int(top.d[q]), top.j[q]);
+    // the last actual slice also writes the empty lists of the slices past nb
+    if (cell.slice == cell.n_slices_act - 1)
+      for (int sl = cell.n_slices_act; sl < slices; ++sl)
+#pragma unroll
+        for (int q = 0; q < kTopK; ++q) row[(size_t)sl * (2 * kTopK) + q] = make_int2(__float_as_int(INFINITY), -1);
   }
 }
 
