@@ -203,6 +203,16 @@ struct TurnTable {
   int c[8], s[8];  // round(2^16 cos(k pi / N_o)), round(2^16 sin(k pi / N_o))
 };
 
+// Every sample a keypoint needs -- the disc and both turned grids -- lies in
+// the square of offsets [-R, R) around it: |c U + s V| <= |(c, s)| |(U, V)|
+// < 2^16 (1 + 2^-15) (P - 1) sqrt 2, so (c U + s V) >> 17 lies in
+// [-(R - 1) - 1, R - 1].  The block first copies that window of the MIM into
+// LDS with whole-row (coalesced) loads, values masked to 3 bits and pixels
+// outside the image marked by bit 7; the turned samples are then gathered
+// from LDS instead of each touching its own cache line in global memory.
+template <int P>
+constexpr int turn_reach() { return ((P - 1) * 70712 + 99999) / 100000 + 1; }
+
 template <int P, int G, int NO>
 __global__ void __launch_bounds__(P * desc_kpb<P>()) k_describe_turn(const uint8_t* __restrict__ mim, int H, int W,
                                                                      const int* __restrict__ kpts,
@@ -217,8 +227,14 @@ __global__ void __launch_bounds__(P * desc_kpb<P>()) k_describe_turn(const uint8
   constexpr int KPB = desc_kpb<P>();
   constexpr int CS = P / G;
   constexpr int D = G * G * NO;
+  constexpr int R = turn_reach<P>();
+  static_assert((R - 1) * 100000 >= (P - 1) * 70712, "window reach");
+  constexpr int WR = 2 * R;                // window rows and columns
+  constexpr int NWD = (WR + 3 + 3) / 4;    // dwords loaded per window row (start aligned down to 4)
+  constexpr int WS = 4 * (NWD | 1);        // LDS row stride in bytes: an odd number of dwords
   static_assert(CS == 8 || CS == 16 || CS == 32, "cell side");
   static_assert(NO >= 2 && NO <= 8, "orientations");
+  __shared__ uint32_t win[KPB][WR * WS / 4];
   __shared__ uint32_t h[KPB][G * G][NO];
   __shared__ uint32_t hist[KPB][NO];
   __shared__ int sh_s[KPB], sh_s2[KPB], sh_two[KPB];
@@ -234,17 +250,63 @@ __global__ void __launch_bounds__(P * desc_kpb<P>()) k_describe_turn(const uint8
   }
   if (x < NO) hist[local][x] = 0u;
   if (x < 2) sh_n2[local][x] = 0u;
+  // window of the MIM: rows ky - R .., columns from x0a (x0 = kx - R aligned down to 4)
+  const int x0 = kx - R;
+  const int xo = x0 & 3;  // two's complement: x0 - xo is the multiple of 4 at or below x0
+  const int x0a = x0 - xo;
+  const uint8_t* wb = (const uint8_t*)win[local];
+  if (active) {
+    // whole dwords when every row start is 4-byte aligned (then a dword is
+    // either inside [0, W) or outside it), single bytes otherwise
+    const bool words = ((reinterpret_cast<uintptr_t>(mim) | (uintptr_t)W) & 3u) == 0;
+    if (words) {
+      // branch-free body (the load address is clamped into the image and the
+      // result masked), so the unrolled loads are all in flight together
+#pragma unroll 8
+      for (int d = x; d < WR * NWD; d += P) {
+        const int row = d / NWD, c = d - row * NWD;
+        const int gy = ky - R + row, gx = x0a + 4 * c;
+        const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+        const int cy = min(max(gy, 0), H - 1), cx = min(max(gx, 0), W - 4);
+        const uint32_t raw = *(const uint32_t*)(mim + (size_t)cy * W + cx);
+        win[local][row * (WS / 4) + c] = in ? (raw & 0x07070707u) : 0x80808080u;
+      }
+    } else {
+      for (int d = x; d < WR * NWD; d += P) {
+        const int row = d / NWD, c = d - row * NWD;
+        const int gy = ky - R + row, gx = x0a + 4 * c;
+        uint32_t v = 0x80808080u;
+        if (gy >= 0 && gy < H) {
+          const uint8_t* src = mim + (size_t)gy * W;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int xx = gx + e;
+            const uint32_t byte = (xx >= 0 && xx < W) ? (uint32_t)(src[xx] & 7) : 0x80u;
+            v = (v & ~(0xffu << (8 * e))) | (byte << (8 * e));
+          }
+        }
+        win[local][row * (WS / 4) + c] = v;
+      }
+    }
+  }
   __syncthreads();
   // disc histogram: this thread's column, offsets U = 2x - P + 1
   {
     const int U = 2 * x - P + 1;
-    const int gx = kx + x - P / 2;
+    const int lx = x - P / 2 + R + xo;
     uint64_t cnt = 0;  // 8-bit field per value; a column holds at most P < 256 pixels
-    if (active && gx >= 0 && gx < W) {
-      for (int j = 0; j < P; ++j) {
-        const int V = 2 * j - P + 1;
-        const int gy = ky + j - P / 2;
-        if (U * U + V * V <= P * P && gy >= 0 && gy < H) cnt += 1ull << (8 * (mim[(size_t)gy * W + gx] & 7));
+    if (active) {
+      // batches of 16 reads in flight, then branch-free counting
+      for (int j0 = 0; j0 < P; j0 += 16) {
+        uint32_t vv[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) vv[e] = j0 + e < P ? wb[(j0 + e - P / 2 + R) * WS + lx] : 0x80u;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int V = 2 * (j0 + e) - P + 1;
+          const bool in = U * U + V * V <= P * P && vv[e] < 0x80u;
+          cnt += (uint64_t)(in ? 1u : 0u) << (8 * (vv[e] & 7u));
+        }
       }
     }
 #pragma unroll
@@ -277,15 +339,25 @@ __global__ void __launch_bounds__(P * desc_kpb<P>()) k_describe_turn(const uint8
     for (int cy = 0; cy < G; ++cy) {
       uint64_t cnt = 0;
       if (live) {
+        // all CS reads of the band in flight, then branch-free counting
+        uint32_t vv[CS];
+        // the turned offsets advance by (2 s, 2 c) per grid row: products once
+        // per band (24-bit operands: |c|, |s| <= 2^16, |U|, |V| < P), sums after
+        const int V0 = 2 * cy * CS - P + 1;
+        int tx = __mul24(cq, U) + __mul24(sq, V0), ty = __mul24(cq, V0) - __mul24(sq, U);
+#pragma unroll
         for (int rr = 0; rr < CS; ++rr) {
-          const int V = 2 * (cy * CS + rr) - P + 1;
-          const int X = kx + ((cq * U + sq * V) >> 17);
-          const int Y = ky + ((-sq * U + cq * V) >> 17);
-          if (X >= 0 && X < W && Y >= 0 && Y < H) {
-            int b = (int)(mim[(size_t)Y * W + X] & 7) - r;
-            if (b < 0) b += NO;
-            cnt += 1ull << (8 * b);
-          }
+          const int lx = (tx >> 17) + R + xo;
+          const int ly = (ty >> 17) + R;
+          vv[rr] = wb[ly * WS + lx];
+          tx += 2 * sq;
+          ty += 2 * cq;
+        }
+#pragma unroll
+        for (int rr = 0; rr < CS; ++rr) {
+          int b = (int)(vv[rr] & 7u) - r;
+          b += b < 0 ? NO : 0;
+          cnt += (uint64_t)(vv[rr] < 0x80u ? 1u : 0u) << (8 * b);
         }
       }
       const uint32_t lo = (uint32_t)cnt, hi = (uint32_t)(cnt >> 32);
