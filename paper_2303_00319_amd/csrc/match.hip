@@ -141,11 +141,12 @@ __device__ __forceinline__ void tile_epilogue(const floatx16_t& acc, int lane, i
 }
 
 // Candidate tiles of 32 rows are copied from the table straight into LDS
-// (global_load_lds, no staging registers; double buffered: the next tile's
-// copy is in flight while the current one is multiplied) and read by the
-// block's 4 waves, each holding 32 queries in registers.  The table rows
-// already carry the LDS row stride RS, so a tile is one contiguous block.
-// grid = (ceil(rows_a / 128), S).
+// (global_load_lds, no staging registers; the BF16 kernel double buffers, so
+// the next tile's copy is in flight while the current one is multiplied) and
+// read by the block's 4 waves, each holding 32 queries in registers.  The
+// table rows already carry the LDS row stride RS, so a tile is one contiguous
+// block.  The FP32 and FP8 grids are (ceil(rows_a / 128), S); the BF16 grid
+// is one-dimensional (gemm_cell).
 template <typename TE, int RS>
 struct TileCopy {
   static constexpr int BYTES = 32 * RS * (int)sizeof(TE);
