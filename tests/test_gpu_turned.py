@@ -29,7 +29,8 @@ def _gpu():
     return r2, torch.device("cuda:0")
 
 
-def _check(r2, dev, mim, kpts, tag, n_orient=6):
+def _check(r2, dev, mim, kpts, tag, n_orient=6, byte_offset=0):
+    """byte_offset > 0 places the MIM that many bytes into its device buffer (rows not 4-byte aligned)."""
     print(f"[turned parity] {tag} n={len(kpts)} N_o={n_orient}", flush=True)
     dp = r2.defaults()[2]
     dp.n_orient = n_orient
@@ -37,7 +38,11 @@ def _check(r2, dev, mim, kpts, tag, n_orient=6):
     c_ref, k_ref, _ = describe.describe_rotated(mim, kpts, oracle.DescParams(n_orient=n_orient))
     kp = np.zeros((max(len(kpts), 1), 3), dtype=np.int32)
     kp[:len(kpts), :2] = kpts
-    d, inv, dk, nd = r2.describe(torch.from_numpy(mim).to(dev), torch.from_numpy(kp).to(dev),
+    buf = torch.zeros(mim.size + byte_offset, dtype=torch.uint8, device=dev)
+    buf[byte_offset:] = torch.from_numpy(mim.reshape(-1)).to(dev)
+    mim_dev = buf[byte_offset:].view(mim.shape)
+    assert mim_dev.data_ptr() % 4 == byte_offset % 4
+    d, inv, dk, nd = r2.describe(mim_dev, torch.from_numpy(kp).to(dev),
                                  torch.tensor([len(kpts)], dtype=torch.int32, device=dev), dp)
     nd = int(nd.item())
     assert nd == len(c_ref), f"{tag}: {nd} vs {len(c_ref)} rows"
@@ -61,6 +66,13 @@ def test_turned_rows_bitexact():
     mim2 = (rng.integers(0, 2, size=(200, 230)) * 3).astype(np.uint8)  # two values: many second rows
     pts = np.stack([rng.integers(30, 200, 333), rng.integers(30, 170, 333)], 1).astype(np.int32)
     assert _check(r2, dev, mim2, pts, "two-valued") > 100
+    # the kernel copies each keypoint's MIM window with dword loads when every row starts 4-byte
+    # aligned and byte by byte otherwise: an odd width, and a MIM starting one byte into its buffer
+    mim3 = rng.integers(0, 6, size=(211, 257)).astype(np.uint8)
+    pts = np.stack([rng.integers(0, 257, 301), rng.integers(0, 211, 301)], 1).astype(np.int32)
+    _check(r2, dev, mim3, pts, "odd width, all positions")
+    _check(r2, dev, mim8, np.stack([rng.integers(0, 260, 201), rng.integers(0, 300, 201)], 1).astype(np.int32),
+           "N_o=8, MIM one byte into its buffer", n_orient=8, byte_offset=1)
 
 
 def test_turned_pipeline_matches_a_rotated_pair_and_ransac_recovers_it():
