@@ -719,16 +719,13 @@ rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32
     return launch_status();
   }
   ProfScope ps7(7, st);
-  if (bf) {
-    hipLaunchKernelGGL(k_match_prep<true>, dim3(512), dim3(256), 0, st, desc_a, nA_dev, cap_a, D, L.rs, L.rows_a, ta, best,
-                       cap_a);
-    hipLaunchKernelGGL(k_match_prep<true>, dim3(512), dim3(256), 0, st, desc_b, nB_dev, cap_b, D, L.rs, L.rows_b, tb,
-                       (uint64_t*)nullptr, 0);
-  } else {
-    hipLaunchKernelGGL(k_match_prep<false>, dim3(512), dim3(256), 0, st, desc_a, nA_dev, cap_a, D, L.rs, L.rows_a, ta, best,
-                       cap_a);
-    hipLaunchKernelGGL(k_match_prep<false>, dim3(512), dim3(256), 0, st, desc_b, nB_dev, cap_b, D, L.rs, L.rows_b, tb,
-                       (uint64_t*)nullptr, 0);
+  {
+    const PrepJob ja{desc_a, nA_dev, cap_a, L.rows_a, ta, best, cap_a};
+    const PrepJob jb{desc_b, nB_dev, cap_b, L.rows_b, tb, nullptr, 0};
+    if (bf)
+      hipLaunchKernelGGL(k_match_prep<true>, dim3(512, 2), dim3(256), 0, st, ja, jb, D, L.rs);
+    else
+      hipLaunchKernelGGL(k_match_prep<false>, dim3(512, 2), dim3(256), 0, st, ja, jb, D, L.rs);
   }
   ps7.finish();
   const dim3 grid((L.rows_a + 127) / 128, L.slices);

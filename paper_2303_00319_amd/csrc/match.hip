@@ -41,14 +41,26 @@ __device__ __forceinline__ uint16_t bf16_bits_of_count(uint32_t c) {
 // MFMA depth plus a zero pad that staggers the rows over the LDS banks.  One
 // work item = CH consecutive elements of a row (8 for BF16: 16-byte load and
 // store; 4 for FP32: 8-byte load, 16-byte store; D and RS are multiples).
+// One table of a match call: its counts, actual row count and capacity, the
+// padded table it fills, and (table A only) the per-keypoint best slots.
+struct PrepJob {
+  const uint16_t* desc;
+  const int32_t* n_dev;
+  int cap, rows_pad;
+  void* table;
+  uint64_t* best;
+  int n_best;
+};
+
+// Both tables of a match call in one launch: blockIdx.y picks the table.
 template <bool BF16>
-__global__ void __launch_bounds__(256) k_match_prep(const uint16_t* __restrict__ desc, const int32_t* __restrict__ n_dev,
-                                                    int cap, int D, int RS, int rows_pad, void* __restrict__ table,
-                                                    uint64_t* __restrict__ best, int n_best) {
+__global__ void __launch_bounds__(256) k_match_prep(PrepJob ja, PrepJob jb, int D, int RS) {
+  const PrepJob j = blockIdx.y ? jb : ja;
+  const uint16_t* __restrict__ desc = j.desc;
   constexpr int CH = BF16 ? 8 : 4;
-  const int n = min(*n_dev, cap);
+  const int n = min(*j.n_dev, j.cap);
   const int chunks = RS / CH;
-  const size_t total = (size_t)rows_pad * chunks;
+  const size_t total = (size_t)j.rows_pad * chunks;
   for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < total; w += (size_t)gridDim.x * blockDim.x) {
     const int r = (int)(w / chunks), k0 = CH * (int)(w % chunks);
     const bool in = r < n && k0 < D;
@@ -60,16 +72,16 @@ __global__ void __launch_bounds__(256) k_match_prep(const uint16_t* __restrict__
 #pragma unroll
       for (int e = 0; e < 4; ++e)
         o[e] = (uint32_t)bf16_bits_of_count(word[e] & 0xffffu) | ((uint32_t)bf16_bits_of_count(word[e] >> 16) << 16);
-      *(uint4*)((uint16_t*)table + (size_t)r * RS + k0) = make_uint4(o[0], o[1], o[2], o[3]);
+      *(uint4*)((uint16_t*)j.table + (size_t)r * RS + k0) = make_uint4(o[0], o[1], o[2], o[3]);
     } else {
       uint2 raw = make_uint2(0u, 0u);
       if (in) raw = *(const uint2*)(desc + (size_t)r * D + k0);
-      *(float4*)((float*)table + (size_t)r * RS + k0) =
+      *(float4*)((float*)j.table + (size_t)r * RS + k0) =
           make_float4((float)(raw.x & 0xffffu), (float)(raw.x >> 16), (float)(raw.y & 0xffffu), (float)(raw.y >> 16));
     }
   }
-  if (best) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_best; i += gridDim.x * blockDim.x) best[i] = ~0ull;
+  if (j.best) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < j.n_best; i += gridDim.x * blockDim.x) j.best[i] = ~0ull;
   }
 }
 
