@@ -136,8 +136,10 @@ MatchLayout match_layout(int cap_a, int cap_b, int D, int precision) {
   L.rows_a = round_up(cap_a, 32);
   L.rows_b = round_up(cap_b, 32);
   const int blocks_x = (L.rows_a + 127) / 128;
-  // enough blocks to fill the chip several times over (256 CUs x 2 blocks), slices of >= 2 tiles
-  int slices = (4096 + blocks_x - 1) / blocks_x;
+  // enough blocks to fill the chip several times over (256 CUs x 2 blocks), slices of >= 2 tiles; the
+  // FP32 kernel (long MFMA chain per tile, one tile buffer) measured best with more, shorter slices
+  const int target_blocks = (bf || f8) ? 4096 : 6144;
+  int slices = (target_blocks + blocks_x - 1) / blocks_x;
   const int max_slices = (L.rows_b + 63) / 64;
   if (slices > max_slices) slices = max_slices;
   if (slices < 1) slices = 1;
