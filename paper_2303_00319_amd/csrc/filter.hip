@@ -402,7 +402,8 @@ __global__ void __launch_bounds__(W / P) k_pass_b_orient(const float2* __restric
                                                          float* __restrict__ amp) {
   constexpr int T = W / P;
   // scales past the first are transformed two at a time (shared exchanges)
-  // where the second LDS line leaves the occupancy alone
+  // where the second LDS line leaves the occupancy alone; a row team of one
+  // wave (T = 64) exchanges with wave barriers only
   constexpr bool PAIR = W <= 2048;
   __shared__ float2 line[PAIR ? 2 : 1][lds_line<W, T>()];
   const int t = threadIdx.x;
@@ -420,11 +421,11 @@ __global__ void __launch_bounds__(W / P) k_pass_b_orient(const float2* __restric
   for (int s = 1; s < NS; s += PAIR ? 2 : 1) {
     if constexpr (PAIR) {
       if (s + 1 < NS) {
-        fft_line2<+1, W, P>(zs[s], zs[s + 1], t, line[0], line[PAIR ? 1 : 0]);
+        fft_line2<+1, W, P, T == 64>(zs[s], zs[s + 1], t, line[0], line[PAIR ? 1 : 0]);
         continue;
       }
     }
-    fft_line<+1, W, P>(zs[s], t, line[0]);
+    fft_line<+1, W, P, T == 64>(zs[s], t, line[0]);
   }
   float sa[P], mx[P];
 #pragma unroll
