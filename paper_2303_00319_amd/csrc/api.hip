@@ -324,7 +324,7 @@ bool pass_b_w(int W, int H, const float2* y, const PCConsts& pcc, const float* t
     case 1024: launch_pass_b_split<1024, 16, NS, NO>(H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st); return true;
     case 1536: launch_pass_b_split<1536, 12, NS, NO>(H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st); return true;
     case 2048: launch_pass_b_split<2048, 8, NS, NO>(H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st); return true;
-    case 4096: launch_pass_b_split<4096, 8, NS, NO>(H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st); return true;
+    case 4096: launch_pass_b_split<4096, 16, NS, NO>(H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st); return true;
     default: return false;
   }
 }
