@@ -154,6 +154,8 @@ def test_plane_wave_phase_congruency_closed_form():
     tot = tau * (1 - p.mult ** -p.n_scales) / (1 - 1 / p.mult)
     T = tot * math.sqrt(math.pi / 2) + p.k * tot * math.sqrt((4 - math.pi) / 2)
     assert fb.noise_threshold(np.abs(eo[0]), p) == pytest.approx(T, rel=1e-9)
+    # the whole stage takes its orientation-0 threshold from the smallest scale's amplitude
+    assert fb.filter_mim(f, p)["T"][0] == pytest.approx(T, rel=1e-9)
     spread = (S / (max(amps) + p.eps) - 1) / (p.n_scales - 1)
     wgt = 1 / (1 + math.exp(p.g * (p.cutoff - spread)))
     expect = wgt * max(S * S / (S + p.eps) - T, 0.0) / (S + p.eps)
@@ -247,3 +249,131 @@ def test_noise_threshold_against_sampled_rayleigh_noise():
     assert got == pytest.approx(want, rel=3e-3)
     # the threshold scales linearly with the noise level
     assert fb.noise_threshold(4.0 * a0, p) == pytest.approx(4.0 * got, rel=1e-12)
+
+
+# ---------------------------------------------------------------- phase congruency, pinned to the
+# published energy model (Section 2.1 names a one-dimensional phase congruency per orientation; the
+# model is the noise-compensated energy form of the log-Gabor phase-congruency literature): each
+# scale's response z_s = A_s e^{i phi_s} contributes A_s (cos(phi_s - phibar) - |sin(phi_s - phibar)|),
+# phibar = arg sum_s z_s, and the sum is weighted by a logistic of the normalised frequency spread.
+# The oracle evaluates the same energy in rectangular form (e, o, phi_e, phi_o); the polar form below
+# is the definition, so a sign flip or swapped component in the deviation term fails here.
+
+def _polar_energy(zs, eps):
+    z = sum(zs)
+    bar = np.angle(z)
+    en = sum(np.abs(q) * (np.cos(np.angle(q) - bar) - np.abs(np.sin(np.angle(q) - bar))) for q in zs)
+    return en * np.abs(z) / (np.abs(z) + eps)
+
+
+def _logit(w):
+    return np.log(w / (1.0 - w))
+
+
+@pytest.mark.parametrize("n_scales,amps,spread", [
+    (4, (1.0, 0.5, 0.5, 0.5), 0.5),      # sum/max = 2.5 -> (2.5 - 1)/3: the sigmoid's midpoint
+    (4, (2.0, 0.0, 0.0, 0.0), 0.0),      # one active scale: no spread
+    (4, (0.7, 0.7, 0.7, 0.7), 1.0),      # flat over the scales: full spread
+    (5, (1.0, 0.25, 0.25, 0.25, 0.25), 0.25),
+    (5, (0.3, 0.3, 0.3, 0.3, 0.3), 1.0),
+])
+def test_spread_weight_is_a_logistic_of_the_normalised_spread(n_scales, amps, spread):
+    """With every scale in phase and no noise threshold the energy equals sum_s A_s, so PC is the
+    weight itself; its logit must be g (spread - cutoff) with spread normalised to [0, 1]
+    (0 for one active scale, 1 for equal amplitudes).  Dropping the (N_s - 1) normalisation, moving
+    the cutoff or changing the gain fails."""
+    p = PCParams(n_scales=n_scales, eps=0.0)
+    phase = 0.3
+    zs = [np.array([a * np.exp(1j * phase)]) for a in amps]
+    pc, s_a = fb.phase_congruency(zs, 0.0, p)
+    assert s_a[0] == pytest.approx(sum(amps), rel=1e-15)
+    assert _logit(pc[0]) == pytest.approx(p.g * (spread - p.cutoff), abs=1e-9)
+    if spread == p.cutoff:
+        assert pc[0] == pytest.approx(0.5, abs=1e-15)
+
+
+def test_phase_congruency_energy_matches_the_polar_definition():
+    """Random per-scale phases and amplitudes at the spread cutoff (weight exactly 1/2, eps = 0):
+    PC = max(En - T, 0) / (2 sum A) with En from the polar definition."""
+    p = PCParams(eps=0.0)
+    rng = np.random.default_rng(21)
+    n = 4000
+    amps = np.array([1.0, 0.5, 0.5, 0.5])
+    scale = rng.uniform(0.1, 50.0, size=n)
+    phases = [rng.uniform(-np.pi, np.pi, size=n) for _ in range(p.n_scales)]
+    # half the pixels nearly in phase (large energy), half random
+    for s in range(1, p.n_scales):
+        phases[s][: n // 2] = phases[0][: n // 2] + rng.normal(0.0, 0.2, size=n // 2)
+    zs = [amps[s] * scale * np.exp(1j * phases[s]) for s in range(p.n_scales)]
+    for t in (0.0, 3.0):
+        pc, s_a = fb.phase_congruency(zs, t, p)
+        en = _polar_energy(zs, 0.0)
+        want = 0.5 * np.maximum(en - t, 0.0) / s_a
+        assert np.allclose(pc, want, rtol=1e-12, atol=1e-14)
+        assert np.count_nonzero(want) > n // 3  # the deviation term is exercised where En > T
+
+
+def test_phase_congruency_deviation_term_has_its_sign():
+    """Two equal responses a half-angle delta either side of their mean phase: the energy is
+    2 A (cos delta - |sin delta|) (times |Z| / (|Z| + eps)), which is negative past 45 degrees."""
+    p = PCParams(n_scales=2, eps=1e-4)
+    for delta, a in ((0.1, 5.0), (0.5, 2.0), (np.pi / 4, 3.0), (1.2, 1.0)):
+        bar = 0.7
+        zs = [np.array([a * np.exp(1j * (bar + delta))]), np.array([a * np.exp(1j * (bar - delta))])]
+        zmag = 2 * a * np.cos(delta)
+        en = 2 * a * (np.cos(delta) - abs(np.sin(delta))) * zmag / (zmag + p.eps)
+        # equal amplitudes over two scales: spread 1 (up to eps), weight of the logistic at 1
+        sp = (2 * a / (a + p.eps) - 1.0)
+        w = 1.0 / (1.0 + np.exp(p.g * (p.cutoff - sp)))
+        pc, _ = fb.phase_congruency(zs, 0.0, p)
+        assert pc[0] == pytest.approx(w * max(en, 0.0) / (2 * a + p.eps), rel=1e-12, abs=1e-15)
+        if delta > np.pi / 4:
+            assert pc[0] == 0.0
+
+
+def test_two_spectral_lines_phase_congruency_closed_form():
+    """f = cos(2 pi l1 x / n) + cos(2 pi l2 x / n + psi): along orientation 0 every scale's response is
+    (G_s(l1) e^{i theta1} + G_s(l2) e^{i theta2}) / 2 (the mirrored lines fall where the one-sided
+    angular factor is below 1e-11), so the scales' phases differ pixel by pixel.  The oracle's PC of
+    orientation 0 must equal the polar-form PC of these closed-form responses."""
+    p = PCParams()
+    n = 64
+    l1, l2, psi = 5, 13, 1.1
+    xs = np.mgrid[0:n, 0:n][1].astype(np.float64)
+    th1 = 2 * np.pi * l1 * xs / n
+    th2 = 2 * np.pi * l2 * xs / n + psi
+    f = np.cos(th1) + np.cos(th2)
+    eo = fb.responses(fb.spectrum(f), 0, p)
+    zs = []
+    for s in range(p.n_scales):
+        g = fb.log_gabor(n, n, s, 0, p)
+        zs.append(0.5 * (g[0, l1] * np.exp(1j * th1) + g[0, l2] * np.exp(1j * th2)))
+        assert np.max(np.abs(eo[s] - zs[-1])) < 1e-10
+    amps = [np.abs(z) for z in zs]
+    t = fb.noise_threshold(amps[0], p)
+    # the exact order statistic of the closed-form amplitudes (library median as the primitive)
+    med = float(np.median(amps[0]))
+    tot = med / math.sqrt(math.log(4)) * (1 - p.mult ** -p.n_scales) / (1 - 1 / p.mult)
+    assert t == pytest.approx(tot * (math.sqrt(math.pi / 2) + p.k * math.sqrt((4 - math.pi) / 2)), rel=1e-12)
+    sa = sum(amps)
+    mx = np.maximum.reduce(amps)
+    sp = (sa / (mx + p.eps) - 1.0) / (p.n_scales - 1)
+    w = 1.0 / (1.0 + np.exp(p.g * (p.cutoff - sp)))
+    want = w * np.maximum(_polar_energy(zs, p.eps) - t, 0.0) / (sa + p.eps)
+    pc, _ = fb.phase_congruency(eo, t, p)
+    assert np.max(np.abs(pc - want)) < 1e-9
+    # the scales really disagree in phase somewhere, and PC is positive somewhere
+    dev = np.abs(np.angle(zs[0] * np.conj(zs[2])))
+    assert dev.max() > 1.0 and (want > 0.05).any()
+
+
+def test_lowpass_is_a_butterworth_of_the_stated_order():
+    """1/2 at the cutoff, 1 at DC, and an asymptotic log-log slope of -2 n (n = lp_order)."""
+    for order in (15, 7):
+        p = PCParams(lp_order=order)
+        assert fb.lowpass_factor(np.array([p.lp_cutoff]), p)[0] == pytest.approx(0.5, abs=1e-15)
+        assert fb.lowpass_factor(np.array([0.0]), p)[0] == 1.0
+        r1, r2 = 4.0 * p.lp_cutoff, 8.0 * p.lp_cutoff
+        l1, l2 = fb.lowpass_factor(np.array([r1, r2]), p)
+        slope = (math.log(l2) - math.log(l1)) / (math.log(r2) - math.log(r1))
+        assert slope == pytest.approx(-2.0 * order, rel=1e-6)
