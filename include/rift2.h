@@ -33,7 +33,13 @@
  *   RIFT2_ERR_UNSUPPORTED (size or parameter outside what the kernels are
  *   built for), RIFT2_ERR_WORKSPACE (workspace too small), RIFT2_ERR_DEVICE
  *   (a HIP call or launch failed; device faults surface at the next
- *   synchronisation).  On error nothing further is enqueued.
+ *   synchronisation), RIFT2_ERR_NOT_INITIALIZED (a call that runs FFTs on a
+ *   device where rift2_init has not run).  On error nothing further is
+ *   enqueued.
+ * - Capacities cannot overflow: detect writes at most max_keypoints records,
+ *   describe at most rows-per-keypoint x kpt_cap rows (checked against
+ *   desc_cap on the host) and match at most one record per A keypoint, so no
+ *   call truncates its output.
  */
 #ifndef RIFT2_H
 #define RIFT2_H
@@ -50,7 +56,8 @@ typedef enum {
   RIFT2_ERR_INVALID_ARG = 1,
   RIFT2_ERR_UNSUPPORTED = 2,
   RIFT2_ERR_WORKSPACE = 3,
-  RIFT2_ERR_DEVICE = 4
+  RIFT2_ERR_DEVICE = 4,
+  RIFT2_ERR_NOT_INITIALIZED = 5
 } rift2_status;
 
 typedef enum { RIFT2_U8 = 0, RIFT2_U16 = 1, RIFT2_F32 = 2 } rift2_dtype;
@@ -130,11 +137,19 @@ typedef struct {
  * against all R ring rows of every B keypoint (candidate order: B keypoint
  * r's ring row w is candidate r R + w); A row g R + w paired with B row r
  * gives the same dot product as A's plain row with ring row (R - w) mod R of
- * B keypoint r, so A carries the R-fold rows and the cost. */
+ * B keypoint r, so A carries the R-fold rows and the cost.
+ * mutual = 1 (a stricter form of Section 4's nearest-distance rule): an A row
+ * that passes the ratio test with nearest B row j1 is kept only if the
+ * nearest A row of j1 -- the smallest argmin over all A rows of the same d2
+ * values, ties to the lowest row -- belongs to its own A keypoint.  The check
+ * runs a second distance GEMM with the roles swapped (twice the matching
+ * work); in the FP8 form that reverse nearest row is the exact nearest of its
+ * 8 re-ranked candidates.  Not combined with ring. */
 typedef struct {
   float ratio_sq;
   int32_t precision; /* rift2_precision of the distance GEMM */
   int32_t ring;      /* 0, or rows per A keypoint of a ring matching */
+  int32_t mutual;    /* 0 or 1: mutual nearest-neighbour check (ring = 0 only) */
 } rift2_match_params;
 
 typedef struct {
@@ -152,8 +167,8 @@ typedef struct {
 /* Defaults: n_scales 4, n_orient 6, min_wavelength 3, mult 2.1, sigma_onf
  * 0.55, dtheta_on_sigma 1.2, lp 0.45/15, k 2, cutoff 0.5, g 10, eps 1e-4;
  * FAST 0.001, 5000 keypoints, patch 96; grid 6, ratio 4/5; ratio_sq 0.81,
- * FP32, no ring; descriptor form RIFT2_DESC_DOMINANT.  Any argument may be
- * NULL. */
+ * FP32, no ring, no mutual check; descriptor form RIFT2_DESC_DOMINANT.  Any
+ * argument may be NULL. */
 void rift2_default_params(rift2_pc_params* pc, rift2_detect_params* det, rift2_desc_params* desc,
                           rift2_match_params* match);
 
@@ -183,11 +198,44 @@ size_t rift2_match_workspace_size(int32_t cap_a, int32_t cap_b, int32_t D, const
  *   amp_sums    n_orient x H x W float, A_o (may be NULL)
  * mim must be 4-byte aligned, max_moment and min_moment 16-byte aligned
  * (RIFT2_ERR_INVALID_ARG otherwise).  Circular (periodic) convolution, raw
- * pixel values. */
+ * pixel values.  RIFT2_ERR_NOT_INITIALIZED if rift2_init has not run on the
+ * current device. */
 rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t W, int64_t pitch,
                               const rift2_pc_params* pc, uint8_t* mim, float* max_moment,
                               float* min_moment, float* amp_sums, void* workspace,
                               size_t workspace_bytes, void* stream);
+
+/* Diagnostics of the filter stage (not needed for computing).
+ *
+ * rift2_debug_response: the complex response EO_{s,o} = IDFT2(DFT2(img) G_{s,o})
+ * of one filter of the bank (Section 2.2: the response components of the
+ * log-Gabor filter, whose amplitudes rift2_filter_mim sums per orientation),
+ * computed by the same kernels as rift2_filter_mim.
+ *   scale, orient  0 <= scale < n_scales, 0 <= orient < n_orient
+ *   eo             H x W complex values as interleaved float pairs (re, im),
+ *                  8-byte aligned
+ *   workspace      as for rift2_filter_mim (rift2_filter_workspace_size);
+ *                  its previous contents are overwritten
+ * Errors as rift2_filter_mim; RIFT2_ERR_INVALID_ARG for a filter index out of
+ * range. */
+rift2_status rift2_debug_response(const void* img, int32_t dtype, int32_t H, int32_t W, int64_t pitch,
+                                  const rift2_pc_params* pc, int32_t scale, int32_t orient, float* eo,
+                                  void* workspace, size_t workspace_bytes, void* stream);
+
+/* rift2_debug_noise: the noise-threshold intermediates (Section 2.1's phase
+ * congruency; median of the smallest-scale amplitude, Rayleigh model) that
+ * the last rift2_filter_mim call on `workspace` left in it, copied on
+ * `stream` (enqueue it after that call, on the same stream):
+ *   a0           n_orient x H x W float, A0_o = |EO_{0,o}| as the selection
+ *                saw it (may be NULL)
+ *   order_stats  n_orient x 2 float: the order statistics of rank HW/2 - 1
+ *                and HW/2 of A0_o (their mean is the median; may be NULL)
+ *   t_o          n_orient double: the threshold T_o, evaluated in FP64
+ *                (may be NULL)
+ * H, W and pc must be those of the rift2_filter_mim call. */
+rift2_status rift2_debug_noise(const void* workspace, size_t workspace_bytes, int32_t H, int32_t W,
+                               const rift2_pc_params* pc, float* a0, float* order_stats, double* t_o,
+                               void* stream);
 
 /* FAST keypoints on `moment` (H x W float, normally the max moment map):
  * min-max normalisation to [0, 1], 16-pixel segment test with arc 9 and
@@ -228,6 +276,14 @@ rift2_status rift2_describe(const uint8_t* mim, int32_t H, int32_t W, const rift
                             uint16_t* desc, float* inv_norm, int32_t* desc_kp, int32_t desc_cap,
                             int32_t* n_desc_dev, void* workspace, size_t workspace_bytes,
                             void* stream);
+
+/* FP32 view of descriptor rows: out[r][d] = fl(desc[r][d] * inv_norm[r]),
+ * the L2-normalised vectors whose Euclidean distances rift2_match compares
+ * (Section 2.2 concatenates the cell histograms into the feature vector),
+ * for the first *n_rows_dev rows (at most cap rows of D values).  out is
+ * cap x D floats; rows past *n_rows_dev are left alone. */
+rift2_status rift2_desc_normalize(const uint16_t* desc, const float* inv_norm, const int32_t* n_rows_dev,
+                                  int32_t cap, int32_t D, float* out, void* stream);
 
 /* Brute-force matching of descriptor rows A against B (Section 4).  The
  * squared distance of normalised count vectors is evaluated as
@@ -333,6 +389,9 @@ typedef struct {
   int32_t max_keypoints;      /* K per image; <= 0 selects floor(2e-3 * H * W) */
   rift2_correspondence* out;  /* device, capacity 2 K entries (written by the match stage) */
   int32_t* n_out;             /* device int32: number of matches */
+  void* ready;                /* hipEvent_t recorded once the images and out / n_out are ready
+                                 (the request's first stage waits for it), or NULL if they
+                                 already are */
 } rift2_request;
 
 typedef struct {

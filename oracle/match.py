@@ -8,6 +8,10 @@ distance.  Readings where it is silent:
 * j1 = nearest B row (ties -> lowest row); j2 = nearest B row that belongs to a
   different B keypoint than j1 (a keypoint has at most two rows);
 * accept row i iff d^2(i, j1) < r^2 d^2(i, j2) with r = 0.9; no j2 -> reject;
+* mutual mode (off by default; a mutual nearest-neighbour check as a stricter
+  form of the nearest-distance rule): row i with nearest B row j1 is kept
+  only if the nearest A row of j1 (the smallest argmin over all A rows of the
+  same d^2 matrix, ties -> lowest row) belongs to row i's A keypoint;
 * each A keypoint keeps its accepted row with the smallest d^2 (ties -> lower
   row); the result is sorted by A keypoint.
 
@@ -69,15 +73,26 @@ def match(ca, kp_a, cb, kp_b, p: MatchParams = MatchParams(), dtype=np.float64, 
         z = np.zeros((0,), np.int32)
         return z, z.copy(), np.zeros((0,), dtype)
     j1s, d1s, accs = [], [], []
+    n_b = cb.shape[0]
+    col_d = np.full(n_b, np.inf)   # reverse nearest neighbour: column minimum of d^2
+    col_i = np.full(n_b, -1, dtype=np.int64)
     for r0 in range(0, n_a, chunk):
         d2 = distances(ca[r0:r0 + chunk], cb, dtype)
         j1, d1, acc = _row_decisions(d2, kp_b, p.ratio_sq, dtype)
         j1s.append(j1)
         d1s.append(d1)
         accs.append(acc)
+        if p.mutual:
+            ci = np.argmin(d2, axis=0)  # first occurrence: lowest row of this chunk
+            cd = d2[ci, np.arange(n_b)].astype(np.float64)
+            upd = cd < col_d  # chunks ascend, so ties keep the earlier (lower) row
+            col_d = np.where(upd, cd, col_d)
+            col_i = np.where(upd, ci + r0, col_i)
     j1 = np.concatenate(j1s)
     d1 = np.concatenate(d1s)
     acc = np.concatenate(accs)
+    if p.mutual:
+        acc = acc & (kp_a[col_i[j1]] == kp_a)
     best = {}
     for i in range(n_a):
         if not acc[i]:
@@ -114,7 +129,14 @@ def match_bruteforce(ca, kp_a, cb, kp_b, p: MatchParams = MatchParams()):
             rows.append(None)
             continue
         j2 = min(others, key=lambda j: (ds[j], j))
-        rows.append((j1, ds[j1]) if ds[j1] < p.ratio_sq * ds[j2] else None)
+        ok = ds[j1] < p.ratio_sq * ds[j2]
+        if ok and p.mutual:
+            back = []
+            for i2, c2 in enumerate(ca):
+                dot = sum(int(u) * int(v) for u, v in zip(c2, cb[j1]))
+                back.append((2.0 - 2.0 * dot / (na[i2] * nb[j1]), i2))
+            ok = int(kp_a[min(back)[1]]) == int(kp_a[i])
+        rows.append((j1, ds[j1]) if ok else None)
     best = {}
     for i, r in enumerate(rows):
         if r is None:

@@ -50,3 +50,5 @@ class DescParams:
 class MatchParams:
     # accept iff d1^2 < ratio_sq * d2^2 (ratio 0.9)
     ratio_sq: float = 0.81
+    # also require the accepted row's nearest B row to have this A keypoint's row as its own nearest
+    mutual: bool = False

@@ -18,7 +18,8 @@ __all__ = [
     "profile_enable", "profile_read", "PCParams", "DetectParams", "DescParams", "MatchParams", "Engine",
     "PREC_FP32", "PREC_BF16", "PREC_FP8", "STAGES", "RansacParams", "ransac", "consensus", "ransac_workspace_bytes",
     "SIMILARITY_BYTES", "CONSENSUS_BYTES", "similarity_fields", "consensus_fields", "DESC_DOMINANT", "DESC_PLAIN",
-    "DESC_RING", "DESC_TURNED", "rows_per_keypoint", "detect_union",
+    "DESC_RING", "DESC_TURNED", "rows_per_keypoint", "detect_union", "debug_response", "debug_noise",
+    "desc_normalize", "filter_workspace_bytes",
 ]
 
 
@@ -267,6 +268,49 @@ def match(desc_a, inv_a, kp_a, n_a, desc_b, inv_b, kp_b, n_b, mp: MatchParams | 
                                                              dtype=torch.uint8, device=dev)
     match_into(desc_a, inv_a, kp_a, n_a, desc_b, inv_b, kp_b, n_b, mp, out, n, ws, stream)
     return out, n
+
+
+def debug_response(img, scale, orient, pc: PCParams | None = None, workspace=None, stream=None):
+    """Complex response EO_{scale,orient} (complex64 H x W) of one filter of the bank, by the library's kernels."""
+    torch = _torch()
+    if pc is None:
+        pc = defaults()[0]
+    init(img.device.index or 0)
+    h, w = img.shape
+    eo = torch.empty((h, w, 2), dtype=torch.float32, device=img.device)
+    ws = workspace if workspace is not None else torch.empty(filter_workspace_bytes(h, w, pc), dtype=torch.uint8,
+                                                             device=img.device)
+    st = _lib.load().rift2_debug_response(_ptr(img), _image_dtype(img), h, w, img.stride(0), ctypes.byref(pc),
+                                          int(scale), int(orient), _ptr(eo), _ptr(ws), _nbytes(ws), _stream(stream))
+    _lib.check(st, "rift2_debug_response")
+    return torch.view_as_complex(eo)
+
+
+def debug_noise(workspace, h, w, pc: PCParams | None = None, stream=None):
+    """(A0 float [N_o, H, W], order statistics float [N_o, 2], T_o float64 [N_o]) that the last
+    filter_mim on `workspace` left there."""
+    torch = _torch()
+    if pc is None:
+        pc = defaults()[0]
+    dev = workspace.device
+    a0 = torch.empty((pc.n_orient, h, w), dtype=torch.float32, device=dev)
+    ostat = torch.empty((pc.n_orient, 2), dtype=torch.float32, device=dev)
+    t_o = torch.empty((pc.n_orient,), dtype=torch.float64, device=dev)
+    st = _lib.load().rift2_debug_noise(_ptr(workspace), _nbytes(workspace), h, w, ctypes.byref(pc), _ptr(a0),
+                                       _ptr(ostat), _ptr(t_o), _stream(stream))
+    _lib.check(st, "rift2_debug_noise")
+    return a0, ostat, t_o
+
+
+def desc_normalize(desc, inv_norm, n_rows, stream=None):
+    """FP32 view fl(count * inv_norm) of the first n_rows descriptor rows (rows past it are zero)."""
+    torch = _torch()
+    cap, d = desc.shape
+    out = torch.zeros((cap, d), dtype=torch.float32, device=desc.device)
+    st = _lib.load().rift2_desc_normalize(_ptr(desc), _ptr(inv_norm), _ptr(n_rows), cap, d, _ptr(out),
+                                          _stream(stream))
+    _lib.check(st, "rift2_desc_normalize")
+    return out
 
 
 SIMILARITY_BYTES = 48  # rift2_similarity
@@ -533,8 +577,10 @@ class Engine:
 
     The arena (the HBM budget) is one device tensor; requests are admitted in
     arrival order as their buffers fit into it and a stream pair is free.
-    Inputs must be complete on the device when submitted; the engine keeps a
-    reference to every tensor of a request until its completion is polled.
+    submit() records an event on the current stream, and the request's first
+    stage waits for it, so inputs still being written there are safe; the
+    engine keeps a reference to every tensor of a request until its
+    completion is polled.
     """
 
     def __init__(self, arena_bytes, max_inflight=8, pc=None, det=None, dp=None, mp=None, device=0):
@@ -569,11 +615,13 @@ class Engine:
         if out is None:
             out = torch.empty((2 * k, 3), dtype=torch.int32, device=self.dev)
         if n_out is None:
-            n_out = torch.zeros((1,), dtype=torch.int32, device=self.dev)
+            n_out = torch.empty((1,), dtype=torch.int32, device=self.dev)  # the match stage always writes it
+        ready = torch.cuda.Event()
+        ready.record(torch.cuda.current_stream(self.dev))
         r = _lib.Request(int(rid), img_a.data_ptr(), img_b.data_ptr(), _image_dtype(img_a), h, w, max_keypoints,
-                         out.data_ptr(), n_out.data_ptr())
+                         out.data_ptr(), n_out.data_ptr(), ready.cuda_event)
         _lib.check(_lib.load().rift2_engine_submit(self._h, ctypes.byref(r)), "rift2_engine_submit")
-        self._live[int(rid)] = (img_a, img_b, out, n_out)
+        self._live[int(rid)] = (img_a, img_b, out, n_out, ready)
         return out, n_out
 
     def poll(self, max_done=256):

@@ -7,7 +7,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librift2.so")
 
-OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_DEVICE = 0, 1, 2, 3, 4
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_DEVICE, ERR_NOT_INITIALIZED = 0, 1, 2, 3, 4, 5
 U8, U16, F32 = 0, 1, 2
 PREC_FP32, PREC_BF16, PREC_FP8 = 0, 1, 2
 DESC_DOMINANT, DESC_PLAIN, DESC_RING, DESC_TURNED = 0, 1, 2, 3
@@ -46,7 +46,8 @@ class DescParams(ctypes.Structure):
 
 
 class MatchParams(ctypes.Structure):
-    _fields_ = [("ratio_sq", ctypes.c_float), ("precision", ctypes.c_int32), ("ring", ctypes.c_int32)]
+    _fields_ = [("ratio_sq", ctypes.c_float), ("precision", ctypes.c_int32), ("ring", ctypes.c_int32),
+                ("mutual", ctypes.c_int32)]
 
 
 class RansacParams(ctypes.Structure):
@@ -64,6 +65,7 @@ class Request(ctypes.Structure):
         ("max_keypoints", ctypes.c_int32),
         ("out", ctypes.c_void_p),
         ("n_out", ctypes.c_void_p),
+        ("ready", ctypes.c_void_p),
     ]
 
 
@@ -84,7 +86,7 @@ EXPORTS = [
     "rift2_profile_enable", "rift2_profile_read", "rift2_engine_request_bytes", "rift2_engine_create",
     "rift2_engine_submit", "rift2_engine_poll", "rift2_engine_pending", "rift2_engine_destroy",
     "rift2_ransac_workspace_size", "rift2_ransac", "rift2_consensus", "rift2_detect_union_workspace_size",
-    "rift2_detect_union",
+    "rift2_detect_union", "rift2_debug_response", "rift2_debug_noise", "rift2_desc_normalize",
 ]
 STAGES = ["row_dft", "pass_a", "noise_pre", "noise_sel", "pass_b", "detect", "describe", "match_prep",
           "match_gemm", "match_merge", "pass_b_reduce", "ransac"]
@@ -142,6 +144,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rift2_ransac.restype = ctypes.c_int
     lib.rift2_consensus.argtypes = [vp, vp, vp, i32, vp, i32, vp, i32, ctypes.c_double, vp, vp, vp, sz, vp]
     lib.rift2_consensus.restype = ctypes.c_int
+    lib.rift2_debug_response.argtypes = [vp, i32, i32, i32, i64, P(PCParams), i32, i32, vp, vp, sz, vp]
+    lib.rift2_debug_response.restype = ctypes.c_int
+    lib.rift2_debug_noise.argtypes = [vp, sz, i32, i32, P(PCParams), vp, vp, vp, vp]
+    lib.rift2_debug_noise.restype = ctypes.c_int
+    lib.rift2_desc_normalize.argtypes = [vp, vp, vp, i32, i32, vp, vp]
+    lib.rift2_desc_normalize.restype = ctypes.c_int
     lib.rift2_profile_enable.argtypes = [ctypes.c_int]
     lib.rift2_profile_enable.restype = ctypes.c_int
     lib.rift2_profile_read.argtypes = [P(ctypes.c_double), P(ctypes.c_int64), ctypes.c_int]

@@ -59,7 +59,7 @@ bool pc_built(const rift2_pc_params* p) {
 }
 
 struct FilterLayout {
-  size_t rrow, yplanes, a0, cand, spc, zero, t32, t64, total;
+  size_t rrow, yplanes, a0, cand, spc, zero, t32, t64, ostat, total;
   int zero_words;
 };
 
@@ -77,6 +77,7 @@ FilterLayout filter_layout(int H, int W, const rift2_pc_params* p) {
   L.zero = c.take((size_t)L.zero_words * sizeof(uint32_t));
   L.t32 = c.take(p->n_orient * sizeof(float));
   L.t64 = c.take(p->n_orient * sizeof(double));
+  L.ostat = c.take(2 * p->n_orient * sizeof(float));
   L.total = c.off;
   return L;
 }
@@ -110,14 +111,36 @@ DetectLayout detect_layout(int H, int W, const rift2_detect_params* d, int maps 
   return L;
 }
 
-struct MatchLayout {
-  size_t ta, tb, wa, wb, part, best, rowj, rowd, total;
-  int dp, rs, rows_a, rows_b, slices, slice_rows, topk;
+// How one GEMM direction splits its candidate rows into slices.
+struct SliceShape {
+  int slices, slice_rows;
 };
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
-MatchLayout match_layout(int cap_a, int cap_b, int D, int precision) {
+SliceShape slice_shape(int rows_q, int rows_c, bool fp32) {
+  SliceShape s;
+  const int blocks_x = (rows_q + 127) / 128;
+  // enough blocks to fill the chip several times over (256 CUs x 2 blocks), slices of >= 2 tiles; the
+  // FP32 kernel (long MFMA chain per tile, one tile buffer) measured best with more, shorter slices
+  const int target_blocks = fp32 ? 6144 : 4096;
+  int slices = (target_blocks + blocks_x - 1) / blocks_x;
+  const int max_slices = (rows_c + 63) / 64;
+  if (slices > max_slices) slices = max_slices;
+  if (slices < 1) slices = 1;
+  s.slice_rows = round_up((rows_c + slices - 1) / slices, 32);
+  s.slices = (rows_c + s.slice_rows - 1) / s.slice_rows;
+  return s;
+}
+
+// Mutual mode adds the reverse GEMM's lists (B rows as queries, A rows as
+// candidates) and each B row's nearest A row.
+struct MatchLayout {
+  size_t ta, tb, wa, wb, part, best, rowj, rowd, part_r, a1, total;
+  int dp, rs, rows_a, rows_b, slices, slice_rows, topk, slices_r, slice_rows_r;
+};
+
+MatchLayout match_layout(int cap_a, int cap_b, int D, int precision, bool mutual = false) {
   MatchLayout L;
   const bool bf = precision == RIFT2_PREC_BF16;
   const bool f8 = precision == RIFT2_PREC_FP8;
@@ -135,16 +158,12 @@ MatchLayout match_layout(int cap_a, int cap_b, int D, int precision) {
   L.topk = f8 ? kTopK8 : kTopK;
   L.rows_a = round_up(cap_a, 32);
   L.rows_b = round_up(cap_b, 32);
-  const int blocks_x = (L.rows_a + 127) / 128;
-  // enough blocks to fill the chip several times over (256 CUs x 2 blocks), slices of >= 2 tiles; the
-  // FP32 kernel (long MFMA chain per tile, one tile buffer) measured best with more, shorter slices
-  const int target_blocks = (bf || f8) ? 4096 : 6144;
-  int slices = (target_blocks + blocks_x - 1) / blocks_x;
-  const int max_slices = (L.rows_b + 63) / 64;
-  if (slices > max_slices) slices = max_slices;
-  if (slices < 1) slices = 1;
-  L.slice_rows = round_up((L.rows_b + slices - 1) / slices, 32);
-  L.slices = (L.rows_b + L.slice_rows - 1) / L.slice_rows;
+  const SliceShape fw = slice_shape(L.rows_a, L.rows_b, !(bf || f8));
+  L.slices = fw.slices;
+  L.slice_rows = fw.slice_rows;
+  const SliceShape rv = slice_shape(L.rows_b, L.rows_a, !(bf || f8));
+  L.slices_r = mutual ? rv.slices : 0;
+  L.slice_rows_r = mutual ? rv.slice_rows : 0;
   const size_t el = f8 ? 1 : (bf ? 2 : 4);
   Carver c;
   L.ta = c.take((size_t)L.rows_a * L.rs * el);
@@ -155,6 +174,8 @@ MatchLayout match_layout(int cap_a, int cap_b, int D, int precision) {
   L.best = c.take((size_t)cap_a * sizeof(uint64_t));
   L.rowj = c.take((size_t)cap_a * sizeof(int32_t));
   L.rowd = c.take((size_t)cap_a * sizeof(float));
+  L.part_r = c.take(mutual ? (size_t)L.rows_b * L.slices_r * 2 * L.topk * sizeof(int2) : 0);
+  L.a1 = c.take(mutual ? (size_t)cap_b * sizeof(int32_t) : 0);
   L.total = c.off;
   return L;
 }
@@ -183,6 +204,14 @@ rift2_status launch_status() {
 
 std::mutex g_init_mu;
 bool g_init_done[64] = {};
+
+// The FFT kernels read the twiddle tables that rift2_init loads per device.
+bool current_device_ready() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+  std::lock_guard<std::mutex> lock(g_init_mu);
+  return g_init_done[dev];
+}
 
 // ---- stage timing (diagnostics)
 constexpr int kProfGroups = 12;
@@ -302,6 +331,25 @@ bool dispatch_noise_pre(int W, int H, int n_orient, int n_scales, float2* y, flo
   }
 }
 
+template <int W, int P>
+void launch_rows_inverse(int H, const float2* y, float2* out, hipStream_t st) {
+  constexpr int LINES = 256 / FftPlan<W, P>::T;
+  hipLaunchKernelGGL((k_rows_inverse<W, P>), dim3(H / LINES), dim3(256), 0, st, y, out);
+}
+
+bool dispatch_rows_inverse(int W, int H, const float2* y, float2* out, hipStream_t st) {
+  switch (W) {
+    case 256: launch_rows_inverse<256, 16>(H, y, out, st); return true;
+    case 512: launch_rows_inverse<512, 16>(H, y, out, st); return true;
+    case 768: launch_rows_inverse<768, 12>(H, y, out, st); return true;
+    case 1024: launch_rows_inverse<1024, 16>(H, y, out, st); return true;
+    case 1536: launch_rows_inverse<1536, 12>(H, y, out, st); return true;
+    case 2048: launch_rows_inverse<2048, 16>(H, y, out, st); return true;
+    case 4096: launch_rows_inverse<4096, 16>(H, y, out, st); return true;
+    default: return false;
+  }
+}
+
 template <int W, int P, int NS, int NO>
 void launch_pass_b_split(int H, const float2* y, const PCConsts& pcc, const float* t_o, float2* spc, uint8_t* mim,
                          float* mmax, float* mmin, float* amp, hipStream_t st) {
@@ -336,6 +384,78 @@ bool dispatch_pass_b(int ns, int no, int W, int H, const float2* y, const PCCons
   if (ns == 4 && no == 8) return pass_b_w<4, 8>(W, H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st);
   if (ns == 5 && no == 6) return pass_b_w<5, 6>(W, H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st);
   return false;
+}
+
+// FP32 or BF16 distance GEMM of one direction: queries q against candidates c.
+template <bool CF>
+void launch_gemm_exact(bool bf, int dp, const void* tq, const float* inv_q, const int32_t* nq_dev, int cap_q,
+                       const void* tc, const float* inv_c, const int32_t* nc_dev, int cap_c, int rows_q,
+                       int slice_rows, int slices, int2* part, hipStream_t st) {
+  const dim3 grid((rows_q + 127) / 128, slices);
+  if (bf) {
+    // the BF16 GEMM deals its cells to the XCDs itself (gemm_cell): 1-D grid
+    const dim3 grid_xcd(8 * ((grid.x + 1) / 2) * ((slices + 3) / 4));
+    if (dp == 224)
+      hipLaunchKernelGGL((k_match_gemm_bf16<224, CF>), grid_xcd, dim3(256), 0, st, (const uint16_t*)tq, inv_q, nq_dev,
+                         (const uint16_t*)tc, inv_c, nc_dev, cap_q, cap_c, slice_rows, slices, part);
+    else
+      hipLaunchKernelGGL((k_match_gemm_bf16<288, CF>), grid_xcd, dim3(256), 0, st, (const uint16_t*)tq, inv_q, nq_dev,
+                         (const uint16_t*)tc, inv_c, nc_dev, cap_q, cap_c, slice_rows, slices, part);
+  } else {
+    if (dp == 216)
+      hipLaunchKernelGGL((k_match_gemm_f32<216, CF>), grid, dim3(256), 0, st, (const float*)tq, inv_q, nq_dev,
+                         (const float*)tc, inv_c, nc_dev, cap_q, cap_c, slice_rows, part);
+    else
+      hipLaunchKernelGGL((k_match_gemm_f32<288, CF>), grid, dim3(256), 0, st, (const float*)tq, inv_q, nq_dev,
+                         (const float*)tc, inv_c, nc_dev, cap_q, cap_c, slice_rows, part);
+  }
+}
+
+void launch_gemm_fp8(int dp, const uint8_t* tq, const float* wq, const int32_t* nq_dev, int cap_q, const uint8_t* tc,
+                     const float* wc, const int32_t* nc_dev, int cap_c, int rows_q, int slice_rows, int slices,
+                     int2* part, hipStream_t st) {
+  const dim3 grid((rows_q + 127) / 128, slices);
+  if (dp == 256)
+    hipLaunchKernelGGL(k_match_gemm_fp8<256>, grid, dim3(256), 0, st, tq, wq, nq_dev, tc, wc, nc_dev, cap_q, cap_c,
+                       slice_rows, part);
+  else
+    hipLaunchKernelGGL(k_match_gemm_fp8<320>, grid, dim3(256), 0, st, tq, wq, nq_dev, tc, wc, nc_dev, cap_q, cap_c,
+                       slice_rows, part);
+}
+
+// Constants of the filter bank, phase congruency and noise model for the kernels.
+void filter_consts(int H, int W, const rift2_pc_params* pc, FilterConsts* fcp, PCConsts* pccp, NoiseConsts* ncp) {
+  FilterConsts& fc = *fcp;
+  std::memset(&fc, 0, sizeof(fc));
+  fc.H = H;
+  fc.W = W;
+  fc.n_scales = pc->n_scales;
+  fc.n_orient = pc->n_orient;
+  const double ls = std::log((double)pc->sigma_onf);
+  fc.inv_2ln2_sigma = (float)(1.0 / (2.0 * ls * ls));
+  for (int s = 0; s < pc->n_scales; ++s)
+    fc.log_f0[s] = (float)std::log(1.0 / ((double)pc->min_wavelength * std::pow((double)pc->mult, (double)s)));
+  fc.log_lp_cutoff = (float)std::log((double)pc->lp_cutoff);
+  fc.two_n = (float)(2 * pc->lp_order);
+  PCConsts& pcc = *pccp;
+  std::memset(&pcc, 0, sizeof(pcc));
+  for (int o = 0; o < pc->n_orient; ++o) {
+    const double th = o * M_PI / pc->n_orient;
+    fc.theta_o[o] = (float)th;
+    pcc.cos_o[o] = (float)std::cos(th);
+    pcc.sin_o[o] = (float)std::sin(th);
+  }
+  const double sig_th = (M_PI / pc->n_orient) / (double)pc->dtheta_on_sigma;
+  fc.inv_2sig_theta2 = (float)(1.0 / (2.0 * sig_th * sig_th));
+  fc.inv_hw = (float)(1.0 / ((double)H * (double)W));
+  pcc.eps = pc->eps;
+  pcc.g = pc->g;
+  pcc.cutoff = pc->cutoff;
+  NoiseConsts& nc = *ncp;
+  nc.mult = pc->mult;
+  nc.k = pc->k;
+  nc.n_scales = pc->n_scales;
+
 }
 
 }  // namespace
@@ -377,6 +497,7 @@ void rift2_default_params(rift2_pc_params* pc, rift2_detect_params* det, rift2_d
     match->ratio_sq = 0.81f;
     match->precision = RIFT2_PREC_FP32;
     match->ring = 0;
+    match->mutual = 0;
   }
 }
 
@@ -387,6 +508,7 @@ const char* rift2_status_string(rift2_status s) {
     case RIFT2_ERR_UNSUPPORTED: return "unsupported size or parameter";
     case RIFT2_ERR_WORKSPACE: return "workspace too small";
     case RIFT2_ERR_DEVICE: return "device error";
+    case RIFT2_ERR_NOT_INITIALIZED: return "rift2_init has not run on the current device";
     default: return "unknown status";
   }
 }
@@ -454,7 +576,7 @@ size_t rift2_describe_workspace_size(int32_t kpt_cap) {
 
 size_t rift2_match_workspace_size(int32_t cap_a, int32_t cap_b, int32_t D, const rift2_match_params* mp) {
   if (cap_a <= 0 || cap_b <= 0 || D <= 0 || !mp) return 0;
-  return match_layout(cap_a, cap_b, D, mp->precision).total;
+  return match_layout(cap_a, cap_b, D, mp->precision, mp->mutual != 0).total;
 }
 
 rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t W, int64_t pitch,
@@ -471,6 +593,7 @@ rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t
   if (!size_ok(H) || !size_ok(W) || !pc_built(pc)) return RIFT2_ERR_UNSUPPORTED;
   const FilterLayout L = filter_layout(H, W, pc);
   if (workspace_bytes < L.total) return RIFT2_ERR_WORKSPACE;
+  if (!current_device_ready()) return RIFT2_ERR_NOT_INITIALIZED;
   hipStream_t st = (hipStream_t)stream;
   char* ws = (char*)workspace;
   float2* rrow = (float2*)(ws + L.rrow);
@@ -488,38 +611,12 @@ rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t
   nws.cand = cand;
   float* t32 = (float*)(ws + L.t32);
   double* t64 = (double*)(ws + L.t64);
+  float* ostat = (float*)(ws + L.ostat);
 
   FilterConsts fc;
-  std::memset(&fc, 0, sizeof(fc));
-  fc.H = H;
-  fc.W = W;
-  fc.n_scales = pc->n_scales;
-  fc.n_orient = pc->n_orient;
-  const double ls = std::log((double)pc->sigma_onf);
-  fc.inv_2ln2_sigma = (float)(1.0 / (2.0 * ls * ls));
-  for (int s = 0; s < pc->n_scales; ++s)
-    fc.log_f0[s] = (float)std::log(1.0 / ((double)pc->min_wavelength * std::pow((double)pc->mult, (double)s)));
-  fc.log_lp_cutoff = (float)std::log((double)pc->lp_cutoff);
-  fc.two_n = (float)(2 * pc->lp_order);
   PCConsts pcc;
-  std::memset(&pcc, 0, sizeof(pcc));
-  for (int o = 0; o < pc->n_orient; ++o) {
-    const double th = o * M_PI / pc->n_orient;
-    fc.theta_o[o] = (float)th;
-    pcc.cos_o[o] = (float)std::cos(th);
-    pcc.sin_o[o] = (float)std::sin(th);
-  }
-  const double sig_th = (M_PI / pc->n_orient) / (double)pc->dtheta_on_sigma;
-  fc.inv_2sig_theta2 = (float)(1.0 / (2.0 * sig_th * sig_th));
-  fc.inv_hw = (float)(1.0 / ((double)H * (double)W));
-  pcc.eps = pc->eps;
-  pcc.g = pc->g;
-  pcc.cutoff = pc->cutoff;
   NoiseConsts nc;
-  nc.mult = pc->mult;
-  nc.k = pc->k;
-  nc.n_scales = pc->n_scales;
-
+  filter_consts(H, W, pc, &fc, &pcc, &nc);
   (void)hipGetLastError();
   {
     ProfScope ps(0, st);
@@ -536,16 +633,72 @@ rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t
   const int hw = H * W;
   {
     ProfScope ps(3, st);
-    hipLaunchKernelGGL(k_noise_bins<1>, dim3(pc->n_orient), dim3(256), 0, st, hw, nws, nc, t32, t64);
+    hipLaunchKernelGGL(k_noise_bins<1>, dim3(pc->n_orient), dim3(256), 0, st, hw, nws, nc, t32, t64, ostat);
     hipLaunchKernelGGL(k_noise_sel1, dim3(kNoiseRegions, pc->n_orient), dim3(256), 0, st, a0, hw, nws);
-    hipLaunchKernelGGL(k_noise_bins<2>, dim3(pc->n_orient), dim3(256), 0, st, hw, nws, nc, t32, t64);
+    hipLaunchKernelGGL(k_noise_bins<2>, dim3(pc->n_orient), dim3(256), 0, st, hw, nws, nc, t32, t64, ostat);
     hipLaunchKernelGGL(k_noise_sel2, dim3(kNoiseRegions, pc->n_orient), dim3(256), 0, st, hw, nws);
-    hipLaunchKernelGGL(k_noise_bins<3>, dim3(pc->n_orient), dim3(256), 0, st, hw, nws, nc, t32, t64);
+    hipLaunchKernelGGL(k_noise_bins<3>, dim3(pc->n_orient), dim3(256), 0, st, hw, nws, nc, t32, t64, ostat);
   }
   {
     dispatch_pass_b(pc->n_scales, pc->n_orient, W, H, yp, pcc, t32, (float2*)(ws + L.spc), mim, max_moment,
                     min_moment, amp_sums, st);
   }
+  return launch_status();
+}
+
+rift2_status rift2_debug_response(const void* img, int32_t dtype, int32_t H, int32_t W, int64_t pitch,
+                                  const rift2_pc_params* pc, int32_t scale, int32_t orient, float* eo,
+                                  void* workspace, size_t workspace_bytes, void* stream) {
+  if (!img || !pc || !eo || !workspace) return RIFT2_ERR_INVALID_ARG;
+  if (dtype != RIFT2_U8 && dtype != RIFT2_U16 && dtype != RIFT2_F32) return RIFT2_ERR_INVALID_ARG;
+  if (pitch < W || ((uintptr_t)eo & 7u)) return RIFT2_ERR_INVALID_ARG;
+  if (!pc_ok(pc)) return RIFT2_ERR_INVALID_ARG;
+  if (scale < 0 || scale >= pc->n_scales || orient < 0 || orient >= pc->n_orient) return RIFT2_ERR_INVALID_ARG;
+  if (!size_ok(H) || !size_ok(W)) return RIFT2_ERR_UNSUPPORTED;
+  const FilterLayout L = filter_layout(H, W, pc);
+  if (workspace_bytes < L.total) return RIFT2_ERR_WORKSPACE;
+  if (!current_device_ready()) return RIFT2_ERR_NOT_INITIALIZED;
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  float2* rrow = (float2*)(ws + L.rrow);
+  float2* yp = (float2*)(ws + L.yplanes);
+  FilterConsts fc;
+  PCConsts pcc;
+  NoiseConsts nc;
+  filter_consts(H, W, pc, &fc, &pcc, &nc);
+  (void)hipGetLastError();
+  dispatch_fwd_rows(W, dtype, img, pitch, H, rrow, (uint32_t*)(ws + L.zero), 0, st);
+  dispatch_pass_a(H, W, rrow, fc, yp, st);
+  const float2* plane = yp + (size_t)(orient * pc->n_scales + scale) * H * W;
+  dispatch_rows_inverse(W, H, plane, (float2*)eo, st);
+  return launch_status();
+}
+
+rift2_status rift2_debug_noise(const void* workspace, size_t workspace_bytes, int32_t H, int32_t W,
+                               const rift2_pc_params* pc, float* a0, float* order_stats, double* t_o, void* stream) {
+  if (!workspace || !pc || !pc_ok(pc)) return RIFT2_ERR_INVALID_ARG;
+  if (!size_ok(H) || !size_ok(W)) return RIFT2_ERR_UNSUPPORTED;
+  const FilterLayout L = filter_layout(H, W, pc);
+  if (workspace_bytes < L.total) return RIFT2_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  const char* ws = (const char*)workspace;
+  const size_t no = (size_t)pc->n_orient;
+  bool ok = true;
+  if (a0) ok = ok && hipMemcpyAsync(a0, ws + L.a0, no * H * W * sizeof(float), hipMemcpyDeviceToDevice, st) == hipSuccess;
+  if (order_stats)
+    ok = ok && hipMemcpyAsync(order_stats, ws + L.ostat, 2 * no * sizeof(float), hipMemcpyDeviceToDevice, st) == hipSuccess;
+  if (t_o) ok = ok && hipMemcpyAsync(t_o, ws + L.t64, no * sizeof(double), hipMemcpyDeviceToDevice, st) == hipSuccess;
+  return ok ? RIFT2_OK : RIFT2_ERR_DEVICE;
+}
+
+rift2_status rift2_desc_normalize(const uint16_t* desc, const float* inv_norm, const int32_t* n_rows_dev, int32_t cap,
+                                  int32_t D, float* out, void* stream) {
+  if (!desc || !inv_norm || !n_rows_dev || !out || cap <= 0 || D <= 0) return RIFT2_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  (void)hipGetLastError();
+  const int64_t total = (int64_t)cap * D;
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_desc_normalize, dim3(blocks), dim3(256), 0, st, desc, inv_norm, n_rows_dev, cap, D, out);
   return launch_status();
 }
 
@@ -676,18 +829,22 @@ rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32
   if (!(mp->ratio_sq > 0.0f) ||
       (mp->precision != RIFT2_PREC_FP32 && mp->precision != RIFT2_PREC_BF16 && mp->precision != RIFT2_PREC_FP8))
     return RIFT2_ERR_INVALID_ARG;
+  if (mp->mutual != 0 && mp->mutual != 1) return RIFT2_ERR_INVALID_ARG;
   if (D != 216 && D != 288) return RIFT2_ERR_UNSUPPORTED;
   if (mp->ring < 0 || mp->ring == 1 || mp->ring > kMaxOrient) return RIFT2_ERR_INVALID_ARG;
-  if (mp->ring && mp->precision == RIFT2_PREC_FP8) return RIFT2_ERR_UNSUPPORTED;
+  if (mp->ring && (mp->precision == RIFT2_PREC_FP8 || mp->mutual)) return RIFT2_ERR_UNSUPPORTED;
   // the table preparation reads descriptor rows as 16-byte vectors
   if (((uintptr_t)desc_a & 15u) || ((uintptr_t)desc_b & 15u)) return RIFT2_ERR_INVALID_ARG;
-  const MatchLayout L = match_layout(cap_a, cap_b, D, mp->precision);
+  const bool mutual = mp->mutual != 0;
+  const MatchLayout L = match_layout(cap_a, cap_b, D, mp->precision, mutual);
   if (workspace_bytes < L.total) return RIFT2_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   char* ws = (char*)workspace;
   void* ta = ws + L.ta;
   void* tb = ws + L.tb;
   int2* part = (int2*)(ws + L.part);
+  int2* part_r = (int2*)(ws + L.part_r);
+  int32_t* a1 = mutual ? (int32_t*)(ws + L.a1) : nullptr;
   uint64_t* best = (uint64_t*)(ws + L.best);
   int32_t* rowj = (int32_t*)(ws + L.rowj);
   float* rowd = (float*)(ws + L.rowd);
@@ -705,17 +862,18 @@ rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32
     }
     {
       ProfScope ps8(8, st);
-      const dim3 grid((L.rows_a + 127) / 128, L.slices);
-      if (L.dp == 256)
-        hipLaunchKernelGGL(k_match_gemm_fp8<256>, grid, dim3(256), 0, st, (const uint8_t*)ta, wa, nA_dev,
-                           (const uint8_t*)tb, wb, nB_dev, cap_a, cap_b, L.slice_rows, part);
-      else
-        hipLaunchKernelGGL(k_match_gemm_fp8<320>, grid, dim3(256), 0, st, (const uint8_t*)ta, wa, nA_dev,
-                           (const uint8_t*)tb, wb, nB_dev, cap_a, cap_b, L.slice_rows, part);
+      launch_gemm_fp8(L.dp, (const uint8_t*)ta, wa, nA_dev, cap_a, (const uint8_t*)tb, wb, nB_dev, cap_b, L.rows_a,
+                      L.slice_rows, L.slices, part, st);
+      if (mutual)
+        launch_gemm_fp8(L.dp, (const uint8_t*)tb, wb, nB_dev, cap_b, (const uint8_t*)ta, wa, nA_dev, cap_a, L.rows_b,
+                        L.slice_rows_r, L.slices_r, part_r, st);
     }
     ProfScope ps9(9, st);
+    if (mutual)
+      hipLaunchKernelGGL(k_match_rnn8, dim3((cap_b + 3) / 4), dim3(256), 0, st, part_r, 2 * L.slices_r, nB_dev, cap_b,
+                         desc_a, inv_a, desc_b, inv_b, D, a1);
     hipLaunchKernelGGL(k_match_merge8, dim3((cap_a + 3) / 4), dim3(256), 0, st, part, 2 * L.slices, nA_dev, desc_a, inv_a,
-                       kp_a, desc_b, inv_b, kp_b, D, mp->ratio_sq, cap_a, best, rowj, rowd);
+                       kp_a, desc_b, inv_b, kp_b, D, mp->ratio_sq, cap_a, (const int32_t*)a1, best, rowj, rowd);
     hipLaunchKernelGGL(k_match_emit, dim3((cap_a + 255) / 256), dim3(256), 0, st, best, cap_a, rowj, rowd, kp_b,
                        (MatchOut*)out, n_out_dev);
     return launch_status();
@@ -730,33 +888,22 @@ rift2_status rift2_match(const uint16_t* desc_a, const float* inv_a, const int32
       hipLaunchKernelGGL(k_match_prep<false>, dim3(512, 2), dim3(256), 0, st, ja, jb, D, L.rs);
   }
   ps7.finish();
-  const dim3 grid((L.rows_a + 127) / 128, L.slices);
-  // the BF16 GEMM deals its cells to the XCDs itself (gemm_cell): 1-D grid
-  const dim3 grid_xcd(8 * ((grid.x + 1) / 2) * ((L.slices + 3) / 4));
   ProfScope ps8(8, st);
-  if (bf) {
-    if (L.dp == 224)
-      hipLaunchKernelGGL(k_match_gemm_bf16<224>, grid_xcd, dim3(256), 0, st, (const uint16_t*)ta, inv_a, nA_dev,
-                         (const uint16_t*)tb, inv_b, nB_dev, cap_a, cap_b, L.slice_rows, L.slices, part);
-    else
-      hipLaunchKernelGGL(k_match_gemm_bf16<288>, grid_xcd, dim3(256), 0, st, (const uint16_t*)ta, inv_a, nA_dev,
-                         (const uint16_t*)tb, inv_b, nB_dev, cap_a, cap_b, L.slice_rows, L.slices, part);
-  } else {
-    if (L.dp == 216)
-      hipLaunchKernelGGL(k_match_gemm_f32<216>, grid, dim3(256), 0, st, (const float*)ta, inv_a, nA_dev,
-                         (const float*)tb, inv_b, nB_dev, cap_a, cap_b, L.slice_rows, part);
-    else
-      hipLaunchKernelGGL(k_match_gemm_f32<288>, grid, dim3(256), 0, st, (const float*)ta, inv_a, nA_dev,
-                         (const float*)tb, inv_b, nB_dev, cap_a, cap_b, L.slice_rows, part);
-  }
+  launch_gemm_exact<false>(bf, L.dp, ta, inv_a, nA_dev, cap_a, tb, inv_b, nB_dev, cap_b, L.rows_a, L.slice_rows,
+                           L.slices, part, st);
+  if (mutual)
+    launch_gemm_exact<true>(bf, L.dp, tb, inv_b, nB_dev, cap_b, ta, inv_a, nA_dev, cap_a, L.rows_b, L.slice_rows_r,
+                            L.slices_r, part_r, st);
   ps8.finish();
   ProfScope ps9(9, st);
+  if (mutual)
+    hipLaunchKernelGGL(k_match_rnn, dim3((cap_b + 3) / 4), dim3(256), 0, st, part_r, 2 * L.slices_r, nB_dev, cap_b, a1);
   if (mp->ring)
     hipLaunchKernelGGL(k_match_merge_ring, dim3((cap_a / mp->ring + 3) / 4), dim3(256), 0, st, part, 2 * L.slices,
                        (int)mp->ring, nA_dev, kp_a, kp_b, mp->ratio_sq, cap_a, best, rowj, rowd);
   else
     hipLaunchKernelGGL(k_match_merge, dim3((cap_a + 3) / 4), dim3(256), 0, st, part, 2 * L.slices, nA_dev, kp_a, kp_b,
-                       mp->ratio_sq, cap_a, best, rowj, rowd);
+                       mp->ratio_sq, cap_a, (const int32_t*)a1, best, rowj, rowd);
   // ring rows come R per keypoint, so keypoint indices stay below cap_a / R
   const int kp_range = mp->ring ? cap_a / mp->ring : cap_a;
   hipLaunchKernelGGL(k_match_emit, dim3((kp_range + 255) / 256), dim3(256), 0, st, best, kp_range, rowj, rowd, kp_b,

@@ -471,4 +471,17 @@ __global__ void __launch_bounds__(256) k_describe2(const int32_t* __restrict__ n
   }
 }
 
+// FP32 view of descriptor rows: fl(count * inv_norm) for the first n rows
+// (grid-stride over row-major elements).
+__global__ void __launch_bounds__(256) k_desc_normalize(const uint16_t* __restrict__ desc,
+                                                        const float* __restrict__ inv_norm,
+                                                        const int32_t* __restrict__ n_dev, int cap, int D,
+                                                        float* __restrict__ out) {
+  const int n = min(*n_dev, cap);
+  const int64_t total = (int64_t)n * D;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = __fmul_rn((float)desc[e], inv_norm[e / D]);
+}
+
 }  // namespace rift2
+

@@ -160,6 +160,8 @@ inline int32_t engine_launch(rift2_engine* e, EngineReq& q) {
   char* base = e->arena + q.off;
   rift2_detect_params det = e->det;
   det.max_keypoints = q.K;
+  // the caller's inputs may still be in flight on its own stream
+  if (q.req.ready && hipStreamWaitEvent(s.sa, (hipEvent_t)q.req.ready, 0) != hipSuccess) return RIFT2_ERR_DEVICE;
   if (hipEventRecord(s.admit, s.sa) != hipSuccess) return RIFT2_ERR_DEVICE;
   // image B's stages start after the admission mark too
   if (hipStreamWaitEvent(s.sb, s.admit, 0) != hipSuccess) return RIFT2_ERR_DEVICE;

@@ -243,7 +243,7 @@ __global__ void __launch_bounds__(256) k_noise_pre(float2* __restrict__ y_in, in
 // noise threshold, evaluated in FP64.
 template <int LEVEL>
 __global__ void __launch_bounds__(256) k_noise_bins(int hw, NoiseWs ws, NoiseConsts nc, float* __restrict__ t_out,
-                                                    double* __restrict__ t_out64) {
+                                                    double* __restrict__ t_out64, float* __restrict__ ostat) {
   __shared__ uint32_t scratch[4];
   __shared__ int s_bin[2];
   __shared__ uint32_t s_below[2];
@@ -278,6 +278,9 @@ __global__ void __launch_bounds__(256) k_noise_bins(int hw, NoiseWs ws, NoiseCon
       vals[q] = __uint_as_float((((st[q] << 10) | st[4 + q]) << 9) | (uint32_t)s_bin[q]);
     }
     if (threadIdx.x == 0) {
+      // the two middle order statistics stay in the workspace for diagnostics
+      ostat[2 * o] = vals[0];
+      ostat[2 * o + 1] = vals[1];
       const double med = 0.5 * ((double)vals[0] + (double)vals[1]);
       const double tau = med / sqrt(log(4.0));
       const double total = tau * (1.0 - pow(1.0 / nc.mult, (double)nc.n_scales)) / (1.0 - 1.0 / nc.mult);
@@ -386,6 +389,24 @@ __global__ void __launch_bounds__(256) k_noise_sel2(int hw, NoiseWs ws) {
     const uint32_t c = (&h3[0][0])[i];
     if (c) atomicAdd(&gh3[i], c);
   }
+}
+
+// Row IDFT of one column-inverted plane into `out` (the complex response
+// EO_{s,o} itself, for diagnostics).  Block = LINES rows.
+template <int W, int P>
+__global__ void __launch_bounds__(256) k_rows_inverse(const float2* __restrict__ y_in, float2* __restrict__ out) {
+  using PL = FftPlan<W, P>;
+  constexpr int T = PL::T;
+  constexpr int LINES = 256 / T;
+  __shared__ float2 lines[LINES][lds_line<W, T>()];
+  const int team = threadIdx.x / T, t = threadIdx.x % T;
+  const size_t row = (size_t)(blockIdx.x * LINES + team) * W;
+  float2 v[P];
+#pragma unroll
+  for (int m = 0; m < P; ++m) v[m] = y_in[row + t + T * m];
+  fft_line<+1, W, P, T == 64>(v, t, lines[team]);
+#pragma unroll
+  for (int m = 0; m < P; ++m) out[row + t + T * m] = v[m];
 }
 
 // ---------------------------------------------------------------- pass B

@@ -116,7 +116,11 @@ __device__ __forceinline__ void top3_insert(Top3& t, float d, int j) {
 // `ibt` holds the tile's 32 candidate inverse norms (LDS), so the four rows
 // 8k + 4g .. 8k + 4g + 3 of register group k are one 16-byte read.  All 16
 // distances are formed first; the insertion runs only where one of them can
-// enter the lane's top 3.
+// enter the lane's top 3.  CF (candidate first) multiplies by the candidate's
+// inverse norm before the query's: the reverse pass of the mutual check (B rows
+// as queries) then forms exactly the d2 of the forward pass, fl(fl(dot ia) ib)
+// with ia the A row's and ib the B row's inverse norm.
+template <bool CF = false>
 __device__ __forceinline__ void tile_epilogue(const floatx16_t& acc, int lane, int j0, int j_end, float ia,
                                               const float* ibt, Top3& top) {
   const int g = lane >> 5;
@@ -128,7 +132,7 @@ __device__ __forceinline__ void tile_epilogue(const floatx16_t& acc, int lane, i
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int r = 4 * k + e;
-      const float t2 = __fmul_rn(__fmul_rn(acc[r], ia), ibv[e]);
+      const float t2 = CF ? __fmul_rn(__fmul_rn(acc[r], ibv[e]), ia) : __fmul_rn(__fmul_rn(acc[r], ia), ibv[e]);
       // 2 t2 is exact, so one fused rounding equals fl(2 - fl(2 t2))
       d2[r] = __fmaf_rn(-2.0f, t2, 2.0f);
     }
@@ -250,7 +254,7 @@ __device__ __forceinline__ GemmCell gemm_cell(int na, int nb, int slice_rows, in
   return c;
 }
 
-template <int DP>
+template <int DP, bool CF>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_match_gemm_bf16(const uint16_t* __restrict__ ta, const float* __restrict__ inv_a,
                                                          const int32_t* __restrict__ na_dev,
                                                          const uint16_t* __restrict__ tb, const float* __restrict__ inv_b,
@@ -303,7 +307,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
       tile_copy<uint16_t, RS>(tb, j0 + 32, tn);
       ib_next = tile_inv_load(inv_b, j0 + 32, nb);
     }
-    if (active) tile_epilogue(bf16_tile_products<KS, RS>(tc, lane, qa), lane, j0, j_end, ia, ic, top);
+    if (active) tile_epilogue<CF>(bf16_tile_products<KS, RS>(tc, lane, qa), lane, j0, j_end, ia, ic, top);
     if (more) {
       if (threadIdx.x < 32) in[threadIdx.x] = ib_next;
       tile_copy_wait();
@@ -333,7 +337,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 // (<= 256), held exactly as FP16 pairs and widened to FP32 for each MFMA,
 // which halves their registers; with one tile buffer (28 KB of LDS) three
 // blocks share a CU, and they cover each other's tile copies.
-template <int DP>
+template <int DP, bool CF>
 __global__ void __launch_bounds__(256) k_match_gemm_f32(const float* __restrict__ ta, const float* __restrict__ inv_a,
                                                         const int32_t* __restrict__ na_dev,
                                                         const float* __restrict__ tb, const float* __restrict__ inv_b,
@@ -394,7 +398,7 @@ __global__ void __launch_bounds__(256) k_match_gemm_f32(const float* __restrict_
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.z, (float)qh[c][1].x, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cb.w, (float)qh[c][1].y, acc, 0, 0, 0);
       }
-      tile_epilogue(acc, lane, j0, j_end, ia, ibt[0], top);
+      tile_epilogue<CF>(acc, lane, j0, j_end, ia, ibt[0], top);
     }
   }
   if (active && qi < na) {
@@ -420,11 +424,13 @@ __device__ __forceinline__ void wave_argmin(float& d, int& j) {
 }
 
 // One wave per A row: merge the 2 x S top-3 lists, ratio test, keypoint best.
+// With `a1` (the mutual check) an accepted row also needs the nearest A row of
+// its j1 to belong to its own keypoint.
 __global__ void __launch_bounds__(256) k_match_merge(const int2* __restrict__ part, int lists,
                                                      const int32_t* __restrict__ na_dev, const int32_t* __restrict__ kp_a,
                                                      const int32_t* __restrict__ kp_b, float ratio_sq, int cap_a,
-                                                     uint64_t* __restrict__ best, int32_t* __restrict__ row_j1,
-                                                     float* __restrict__ row_d1) {
+                                                     const int32_t* __restrict__ a1, uint64_t* __restrict__ best,
+                                                     int32_t* __restrict__ row_j1, float* __restrict__ row_d1) {
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int na = min(*na_dev, cap_a);
@@ -462,6 +468,10 @@ __global__ void __launch_bounds__(256) k_match_merge(const int2* __restrict__ pa
   if (!(d1 < __fmul_rn(ratio_sq, d2))) return;
   const int ka = kp_a[i];
   if (ka < 0 || ka >= cap_a) return;
+  if (a1) {
+    const int back = a1[j1];
+    if (back < 0 || back >= na || kp_a[back] != ka) return;
+  }
   // order-preserving key: rounding can make d1 slightly negative for identical rows
   const uint32_t b = __float_as_uint(d1);
   const uint32_t ok = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
@@ -534,6 +544,32 @@ __global__ void __launch_bounds__(256) k_match_merge_ring(const int2* __restrict
   const uint32_t ok = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
   const uint64_t key = ((uint64_t)ok << 32) | (uint32_t)g;
   atomicMin((unsigned long long*)&best[ka], (unsigned long long)key);
+}
+
+// Reverse pass of the mutual check: one wave per B row (the queries of the
+// swapped GEMM) merges its lists into the nearest A row, ties to the lowest
+// row; -1 when there is none.
+__global__ void __launch_bounds__(256) k_match_rnn(const int2* __restrict__ part, int lists,
+                                                   const int32_t* __restrict__ nb_dev, int cap_b,
+                                                   int32_t* __restrict__ a1) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int nb = min(*nb_dev, cap_b);
+  if (j >= nb) return;
+  const int2* src = part + (size_t)j * lists * kTopK;
+  const int total = lists * kTopK;
+  float d1 = INFINITY;
+  int i1 = -1;
+  for (int q = lane; q < total; q += 64) {
+    const int2 e = src[q];
+    const float d = __int_as_float(e.x);
+    if (e.y >= 0 && (i1 < 0 || better(d, e.y, d1, i1))) {
+      d1 = d;
+      i1 = e.y;
+    }
+  }
+  wave_argmin(d1, i1);
+  if (lane == 0) a1[j] = i1;
 }
 
 struct MatchOut {

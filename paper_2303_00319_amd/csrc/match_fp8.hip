@@ -212,8 +212,8 @@ __global__ void __launch_bounds__(256) k_match_merge8(const int2* __restrict__ p
                                                       const int32_t* __restrict__ kp_a,
                                                       const uint16_t* __restrict__ desc_b, const float* __restrict__ inv_b,
                                                       const int32_t* __restrict__ kp_b, int D, float ratio_sq, int cap_a,
-                                                      uint64_t* __restrict__ best, int32_t* __restrict__ row_j1,
-                                                      float* __restrict__ row_d1) {
+                                                      const int32_t* __restrict__ a1, uint64_t* __restrict__ best,
+                                                      int32_t* __restrict__ row_j1, float* __restrict__ row_d1) {
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int na = min(*na_dev, cap_a);
@@ -286,10 +286,75 @@ __global__ void __launch_bounds__(256) k_match_merge8(const int2* __restrict__ p
   if (!(d1 < __fmul_rn(ratio_sq, dd2))) return;
   const int ka = kp_a[i];
   if (ka < 0 || ka >= cap_a) return;
+  if (a1) {
+    const int back = a1[j1];
+    if (back < 0 || back >= na || kp_a[back] != ka) return;
+  }
   const uint32_t b = __float_as_uint(d1);
   const uint32_t ok = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
   const uint64_t key = ((uint64_t)ok << 32) | (uint32_t)i;
   atomicMin((unsigned long long*)&best[ka], (unsigned long long)key);
+}
+
+// Reverse pass of the mutual check in the FP8 form: one wave per B row (the
+// queries of the swapped GEMM) takes the 8 best approximate candidates (A
+// rows), re-ranks them with exact dots and d2 = fl(2 - 2 fl(fl(dot ia) ib)),
+// the forward pass's rounding, and keeps the nearest (ties to the lowest row).
+__global__ void __launch_bounds__(256) k_match_rnn8(const int2* __restrict__ part, int lists,
+                                                    const int32_t* __restrict__ nb_dev, int cap_b,
+                                                    const uint16_t* __restrict__ desc_a, const float* __restrict__ inv_a,
+                                                    const uint16_t* __restrict__ desc_b, const float* __restrict__ inv_b,
+                                                    int D, int32_t* __restrict__ a1) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int nb = min(*nb_dev, cap_b);
+  if (j >= nb) return;
+  const int2* src = part + (size_t)j * lists * kTopK8;
+  const int total = lists * kTopK8;
+  int cand[kTopK8];
+  float last_d = -INFINITY;
+  int last_i = -1;
+#pragma unroll
+  for (int q = 0; q < kTopK8; ++q) {
+    float bd = INFINITY;
+    int bi = -1;
+    for (int e = lane; e < total; e += 64) {
+      const int2 v = src[e];
+      const float d = __int_as_float(v.x);
+      if (v.y < 0) continue;
+      const bool after = d > last_d || (d == last_d && v.y > last_i);
+      if (after && (bi < 0 || better(d, v.y, bd, bi))) {
+        bd = d;
+        bi = v.y;
+      }
+    }
+    wave_argmin(bd, bi);
+    cand[q] = bi;
+    if (bi >= 0) {
+      last_d = bd;
+      last_i = bi;
+    }
+  }
+  const float ib = inv_b[j];
+  const uint16_t* rb = desc_b + (size_t)j * D;
+  float d1 = INFINITY;
+  int i1 = -1;
+#pragma unroll
+  for (int q = 0; q < kTopK8; ++q) {
+    const int i = cand[q];
+    if (i < 0) continue;
+    const uint16_t* ra = desc_a + (size_t)i * D;
+    uint32_t dot = 0;
+    for (int k = lane; k < D; k += 64) dot += (uint32_t)ra[k] * (uint32_t)rb[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) dot += (uint32_t)__shfl_xor((int)dot, off);
+    const float d = __fsub_rn(2.0f, __fmul_rn(2.0f, __fmul_rn(__fmul_rn((float)dot, inv_a[i]), ib)));
+    if (i1 < 0 || better(d, i, d1, i1)) {
+      d1 = d;
+      i1 = i;
+    }
+  }
+  if (lane == 0) a1[j] = i1;
 }
 
 }  // namespace rift2

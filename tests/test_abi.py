@@ -198,3 +198,64 @@ def test_variant_forms_are_validated_on_the_host():
     handle = ctypes.c_void_p(0)
     assert lib.rift2_engine_create(0, ctypes.c_void_p(0x10000), 1 << 30, 4, ctypes.byref(pc), ctypes.byref(det),
                                    ctypes.byref(ring_dp), ctypes.byref(mp), ctypes.byref(handle)) == _l.ERR_UNSUPPORTED
+
+
+def test_fft_calls_refuse_a_device_without_rift2_init():
+    """Without rift2_init on the current device (here: no device at all) the FFT calls return
+    RIFT2_ERR_NOT_INITIALIZED instead of running against empty twiddle tables."""
+    _l, lib = _lib()
+    try:
+        import torch
+
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present; this process may already have initialised it")
+    except ImportError:
+        pass
+    pc = _l.PCParams()
+    lib.rift2_default_params(ctypes.byref(pc), None, None, None)
+    fake = ctypes.c_void_p(0x1000)
+    null = ctypes.c_void_p(0)
+    assert lib.rift2_filter_mim(fake, 0, 1024, 1024, 1024, ctypes.byref(pc), fake, fake, null, null, fake,
+                                1 << 40, null) == _l.ERR_NOT_INITIALIZED
+    assert lib.rift2_debug_response(fake, 0, 512, 512, 512, ctypes.byref(pc), 1, 2, fake, fake, 1 << 40,
+                                    null) == _l.ERR_NOT_INITIALIZED
+    assert b"rift2_init" in lib.rift2_status_string(_l.ERR_NOT_INITIALIZED)
+
+
+def test_debug_and_normalize_calls_validate_on_the_host():
+    _l, lib = _lib()
+    pc = _l.PCParams()
+    lib.rift2_default_params(ctypes.byref(pc), None, None, None)
+    fake = ctypes.c_void_p(0x1000)
+    null = ctypes.c_void_p(0)
+    # filter index out of range, misaligned output, unsupported size, small workspace
+    for s, o in ((4, 0), (0, 6), (-1, 0)):
+        assert lib.rift2_debug_response(fake, 0, 256, 256, 256, ctypes.byref(pc), s, o, fake, fake, 1 << 40,
+                                        null) == _l.ERR_INVALID_ARG
+    assert lib.rift2_debug_response(fake, 0, 256, 256, 256, ctypes.byref(pc), 0, 0, ctypes.c_void_p(0x1004), fake,
+                                    1 << 40, null) == _l.ERR_INVALID_ARG
+    assert lib.rift2_debug_response(fake, 0, 250, 256, 256, ctypes.byref(pc), 0, 0, fake, fake, 1 << 40,
+                                    null) == _l.ERR_UNSUPPORTED
+    assert lib.rift2_debug_response(fake, 0, 256, 256, 256, ctypes.byref(pc), 0, 0, fake, fake, 64,
+                                    null) == _l.ERR_WORKSPACE
+    assert lib.rift2_debug_noise(null, 1 << 40, 256, 256, ctypes.byref(pc), fake, fake, fake, null) == _l.ERR_INVALID_ARG
+    assert lib.rift2_debug_noise(fake, 64, 256, 256, ctypes.byref(pc), fake, fake, fake, null) == _l.ERR_WORKSPACE
+    assert lib.rift2_desc_normalize(null, fake, fake, 10, 216, fake, null) == _l.ERR_INVALID_ARG
+    assert lib.rift2_desc_normalize(fake, fake, fake, 0, 216, fake, null) == _l.ERR_INVALID_ARG
+
+
+def test_mutual_matching_is_validated_and_sized():
+    _l, lib = _lib()
+    fake = ctypes.c_void_p(0x1000)
+    null = ctypes.c_void_p(0)
+    for prec in (_l.PREC_FP32, _l.PREC_BF16, _l.PREC_FP8):
+        plain = lib.rift2_match_workspace_size(10000, 9000, 216, ctypes.byref(_l.MatchParams(0.81, prec, 0, 0)))
+        mutual = lib.rift2_match_workspace_size(10000, 9000, 216, ctypes.byref(_l.MatchParams(0.81, prec, 0, 1)))
+        # the reverse pass adds its candidate lists and one nearest A row per B row
+        assert mutual >= plain + 9000 * 4 + 9000 * 6 * 8
+    bad = _l.MatchParams(0.81, 0, 0, 2)
+    assert lib.rift2_match(fake, fake, fake, fake, 10, fake, fake, fake, fake, 10, 216, ctypes.byref(bad), fake, fake,
+                           fake, 1 << 30, null) == _l.ERR_INVALID_ARG
+    ring = _l.MatchParams(0.81, 0, 6, 1)
+    assert lib.rift2_match(fake, fake, fake, fake, 60, fake, fake, fake, fake, 10, 216, ctypes.byref(ring), fake, fake,
+                           fake, 1 << 30, null) == _l.ERR_UNSUPPORTED

@@ -1,9 +1,14 @@
 """GPU parity of every stage of the HIP path against the CPU oracle.
 
 Tolerances (written here, derived in the design notes):
-* amplitude sums A_o: |gpu - oracle| <= 1e-4 * max(A_o(x), RMS(A_o)) (FP32 FFT error)
+* amplitude sums A_o and every filter's amplitude |EO_{s,o}|:
+  |gpu - oracle| <= 1e-4 * max(A(x), RMS(A)) (FP32 FFT error)
 * MIM: >= 99.9 % equal; every disagreement is a near-tie of the oracle's top
-  two amplitude sums (gap < 1e-4 relative)
+  two amplitude sums: gap < 1e-5 relative to max(A_top(x), RMS(A)) (the gap
+  relative to A_top(x) alone is printed as well)
+* noise threshold: the two middle order statistics of the GPU's own A0 are
+  bit-exact against a full sort; T_o is the oracle's threshold of that median
+  within 1e-12, and the oracle's end-to-end T_o within 1e-4
 * max moment M: |gpu - oracle| <= 2e-3 * max(M)
 * FAST keypoints, descriptors, matches: bit-exact when fed the oracle's
   FP32-cast inputs (these stages are integer / correctly-rounded FP32)
@@ -43,11 +48,55 @@ def _pcparams(r2, n_scales=4, n_orient=6):
     return pc
 
 
-def _check_filter(r2, dev, img, ref, pc, tag):
+def _check_noise(r2, ws, img, ref, pc, tag):
+    """Order statistics bit-exact against a full sort of the GPU's own A0; T_o against the oracle."""
+    h, w = img.shape
+    a0, ostat, t_o = r2.debug_noise(ws, h, w, pc)
+    torch.cuda.synchronize()
+    a0 = a0.cpu().numpy()
+    ostat = ostat.cpu().numpy()
+    t_o = t_o.cpu().numpy()
+    p = oracle.PCParams(n_scales=pc.n_scales, n_orient=pc.n_orient)
+    hw = h * w
+    worst = 0.0
+    for o in range(pc.n_orient):
+        srt = np.sort(a0[o].ravel())
+        assert srt[hw // 2 - 1].view(np.uint32) == ostat[o, 0].view(np.uint32), f"{tag}: order statistic o={o}"
+        assert srt[hw // 2].view(np.uint32) == ostat[o, 1].view(np.uint32), f"{tag}: order statistic o={o}"
+        own = filterbank.noise_threshold(a0[o].astype(np.float64), p)
+        assert abs(t_o[o] - own) <= 1e-12 * own, f"{tag}: T_o arithmetic o={o}"
+        worst = max(worst, abs(t_o[o] - ref["T"][o]) / ref["T"][o])
+    assert worst <= 1e-4, f"{tag}: T_o vs oracle {worst:.2e}"
+    return worst
+
+
+def _check_responses(r2, dev, img, pc, tag):
+    """Every filter's amplitude |EO_{s,o}| against the FP64 oracle's response."""
+    t = torch.from_numpy(img).to(dev)
+    p = oracle.PCParams(n_scales=pc.n_scales, n_orient=pc.n_orient)
+    spec = filterbank.spectrum(img)
+    ws = torch.empty(r2.filter_workspace_bytes(img.shape[0], img.shape[1], pc), dtype=torch.uint8, device=dev)
+    worst = 0.0
+    for o in range(pc.n_orient):
+        ref = filterbank.responses(spec, o, p)
+        for s in range(pc.n_scales):
+            got = np.abs(r2.debug_response(t, s, o, pc, workspace=ws).cpu().numpy().astype(np.complex128))
+            want = np.abs(ref[s])
+            scale = np.maximum(want, np.sqrt(np.mean(want * want)))
+            err = float(np.max(np.abs(got - want) / scale))
+            worst = max(worst, err)
+            assert err <= 1e-4, f"{tag}: |EO| s={s} o={o} rel err {err:.2e}"
+    print(f"  every |EO_so| within {worst:.2e}", flush=True)
+    return worst
+
+
+def _check_filter(r2, dev, img, ref, pc, tag, responses=False):
     print(f"[filter parity] {tag} shape={img.shape} dtype={img.dtype}", flush=True)
     t = torch.from_numpy(img).to(dev)
-    fm = r2.filter_mim(t, pc, want_amp=True, want_min=True)
+    ws = torch.empty(r2.filter_workspace_bytes(img.shape[0], img.shape[1], pc), dtype=torch.uint8, device=dev)
+    fm = r2.filter_mim(t, pc, want_amp=True, want_min=True, workspace=ws)
     torch.cuda.synchronize()
+    t_err = _check_noise(r2, ws, img, ref, pc, tag)
     amp = fm["amp"].cpu().numpy().astype(np.float64)
     ra = ref["amp"]
     scale = np.maximum(ra, np.sqrt(np.mean(ra * ra, axis=(1, 2), keepdims=True)))
@@ -58,9 +107,13 @@ def _check_filter(r2, dev, img, ref, pc, tag):
     agree = 1.0 - diff.mean()
     srt = np.sort(ra, axis=0)
     gap = (srt[-1] - srt[-2]) / np.maximum(srt[-1], np.sqrt(np.mean(ra * ra)))
+    gap_top = (srt[-1] - srt[-2]) / np.maximum(srt[-1], 1e-300)
     assert agree >= 0.999, f"{tag}: MIM agreement {agree}"
-    if diff.any():
-        assert gap[diff].max() < 1e-4, f"{tag}: MIM disagreement away from ties (gap {gap[diff].max():.2e})"
+    max_gap = float(gap[diff].max()) if diff.any() else 0.0
+    max_gap_top = float(gap_top[diff].max()) if diff.any() else 0.0
+    print(f"  MIM: {int(diff.sum())} disagreements, largest top-two gap {max_gap:.2e} "
+          f"(relative to A_top alone {max_gap_top:.2e}); T_o err {t_err:.2e}", flush=True)
+    assert max_gap < 1e-5, f"{tag}: MIM disagreement away from ties (gap {max_gap:.2e})"
     mm = fm["M"].cpu().numpy().astype(np.float64)
     merr = np.abs(mm - ref["M"]).max() / max(ref["M"].max(), 1e-30)
     assert merr <= 2e-3, f"{tag}: max moment rel err {merr:.3e}"
@@ -68,6 +121,8 @@ def _check_filter(r2, dev, img, ref, pc, tag):
     nerr = np.abs(mn - ref["m"]).max() / max(ref["M"].max(), 1e-30)
     assert nerr <= 2e-3, f"{tag}: min moment rel err {nerr:.3e}"
     print(f"  amp err {err.max():.2e}  MIM agree {agree:.6f}  M err {merr:.2e}  m err {nerr:.2e}", flush=True)
+    if responses:
+        _check_responses(r2, dev, img, pc, tag)
     return fm
 
 
@@ -75,17 +130,17 @@ def test_filter_mim_256_pair():
     r2, dev = _gpu()
     a, b, _ = make_pair(0, 0)
     pc = _pcparams(r2)
-    _check_filter(r2, dev, a, _ref_fm(("c0", 0, "a"), a), pc, "c0 A")
+    _check_filter(r2, dev, a, _ref_fm(("c0", 0, "a"), a), pc, "c0 A", responses=True)
     _check_filter(r2, dev, b, _ref_fm(("c0", 0, "b"), b), pc, "c0 B")
 
 
 def test_filter_mim_1024():
     r2, dev = _gpu()
     a, _, _ = make_pair(1, 0)
-    _check_filter(r2, dev, a, _ref_fm(("c1", 0, "a"), a), _pcparams(r2), "c1 A")
+    _check_filter(r2, dev, a, _ref_fm(("c1", 0, "a"), a), _pcparams(r2), "c1 A", responses=True)
 
 
-@pytest.mark.parametrize("h,w", [(768, 768), (256, 512), (512, 256), (1536, 256)])
+@pytest.mark.parametrize("h,w", [(768, 768), (256, 512), (512, 256), (1536, 256), (256, 1536), (1536, 1536)])
 def test_filter_mim_mixed_radix_and_rectangular(h, w):
     r2, dev = _gpu()
     a, _, _ = make_pair(1, 3, size=max(h, w))
@@ -102,6 +157,15 @@ def test_filter_mim_u16_and_f32_inputs():
     _check_filter(r2, dev, a16.view(np.int16), ref, _pcparams(r2, 5, 8), "u16 5x8")
     f = a.astype(np.float32) / 255.0
     _check_filter(r2, dev, f, filterbank.filter_mim(f, oracle.PCParams()), _pcparams(r2), "f32")
+
+
+@pytest.mark.parametrize("ns,no", [(4, 8), (5, 6), (5, 8)])
+def test_filter_mim_every_built_bank(ns, no):
+    """Each instantiated (N_s, N_o) of the row pass against the oracle, every filter included."""
+    r2, dev = _gpu()
+    a, _, _ = make_pair(0, 4)
+    ref = filterbank.filter_mim(a, oracle.PCParams(n_scales=ns, n_orient=no))
+    _check_filter(r2, dev, a, ref, _pcparams(r2, ns, no), f"bank {ns}x{no}", responses=True)
 
 
 def test_filter_mim_constant_image():
@@ -192,11 +256,12 @@ def test_describe_bitexact_on_oracle_mim():
     _check_describe(r2, dev, mim6, pts, "two-valued")
 
 
-def _check_match(r2, dev, ca, ka, cb, kb, precision, tag):
-    print(f"[match parity] {tag} nA={len(ca)} nB={len(cb)} prec={precision}", flush=True)
+def _check_match(r2, dev, ca, ka, cb, kb, precision, tag, mutual=False):
+    print(f"[match parity] {tag} nA={len(ca)} nB={len(cb)} prec={precision} mutual={mutual}", flush=True)
     mp = r2.defaults()[3]
     mp.precision = precision
-    ref = match.match(ca, ka, cb, kb, dtype=np.float32)
+    mp.mutual = int(mutual)
+    ref = match.match(ca, ka, cb, kb, oracle.MatchParams(mutual=mutual), dtype=np.float32)
 
     def dev_set(c, k):
         cap = len(c) + 5
@@ -230,6 +295,9 @@ def test_match_exact_on_oracle_descriptors():
     for prec in (r2.PREC_FP32, r2.PREC_BF16):
         n = _check_match(r2, dev, fa["desc"], fa["desc_kp"], fb["desc"], fb["desc_kp"], prec, "c0 shifted")
         assert n > 100
+        nm = _check_match(r2, dev, fa["desc"], fa["desc_kp"], fb["desc"], fb["desc_kp"], prec, "c0 shifted",
+                          mutual=True)
+        assert 50 < nm <= n
     # FP8: approximate candidate choice on the real counts (up to 256), exact re-rank
     jac = _match_agreement(r2, dev, fa["desc"], fa["desc_kp"], fb["desc"], fb["desc_kp"], r2.PREC_FP8, "c0 shifted fp8")
     assert jac >= 0.98
@@ -269,11 +337,35 @@ def test_match_random_sets_with_ties_and_ragged_sizes():
         kb = np.arange(nb) // 2
         for prec in (r2.PREC_FP32, r2.PREC_BF16, r2.PREC_FP8):
             _check_match(r2, dev, ca, ka, cb, kb, prec, f"random {na}x{nb}")
+            _check_match(r2, dev, ca, ka, cb, kb, prec, f"random {na}x{nb}", mutual=True)
     # 288-d (N_o = 8) descriptors
     ca = rng.integers(0, 9, size=(300, 288)).astype(np.uint16)
     cb = np.concatenate([ca[:150], rng.integers(0, 9, size=(200, 288)).astype(np.uint16)])
     for prec in (r2.PREC_FP32, r2.PREC_BF16, r2.PREC_FP8):
         _check_match(r2, dev, ca, np.arange(300), cb, np.arange(350), prec, "288-d")
+        _check_match(r2, dev, ca, np.arange(300), cb, np.arange(350), prec, "288-d", mutual=True)
+    # mutual: two A keypoints whose rows are nearest to the same B row; only the one B picks survives
+    ca = rng.integers(0, 4, size=(40, 216)).astype(np.uint16)
+    cb = rng.integers(0, 4, size=(50, 216)).astype(np.uint16)
+    cb[:20] = ca[:20]
+    ca[20:30] = ca[:10]
+    ca[20:30, :3] += 1
+    for prec in (r2.PREC_FP32, r2.PREC_BF16, r2.PREC_FP8):
+        _check_match(r2, dev, ca, np.arange(40), cb, np.arange(50), prec, "shared nearest", mutual=True)
+
+
+def test_desc_normalize_is_the_correctly_rounded_product():
+    r2, dev = _gpu()
+    rng = np.random.default_rng(12)
+    c = rng.integers(0, 257, size=(333, 216)).astype(np.uint16)
+    inv = match.inv_norms(c, np.float32)
+    ct = torch.from_numpy(c.astype(np.int16)).to(dev)
+    it = torch.from_numpy(inv).to(dev)
+    n = torch.tensor([300], dtype=torch.int32, device=dev)
+    out = r2.desc_normalize(ct, it, n).cpu().numpy()
+    want = (c[:300].astype(np.float32) * inv[:300, None]).astype(np.float32)
+    assert np.array_equal(out[:300], want)
+    assert not out[300:].any()
 
 
 def test_end_to_end_pair_agreement():

@@ -327,6 +327,44 @@ def test_match_equals_pure_python_bruteforce():
     assert len(ref[0]) >= 5
 
 
+def test_mutual_match_equals_bruteforce_and_is_a_subset():
+    """Mutual mode against the pure-Python brute force (reverse nearest neighbour over all A rows),
+    at several chunk sizes of the vectorised oracle; its matches are a subset of the plain mode's."""
+    rng = np.random.default_rng(26)
+    for trial in range(4):
+        ca, ka = _random_descriptors(rng, 30, d=24)
+        cb, kb = _random_descriptors(rng, 28, d=24)
+        cb[:12] = ca[:12] + rng.integers(0, 2, size=(12, 24))
+        # a B row that is the nearest of two A keypoints' rows: only one of them can be mutual
+        cb[12] = ca[13]
+        ca[14] = ca[13] + rng.integers(0, 2, size=24)
+        pm = MatchParams(mutual=True)
+        ref = mt.match_bruteforce(ca, ka, cb, kb, pm)
+        for chunk in (7, 2048):
+            got = mt.match(ca, ka, cb, kb, pm, chunk=chunk)
+            assert list(got[0]) == ref[0] and list(got[1]) == ref[1]
+            assert np.allclose(got[2], ref[2], rtol=1e-12, atol=1e-15)
+        plain = mt.match(ca, ka, cb, kb, MatchParams())
+        pairs = set(zip(plain[0].tolist(), plain[1].tolist()))
+        assert set(zip(ref[0], ref[1])) <= pairs
+        assert len(ref[0]) >= 3
+
+
+def test_mutual_mode_rejects_a_one_sided_nearest_neighbour():
+    """Hand-built: B's only row is nearest to both A rows, and the ratio test passes for both
+    (no second B keypoint exists... so a second B keypoint far away); the mutual check keeps only
+    the A keypoint that B's row itself picks."""
+    e = np.eye(8, dtype=np.uint16) * 10
+    ca = np.stack([e[0] + e[1] // 10, e[0] + 2 * (e[2] // 10)])  # A0 closer to B0 than A1 is
+    cb = np.stack([e[0], e[5]])
+    ka = np.array([0, 1])
+    kb = np.array([0, 1])
+    plain = mt.match(ca, ka, cb, kb, MatchParams())
+    mutual = mt.match(ca, ka, cb, kb, MatchParams(mutual=True))
+    assert list(plain[0]) == [0, 1] and list(plain[1]) == [0, 0]
+    assert list(mutual[0]) == [0] and list(mutual[1]) == [0]
+
+
 def test_match_float32_agrees_with_float64_away_from_ties():
     rng = np.random.default_rng(17)
     ca, ka = _random_descriptors(rng, 200)
