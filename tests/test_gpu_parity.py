@@ -56,7 +56,9 @@ def _check_noise(r2, ws, img, ref, pc, tag):
     a0 = a0.cpu().numpy()
     ostat = ostat.cpu().numpy()
     t_o = t_o.cpu().numpy()
-    p = oracle.PCParams(n_scales=pc.n_scales, n_orient=pc.n_orient)
+    # the library's parameter record holds FP32 values (mult = fl32(2.1), k = 2): its FP64 threshold
+    # arithmetic is checked on exactly those values
+    p = oracle.PCParams(n_scales=pc.n_scales, n_orient=pc.n_orient, mult=float(pc.mult), k=float(pc.k))
     hw = h * w
     worst = 0.0
     for o in range(pc.n_orient):
