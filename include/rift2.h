@@ -249,6 +249,23 @@ rift2_status rift2_detect(const float* moment, int32_t H, int32_t W, const rift2
                           rift2_keypoint* kpts, int32_t* n_kpts_dev, void* workspace,
                           size_t workspace_bytes, void* stream);
 
+/* rift2_detect without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The scratch is a 20 MiB array that the
+ * library keeps in device memory on every device where rift2_init has run,
+ * until the process ends; the call itself allocates nothing.  It covers every
+ * image and keypoint count whose rift2_detect_workspace_size is at most
+ * 20 MiB (e.g. 2048 x 2048 with 50 000 keypoints; not 4096 x 4096).
+ * Results are those of rift2_detect on the same arguments.
+ *   RIFT2_ERR_WORKSPACE        rift2_detect_workspace_size(H, W, det) > 20 MiB
+ *   RIFT2_ERR_NOT_INITIALIZED  rift2_init has not run on the current device
+ * Every call on one device shares that device's array, and it keeps the last
+ * call's contents (each call initialises what it reads): calls that can
+ * overlap on one device (concurrent streams, host threads) race and give
+ * wrong results; serialise them on one stream.  No stage timing is recorded. */
+rift2_status rift2_detect_noalloc(const float* moment, int32_t H, int32_t W, const rift2_detect_params* det,
+                                  rift2_keypoint* kpts, int32_t* n_kpts_dev, void* stream);
+
 /* RIFT's full detector (Section 2.1): FAST points on the maximum-moment map
  * (edge features) and on the minimum-moment map (corners), each map with its
  * own min-max normalisation, scores, 3x3 suppression and border mask as in

@@ -122,6 +122,14 @@ def detect_into(moment, det, kpts, n, ws, stream=None):
     _lib.check(st, "rift2_detect")
 
 
+def detect_noalloc_into(moment, det, kpts, n, stream=None):
+    """rift2_detect_noalloc: detection on the library's own scratch (no workspace argument)."""
+    lib = _lib.load()
+    h, w = moment.shape
+    st = lib.rift2_detect_noalloc(_ptr(moment), h, w, ctypes.byref(det), _ptr(kpts), _ptr(n), _stream(stream))
+    _lib.check(st, "rift2_detect_noalloc")
+
+
 def detect_union_into(max_moment, min_moment, det, kpts, n, ws, stream=None):
     lib = _lib.load()
     h, w = max_moment.shape

@@ -87,6 +87,7 @@ EXPORTS = [
     "rift2_engine_submit", "rift2_engine_poll", "rift2_engine_pending", "rift2_engine_destroy",
     "rift2_ransac_workspace_size", "rift2_ransac", "rift2_consensus", "rift2_detect_union_workspace_size",
     "rift2_detect_union", "rift2_debug_response", "rift2_debug_noise", "rift2_desc_normalize",
+    "rift2_detect_noalloc",
 ]
 STAGES = ["row_dft", "pass_a", "noise_pre", "noise_sel", "pass_b", "detect", "describe", "match_prep",
           "match_gemm", "match_merge", "pass_b_reduce", "ransac"]
@@ -130,6 +131,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rift2_filter_mim.restype = ctypes.c_int
     lib.rift2_detect.argtypes = [vp, i32, i32, P(DetectParams), vp, vp, vp, sz, vp]
     lib.rift2_detect.restype = ctypes.c_int
+    lib.rift2_detect_noalloc.argtypes = [vp, i32, i32, P(DetectParams), vp, vp, vp]
+    lib.rift2_detect_noalloc.restype = ctypes.c_int
     lib.rift2_describe.argtypes = [vp, i32, i32, vp, vp, i32, P(DescParams), vp, vp, vp, i32, vp, vp, sz, vp]
     lib.rift2_describe.restype = ctypes.c_int
     lib.rift2_match.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, i32, i32, P(MatchParams), vp, vp, vp, sz, vp]

@@ -21,6 +21,14 @@
 
 using namespace rift2;
 
+// Detection scratch of rift2_detect_noalloc: the library holds it on every
+// device it runs on until the process ends.  In host code `scratch` names a
+// host-side stand-in, never the device memory; rift2_init looks up each
+// device's own address of it with hipGetSymbolAddress, and only that address
+// is passed to kernels.
+constexpr size_t kNoAllocScratchBytes = (size_t)20 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -204,6 +212,8 @@ rift2_status launch_status() {
 
 std::mutex g_init_mu;
 bool g_init_done[64] = {};
+// Device address of `scratch` on each device, taken by rift2_init with that device current.
+void* g_scratch_dev[64] = {};
 
 // The FFT kernels read the twiddle tables that rift2_init loads per device.
 bool current_device_ready() {
@@ -228,8 +238,8 @@ struct ProfScope {
   int group;
   hipStream_t st;
   hipEvent_t a = nullptr, b = nullptr;
-  ProfScope(int g, hipStream_t s) : group(g), st(s) {
-    if (!g_prof_on) return;
+  ProfScope(int g, hipStream_t s, bool timed = true) : group(g), st(s) {
+    if (!g_prof_on || !timed) return;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess ||
         hipEventRecord(a, st) != hipSuccess) {
       a = b = nullptr;
@@ -531,8 +541,11 @@ rift2_status rift2_init(int device) {
     }
   }
   const hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(g_twiddle), host_tw, sizeof(host_tw), 0, hipMemcpyHostToDevice);
+  void* sp = nullptr;
+  const hipError_t es = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
   (void)hipSetDevice(prev);
-  if (e != hipSuccess) return RIFT2_ERR_DEVICE;
+  if (e != hipSuccess || es != hipSuccess || sp == nullptr) return RIFT2_ERR_DEVICE;
+  g_scratch_dev[device] = sp;
   g_init_done[device] = true;
   return RIFT2_OK;
 }
@@ -704,7 +717,7 @@ rift2_status rift2_desc_normalize(const uint16_t* desc, const float* inv_norm, c
 
 static rift2_status detect_launch(const float* edge, const float* corner, int32_t H, int32_t W,
                                   const rift2_detect_params* det, rift2_keypoint* kpts, int32_t* n_kpts_dev,
-                                  void* workspace, size_t workspace_bytes, void* stream) {
+                                  void* workspace, size_t workspace_bytes, void* stream, bool timed = true) {
   if (!edge || !det || !kpts || !n_kpts_dev || !workspace) return RIFT2_ERR_INVALID_ARG;
   if (((uintptr_t)edge & 15u) || ((uintptr_t)corner & 15u)) return RIFT2_ERR_INVALID_ARG;  // 16-byte loads
   if (H < 8 || W < 8 || (int64_t)H * W >= (1ll << 31)) return RIFT2_ERR_INVALID_ARG;
@@ -725,7 +738,7 @@ static rift2_status detect_launch(const float* edge, const float* corner, int32_
   uint64_t* fin = (uint64_t*)(ws + L.fin);
   uint32_t* part = (uint32_t*)(ws + L.part);
   (void)hipGetLastError();
-  ProfScope ps(5, st);
+  ProfScope ps(5, st, timed);
   const int n = H * W;
   const dim3 tiles((W + kTileX - 1) / kTileX, (H + kTileY - 1) / kTileY);
   hipLaunchKernelGGL(k_det_minmax, dim3(kMinMaxBlocks), dim3(256), 0, st, edge, n, mm, hist);
@@ -753,6 +766,23 @@ rift2_status rift2_detect(const float* moment, int32_t H, int32_t W, const rift2
                           rift2_keypoint* kpts, int32_t* n_kpts_dev, void* workspace, size_t workspace_bytes,
                           void* stream) {
   return detect_launch(moment, nullptr, H, W, det, kpts, n_kpts_dev, workspace, workspace_bytes, stream);
+}
+
+rift2_status rift2_detect_noalloc(const float* moment, int32_t H, int32_t W, const rift2_detect_params* det,
+                                  rift2_keypoint* kpts, int32_t* n_kpts_dev, void* stream) {
+  if (!moment || !det || !kpts || !n_kpts_dev) return RIFT2_ERR_INVALID_ARG;
+  if (H < 8 || W < 8 || (int64_t)H * W >= (1ll << 31) || det->max_keypoints <= 0) return RIFT2_ERR_INVALID_ARG;
+  if (rift2_detect_workspace_size(H, W, det) > kNoAllocScratchBytes) return RIFT2_ERR_WORKSPACE;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return RIFT2_ERR_NOT_INITIALIZED;
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_init_mu);
+    if (g_init_done[dev]) ws = g_scratch_dev[dev];
+  }
+  if (!ws) return RIFT2_ERR_NOT_INITIALIZED;
+  // no stage timing: its events are allocated by the runtime
+  return detect_launch(moment, nullptr, H, W, det, kpts, n_kpts_dev, ws, kNoAllocScratchBytes, stream, false);
 }
 
 rift2_status rift2_detect_union(const float* max_moment, const float* min_moment, int32_t H, int32_t W,

@@ -259,3 +259,27 @@ def test_mutual_matching_is_validated_and_sized():
     ring = _l.MatchParams(0.81, 0, 6, 1)
     assert lib.rift2_match(fake, fake, fake, fake, 60, fake, fake, fake, fake, 10, 216, ctypes.byref(ring), fake, fake,
                            fake, 1 << 30, null) == _l.ERR_UNSUPPORTED
+
+
+def test_detect_noalloc_validates_on_the_host():
+    """rift2_detect_noalloc checks its arguments and its 20 MiB scratch limit before touching a device."""
+    _l, lib = _lib()
+    det = _l.DetectParams()
+    lib.rift2_default_params(None, ctypes.byref(det), None, None)
+    fake = ctypes.c_void_p(0x1000)
+    null = ctypes.c_void_p(0)
+    assert lib.rift2_detect_noalloc(null, 1024, 1024, ctypes.byref(det), fake, fake, null) == _l.ERR_INVALID_ARG
+    assert lib.rift2_detect_noalloc(fake, 4, 1024, ctypes.byref(det), fake, fake, null) == _l.ERR_INVALID_ARG
+    det.max_keypoints = 50000
+    assert lib.rift2_detect_workspace_size(4096, 4096, ctypes.byref(det)) > 20 << 20
+    assert lib.rift2_detect_noalloc(fake, 4096, 4096, ctypes.byref(det), fake, fake, null) == _l.ERR_WORKSPACE
+    assert lib.rift2_detect_workspace_size(2048, 2048, ctypes.byref(det)) <= 20 << 20
+    try:
+        import torch
+
+        if torch.cuda.is_available():
+            return
+    except ImportError:
+        pass
+    # no device at all: nothing has been initialised
+    assert lib.rift2_detect_noalloc(fake, 2048, 2048, ctypes.byref(det), fake, fake, null) == _l.ERR_NOT_INITIALIZED
