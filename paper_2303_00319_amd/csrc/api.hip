@@ -646,16 +646,12 @@ rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t
   const int hw = H * W;
   {
     ProfScope ps(3, st);
-    hipLaunchKernelGGL(k_noise_bins<1>, dim3(pc->n_orient), dim3(256), 0, st, hw, nws, nc, t32, t64, ostat);
     hipLaunchKernelGGL(k_noise_sel1, dim3(kNoiseRegions, pc->n_orient), dim3(256), 0, st, a0, hw, nws);
-    hipLaunchKernelGGL(k_noise_bins<2>, dim3(pc->n_orient), dim3(256), 0, st, hw, nws, nc, t32, t64, ostat);
     hipLaunchKernelGGL(k_noise_sel2, dim3(kNoiseRegions, pc->n_orient), dim3(256), 0, st, hw, nws);
-    hipLaunchKernelGGL(k_noise_bins<3>, dim3(pc->n_orient), dim3(256), 0, st, hw, nws, nc, t32, t64, ostat);
+    hipLaunchKernelGGL(k_noise_threshold, dim3(pc->n_orient), dim3(256), 0, st, hw, nws, nc, NoiseOut{t32, t64, ostat});
   }
-  {
-    dispatch_pass_b(pc->n_scales, pc->n_orient, W, H, yp, pcc, t32, (float2*)(ws + L.spc), mim, max_moment,
-                    min_moment, amp_sums, st);
-  }
+  dispatch_pass_b(pc->n_scales, pc->n_orient, W, H, yp, pcc, t32, (float2*)(ws + L.spc), mim, max_moment, min_moment,
+                  amp_sums, st);
   return launch_status();
 }
 

@@ -10,8 +10,9 @@
 //   k_noise_pre  row IDFT of the s = 0 planes, written back in place as
 //                EO_{0,o}, -> A0_o = |EO_{0,o}| and a 12-bit radix histogram
 //                of its float bits per orientation
-//   k_noise_sel  exact median of A0_o (radix select over the candidate bin)
-//                and the noise threshold T_o, evaluated in FP64
+//   k_noise_sel1/2, k_noise_threshold  exact median of A0_o (radix select
+//                over the candidates of the level-1 and level-2 bins) and the
+//                noise threshold T_o, evaluated in FP64
 //   k_pass_b_orient  per row and orientation: row IDFTs of the other scales;
 //                per-pixel amplitude sum and phase congruency
 //   k_pass_b_reduce  per pixel over orientations: MIM argmax and moments
@@ -177,11 +178,14 @@ __global__ void __launch_bounds__(C * (H / P)) k_pass_a(const float2* __restrict
 // Exact median of A0_o (mean of the order statistics of rank HW/2-1 and HW/2)
 // by a three-level radix selection on the float bit patterns (values are
 // non-negative, so the bits order like the values): 13 bits (histogram built
-// by k_noise_pre), 10 bits (k_noise_sel1), 9 bits (k_noise_sel2).  After each
-// histogram a one-block-per-orientation k_noise_bins resolves that level and
-// publishes the bins: the kernel boundary orders the histogram merges before
-// the search without a device-wide fence (which would write back every XCD's
-// L2, full of the freshly written planes).
+// by k_noise_pre), 10 bits (k_noise_sel1), 9 bits (k_noise_sel2).  Each level
+// is resolved at the start of the next kernel by every block that needs it
+// (the kernel boundary orders the histogram merges before the search, with no
+// device-wide fence, which would write back every XCD's L2 full of freshly
+// written planes); block 0 of each orientation publishes the level's bins in
+// state[o] for the kernels after it.  One block per orientation resolves the
+// last level and evaluates the threshold T_o in FP64 (k_noise_threshold):
+// done by every row-pass block instead, it measured 8 us slower at 1024^2.
 constexpr int kHist2 = 1024, kHist3 = 512;
 
 struct NoiseConsts {
@@ -198,6 +202,28 @@ struct NoiseWs {
   int regions;      // k_noise_sel1 / k_noise_sel2 blocks per orientation
   uint32_t* cand;   // [N_o][HW] candidate bit patterns
 };
+
+// Where the row pass leaves the threshold and the two middle order
+// statistics (diagnostics).
+struct NoiseOut {
+  float* t32;
+  double* t64;
+  float* ostat;
+};
+
+// Ranks of the two middle order statistics.
+__device__ __forceinline__ uint32_t noise_rank(int hw, int q) { return (uint32_t)(hw / 2 - 1 + q); }
+
+// T_o from the median of A0_o in FP64: tau = median / sqrt(ln 4), the
+// expected total amplitude over the geometric series of scales, then mean +
+// k sigma of the Rayleigh-distributed noise energy.
+__device__ __forceinline__ double noise_threshold(float v0, float v1, const NoiseConsts& nc) {
+  const double med = 0.5 * ((double)v0 + (double)v1);
+  const double tau = med / sqrt(log(4.0));
+  const double total = tau * (1.0 - pow(1.0 / nc.mult, (double)nc.n_scales)) / (1.0 - 1.0 / nc.mult);
+  const double pi = 3.14159265358979323846;
+  return total * sqrt(pi / 2.0) + nc.k * total * sqrt((4.0 - pi) / 2.0);
+}
 
 // Block = LINES rows of one orientation.  A0 = |EO_{0,o}| written as float,
 // level-1 histogram of its bit pattern (bits >> 19) merged into hist1[o].
@@ -238,60 +264,6 @@ __global__ void __launch_bounds__(256) k_noise_pre(float2* __restrict__ y_in, in
   }
 }
 
-// One block per orientation: resolves level LEVEL of the selection for both
-// ranks and publishes it in state[o]; level 3 ends with the median and the
-// noise threshold, evaluated in FP64.
-template <int LEVEL>
-__global__ void __launch_bounds__(256) k_noise_bins(int hw, NoiseWs ws, NoiseConsts nc, float* __restrict__ t_out,
-                                                    double* __restrict__ t_out64, float* __restrict__ ostat) {
-  __shared__ uint32_t scratch[4];
-  __shared__ int s_bin[2];
-  __shared__ uint32_t s_below[2];
-  const int o = blockIdx.x;
-  uint32_t* st = ws.state + 8 * o;
-  const uint32_t rank[2] = {(uint32_t)(hw / 2 - 1), (uint32_t)(hw / 2)};
-  if (LEVEL == 1) {
-    const uint32_t* h = ws.hist1 + (size_t)o * kHist1;
-    for (int q = 0; q < 2; ++q) block_find_rank<kHist1, 256, false>(h, rank[q], &s_bin[q], &s_below[q], scratch);
-    if (threadIdx.x == 0) {
-      st[0] = (uint32_t)s_bin[0];
-      st[1] = (uint32_t)s_bin[1];
-      st[2] = s_below[0];
-      st[3] = s_below[1];
-    }
-  } else if (LEVEL == 2) {
-    const uint32_t* h = ws.hist2 + (size_t)o * 2 * kHist2;
-    for (int q = 0; q < 2; ++q)
-      block_find_rank<kHist2, 256, false>(h + q * kHist2, rank[q] - st[2 + q], &s_bin[q], &s_below[q], scratch);
-    if (threadIdx.x == 0) {
-      st[4] = (uint32_t)s_bin[0];
-      st[5] = (uint32_t)s_bin[1];
-      st[6] = s_below[0];
-      st[7] = s_below[1];
-    }
-  } else {
-    const uint32_t* h = ws.hist3 + (size_t)o * 2 * kHist3;
-    float vals[2];
-    for (int q = 0; q < 2; ++q) {
-      block_find_rank<kHist3, 256, false>(h + q * kHist3, rank[q] - st[2 + q] - st[6 + q], &s_bin[q], &s_below[q],
-                                          scratch);
-      vals[q] = __uint_as_float((((st[q] << 10) | st[4 + q]) << 9) | (uint32_t)s_bin[q]);
-    }
-    if (threadIdx.x == 0) {
-      // the two middle order statistics stay in the workspace for diagnostics
-      ostat[2 * o] = vals[0];
-      ostat[2 * o + 1] = vals[1];
-      const double med = 0.5 * ((double)vals[0] + (double)vals[1]);
-      const double tau = med / sqrt(log(4.0));
-      const double total = tau * (1.0 - pow(1.0 / nc.mult, (double)nc.n_scales)) / (1.0 - 1.0 / nc.mult);
-      const double pi = 3.14159265358979323846;
-      const double tt = total * sqrt(pi / 2.0) + nc.k * total * sqrt((4.0 - pi) / 2.0);
-      t_out[o] = (float)tt;
-      t_out64[o] = tt;
-    }
-  }
-}
-
 // Appends the taking lanes' values to this block's own list region; the
 // position comes from a block-local LDS counter (no global atomics).
 __device__ __forceinline__ void block_append(bool take, uint32_t value, uint32_t* lds_count, uint32_t* region) {
@@ -311,11 +283,23 @@ __device__ __forceinline__ void block_append(bool take, uint32_t value, uint32_t
 __global__ void __launch_bounds__(256) k_noise_sel1(const float* __restrict__ a0, int hw, NoiseWs ws) {
   __shared__ uint32_t h2[2][kHist2];
   __shared__ uint32_t s_count;
+  __shared__ uint32_t scratch[4];
+  __shared__ int s_bin[2];
+  __shared__ uint32_t s_below[2];
   const int o = blockIdx.y;
   for (int i = threadIdx.x; i < 2 * kHist2; i += 256) (&h2[0][0])[i] = 0u;
   if (threadIdx.x == 0) s_count = 0u;
-  const uint32_t* st = ws.state + 8 * o;
-  const uint32_t b0 = st[0], b1 = st[1];
+  // level 1: the bins of both ranks in the histogram k_noise_pre completed
+  const uint32_t* h1 = ws.hist1 + (size_t)o * kHist1;
+  for (int q = 0; q < 2; ++q) block_find_rank<kHist1, 256, false>(h1, noise_rank(hw, q), &s_bin[q], &s_below[q], scratch);
+  const uint32_t b0 = (uint32_t)s_bin[0], b1 = (uint32_t)s_bin[1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    uint32_t* st = ws.state + 8 * o;
+    st[0] = b0;
+    st[1] = b1;
+    st[2] = s_below[0];
+    st[3] = s_below[1];
+  }
   __syncthreads();
   const float* src = a0 + (size_t)o * hw;
   const int per_block = (hw + gridDim.x - 1) / gridDim.x;
@@ -352,11 +336,24 @@ __global__ void __launch_bounds__(256) k_noise_sel1(const float* __restrict__ a0
 // candidates that share both upper levels of a rank.
 __global__ void __launch_bounds__(256) k_noise_sel2(int hw, NoiseWs ws) {
   __shared__ uint32_t h3[2][kHist3];
+  __shared__ uint32_t scratch[4];
+  __shared__ int s_bin[2];
+  __shared__ uint32_t s_below[2];
   const int o = blockIdx.y;
   for (int i = threadIdx.x; i < 2 * kHist3; i += 256) (&h3[0][0])[i] = 0u;
-  const uint32_t* st = ws.state + 8 * o;
-  const uint32_t p0 = (st[0] << 10) | st[4];
-  const uint32_t p1 = (st[1] << 10) | st[5];
+  uint32_t* st = ws.state + 8 * o;
+  // level 2: the sub-bins of both ranks inside their level-1 bins
+  const uint32_t* h2 = ws.hist2 + (size_t)o * 2 * kHist2;
+  for (int q = 0; q < 2; ++q)
+    block_find_rank<kHist2, 256, false>(h2 + q * kHist2, noise_rank(hw, q) - st[2 + q], &s_bin[q], &s_below[q], scratch);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st[4] = (uint32_t)s_bin[0];
+    st[5] = (uint32_t)s_bin[1];
+    st[6] = s_below[0];
+    st[7] = s_below[1];
+  }
+  const uint32_t p0 = (st[0] << 10) | (uint32_t)s_bin[0];
+  const uint32_t p1 = (st[1] << 10) | (uint32_t)s_bin[1];
   const int per_region = (hw + ws.regions - 1) / ws.regions;
   const int rg = blockIdx.x;
   const uint32_t n = ws.cnt[(size_t)o * ws.regions + rg];
@@ -388,6 +385,31 @@ __global__ void __launch_bounds__(256) k_noise_sel2(int hw, NoiseWs ws) {
   for (int i = threadIdx.x; i < 2 * kHist3; i += 256) {
     const uint32_t c = (&h3[0][0])[i];
     if (c) atomicAdd(&gh3[i], c);
+  }
+}
+
+// One block per orientation: the last selection level, the two middle order
+// statistics (kept for diagnostics) and the threshold T_o (FP64; FP32 copy
+// for the row pass).
+__global__ void __launch_bounds__(256) k_noise_threshold(int hw, NoiseWs ws, NoiseConsts nc, NoiseOut out) {
+  __shared__ uint32_t scratch[4];
+  __shared__ int s_bin[2];
+  __shared__ uint32_t s_below[2];
+  const int o = blockIdx.x;
+  const uint32_t* st = ws.state + 8 * o;
+  const uint32_t* h3 = ws.hist3 + (size_t)o * 2 * kHist3;
+  float vals[2];
+  for (int q = 0; q < 2; ++q) {
+    block_find_rank<kHist3, 256, false>(h3 + q * kHist3, noise_rank(hw, q) - st[2 + q] - st[6 + q], &s_bin[q],
+                                        &s_below[q], scratch);
+    vals[q] = __uint_as_float((((st[q] << 10) | st[4 + q]) << 9) | (uint32_t)s_bin[q]);
+  }
+  if (threadIdx.x == 0) {
+    const double tt = noise_threshold(vals[0], vals[1], nc);
+    out.ostat[2 * o] = vals[0];
+    out.ostat[2 * o + 1] = vals[1];
+    out.t32[o] = (float)tt;
+    out.t64[o] = tt;
   }
 }
 

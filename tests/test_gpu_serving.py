@@ -119,3 +119,57 @@ def test_engine_equals_direct_stage_calls():
     eng.submit(rid, a, b)
     got = _result(eng.drain()[0])
     assert np.array_equal(got, want)
+
+
+def test_served_requests_match_the_oracle_at_1536_and_2048():
+    """Two served requests of the serving sizes 1536^2 and 2048^2 (shifted, inverted pairs, so that
+    thousands of matches exist; K = 2e-3 HW keypoints; BF16 matching), in flight together, against
+    the FP64 oracle: (i) stage-isolated, the oracle matching the GPU's own descriptor rows (the
+    engine's stages are the direct calls, which reproduce them), >= 99.5 %; (ii) end to end, the
+    oracle's whole FP64 pipeline against the served matches, identified by keypoint coordinates,
+    Jaccard >= 0.9 (as at the headline size)."""
+    import oracle
+    from oracle import match, pipeline
+    from synth import make_shifted_pair
+
+    r2, dev = _gpu()
+    sizes = (1536, 2048)
+    pairs = {}
+    eng = _engine(r2, 8 << 30, 2)
+    for i, n in enumerate(sizes):
+        a, b, _ = make_shifted_pair(3, i, size=n)
+        ta, tb = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+        pairs[n] = (a, b, ta, tb)
+        eng.submit(n, ta, tb)
+    done = {d["id"]: d for d in eng.drain()}
+    eng.close()
+    assert sorted(done) == list(sizes)
+    pc, det, dp, mp = r2.defaults()
+    for n in sizes:
+        a, b, ta, tb = pairs[n]
+        k = int(2e-3 * n * n)
+        served = _result(done[n])
+        det.max_keypoints = k
+        print(f"[serving vs oracle] {n}^2, K = {k}: {len(served)} served matches", flush=True)
+        feats = []
+        for t in (ta, tb):
+            fm = r2.filter_mim(t, pc)
+            kp, nk = r2.detect(fm["M"], det)
+            desc, inv, dkp, nd = r2.describe(fm["mim"], kp, nk, dp)
+            torch.cuda.synchronize()
+            nk, nd = int(nk.item()), int(nd.item())
+            feats.append((kp[:nk, :2].cpu().numpy(), desc[:nd].cpu().numpy().astype(np.uint16),
+                          dkp[:nd].cpu().numpy()))
+        (ka, da, pa), (kb, db, pb) = feats
+        ref = match.match(da, pa, db, pb, dtype=np.float64)
+        iso = {(int(x), int(y)) for x, y in zip(ref[0], ref[1])}
+        got = {(int(r[0]), int(r[1])) for r in served}
+        jac = len(got & iso) / max(1, len(got | iso))
+        print(f"  stage-isolated: oracle {len(iso)}, Jaccard {jac:.5f}", flush=True)
+        assert len(iso) > 1000 and jac >= 0.995
+        got_xy = {(tuple(ka[i]), tuple(kb[j])) for i, j in got}
+        fa, fb, mref = pipeline.match_pair(a, b, det=oracle.DetectParams(max_keypoints=k))
+        want = {(tuple(fa["kpts"][i]), tuple(fb["kpts"][j])) for i, j in zip(mref[0], mref[1])}
+        jac = len(got_xy & want) / max(1, len(got_xy | want))
+        print(f"  end to end: oracle pipeline {len(want)}, Jaccard {jac:.5f}", flush=True)
+        assert jac >= 0.9
