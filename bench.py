@@ -53,9 +53,9 @@ FP64_PEAK_TFLOPS = 78.6  # vector FP64, FMA counted as two flops
 # (N_s = 4, N_o = 6, 5000 keypoints), valid only for the sources they were
 # taken on (hash of the listed files).
 MEASURED_TRAFFIC = {
-    "pass_a": {"sources": ("fft.hpp", "filter.hip", "api.hip"), "sha": "93d7b8ef23a1da89", "bytes": 213153557},
-    "pass_b": {"sources": ("fft.hpp", "filter.hip", "api.hip"), "sha": "93d7b8ef23a1da89", "bytes": 251940626},
-    "match_gemm": {"sources": ("match.hip", "api.hip"), "sha": "d48d415d3962cfce", "bytes": 419583796},
+    "pass_a": {"sources": ("fft.hpp", "filter.hip", "api.hip"), "sha": "54858d0b849a4b49", "bytes": 213201408},
+    "pass_b": {"sources": ("fft.hpp", "filter.hip", "api.hip"), "sha": "54858d0b849a4b49", "bytes": 251979776},
+    "match_gemm": {"sources": ("match.hip", "api.hip"), "sha": "0d0cdd422524779f", "bytes": 419923046},
 }
 
 
@@ -112,6 +112,10 @@ def parse():
     ap.add_argument("--serve-sizes", default=None, help="--serve: comma-separated square sizes (default: the mix)")
     ap.add_argument("--serve-keypoints", type=int, default=0, help="--serve: keypoints per image (0: 2e-3 HW)")
     ap.add_argument("--serve-form", default="bf16", choices=("fp32", "bf16", "fp8"), help="--serve: matching form")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the short serving sweep of the default line (rates 5..80 pairs/s + saturation)")
+    ap.add_argument("--sweep-requests", type=int, default=48,
+                    help="requests per arrival rate in the default line's serving sweep (saturation: --requests)")
     ap.add_argument("--ransac", type=int, default=0,
                     help="hypotheses of an outlier-removal stage appended to every pair step (0: none)")
     ap.add_argument("--ransac-matches", type=int, default=5000,
@@ -269,13 +273,19 @@ def profile_stages(r2, torch, pipe, imgs, steps):
     """
     r2.profile_read()
     r2.profile_enable(True)
+    rows = []
     for k in range(steps):
         a, b = imgs[k % len(imgs)]
         pipe.run_serial(a, b)
+        # this step's row counts (device values, copied in stream order before the next step overwrites them)
+        rows.append((pipe.a.nd.clone(), pipe.b.nd.clone()))
     torch.cuda.synchronize()
     r2.profile_enable(False)
     raw = r2.profile_read()
-    return {k: {"ms_avg": (v[0] / v[1] if v[1] else 0.0), "launches": v[1]} for k, v in raw.items()}
+    out = {k: {"ms_avg": (v[0] / v[1] if v[1] else 0.0), "launches": v[1], "ms_total": v[0]} for k, v in raw.items()}
+    # (n_a, n_b) of every profiled step, for flops summed over exactly the timed launches
+    out["_rows"] = [(int(ra.item()), int(rb.item())) for ra, rb in rows]
+    return out
 
 
 def roofline(stages, h, w, n_scales, n_orient, n_a, n_b, d, gemm_peak=None):
@@ -289,10 +299,14 @@ def roofline(stages, h, w, n_scales, n_orient, n_a, n_b, d, gemm_peak=None):
     """
     hw = h * w
     f = n_scales * n_orient
+    # the GEMM's work: flops of each profiled step's own rows, summed, over the summed launch time
+    # (the resident pairs' row counts differ by ~10 %)
+    step_rows = stages.get("_rows") or [(n_a, n_b)]
+    gemm_flop_avg = sum(2.0 * ra * rb * d for ra, rb in step_rows) / len(step_rows)
     cand = {
         "pass_a": ("hbm", hw * (8 + 8 * f), 2),
         "pass_b": ("hbm", hw * (8 * f + 5), 2),
-        "match_gemm": ("mfma", 2.0 * n_a * n_b * d, 1),
+        "match_gemm": ("mfma", gemm_flop_avg, 1),
     }
 
     def rate(k):
@@ -304,6 +318,8 @@ def roofline(stages, h, w, n_scales, n_orient, n_a, n_b, d, gemm_peak=None):
         return HBM_PEAK_GBS if cand[k][0] == "hbm" else (gemm_peak or FP32_MFMA_PEAK_TFLOPS)
 
     best = max(cand, key=lambda k: cand[k][2] * stages[k]["ms_avg"])
+    if best == "match_gemm" and stages["match_gemm"]["launches"] != len(step_rows):
+        raise RuntimeError("GEMM launches and profiled steps differ")
     bound, work, per_step = cand[best]
     achieved = rate(best)
     traffic = None
@@ -417,32 +433,90 @@ def form_agreement(r2, torch, args, forms, prec):
                for f in forms}}
 
 
-def cpu_baseline(size, keypoints, n_pairs=3):
-    """The FP64 oracle on `n_pairs` full pairs of the same workload, single-threaded."""
+def _oracle_pair_stages(job):
+    """One full pair through the FP64 oracle in this process, single-threaded: seconds per stage
+    (filter bank / MIM / moments, FAST, descriptors for both images; matching) and the match count."""
+    size, keypoints, index = job
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     import oracle
-    from oracle import pipeline
+    from oracle import describe, detect, filterbank, match
     from synth import make_pair
 
+    a, b, _ = make_pair(1, index, size=size)
+    pc = oracle.PCParams()
     det = oracle.DetectParams(max_keypoints=keypoints)
-    total, n_match = 0.0, 0
+    dp = oracle.DescParams(patch_size=det.patch_size, n_orient=pc.n_orient)
+    sec = {"filter": 0.0, "detect": 0.0, "describe": 0.0, "match": 0.0}
+    feats = []
     with threadpool_limits(limits=1):
-        for i in range(n_pairs):
-            a, b, _ = make_pair(1, i, size=size)
+        for img in (a, b):
             t0 = time.perf_counter()
-            _, _, m = pipeline.match_pair(a, b, det=det, dtype=np.float64)
-            total += time.perf_counter() - t0
-            n_match += int(len(m[0]))
-    return {"value": round(n_pairs / total, 5), "unit": "pairs/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_pairs} pairs {size}x{size}, {keypoints} kpts each, FP64 numpy oracle, one thread, "
-                      f"{total:.1f} s total",
-            "matches": n_match}
+            fm = filterbank.filter_mim(img, pc)
+            t1 = time.perf_counter()
+            kpts, _ = detect.detect(fm["M"], det, dtype=np.float64)
+            t2 = time.perf_counter()
+            counts, kp, _ = describe.describe(fm["mim"], kpts, dp)
+            t3 = time.perf_counter()
+            sec["filter"] += t1 - t0
+            sec["detect"] += t2 - t1
+            sec["describe"] += t3 - t2
+            feats.append((counts, kp))
+        t0 = time.perf_counter()
+        m = match.match(feats[0][0], feats[0][1], feats[1][0], feats[1][1], oracle.MatchParams(), dtype=np.float64)
+        sec["match"] += time.perf_counter() - t0
+    return sec, int(len(m[0]))
 
 
-def serve(args, r2, torch):
-    """Serving form: mixed sizes, Poisson arrivals, continuous batching, BF16 matching."""
+def _host_cpu():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
+
+
+def cpu_baseline(size, keypoints, one_thread_pairs=2, max_workers=16):
+    """The FP64 oracle on full pairs of the same workload, timed per stage on the host cores.
+
+    All cores: one single-threaded oracle process per core of this process's CPU set (at most
+    `max_workers`), one pair each, pairs/s = pairs / wall time.  One thread: `one_thread_pairs`
+    pairs in this process.  Runs before anything touches the GPU (the pool's worker processes are
+    started fresh, not forked from a process holding a GPU context)."""
+    import multiprocessing as mp
+
+    host = _host_cpu()
+    workers = max(1, min(max_workers, host["affinity"]))
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_pair_stages, [(size, keypoints, i) for i in range(workers)])
+    wall = time.perf_counter() - t0
+    stage_all = {k: round(1e3 * sum(r[0][k] for r in res) / len(res), 1) for k in res[0][0]}
+    one = [_oracle_pair_stages((size, keypoints, i)) for i in range(one_thread_pairs)]
+    t_one = sum(sum(r[0].values()) for r in one)
+    stage_one = {k: round(1e3 * sum(r[0][k] for r in one) / len(one), 1) for k in one[0][0]}
+    return {"value": round(workers / wall, 5), "unit": "pairs/s", "cores": workers, "kind": "oracle",
+            "sample": f"{workers} pairs {size}x{size}, {keypoints} kpts each, FP64 numpy oracle, {workers} "
+                      f"single-threaded processes, {wall:.1f} s wall (pool start-up included)",
+            "stage_ms_per_pair": stage_all,
+            "one_thread": {"pairs_per_s": round(len(one) / t_one, 5), "pairs": len(one),
+                           "stage_ms_per_pair": stage_one},
+            "host": host,
+            "matches": [r[1] for r in res]}
+
+
+def serve_sweep(args, r2, torch, rates, requests, pool_per_size, saturation_requests=None, serial_saturation=False):
+    """Serving form: mixed sizes, Poisson arrivals at each rate (0 = all at once, saturation),
+    continuous batching; per rate pairs/s and p50/p99 latency (completion minus arrival).  With
+    serial_saturation the saturation run is repeated with one request in flight at a time (no
+    overlap between requests): the rate the same requests reach back to back."""
     import numpy as np
 
     from synth import make_pair
@@ -452,43 +526,47 @@ def serve(args, r2, torch):
     sizes = tuple(int(x) for x in args.serve_sizes.split(",")) if args.serve_sizes else serving_sizes()
     pool = {}
     for n in sizes:
-        for i in range(args.pool):
+        for i in range(pool_per_size):
             a, b, _ = make_pair(3, n * 100 + i, size=n)
             pool[(n, i)] = (torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev))
     torch.cuda.synchronize()
     print(f"[serve] pool of {len(pool)} pairs resident", file=sys.stderr, flush=True)
     rng = np.random.default_rng(1_000_003 * 3)
-    req_size = [int(x) for x in rng.choice(sizes, size=args.requests)]
     pc, det, dp, mp = r2.defaults()
     mp.precision = {"fp32": r2.PREC_FP32, "bf16": r2.PREC_BF16, "fp8": r2.PREC_FP8}[args.serve_form]
     kreq = args.serve_keypoints
     results = []
-    for rate in [float(x) for x in args.rates.split(",")]:
-        gaps = rng.exponential(1.0 / rate, size=args.requests) if rate > 0 else np.zeros(args.requests)
+    runs = [(r, args.inflight) for r in rates]
+    if serial_saturation:
+        runs.append((0.0, 1))
+    for rate, inflight in runs:
+        n_req = saturation_requests if (rate <= 0 and saturation_requests) else requests
+        req_size = [int(x) for x in rng.choice(sizes, size=n_req)]
+        gaps = rng.exponential(1.0 / rate, size=n_req) if rate > 0 else np.zeros(n_req)
         arrive = np.cumsum(gaps) - gaps[0]
-        eng = r2.Engine(int(args.budget_gib * (1 << 30)), max_inflight=args.inflight, pc=pc, det=det, dp=dp, mp=mp)
+        eng = r2.Engine(int(args.budget_gib * (1 << 30)), max_inflight=inflight, pc=pc, det=det, dp=dp, mp=mp)
         # warm: one request of every size
         for j, n in enumerate(sizes):
             eng.submit(-1 - j, *pool[(n, 0)], max_keypoints=kreq)
         eng.drain()
         torch.cuda.synchronize()
         eng.close()
-        eng = r2.Engine(int(args.budget_gib * (1 << 30)), max_inflight=args.inflight, pc=pc, det=det, dp=dp, mp=mp)
+        eng = r2.Engine(int(args.budget_gib * (1 << 30)), max_inflight=inflight, pc=pc, det=det, dp=dp, mp=mp)
         t_epoch = time.perf_counter()
         nxt = 0
         done = []
         arr_ms = {}
-        while len(done) < args.requests:
+        while len(done) < n_req:
             now = time.perf_counter() - t_epoch
-            while nxt < args.requests and arrive[nxt] <= now:
+            while nxt < n_req and arrive[nxt] <= now:
                 n = req_size[nxt]
-                a, b = pool[(n, nxt % args.pool)]
+                a, b = pool[(n, nxt % pool_per_size)]
                 eng.submit(nxt, a, b, max_keypoints=kreq)
                 arr_ms[nxt] = 1000.0 * arrive[nxt]
                 nxt += 1
             got = eng.poll()
             done += got
-            if not got and nxt < args.requests:
+            if not got and nxt < n_req:
                 wait = arrive[nxt] - (time.perf_counter() - t_epoch)
                 if wait > 2e-4:
                     time.sleep(min(wait, 1e-3))
@@ -496,14 +574,23 @@ def serve(args, r2, torch):
         lat = [d["done_ms"] - arr_ms[d["id"]] for d in done]
         span_ms = max(d["done_ms"] for d in done) - min(arr_ms.values())
         matches = sum(int(d["n_out"].item()) for d in done if d["n_out"] is not None)
-        res = {"rate": rate if rate > 0 else "saturation", "pairs_per_s": round(args.requests / (span_ms / 1000.0), 2),
+        res = {"rate": rate if rate > 0 else "saturation", "inflight": inflight, "requests": n_req,
+               "pairs_per_s": round(n_req / (span_ms / 1000.0), 2),
                "p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
                "gpu_ms_p50": round(percentile([d["gpu_ms"] for d in done], 50), 3), "failed": len(bad),
                "matches": matches}
         print(f"[serve] {json.dumps(res)}", file=sys.stderr, flush=True)
         results.append(res)
         eng.close()
-    sat = [r for r in results if r["rate"] == "saturation"]
+    return sizes, results
+
+
+def serve(args, r2, torch):
+    """--serve: the serving form alone, its own JSON line."""
+    sizes, results = serve_sweep(args, r2, torch, [float(x) for x in args.rates.split(",")], args.requests,
+                                 args.pool)
+    kreq = args.serve_keypoints
+    sat = [r for r in results if r["rate"] == "saturation" and r["inflight"] == args.inflight]
     line = {
         "metric": "serving: image pairs/s + p50/p99 latency, mixed sizes, continuous batching",
         "value": sat[0]["pairs_per_s"] if sat else results[-1]["pairs_per_s"],
@@ -527,6 +614,13 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not part of this "
               f"build", file=sys.stderr)
         sys.exit(2)
+    cpu = None
+    if not args.no_cpu and args.config == 1 and not args.serve:
+        # the oracle's worker processes start before this process touches the GPU
+        print("[bench] cpu oracle baseline", file=sys.stderr, flush=True)
+        from synth.gen import CONFIGS as _cfgs
+
+        cpu = cpu_baseline(args.size or _cfgs[1].size, args.keypoints or _cfgs[1].max_keypoints)
     import numpy as np
     import torch
 
@@ -585,15 +679,15 @@ def main():
     ring_stages = {f: profile_stages(r2, torch, ring[f]["pipe"], imgs, args.profile_steps) for f in ring_forms}
     main_form = forms[0]
     d = args.n_orient * 36
-    # matching GEMM utilisation (flops of the last pair's actual row counts)
     n_a, n_b = timed[main_form]["last_pair"]["descriptor_rows"]
-    gemm_flop = 2.0 * n_a * n_b * d
     roof = roofline(stages[main_form], args.size, args.size, args.n_scales, args.n_orient, n_a, n_b, d,
                     peak[main_form])
     mfma = {}
     for f in forms:
-        t = stages[f]["match_gemm"]["ms_avg"] * 1e-3
-        mfma[f] = {"tflops": round(gemm_flop / t / 1e12, 2), "frac": round(gemm_flop / t / (peak[f] * 1e12), 4),
+        # sum of each profiled step's flops over the summed GEMM time
+        flop = sum(2.0 * ra * rb * d for ra, rb in stages[f]["_rows"])
+        t = stages[f]["match_gemm"]["ms_total"] * 1e-3
+        mfma[f] = {"tflops": round(flop / t / 1e12, 2), "frac": round(flop / t / (peak[f] * 1e12), 4),
                    "peak_tflops": peak[f]}
     print("[bench] section 4 metrics", file=sys.stderr, flush=True)
     accuracy = {main_form: section4_metrics(r2, torch, timed[main_form]["pipe"], imgs, gts)}
@@ -603,10 +697,17 @@ def main():
     agreement = form_agreement(r2, torch, args, forms, prec)
     print("[bench] outlier removal", file=sys.stderr, flush=True)
     outliers = time_outliers(r2, torch, args)
-    cpu = None
-    if not args.no_cpu and args.config == 1:
-        print("[bench] cpu oracle baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(args.size, args.keypoints)
+    serving = None
+    if args.config == 1 and not args.no_serve:
+        print("[bench] serving sweep", file=sys.stderr, flush=True)
+        rates = [5.0, 10.0, 20.0, 40.0, 80.0, 0.0]
+        sizes, res = serve_sweep(args, r2, torch, rates, args.sweep_requests, 2, saturation_requests=args.requests,
+                                 serial_saturation=True)
+        serving = {"workload": f"pair requests of sizes uniform over {list(sizes)} (2 resident pairs per size), "
+                               f"keypoints 2e-3 HW, Poisson arrivals, {args.sweep_requests} requests per rate, "
+                               f"{args.requests} all at once for saturation; latency = completion - arrival",
+                   "form": f"f32 filter + {args.serve_form} matching", "budget_gib": args.budget_gib,
+                   "inflight": args.inflight, "rates": res}
     head = timed[main_form]
     metric = ("image pairs/s + p50/p99 latency (1024^2 pair, 5k kpts); mixed vs plain FP32" if args.config == 1 else
               f"image pairs/s + p50/p99 latency ({args.size}^2 pair, {args.keypoints} kpts); " + " vs ".join(forms))
@@ -637,9 +738,10 @@ def main():
         },
         "roofline": roof,
         "mfma": mfma,
-        "stages_ms": {f: {k: round(v["ms_avg"], 5) for k, v in stages[f].items()} for f in forms},
+        "stages_ms": {f: {k: round(v["ms_avg"], 5) for k, v in stages[f].items() if k != "_rows"} for f in forms},
         "cpu_baseline": cpu,
         "outliers": outliers,
+        "serving": serving,
         "accuracy": accuracy,
         "agreement": agreement,
         "rift_ring": None,
@@ -665,7 +767,7 @@ def main():
                 "pairs_per_s": round(t["pairs_per_s"], 2), "ms_per_step": round(t["ms_per_step"], 4),
                 "p50_ms": round(t["p50_ms"], 4), "p99_ms": round(t["p99_ms"], 4),
                 "descriptor_rows": t["last_pair"]["descriptor_rows"], "matches": t["last_pair"]["matches"],
-                "stages_ms": {k: round(v["ms_avg"], 5) for k, v in ring_stages[f].items()},
+                "stages_ms": {k: round(v["ms_avg"], 5) for k, v in ring_stages[f].items() if k != "_rows"},
                 "rift2_speedup": round(base["pairs_per_s"] / t["pairs_per_s"], 3) if base else None,
             }
     if args.ransac > 0:
