@@ -91,8 +91,9 @@ FilterLayout filter_layout(int H, int W, const rift2_pc_params* p) {
 }
 
 struct DetectLayout {
-  size_t hdr, mm, hist, tile_cnt, cand, sel_cnt, sel, fin, part, total;
+  size_t hdr, mm, hist, tile_cnt, cand, sel_cnt, sel, fin, part, above, cursor, total;
   int n_tiles, n_part;
+  bool count_sort;
   uint32_t region;
 };
 
@@ -112,9 +113,18 @@ DetectLayout detect_layout(int H, int W, const rift2_detect_params* d, int maps 
   L.sel = c.take((size_t)L.region * kSelBlocks * sizeof(uint64_t));
   const size_t kmax = d ? (size_t)d->max_keypoints : 0;
   L.fin = c.take(kmax * sizeof(uint64_t) + 8);
+  L.count_sort = kmax >= kCountSortMin;
   const int blocks = (int)((kmax + 255) / 256);
   L.n_part = std::max(1, std::min(32, 512 / std::max(1, blocks)));
-  L.part = c.take((size_t)L.n_part * kmax * sizeof(uint32_t) + 8);
+  if (L.count_sort) {
+    // the winners in score-bin order, the bins' offsets and scatter cursors
+    L.part = c.take(kmax * sizeof(uint64_t) + 8);
+    L.above = c.take(kDetHistBins * sizeof(uint32_t));
+    L.cursor = c.take(kDetHistBins * sizeof(uint32_t));
+  } else {
+    L.part = c.take((size_t)L.n_part * kmax * sizeof(uint32_t) + 8);
+    L.above = L.cursor = 0;
+  }
   L.total = c.off;
   return L;
 }
@@ -752,9 +762,21 @@ static rift2_status detect_launch(const float* edge, const float* corner, int32_
   hipLaunchKernelGGL(k_det_select1, dim3(kSelBlocks), dim3(256), 0, st, hdr, tile_cnt, L.n_tiles, cand, sel, sel_cnt);
   hipLaunchKernelGGL(k_det_select2, dim3(1), dim3(1024), 0, st, hdr, sel, sel_cnt, L.region, fin, kmax);
   const int blocks = (int)((kmax + 255) / 256);
-  hipLaunchKernelGGL(k_det_rank, dim3(blocks, L.n_part), dim3(256), 0, st, hdr, fin, part, kmax);
-  hipLaunchKernelGGL(k_det_emit, dim3(blocks), dim3(256), 0, st, hdr, fin, part, L.n_part, kmax, W,
-                     (KeypointOut*)kpts, n_kpts_dev);
+  if (L.count_sort) {
+    uint64_t* grouped = (uint64_t*)(ws + L.part);
+    uint32_t* above = (uint32_t*)(ws + L.above);
+    uint32_t* cursor = (uint32_t*)(ws + L.cursor);
+    hipLaunchKernelGGL(k_det_offsets, dim3(1), dim3(1024), 0, st, (const uint32_t*)hist, above, cursor);
+    hipLaunchKernelGGL(k_det_group, dim3(blocks), dim3(256), 0, st, (const uint32_t*)hdr, (const uint64_t*)fin, cursor,
+                       grouped);
+    hipLaunchKernelGGL(k_det_rank_bins, dim3(blocks), dim3(256), 0, st, (const uint32_t*)hdr,
+                       (const uint64_t*)grouped, (const uint32_t*)above, (const uint32_t*)hist, W, (KeypointOut*)kpts,
+                       n_kpts_dev);
+  } else {
+    hipLaunchKernelGGL(k_det_rank, dim3(blocks, L.n_part), dim3(256), 0, st, hdr, fin, part, kmax);
+    hipLaunchKernelGGL(k_det_emit, dim3(blocks), dim3(256), 0, st, hdr, fin, part, L.n_part, kmax, W,
+                       (KeypointOut*)kpts, n_kpts_dev);
+  }
   return launch_status();
 }
 

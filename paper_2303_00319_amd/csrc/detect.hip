@@ -16,6 +16,14 @@
 //   k_det_rank    rank of every winner = number of larger keys, counted over
 //                 key chunks in parallel
 //   k_det_emit    output record at its rank
+// Above kCountSortMin keypoints the all-pairs count is replaced by a counting
+// sort over the score bins:
+//   k_det_offsets one block: per bin, the number of candidates in the bins
+//                 above it (every one a winner for bins at or above the
+//                 boundary bin)
+//   k_det_group   winners scattered into score-bin order
+//   k_det_rank_bins  rank = the bin's offset + the larger keys of its own bin;
+//                 output record at its rank
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -495,6 +503,84 @@ __global__ void __launch_bounds__(256) k_det_emit(const uint32_t* __restrict__ h
   for (; s < n_part; ++s) acc[0] += part[(size_t)s * kmax + i];
   const uint32_t rank = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   const uint64_t key = fin[i];
+  const uint32_t raster = ~(uint32_t)(key & 0xffffffffu);
+  KeypointOut kp;
+  kp.x = (int)(raster % (uint32_t)W);
+  kp.y = (int)(raster / (uint32_t)W);
+  kp.score = __uint_as_float((uint32_t)(key >> 32));
+  out[rank] = kp;
+}
+
+// ---- counting sort of the winners by score bin (large K)
+
+// The all-pairs ranking costs K^2 comparisons; from this many keypoints on,
+// the winners are sorted by score bin instead (measured at 1024^2 with 5000
+// keypoints the all-pairs form is faster, 58.7 against 68.3 us for the
+// detection; at 2048^2 / 20000 and 4096^2 / 50000 the counting sort is faster,
+// 162 against 176 us and 491 against 744 us).
+constexpr uint32_t kCountSortMin = 12000;
+
+// One block: above[b] = candidates in the score bins above b, and the
+// scatter cursors, which start there.
+__global__ void __launch_bounds__(1024) k_det_offsets(const uint32_t* __restrict__ hist, uint32_t* __restrict__ above,
+                                                      uint32_t* __restrict__ cursor) {
+  __shared__ uint32_t scratch[16];
+  constexpr int PER = kDetHistBins / 1024;
+  const int top = kDetHistBins - 1 - (int)threadIdx.x * PER;  // this thread's bins, descending
+  uint32_t c[PER];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    c[i] = hist[top - i];
+    sum += c[i];
+  }
+  uint32_t acc = block_inclusive_scan<1024>(sum, scratch) - sum;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    above[top - i] = acc;
+    cursor[top - i] = acc;
+    acc += c[i];
+  }
+}
+
+// Each winner takes the next slot of its score bin (bins ordered from the top).
+__global__ void __launch_bounds__(256) k_det_group(const uint32_t* __restrict__ hdr, const uint64_t* __restrict__ fin,
+                                                   uint32_t* __restrict__ cursor, uint64_t* __restrict__ grouped) {
+  const uint32_t n = hdr[3];
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t key = fin[i];
+  grouped[atomicAdd(&cursor[(uint32_t)(key >> 48)], 1u)] = key;
+}
+
+// Rank of a winner = the winners in higher score bins (its bin's offset) +
+// the larger keys of its own bin, which holds the winners between the bin's
+// offset and the next bin's: all of the bin's candidates above the boundary
+// bin, the rest of the winners in the boundary bin.  The record goes to its
+// rank.
+__global__ void __launch_bounds__(256) k_det_rank_bins(const uint32_t* __restrict__ hdr,
+                                                       const uint64_t* __restrict__ grouped,
+                                                       const uint32_t* __restrict__ above,
+                                                       const uint32_t* __restrict__ hist, int W,
+                                                       KeypointOut* __restrict__ out, int32_t* __restrict__ n_out) {
+  const uint32_t n = hdr[3];
+  const uint32_t bbin = hdr[8];
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *n_out = (int32_t)n;
+  if (i >= n) return;
+  const uint64_t key = grouped[i];
+  const uint32_t b = (uint32_t)(key >> 48);
+  const uint32_t lo = above[b];
+  const uint32_t hi = b == bbin ? n : lo + hist[b];
+  // eight independent counts, so the loads of a chunk are issued together
+  uint32_t cnt[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+  uint32_t q = lo;
+  for (; q + 8 <= hi; q += 8) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) cnt[e] += grouped[q + e] > key ? 1u : 0u;
+  }
+  for (; q < hi; ++q) cnt[0] += grouped[q] > key ? 1u : 0u;
+  const uint32_t rank = lo + ((cnt[0] + cnt[1]) + (cnt[2] + cnt[3])) + ((cnt[4] + cnt[5]) + (cnt[6] + cnt[7]));
   const uint32_t raster = ~(uint32_t)(key & 0xffffffffu);
   KeypointOut kp;
   kp.x = (int)(raster % (uint32_t)W);

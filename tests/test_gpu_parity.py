@@ -221,6 +221,13 @@ def test_detect_ties_and_random_maps():
     _check_detect(r2, dev, m, 200, "quantised")
     m = rng.standard_normal((512, 256)).astype(np.float32)  # negative values, non-square
     _check_detect(r2, dev, m, 3000, "gaussian")
+    # at 12000 keypoints and more the winners are ranked by a counting sort over score bins: a map
+    # with heavy exact ties (whole bins of equal scores, the boundary bin among them) and a smooth one
+    m = (rng.integers(0, 6, size=(1024, 1024)) / 5.0).astype(np.float32)
+    _check_detect(r2, dev, m, 15000, "quantised, counting sort")
+    _check_detect(r2, dev, m, 11999, "quantised, all-pairs ranking")
+    m = rng.standard_normal((1024, 768)).astype(np.float32)
+    _check_detect(r2, dev, m, 12000, "gaussian, counting sort")
 
 
 def _check_describe(r2, dev, mim, kpts, tag, n_orient=6):
