@@ -83,9 +83,10 @@ def parse():
     ap.add_argument("--ring-forms", default=None,
                     help="matching precisions of RIFT's ring form to time beside RIFT2 (default fp32,bf16; "
                          "config 4: bf16; '' for none)")
-    ap.add_argument("--variants", default="turned,union",
+    ap.add_argument("--variants", default="turned,union,batched",
                     help="other forms of the path to time (FP32 matching): turned = descriptor grid turned by the "
-                         "dominant index, union = RIFT's corner + edge detector; '' for none")
+                         "dominant index, union = RIFT's corner + edge detector, batched = both images' filter banks "
+                         "in shared launches (rift2_filter_mim_batch) instead of one image per stream; '' for none")
     ap.add_argument("--size", type=int, default=0, help="override the image side")
     ap.add_argument("--keypoints", type=int, default=0, help="override the keypoints per image")
     ap.add_argument("--direct", action="store_true",
@@ -112,6 +113,8 @@ def parse():
     ap.add_argument("--serve-sizes", default=None, help="--serve: comma-separated square sizes (default: the mix)")
     ap.add_argument("--serve-keypoints", type=int, default=0, help="--serve: keypoints per image (0: 2e-3 HW)")
     ap.add_argument("--serve-form", default="bf16", choices=("fp32", "bf16", "fp8"), help="--serve: matching form")
+    ap.add_argument("--serve-batch", type=int, default=4,
+                    help="serving: queued same-size requests admitted together, filter banks in shared launches")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the short serving sweep of the default line (rates 5..80 pairs/s + saturation)")
     ap.add_argument("--sweep-requests", type=int, default=48,
@@ -165,7 +168,7 @@ def time_single(r2, torch, imgs, args, precision, ring=False, variant=None, grap
         dp.mode = r2.DESC_TURNED
     words = _ransac_words(torch, args.ransac) if args.ransac > 0 else None
     pipe = r2.PairPipeline(args.size, args.size, pc, det, dp, mp, serial=args.serial, ransac_words=words, ring=ring,
-                           union=variant == "union")
+                           union=variant == "union", batched=variant == "batched")
     graphs = []
     if graph:
         for i, (a, b) in enumerate(imgs):
@@ -548,10 +551,12 @@ def serve_sweep(args, r2, torch, rates, requests, pool_per_size, saturation_requ
     mp.precision = {"fp32": r2.PREC_FP32, "bf16": r2.PREC_BF16, "fp8": r2.PREC_FP8}[args.serve_form]
     kreq = args.serve_keypoints
     results = []
-    runs = [(r, args.inflight) for r in rates]
+    runs = [(r, args.inflight, args.serve_batch) for r in rates]
     if serial_saturation:
-        runs.append((0.0, 1))
-    for rate, inflight in runs:
+        # the saturation run again with every request admitted on its own (no shared filter launches),
+        # and with one request in flight at a time
+        runs += [(0.0, args.inflight, 1), (0.0, 1, 1)]
+    for rate, inflight, batch in runs:
         n_req = saturation_requests if (rate <= 0 and saturation_requests) else requests
         # the same seeded draw for runs of the same rate and length (both saturation runs see the same requests)
         rng = np.random.default_rng([1_000_003 * 3, int(rate * 1000), n_req])
@@ -559,6 +564,7 @@ def serve_sweep(args, r2, torch, rates, requests, pool_per_size, saturation_requ
         gaps = rng.exponential(1.0 / rate, size=n_req) if rate > 0 else np.zeros(n_req)
         arrive = np.cumsum(gaps) - gaps[0]
         eng = r2.Engine(int(args.budget_gib * (1 << 30)), max_inflight=inflight, pc=pc, det=det, dp=dp, mp=mp)
+        eng.set_batch(batch)
         # warm: one request of every size
         for j, n in enumerate(sizes):
             eng.submit(-1 - j, *pool[(n, 0)], max_keypoints=kreq)
@@ -566,6 +572,7 @@ def serve_sweep(args, r2, torch, rates, requests, pool_per_size, saturation_requ
         torch.cuda.synchronize()
         eng.close()
         eng = r2.Engine(int(args.budget_gib * (1 << 30)), max_inflight=inflight, pc=pc, det=det, dp=dp, mp=mp)
+        eng.set_batch(batch)
         t_epoch = time.perf_counter()
         nxt = 0
         done = []
@@ -588,7 +595,7 @@ def serve_sweep(args, r2, torch, rates, requests, pool_per_size, saturation_requ
         lat = [d["done_ms"] - arr_ms[d["id"]] for d in done]
         span_ms = max(d["done_ms"] for d in done) - min(arr_ms.values())
         matches = sum(int(d["n_out"].item()) for d in done if d["n_out"] is not None)
-        res = {"rate": rate if rate > 0 else "saturation", "inflight": inflight, "requests": n_req,
+        res = {"rate": rate if rate > 0 else "saturation", "inflight": inflight, "batch": batch, "requests": n_req,
                "pairs_per_s": round(n_req / (span_ms / 1000.0), 2),
                "p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
                "gpu_ms_p50": round(percentile([d["gpu_ms"] for d in done], 50), 3), "failed": len(bad),
@@ -604,7 +611,8 @@ def serve(args, r2, torch):
     sizes, results = serve_sweep(args, r2, torch, [float(x) for x in args.rates.split(",")], args.requests,
                                  args.pool)
     kreq = args.serve_keypoints
-    sat = [r for r in results if r["rate"] == "saturation" and r["inflight"] == args.inflight]
+    sat = [r for r in results if r["rate"] == "saturation" and r["inflight"] == args.inflight
+           and r["batch"] == args.serve_batch]
     line = {
         "metric": "serving: image pairs/s + p50/p99 latency, mixed sizes, continuous batching",
         "value": sat[0]["pairs_per_s"] if sat else results[-1]["pairs_per_s"],
@@ -721,7 +729,7 @@ def main():
                                f"keypoints 2e-3 HW, Poisson arrivals, {args.sweep_requests} requests per rate, "
                                f"{args.requests} all at once for saturation; latency = completion - arrival",
                    "form": f"f32 filter + {args.serve_form} matching", "budget_gib": args.budget_gib,
-                   "inflight": args.inflight, "rates": res}
+                   "inflight": args.inflight, "batch": args.serve_batch, "rates": res}
     head = timed[main_form]
     metric = ("image pairs/s + p50/p99 latency (1024^2 pair, 5k kpts); mixed vs plain FP32" if args.config == 1 else
               f"image pairs/s + p50/p99 latency ({args.size}^2 pair, {args.keypoints} kpts); " + " vs ".join(forms))
@@ -763,7 +771,9 @@ def main():
         "agreement": agreement,
         "rift_ring": None,
         "variants": {v: {"what": {"turned": "descriptor grid turned by the dominant index",
-                                  "union": "RIFT's corner + edge detector union"}[v],
+                                  "union": "RIFT's corner + edge detector union",
+                                  "batched": "both images' filter banks in shared launches, then their keypoints "
+                                             "on two streams"}[v],
                          "pairs_per_s": round(t["pairs_per_s"], 2), "ms_per_step": round(t["ms_per_step"], 4),
                          "p50_ms": round(t["p50_ms"], 4), "last_pair": t["last_pair"],
                          "detect_ms": round(var_stages[v]["detect"]["ms_avg"], 5),

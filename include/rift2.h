@@ -205,6 +205,27 @@ rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t
                               float* min_moment, float* amp_sums, void* workspace,
                               size_t workspace_bytes, void* stream);
 
+/* The filter bank of several images of one size in shared launches: every
+ * kernel of rift2_filter_mim covers all n images (1 <= n <=
+ * RIFT2_MAX_FILTER_BATCH), so small images fill the device together instead
+ * of one after another.  Each job is one image's rift2_filter_mim arguments
+ * (same rules; its own workspace of rift2_filter_workspace_size bytes); the
+ * results are those of n separate calls.  Errors as rift2_filter_mim, checked
+ * for every job before anything is enqueued. */
+#define RIFT2_MAX_FILTER_BATCH 8
+typedef struct {
+  const void* img;
+  uint8_t* mim;
+  float* max_moment;
+  float* min_moment;
+  float* amp_sums;
+  void* workspace;
+  size_t workspace_bytes;
+} rift2_filter_job;
+
+rift2_status rift2_filter_mim_batch(int32_t n, const rift2_filter_job* jobs, int32_t dtype, int32_t H, int32_t W,
+                                    int64_t pitch, const rift2_pc_params* pc, void* stream);
+
 /* Diagnostics of the filter stage (not needed for computing).
  *
  * rift2_debug_response: the complex response EO_{s,o} = IDFT2(DFT2(img) G_{s,o})
@@ -393,7 +414,9 @@ rift2_status rift2_consensus(const double* model, const rift2_correspondence* ma
  * times one pair at a time; this serves a stream of them).  Requests wait in
  * a host queue and are admitted in arrival order as soon as a stream pair is
  * free and the request's buffers fit into the caller's HBM arena (the
- * memory budget); admitted pairs run concurrently on their own streams.
+ * memory budget); queued requests of the same size are admitted with it and
+ * their filter banks share launches (rift2_engine_set_batch); admitted pairs
+ * then run concurrently on their own streams.
  * Every stage is the same call as above, so a request's result does not
  * depend on what else is in flight.  One engine per host thread. */
 typedef struct rift2_engine rift2_engine;
@@ -417,6 +440,8 @@ typedef struct {
   float gpu_ms;     /* admission to completion, on the GPU clock */
   double admit_ms;  /* admission, ms after the engine's creation (GPU clock) */
   double done_ms;   /* completion, ms after the engine's creation (GPU clock) */
+  int32_t batch;    /* requests admitted together with it, itself included (their filter banks
+                       shared launches; 1 = alone) */
 } rift2_completion;
 
 /* Arena bytes one request of this size needs (0 if unsupported); the
@@ -443,6 +468,12 @@ rift2_status rift2_engine_submit(rift2_engine* e, const rift2_request* r);
  * returns the number of completions written, or minus a rift2_status.  A
  * request that can never fit the arena completes with RIFT2_ERR_WORKSPACE. */
 int32_t rift2_engine_poll(rift2_engine* e, rift2_completion* done, int32_t max_done);
+
+/* Up to max_requests (1..RIFT2_MAX_FILTER_BATCH / 2, default 4) queued
+ * requests of one size, type and keypoint count are admitted together and
+ * their filter banks run as one batch (rift2_filter_mim_batch); 1 admits
+ * requests one at a time.  A request's results do not depend on it. */
+rift2_status rift2_engine_set_batch(rift2_engine* e, int32_t max_requests);
 
 /* Requests queued, running, or finished but not yet reported. */
 int32_t rift2_engine_pending(const rift2_engine* e);

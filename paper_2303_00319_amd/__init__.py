@@ -19,7 +19,7 @@ __all__ = [
     "PREC_FP32", "PREC_BF16", "PREC_FP8", "STAGES", "RansacParams", "ransac", "consensus", "ransac_workspace_bytes",
     "SIMILARITY_BYTES", "CONSENSUS_BYTES", "similarity_fields", "consensus_fields", "DESC_DOMINANT", "DESC_PLAIN",
     "DESC_RING", "DESC_TURNED", "rows_per_keypoint", "detect_union", "debug_response", "debug_noise",
-    "desc_normalize", "filter_workspace_bytes",
+    "desc_normalize", "filter_workspace_bytes", "filter_mim_batch_into",
 ]
 
 
@@ -112,6 +112,27 @@ def filter_mim_into(img, pc, mim, mmax, mmin, amp, ws, stream=None):
     st = lib.rift2_filter_mim(_ptr(img), _image_dtype(img), h, w, img.stride(0), ctypes.byref(pc), _ptr(mim),
                               _ptr(mmax), _ptr(mmin), _ptr(amp), _ptr(ws), _nbytes(ws), _stream(stream))
     _lib.check(st, "rift2_filter_mim")
+
+
+def filter_mim_batch_into(imgs, pc, outs, stream=None):
+    """rift2_filter_mim_batch: the filter bank of same-size, same-type images in shared launches.
+    outs[i] = (mim, mmax, mmin or None, amp or None, workspace) of image i."""
+    lib = _lib.load()
+    n = len(imgs)
+    if n != len(outs) or not 1 <= n <= _lib.MAX_FILTER_BATCH:
+        raise ValueError(f"1..{_lib.MAX_FILTER_BATCH} images with one output set each")
+    h, w = imgs[0].shape
+    for im in imgs:
+        if im.shape != (h, w) or im.dtype != imgs[0].dtype or im.stride(0) != imgs[0].stride(0):
+            raise ValueError("a batch holds images of one size, type and pitch")
+    jobs = (_lib.FilterJob * n)()
+    for i, (im, (mim, mmax, mmin, amp, ws)) in enumerate(zip(imgs, outs)):
+        jobs[i] = _lib.FilterJob(im.data_ptr(), mim.data_ptr(), mmax.data_ptr(),
+                                 mmin.data_ptr() if mmin is not None else None,
+                                 amp.data_ptr() if amp is not None else None, ws.data_ptr(), _nbytes(ws))
+    st = lib.rift2_filter_mim_batch(n, jobs, _image_dtype(imgs[0]), h, w, imgs[0].stride(0), ctypes.byref(pc),
+                                    _stream(stream))
+    _lib.check(st, "rift2_filter_mim_batch")
 
 
 def detect_into(moment, det, kpts, n, ws, stream=None):
@@ -403,7 +424,7 @@ class PairPipeline:
     """
 
     def __init__(self, h, w, pc=None, det=None, dp=None, mp=None, device=0, serial=False, ransac_words=None,
-                 ransac_params=None, ring=False, union=False):
+                 ransac_params=None, ring=False, union=False, batched=False):
         """ransac_words: optional device int32 [n_hyp, 2] uniform sample words; when given, every run ends
         with rift2_ransac on the pair's matches (threshold 3 px, 2 refits unless ransac_params says
         otherwise), results in ransac_result / ransac_mask.
@@ -414,7 +435,10 @@ class PairPipeline:
         one plain row per keypoint, and the matching is the ring matching.
 
         union=True detects with RIFT's corner + edge union (FAST on the minimum- and the maximum-moment
-        maps) instead of the maximum-moment map alone."""
+        maps) instead of the maximum-moment map alone.
+
+        batched=True runs both images' filter banks as one batch (rift2_filter_mim_batch: shared
+        launches) before their detection and description, instead of one image per stream."""
         torch = _torch()
         d_pc, d_det, d_dp, d_mp = defaults()
         self.pc = pc or d_pc
@@ -449,6 +473,11 @@ class PairPipeline:
         self.graph = None
         self._side = None
         self.serial = serial
+        self.batched = batched
+
+    def _filter_both(self, img_a, img_b, stream):
+        filter_mim_batch_into([img_a, img_b], self.pc,
+                              [(buf.mim, buf.M, buf.m, None, buf.ws_filter) for buf in (self.a, self.b)], stream)
 
     def _filter(self, img, buf, stream):
         filter_mim_into(img, self.pc, buf.mim, buf.M, buf.m, None, buf.ws_filter, stream)
@@ -474,8 +503,13 @@ class PairPipeline:
 
     def run_serial(self, img_a, img_b, stream=None):
         """Every stage on one stream, in order (used to time kernels one at a time)."""
-        self._image(img_a, self.a, stream)
-        self._image(img_b, self.b, stream)
+        if self.batched:
+            self._filter_both(img_a, img_b, stream)
+            self._keypoints(self.a, stream)
+            self._keypoints(self.b, stream)
+        else:
+            self._image(img_a, self.a, stream)
+            self._image(img_b, self.b, stream)
         self._match(stream)
 
     def run(self, img_a, img_b, stream=None):
@@ -487,9 +521,16 @@ class PairPipeline:
         if self._side is None:
             self._side = torch.cuda.Stream(device=self.dev)
         side = self._side
-        side.wait_stream(main)
-        self._image(img_a, self.a, main)
-        self._image(img_b, self.b, side)
+        if self.batched:
+            # both filter banks in shared launches, then the two images' keypoints side by side
+            self._filter_both(img_a, img_b, main)
+            side.wait_stream(main)
+            self._keypoints(self.a, main)
+            self._keypoints(self.b, side)
+        else:
+            side.wait_stream(main)
+            self._image(img_a, self.a, main)
+            self._image(img_b, self.b, side)
         main.wait_stream(side)
         self._match(main)
 
@@ -606,6 +647,10 @@ class Engine:
         self._h = h
         self._live = {}
 
+    def set_batch(self, max_requests):
+        """Queued requests of one shape admitted together, their filter banks in shared launches (1: none)."""
+        _lib.check(_lib.load().rift2_engine_set_batch(self._h, int(max_requests)), "rift2_engine_set_batch")
+
     def request_bytes(self, h, w, max_keypoints=0):
         return _lib.load().rift2_engine_request_bytes(h, w, max_keypoints, ctypes.byref(self.pc),
                                                       ctypes.byref(self.det), ctypes.byref(self.dp),
@@ -633,7 +678,7 @@ class Engine:
         return out, n_out
 
     def poll(self, max_done=256):
-        """Completed requests: [{id, status, gpu_ms, admit_ms, done_ms, out, n_out}]."""
+        """Completed requests: [{id, status, gpu_ms, admit_ms, done_ms, batch, out, n_out}]."""
         buf = (_lib.Completion * max_done)()
         n = _lib.load().rift2_engine_poll(self._h, buf, max_done)
         if n < 0:
@@ -642,7 +687,7 @@ class Engine:
         for c in buf[:n]:
             live = self._live.pop(int(c.id), None)
             res.append({"id": int(c.id), "status": int(c.status), "gpu_ms": float(c.gpu_ms),
-                        "admit_ms": float(c.admit_ms), "done_ms": float(c.done_ms),
+                        "admit_ms": float(c.admit_ms), "done_ms": float(c.done_ms), "batch": int(c.batch),
                         "out": live[2] if live else None, "n_out": live[3] if live else None})
         return res
 

@@ -54,6 +54,21 @@ class RansacParams(ctypes.Structure):
     _fields_ = [("threshold", ctypes.c_double), ("refine", ctypes.c_int32)]
 
 
+MAX_FILTER_BATCH = 8
+
+
+class FilterJob(ctypes.Structure):
+    _fields_ = [
+        ("img", ctypes.c_void_p),
+        ("mim", ctypes.c_void_p),
+        ("max_moment", ctypes.c_void_p),
+        ("min_moment", ctypes.c_void_p),
+        ("amp_sums", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
 class Request(ctypes.Structure):
     _fields_ = [
         ("id", ctypes.c_int64),
@@ -76,6 +91,7 @@ class Completion(ctypes.Structure):
         ("gpu_ms", ctypes.c_float),
         ("admit_ms", ctypes.c_double),
         ("done_ms", ctypes.c_double),
+        ("batch", ctypes.c_int32),
     ]
 
 
@@ -87,7 +103,7 @@ EXPORTS = [
     "rift2_engine_submit", "rift2_engine_poll", "rift2_engine_pending", "rift2_engine_destroy",
     "rift2_ransac_workspace_size", "rift2_ransac", "rift2_consensus", "rift2_detect_union_workspace_size",
     "rift2_detect_union", "rift2_debug_response", "rift2_debug_noise", "rift2_desc_normalize",
-    "rift2_detect_noalloc",
+    "rift2_detect_noalloc", "rift2_filter_mim_batch", "rift2_engine_set_batch",
 ]
 STAGES = ["row_dft", "pass_a", "noise_pre", "noise_sel", "pass_b", "detect", "describe", "match_prep",
           "match_gemm", "match_merge", "pass_b_reduce", "ransac"]
@@ -129,6 +145,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rift2_match_workspace_size.restype = sz
     lib.rift2_filter_mim.argtypes = [vp, i32, i32, i32, i64, P(PCParams), vp, vp, vp, vp, vp, sz, vp]
     lib.rift2_filter_mim.restype = ctypes.c_int
+    lib.rift2_filter_mim_batch.argtypes = [i32, P(FilterJob), i32, i32, i32, i64, P(PCParams), vp]
+    lib.rift2_filter_mim_batch.restype = ctypes.c_int
+    lib.rift2_engine_set_batch.argtypes = [vp, i32]
+    lib.rift2_engine_set_batch.restype = ctypes.c_int
     lib.rift2_detect.argtypes = [vp, i32, i32, P(DetectParams), vp, vp, vp, sz, vp]
     lib.rift2_detect.restype = ctypes.c_int
     lib.rift2_detect_noalloc.argtypes = [vp, i32, i32, P(DetectParams), vp, vp, vp]

@@ -275,78 +275,78 @@ struct ProfScope {
 
 namespace {
 
+// Every filter-bank launch covers the n images of a batch (grid z).
 template <int W, int P, typename Tin>
-void launch_fwd_rows(const void* img, int64_t pitch, int H, float2* rrow, uint32_t* zero, int n_zero, hipStream_t st) {
+void launch_fwd_rows(const FilterBatch& B, int n, int64_t pitch, int H, int n_zero, hipStream_t st) {
   constexpr int LINES = 256 / FftPlan<W, P>::T;
-  hipLaunchKernelGGL((k_fwd_rows<W, P, Tin>), dim3(H / LINES), dim3(256), 0, st, (const Tin*)img, pitch, H, rrow,
-                     zero, n_zero);
+  hipLaunchKernelGGL((k_fwd_rows<W, P, Tin>), dim3(H / LINES, 1, n), dim3(256), 0, st, B, pitch, H, n_zero);
 }
 
 template <int W, int P>
-bool fwd_rows_dtype(int dtype, const void* img, int64_t pitch, int H, float2* rrow, uint32_t* zero, int n_zero,
-                    hipStream_t st) {
+bool fwd_rows_dtype(int dtype, const FilterBatch& B, int n, int64_t pitch, int H, int n_zero, hipStream_t st) {
   switch (dtype) {
-    case RIFT2_U8: launch_fwd_rows<W, P, uint8_t>(img, pitch, H, rrow, zero, n_zero, st); return true;
-    case RIFT2_U16: launch_fwd_rows<W, P, uint16_t>(img, pitch, H, rrow, zero, n_zero, st); return true;
-    case RIFT2_F32: launch_fwd_rows<W, P, float>(img, pitch, H, rrow, zero, n_zero, st); return true;
+    case RIFT2_U8: launch_fwd_rows<W, P, uint8_t>(B, n, pitch, H, n_zero, st); return true;
+    case RIFT2_U16: launch_fwd_rows<W, P, uint16_t>(B, n, pitch, H, n_zero, st); return true;
+    case RIFT2_F32: launch_fwd_rows<W, P, float>(B, n, pitch, H, n_zero, st); return true;
     default: return false;
   }
 }
 
-bool dispatch_fwd_rows(int W, int dtype, const void* img, int64_t pitch, int H, float2* rrow, uint32_t* zero,
-                       int n_zero, hipStream_t st) {
+bool dispatch_fwd_rows(int W, int dtype, const FilterBatch& B, int n, int64_t pitch, int H, int n_zero,
+                       hipStream_t st) {
   switch (W) {
-    case 256: return fwd_rows_dtype<256, 16>(dtype, img, pitch, H, rrow, zero, n_zero, st);
-    case 512: return fwd_rows_dtype<512, 16>(dtype, img, pitch, H, rrow, zero, n_zero, st);
-    case 768: return fwd_rows_dtype<768, 12>(dtype, img, pitch, H, rrow, zero, n_zero, st);
-    case 1024: return fwd_rows_dtype<1024, 16>(dtype, img, pitch, H, rrow, zero, n_zero, st);
-    case 1536: return fwd_rows_dtype<1536, 12>(dtype, img, pitch, H, rrow, zero, n_zero, st);
-    case 2048: return fwd_rows_dtype<2048, 16>(dtype, img, pitch, H, rrow, zero, n_zero, st);
-    case 4096: return fwd_rows_dtype<4096, 16>(dtype, img, pitch, H, rrow, zero, n_zero, st);
+    case 256: return fwd_rows_dtype<256, 16>(dtype, B, n, pitch, H, n_zero, st);
+    case 512: return fwd_rows_dtype<512, 16>(dtype, B, n, pitch, H, n_zero, st);
+    case 768: return fwd_rows_dtype<768, 12>(dtype, B, n, pitch, H, n_zero, st);
+    case 1024: return fwd_rows_dtype<1024, 16>(dtype, B, n, pitch, H, n_zero, st);
+    case 1536: return fwd_rows_dtype<1536, 12>(dtype, B, n, pitch, H, n_zero, st);
+    case 2048: return fwd_rows_dtype<2048, 16>(dtype, B, n, pitch, H, n_zero, st);
+    case 4096: return fwd_rows_dtype<4096, 16>(dtype, B, n, pitch, H, n_zero, st);
     default: return false;
   }
 }
 
 template <int H, int P, int C>
-void launch_pass_a(int W, const float2* rrow, const FilterConsts& fc, float2* y, hipStream_t st, int min_blocks = 512) {
-  // Split the orientations over grid.y until there are >= min_blocks blocks;
-  // each group recomputes the column DFT of its block (an extra read of Rrow).
+void launch_pass_a(int W, const FilterBatch& B, int n, const FilterConsts& fc, hipStream_t st, int min_blocks = 512) {
+  // Split the orientations over grid.y until there are >= min_blocks blocks
+  // per image; each group recomputes the column DFT of its block (an extra
+  // read of Rrow).
   const int xblocks = W / C;
   int groups = (min_blocks + xblocks - 1) / xblocks;
   if (groups > fc.n_orient) groups = fc.n_orient;
   if (groups < 1) groups = 1;
-  hipLaunchKernelGGL((k_pass_a<H, P, C>), dim3(xblocks, groups), dim3(C * (H / P)), 0, st, rrow, fc, y);
+  hipLaunchKernelGGL((k_pass_a<H, P, C>), dim3(xblocks, groups, n), dim3(C * (H / P)), 0, st, B, fc);
 }
 
-bool dispatch_pass_a(int H, int W, const float2* rrow, const FilterConsts& fc, float2* y, hipStream_t st) {
+bool dispatch_pass_a(int H, int W, const FilterBatch& B, int n, const FilterConsts& fc, hipStream_t st) {
   switch (H) {
-    case 256: launch_pass_a<256, 16, 16>(W, rrow, fc, y, st); return true;
-    case 512: launch_pass_a<512, 16, 16>(W, rrow, fc, y, st); return true;
-    case 768: launch_pass_a<768, 12, 8>(W, rrow, fc, y, st); return true;
-    case 1024: launch_pass_a<1024, 8, 8>(W, rrow, fc, y, st, 256); return true;
-    case 1536: launch_pass_a<1536, 12, 4>(W, rrow, fc, y, st); return true;
-    case 2048: launch_pass_a<2048, 16, 4>(W, rrow, fc, y, st); return true;
-    case 4096: launch_pass_a<4096, 16, 2>(W, rrow, fc, y, st); return true;
+    case 256: launch_pass_a<256, 16, 16>(W, B, n, fc, st); return true;
+    case 512: launch_pass_a<512, 16, 16>(W, B, n, fc, st); return true;
+    case 768: launch_pass_a<768, 12, 8>(W, B, n, fc, st); return true;
+    case 1024: launch_pass_a<1024, 8, 8>(W, B, n, fc, st, 256); return true;
+    case 1536: launch_pass_a<1536, 12, 4>(W, B, n, fc, st); return true;
+    case 2048: launch_pass_a<2048, 16, 4>(W, B, n, fc, st); return true;
+    case 4096: launch_pass_a<4096, 16, 2>(W, B, n, fc, st); return true;
     default: return false;
   }
 }
 
 template <int W, int P>
-void launch_noise_pre(int H, int n_orient, int n_scales, float2* y, float* a0, const NoiseWs& ws, hipStream_t st) {
+void launch_noise_pre(int H, int n_orient, int n_scales, const FilterBatch& B, int n, hipStream_t st) {
   constexpr int LINES = 256 / FftPlan<W, P>::T;
-  hipLaunchKernelGGL((k_noise_pre<W, P>), dim3(H / LINES, n_orient), dim3(256), 0, st, y, H, n_scales, a0, ws);
+  hipLaunchKernelGGL((k_noise_pre<W, P>), dim3(H / LINES, n_orient, n), dim3(256), 0, st, B, H, n_scales, n_orient,
+                     kNoiseRegions);
 }
 
-bool dispatch_noise_pre(int W, int H, int n_orient, int n_scales, float2* y, float* a0, const NoiseWs& ws,
-                        hipStream_t st) {
+bool dispatch_noise_pre(int W, int H, int n_orient, int n_scales, const FilterBatch& B, int n, hipStream_t st) {
   switch (W) {
-    case 256: launch_noise_pre<256, 16>(H, n_orient, n_scales, y, a0, ws, st); return true;
-    case 512: launch_noise_pre<512, 16>(H, n_orient, n_scales, y, a0, ws, st); return true;
-    case 768: launch_noise_pre<768, 12>(H, n_orient, n_scales, y, a0, ws, st); return true;
-    case 1024: launch_noise_pre<1024, 16>(H, n_orient, n_scales, y, a0, ws, st); return true;
-    case 1536: launch_noise_pre<1536, 12>(H, n_orient, n_scales, y, a0, ws, st); return true;
-    case 2048: launch_noise_pre<2048, 16>(H, n_orient, n_scales, y, a0, ws, st); return true;
-    case 4096: launch_noise_pre<4096, 16>(H, n_orient, n_scales, y, a0, ws, st); return true;
+    case 256: launch_noise_pre<256, 16>(H, n_orient, n_scales, B, n, st); return true;
+    case 512: launch_noise_pre<512, 16>(H, n_orient, n_scales, B, n, st); return true;
+    case 768: launch_noise_pre<768, 12>(H, n_orient, n_scales, B, n, st); return true;
+    case 1024: launch_noise_pre<1024, 16>(H, n_orient, n_scales, B, n, st); return true;
+    case 1536: launch_noise_pre<1536, 12>(H, n_orient, n_scales, B, n, st); return true;
+    case 2048: launch_noise_pre<2048, 16>(H, n_orient, n_scales, B, n, st); return true;
+    case 4096: launch_noise_pre<4096, 16>(H, n_orient, n_scales, B, n, st); return true;
     default: return false;
   }
 }
@@ -371,38 +371,35 @@ bool dispatch_rows_inverse(int W, int H, const float2* y, float2* out, hipStream
 }
 
 template <int W, int P, int NS, int NO>
-void launch_pass_b_split(int H, const float2* y, const PCConsts& pcc, const float* t_o, float2* spc, uint8_t* mim,
-                         float* mmax, float* mmin, float* amp, hipStream_t st) {
+void launch_pass_b_split(int H, const FilterBatch& B, int n, const PCConsts& pcc, hipStream_t st) {
   {
     ProfScope ps(4, st);
-    hipLaunchKernelGGL((k_pass_b_orient<W, P, NS>), dim3(H, NO), dim3(W / P), 0, st, y, H, pcc, t_o, spc, amp);
+    hipLaunchKernelGGL((k_pass_b_orient<W, P, NS>), dim3(H, NO, n), dim3(W / P), 0, st, B, H, pcc);
   }
   const int hw = H * W;
   ProfScope ps(10, st);
-  hipLaunchKernelGGL((k_pass_b_reduce<NO>), dim3((hw / 4 + 255) / 256), dim3(256), 0, st, spc, hw, pcc, mim, mmax, mmin);
+  hipLaunchKernelGGL((k_pass_b_reduce<NO>), dim3((hw / 4 + 255) / 256, 1, n), dim3(256), 0, st, B, hw, pcc);
 }
 
 template <int NS, int NO>
-bool pass_b_w(int W, int H, const float2* y, const PCConsts& pcc, const float* t_o, float2* spc, uint8_t* mim,
-              float* mmax, float* mmin, float* amp, hipStream_t st) {
+bool pass_b_w(int W, int H, const FilterBatch& B, int n, const PCConsts& pcc, hipStream_t st) {
   switch (W) {
-    case 256: launch_pass_b_split<256, 4, NS, NO>(H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st); return true;
-    case 512: launch_pass_b_split<512, 8, NS, NO>(H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st); return true;
-    case 768: launch_pass_b_split<768, 12, NS, NO>(H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st); return true;
-    case 1024: launch_pass_b_split<1024, 16, NS, NO>(H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st); return true;
-    case 1536: launch_pass_b_split<1536, 12, NS, NO>(H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st); return true;
-    case 2048: launch_pass_b_split<2048, 8, NS, NO>(H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st); return true;
-    case 4096: launch_pass_b_split<4096, 16, NS, NO>(H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st); return true;
+    case 256: launch_pass_b_split<256, 4, NS, NO>(H, B, n, pcc, st); return true;
+    case 512: launch_pass_b_split<512, 8, NS, NO>(H, B, n, pcc, st); return true;
+    case 768: launch_pass_b_split<768, 12, NS, NO>(H, B, n, pcc, st); return true;
+    case 1024: launch_pass_b_split<1024, 16, NS, NO>(H, B, n, pcc, st); return true;
+    case 1536: launch_pass_b_split<1536, 12, NS, NO>(H, B, n, pcc, st); return true;
+    case 2048: launch_pass_b_split<2048, 8, NS, NO>(H, B, n, pcc, st); return true;
+    case 4096: launch_pass_b_split<4096, 16, NS, NO>(H, B, n, pcc, st); return true;
     default: return false;
   }
 }
 
-bool dispatch_pass_b(int ns, int no, int W, int H, const float2* y, const PCConsts& pcc, const float* t_o,
-                     float2* spc, uint8_t* mim, float* mmax, float* mmin, float* amp, hipStream_t st) {
-  if (ns == 4 && no == 6) return pass_b_w<4, 6>(W, H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st);
-  if (ns == 5 && no == 8) return pass_b_w<5, 8>(W, H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st);
-  if (ns == 4 && no == 8) return pass_b_w<4, 8>(W, H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st);
-  if (ns == 5 && no == 6) return pass_b_w<5, 6>(W, H, y, pcc, t_o, spc, mim, mmax, mmin, amp, st);
+bool dispatch_pass_b(int ns, int no, int W, int H, const FilterBatch& B, int n, const PCConsts& pcc, hipStream_t st) {
+  if (ns == 4 && no == 6) return pass_b_w<4, 6>(W, H, B, n, pcc, st);
+  if (ns == 5 && no == 8) return pass_b_w<5, 8>(W, H, B, n, pcc, st);
+  if (ns == 4 && no == 8) return pass_b_w<4, 8>(W, H, B, n, pcc, st);
+  if (ns == 5 && no == 6) return pass_b_w<5, 6>(W, H, B, n, pcc, st);
   return false;
 }
 
@@ -602,40 +599,57 @@ size_t rift2_match_workspace_size(int32_t cap_a, int32_t cap_b, int32_t D, const
   return match_layout(cap_a, cap_b, D, mp->precision, mp->mutual != 0).total;
 }
 
-rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t W, int64_t pitch,
-                              const rift2_pc_params* pc, uint8_t* mim, float* max_moment, float* min_moment,
-                              float* amp_sums, void* workspace, size_t workspace_bytes, void* stream) {
-  if (!img || !pc || !mim || !max_moment || !workspace) return RIFT2_ERR_INVALID_ARG;
+namespace {
+
+// One image's pointers inside the batch record (workspace regions carved by
+// the filter layout).
+FilterImage filter_image(const FilterLayout& L, const void* img, void* workspace, uint8_t* mim, float* mmax,
+                         float* mmin, float* amp) {
+  char* ws = (char*)workspace;
+  FilterImage I;
+  I.img = img;
+  I.rrow = (float2*)(ws + L.rrow);
+  I.yplanes = (float2*)(ws + L.yplanes);
+  I.a0 = (float*)(ws + L.a0);
+  I.cand = (uint32_t*)(ws + L.cand);
+  I.zero = (uint32_t*)(ws + L.zero);
+  I.t32 = (float*)(ws + L.t32);
+  I.t64 = (double*)(ws + L.t64);
+  I.ostat = (float*)(ws + L.ostat);
+  I.spc = (float2*)(ws + L.spc);
+  I.mim = mim;
+  I.mmax = mmax;
+  I.mmin = mmin;
+  I.amp = amp;
+  return I;
+}
+
+rift2_status filter_batch(int32_t n, const rift2_filter_job* jobs, int32_t dtype, int32_t H, int32_t W, int64_t pitch,
+                          const rift2_pc_params* pc, void* stream) {
+  if (n < 1 || n > RIFT2_MAX_FILTER_BATCH || !jobs || !pc) return RIFT2_ERR_INVALID_ARG;
   if (dtype != RIFT2_U8 && dtype != RIFT2_U16 && dtype != RIFT2_F32) return RIFT2_ERR_INVALID_ARG;
   if (pitch < W) return RIFT2_ERR_INVALID_ARG;
-  // the per-pixel reduction stores 4 pixels at a time
-  if (((uintptr_t)mim & 3u) || ((uintptr_t)max_moment & 15u) || ((uintptr_t)min_moment & 15u) ||
-      ((uintptr_t)amp_sums & 3u))
-    return RIFT2_ERR_INVALID_ARG;
+  for (int i = 0; i < n; ++i) {
+    const rift2_filter_job& j = jobs[i];
+    if (!j.img || !j.mim || !j.max_moment || !j.workspace) return RIFT2_ERR_INVALID_ARG;
+    // the per-pixel reduction stores 4 pixels at a time
+    if (((uintptr_t)j.mim & 3u) || ((uintptr_t)j.max_moment & 15u) || ((uintptr_t)j.min_moment & 15u) ||
+        ((uintptr_t)j.amp_sums & 3u))
+      return RIFT2_ERR_INVALID_ARG;
+  }
   if (!pc_ok(pc)) return RIFT2_ERR_INVALID_ARG;
   if (!size_ok(H) || !size_ok(W) || !pc_built(pc)) return RIFT2_ERR_UNSUPPORTED;
   const FilterLayout L = filter_layout(H, W, pc);
-  if (workspace_bytes < L.total) return RIFT2_ERR_WORKSPACE;
+  for (int i = 0; i < n; ++i)
+    if (jobs[i].workspace_bytes < L.total) return RIFT2_ERR_WORKSPACE;
   if (!current_device_ready()) return RIFT2_ERR_NOT_INITIALIZED;
   hipStream_t st = (hipStream_t)stream;
-  char* ws = (char*)workspace;
-  float2* rrow = (float2*)(ws + L.rrow);
-  float2* yp = (float2*)(ws + L.yplanes);
-  float* a0 = (float*)(ws + L.a0);
-  uint32_t* cand = (uint32_t*)(ws + L.cand);
-  uint32_t* zero = (uint32_t*)(ws + L.zero);
-  NoiseWs nws;
-  nws.hist1 = zero;
-  nws.hist2 = nws.hist1 + pc->n_orient * kHist1;
-  nws.hist3 = nws.hist2 + pc->n_orient * 2 * kHist2;
-  nws.state = nws.hist3 + pc->n_orient * 2 * kHist3;
-  nws.cnt = nws.state + 8 * pc->n_orient;
-  nws.regions = kNoiseRegions;
-  nws.cand = cand;
-  float* t32 = (float*)(ws + L.t32);
-  double* t64 = (double*)(ws + L.t64);
-  float* ostat = (float*)(ws + L.ostat);
-
+  FilterBatch B;
+  std::memset(&B, 0, sizeof(B));
+  for (int i = 0; i < n; ++i) {
+    const rift2_filter_job& j = jobs[i];
+    B.im[i] = filter_image(L, j.img, j.workspace, j.mim, j.max_moment, j.min_moment, j.amp_sums);
+  }
   FilterConsts fc;
   PCConsts pcc;
   NoiseConsts nc;
@@ -643,26 +657,42 @@ rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t
   (void)hipGetLastError();
   {
     ProfScope ps(0, st);
-    dispatch_fwd_rows(W, dtype, img, pitch, H, rrow, zero, L.zero_words, st);
+    dispatch_fwd_rows(W, dtype, B, n, pitch, H, L.zero_words, st);
   }
   {
     ProfScope ps(1, st);
-    dispatch_pass_a(H, W, rrow, fc, yp, st);
+    dispatch_pass_a(H, W, B, n, fc, st);
   }
   {
     ProfScope ps(2, st);
-    dispatch_noise_pre(W, H, pc->n_orient, pc->n_scales, yp, a0, nws, st);
+    dispatch_noise_pre(W, H, pc->n_orient, pc->n_scales, B, n, st);
   }
   const int hw = H * W;
   {
     ProfScope ps(3, st);
-    hipLaunchKernelGGL(k_noise_sel1, dim3(kNoiseRegions, pc->n_orient), dim3(256), 0, st, a0, hw, nws);
-    hipLaunchKernelGGL(k_noise_sel2, dim3(kNoiseRegions, pc->n_orient), dim3(256), 0, st, hw, nws);
-    hipLaunchKernelGGL(k_noise_threshold, dim3(pc->n_orient), dim3(256), 0, st, hw, nws, nc, NoiseOut{t32, t64, ostat});
+    hipLaunchKernelGGL(k_noise_sel1, dim3(kNoiseRegions, pc->n_orient, n), dim3(256), 0, st, B, hw, pc->n_orient,
+                       kNoiseRegions);
+    hipLaunchKernelGGL(k_noise_sel2, dim3(kNoiseRegions, pc->n_orient, n), dim3(256), 0, st, B, hw, pc->n_orient,
+                       kNoiseRegions);
+    hipLaunchKernelGGL(k_noise_threshold, dim3(pc->n_orient, 1, n), dim3(256), 0, st, B, hw, pc->n_orient,
+                       kNoiseRegions, nc);
   }
-  dispatch_pass_b(pc->n_scales, pc->n_orient, W, H, yp, pcc, t32, (float2*)(ws + L.spc), mim, max_moment, min_moment,
-                  amp_sums, st);
+  dispatch_pass_b(pc->n_scales, pc->n_orient, W, H, B, n, pcc, st);
   return launch_status();
+}
+
+}  // namespace
+
+rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t W, int64_t pitch,
+                              const rift2_pc_params* pc, uint8_t* mim, float* max_moment, float* min_moment,
+                              float* amp_sums, void* workspace, size_t workspace_bytes, void* stream) {
+  const rift2_filter_job job{img, mim, max_moment, min_moment, amp_sums, workspace, workspace_bytes};
+  return filter_batch(1, &job, dtype, H, W, pitch, pc, stream);
+}
+
+rift2_status rift2_filter_mim_batch(int32_t n, const rift2_filter_job* jobs, int32_t dtype, int32_t H, int32_t W,
+                                    int64_t pitch, const rift2_pc_params* pc, void* stream) {
+  return filter_batch(n, jobs, dtype, H, W, pitch, pc, stream);
 }
 
 rift2_status rift2_debug_response(const void* img, int32_t dtype, int32_t H, int32_t W, int64_t pitch,
@@ -679,15 +709,17 @@ rift2_status rift2_debug_response(const void* img, int32_t dtype, int32_t H, int
   if (!current_device_ready()) return RIFT2_ERR_NOT_INITIALIZED;
   hipStream_t st = (hipStream_t)stream;
   char* ws = (char*)workspace;
-  float2* rrow = (float2*)(ws + L.rrow);
-  float2* yp = (float2*)(ws + L.yplanes);
+  FilterBatch B;
+  std::memset(&B, 0, sizeof(B));
+  B.im[0] = filter_image(L, img, workspace, nullptr, nullptr, nullptr, nullptr);
+  const float2* yp = B.im[0].yplanes;
   FilterConsts fc;
   PCConsts pcc;
   NoiseConsts nc;
   filter_consts(H, W, pc, &fc, &pcc, &nc);
   (void)hipGetLastError();
-  dispatch_fwd_rows(W, dtype, img, pitch, H, rrow, (uint32_t*)(ws + L.zero), 0, st);
-  dispatch_pass_a(H, W, rrow, fc, yp, st);
+  dispatch_fwd_rows(W, dtype, B, 1, pitch, H, 0, st);
+  dispatch_pass_a(H, W, B, 1, fc, st);
   const float2* plane = yp + (size_t)(orient * pc->n_scales + scale) * H * W;
   dispatch_rows_inverse(W, H, plane, (float2*)eo, st);
   return launch_status();
@@ -1065,7 +1097,7 @@ rift2_status rift2_engine_create(int device, void* arena, size_t arena_bytes, in
     ok = hipStreamCreateWithFlags(&s.sa, hipStreamNonBlocking) == hipSuccess &&
          hipStreamCreateWithFlags(&s.sb, hipStreamNonBlocking) == hipSuccess &&
          hipEventCreate(&s.b_done) == hipSuccess && hipEventCreate(&s.admit) == hipSuccess &&
-         hipEventCreate(&s.done) == hipSuccess;
+         hipEventCreate(&s.done) == hipSuccess && hipEventCreate(&s.filt) == hipSuccess;
     e->free_slots.push_back(max_inflight - 1 - i);
   }
   if (ok) ok = hipEventRecord(e->epoch, e->slots[0].sa) == hipSuccess && hipEventSynchronize(e->epoch) == hipSuccess;
@@ -1112,6 +1144,7 @@ int32_t rift2_engine_poll(rift2_engine* e, rift2_completion* done, int32_t max_d
     rift2_completion c{};
     c.id = it->req.id;
     c.status = q == hipSuccess ? it->status : RIFT2_ERR_DEVICE;
+    c.batch = it->batch;
     float t_admit = 0.0f, t_done = 0.0f;
     if (q == hipSuccess && hipEventElapsedTime(&t_admit, e->epoch, s.admit) == hipSuccess &&
         hipEventElapsedTime(&t_done, e->epoch, s.done) == hipSuccess) {
@@ -1127,6 +1160,12 @@ int32_t rift2_engine_poll(rift2_engine* e, rift2_completion* done, int32_t max_d
   engine_pump(e);
   (void)hipSetDevice(prev);
   return n;
+}
+
+rift2_status rift2_engine_set_batch(rift2_engine* e, int32_t max_requests) {
+  if (!e || max_requests < 1 || max_requests > RIFT2_MAX_FILTER_BATCH / 2) return RIFT2_ERR_INVALID_ARG;
+  e->batch = max_requests;
+  return RIFT2_OK;
 }
 
 int32_t rift2_engine_pending(const rift2_engine* e) {
@@ -1147,6 +1186,7 @@ rift2_status rift2_engine_destroy(rift2_engine* e) {
     if (s.b_done) (void)hipEventDestroy(s.b_done);
     if (s.admit) (void)hipEventDestroy(s.admit);
     if (s.done) (void)hipEventDestroy(s.done);
+    if (s.filt) (void)hipEventDestroy(s.filt);
   }
   if (e->epoch) (void)hipEventDestroy(e->epoch);
   (void)hipSetDevice(prev);

@@ -2,10 +2,14 @@
 //
 // Requests queue on the host; the engine admits the head of the queue as soon
 // as (a) a stream pair is free and (b) its buffers fit into the caller's HBM
-// arena (first-fit over a free list with coalescing).  An admitted pair runs
-// the whole path -- both images' filter bank / detection / description on
-// two streams, then matching -- while later requests are admitted beside it,
-// so their kernels overlap on the device.  Completion is found by polling a
+// arena (first-fit over a free list with coalescing).  Queued requests of the
+// head's size (and type and keypoint count) are admitted with it, up to
+// `batch` requests, as far as streams and memory allow: their filter banks --
+// the bulk of the work, and the part that leaves the device half idle at the
+// small sizes -- run as one batch of shared launches (rift2_filter_mim_batch),
+// then each pair's detection and description run on its own two streams and
+// its matching after them, beside the requests admitted later, so their
+// kernels overlap on the device.  Completion is found by polling a
 // per-request event; the request's memory and streams go back to the pools
 // and the queue is pumped again.  Everything is host code over the C ABI
 // stages; the engine allocates no device memory.
@@ -13,6 +17,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <deque>
@@ -115,7 +120,7 @@ class ArenaAlloc {
 
 struct EngineSlot {
   hipStream_t sa = nullptr, sb = nullptr;
-  hipEvent_t b_done = nullptr, admit = nullptr, done = nullptr;
+  hipEvent_t b_done = nullptr, admit = nullptr, done = nullptr, filt = nullptr;
 };
 
 struct EngineReq {
@@ -124,6 +129,7 @@ struct EngineReq {
   size_t off = 0, bytes = 0;
   int slot = -1;
   int32_t status = RIFT2_OK;
+  int32_t batch = 1;  // requests admitted together with this one
 };
 
 }  // namespace rift2
@@ -143,6 +149,7 @@ struct rift2_engine {
   std::deque<rift2::EngineReq> inflight;
   std::deque<rift2_completion> finished;  // failed at admission, reported by the next poll
   hipEvent_t epoch = nullptr;
+  int batch = 4;  // requests whose filter banks share launches (1: none)
 };
 
 namespace rift2 {
@@ -152,52 +159,77 @@ inline int engine_keypoints(const rift2_request& r) {
   return (int)std::floor(2e-3 * (double)r.H * (double)r.W);
 }
 
-// Enqueues one admitted request on its slot's streams.
-inline int32_t engine_launch(rift2_engine* e, EngineReq& q) {
-  const EngineSlot& s = e->slots[q.slot];
+// Enqueues an admitted group of same-shape requests: their filter banks as
+// one batch on the first request's stream, then each request's detection,
+// description and matching on its own slot's streams.
+inline int32_t engine_launch(rift2_engine* e, EngineReq* const* g, int n) {
+  const EngineReq& q0 = *g[0];
   ReqLayout L;
-  req_layout(q.H, q.W, q.K, &e->pc, &e->det, &e->dp, &e->mp, &L);
-  char* base = e->arena + q.off;
+  req_layout(q0.H, q0.W, q0.K, &e->pc, &e->det, &e->dp, &e->mp, &L);
   rift2_detect_params det = e->det;
-  det.max_keypoints = q.K;
-  // the caller's inputs may still be in flight on its own stream
-  if (q.req.ready && hipStreamWaitEvent(s.sa, (hipEvent_t)q.req.ready, 0) != hipSuccess) return RIFT2_ERR_DEVICE;
-  if (hipEventRecord(s.admit, s.sa) != hipSuccess) return RIFT2_ERR_DEVICE;
-  // image B's stages start after the admission mark too
-  if (hipStreamWaitEvent(s.sb, s.admit, 0) != hipSuccess) return RIFT2_ERR_DEVICE;
-  const void* imgs[2] = {q.req.img_a, q.req.img_b};
-  hipStream_t st[2] = {s.sa, s.sb};
-  for (int i = 0; i < 2; ++i) {
-    const ReqLayout::Img& m = L.img[i];
-    rift2_status r = rift2_filter_mim(imgs[i], q.req.dtype, q.H, q.W, q.W, &e->pc, (uint8_t*)(base + m.mim),
-                                      (float*)(base + m.mmax), nullptr, nullptr, base + m.ws_filter, L.b_filter,
-                                      st[i]);
-    if (r == RIFT2_OK)
-      r = rift2_detect((const float*)(base + m.mmax), q.H, q.W, &det, (rift2_keypoint*)(base + m.kpts),
-                       (int32_t*)(base + m.nk), base + m.ws_detect, L.b_detect, st[i]);
-    if (r == RIFT2_OK)
-      r = rift2_describe((const uint8_t*)(base + m.mim), q.H, q.W, (const rift2_keypoint*)(base + m.kpts),
-                         (const int32_t*)(base + m.nk), q.K, &e->dp, (uint16_t*)(base + m.desc),
-                         (float*)(base + m.inv), (int32_t*)(base + m.dkp), 2 * q.K, (int32_t*)(base + m.nd),
-                         base + m.ws_desc, L.b_desc, st[i]);
-    if (r != RIFT2_OK) return r;
+  det.max_keypoints = q0.K;
+  const EngineSlot& s0 = e->slots[q0.slot];
+  rift2_filter_job jobs[RIFT2_MAX_FILTER_BATCH];
+  for (int i = 0; i < n; ++i) {
+    const EngineReq& q = *g[i];
+    // the caller's inputs may still be in flight on its own stream
+    if (q.req.ready && hipStreamWaitEvent(s0.sa, (hipEvent_t)q.req.ready, 0) != hipSuccess) return RIFT2_ERR_DEVICE;
+    char* base = e->arena + q.off;
+    const void* imgs[2] = {q.req.img_a, q.req.img_b};
+    for (int k = 0; k < 2; ++k) {
+      const ReqLayout::Img& m = L.img[k];
+      jobs[2 * i + k] = rift2_filter_job{imgs[k], (uint8_t*)(base + m.mim), (float*)(base + m.mmax), nullptr, nullptr,
+                                         base + m.ws_filter, L.b_filter};
+    }
   }
-  if (hipEventRecord(s.b_done, s.sb) != hipSuccess) return RIFT2_ERR_DEVICE;
-  if (hipStreamWaitEvent(s.sa, s.b_done, 0) != hipSuccess) return RIFT2_ERR_DEVICE;
-  const ReqLayout::Img& a = L.img[0];
-  const ReqLayout::Img& b = L.img[1];
-  rift2_status r = rift2_match((const uint16_t*)(base + a.desc), (const float*)(base + a.inv),
-                               (const int32_t*)(base + a.dkp), (const int32_t*)(base + a.nd), 2 * q.K,
-                               (const uint16_t*)(base + b.desc), (const float*)(base + b.inv),
-                               (const int32_t*)(base + b.dkp), (const int32_t*)(base + b.nd), 2 * q.K, L.D, &e->mp,
-                               q.req.out, q.req.n_out, base + L.ws_match, L.b_match, s.sa);
+  for (int i = 0; i < n; ++i)
+    if (hipEventRecord(e->slots[g[i]->slot].admit, s0.sa) != hipSuccess) return RIFT2_ERR_DEVICE;
+  rift2_status r = rift2_filter_mim_batch(2 * n, jobs, q0.req.dtype, q0.H, q0.W, q0.W, &e->pc, s0.sa);
   if (r != RIFT2_OK) return r;
-  if (hipEventRecord(s.done, s.sa) != hipSuccess) return RIFT2_ERR_DEVICE;
+  if (hipEventRecord(s0.filt, s0.sa) != hipSuccess) return RIFT2_ERR_DEVICE;
+  for (int i = 0; i < n; ++i) {
+    const EngineReq& q = *g[i];
+    const EngineSlot& s = e->slots[q.slot];
+    if ((i > 0 && hipStreamWaitEvent(s.sa, s0.filt, 0) != hipSuccess) ||
+        hipStreamWaitEvent(s.sb, s0.filt, 0) != hipSuccess)
+      return RIFT2_ERR_DEVICE;
+    char* base = e->arena + q.off;
+    hipStream_t st[2] = {s.sa, s.sb};
+    for (int k = 0; k < 2; ++k) {
+      const ReqLayout::Img& m = L.img[k];
+      r = rift2_detect((const float*)(base + m.mmax), q.H, q.W, &det, (rift2_keypoint*)(base + m.kpts),
+                       (int32_t*)(base + m.nk), base + m.ws_detect, L.b_detect, st[k]);
+      if (r == RIFT2_OK)
+        r = rift2_describe((const uint8_t*)(base + m.mim), q.H, q.W, (const rift2_keypoint*)(base + m.kpts),
+                           (const int32_t*)(base + m.nk), q.K, &e->dp, (uint16_t*)(base + m.desc),
+                           (float*)(base + m.inv), (int32_t*)(base + m.dkp), 2 * q.K, (int32_t*)(base + m.nd),
+                           base + m.ws_desc, L.b_desc, st[k]);
+      if (r != RIFT2_OK) return r;
+    }
+    if (hipEventRecord(s.b_done, s.sb) != hipSuccess) return RIFT2_ERR_DEVICE;
+    if (hipStreamWaitEvent(s.sa, s.b_done, 0) != hipSuccess) return RIFT2_ERR_DEVICE;
+    const ReqLayout::Img& a = L.img[0];
+    const ReqLayout::Img& b = L.img[1];
+    r = rift2_match((const uint16_t*)(base + a.desc), (const float*)(base + a.inv), (const int32_t*)(base + a.dkp),
+                    (const int32_t*)(base + a.nd), 2 * q.K, (const uint16_t*)(base + b.desc),
+                    (const float*)(base + b.inv), (const int32_t*)(base + b.dkp), (const int32_t*)(base + b.nd),
+                    2 * q.K, L.D, &e->mp, q.req.out, q.req.n_out, base + L.ws_match, L.b_match, s.sa);
+    if (r != RIFT2_OK) return r;
+    if (hipEventRecord(s.done, s.sa) != hipSuccess) return RIFT2_ERR_DEVICE;
+  }
   return RIFT2_OK;
 }
 
+inline bool engine_same_shape(const EngineReq& a, const EngineReq& b) {
+  return a.H == b.H && a.W == b.W && a.K == b.K && a.req.dtype == b.req.dtype;
+}
+
 // Admits queued requests in arrival order while a slot and arena space are
-// free; a request larger than the whole arena fails at once.
+// free; with each admitted request go the queued requests of its shape that
+// also fit (up to e->batch, looking at most kLookahead entries ahead).  A
+// request larger than the whole arena fails at once.
+constexpr int kLookahead = 64;
+
 inline void engine_pump(rift2_engine* e) {
   while (!e->pending.empty() && !e->free_slots.empty()) {
     EngineReq& q = e->pending.front();
@@ -216,24 +248,47 @@ inline void engine_pump(rift2_engine* e) {
     q.bytes = L.total;
     q.slot = e->free_slots.back();
     e->free_slots.pop_back();
-    q.status = engine_launch(e, q);
-    if (q.status != RIFT2_OK) {
-      // part of the request may be enqueued: let it drain before the memory
-      // and the streams are reused, then report the failure
-      const EngineSlot& s = e->slots[q.slot];
-      (void)hipStreamSynchronize(s.sa);
-      (void)hipStreamSynchronize(s.sb);
-      e->alloc.release(q.off, q.bytes);
-      e->free_slots.push_back(q.slot);
-      rift2_completion c{};
-      c.id = q.req.id;
-      c.status = q.status;
-      e->finished.push_back(c);
-      e->pending.pop_front();
-      continue;
+    std::vector<size_t> members{0};
+    const int cap = std::max(1, std::min(e->batch, RIFT2_MAX_FILTER_BATCH / 2));
+    for (size_t i = 1; i < e->pending.size() && (int)i <= kLookahead && (int)members.size() < cap &&
+                       !e->free_slots.empty();
+         ++i) {
+      EngineReq& o = e->pending[i];
+      if (!engine_same_shape(o, q) || !e->alloc.alloc(L.total, &off)) continue;
+      o.off = off;
+      o.bytes = L.total;
+      o.slot = e->free_slots.back();
+      e->free_slots.pop_back();
+      members.push_back(i);
     }
-    e->inflight.push_back(q);
-    e->pending.pop_front();
+    EngineReq* group[RIFT2_MAX_FILTER_BATCH];
+    for (size_t k = 0; k < members.size(); ++k) {
+      group[k] = &e->pending[members[k]];
+      group[k]->batch = (int32_t)members.size();
+    }
+    const int32_t status = engine_launch(e, group, (int)members.size());
+    if (status != RIFT2_OK) {
+      // part of the group may be enqueued: let it drain before the memory
+      // and the streams are reused, then report the failure
+      for (size_t k = 0; k < members.size(); ++k) {
+        const EngineSlot& s = e->slots[group[k]->slot];
+        (void)hipStreamSynchronize(s.sa);
+        (void)hipStreamSynchronize(s.sb);
+      }
+      for (size_t k = 0; k < members.size(); ++k) {
+        e->alloc.release(group[k]->off, group[k]->bytes);
+        e->free_slots.push_back(group[k]->slot);
+        rift2_completion c{};
+        c.id = group[k]->req.id;
+        c.status = status;
+        c.batch = group[k]->batch;
+        e->finished.push_back(c);
+      }
+    } else {
+      for (size_t k = 0; k < members.size(); ++k) e->inflight.push_back(*group[k]);
+    }
+    // drop the group's entries from the queue (later indices first)
+    for (size_t k = members.size(); k-- > 0;) e->pending.erase(e->pending.begin() + (std::ptrdiff_t)members[k]);
   }
 }
 

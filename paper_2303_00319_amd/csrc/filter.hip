@@ -55,12 +55,38 @@ struct PCConsts {
   float cos_o[kMaxOrient], sin_o[kMaxOrient];
 };
 
+// Batched launches: the images of one filter-bank call (same size and bank)
+// share every kernel launch, blockIdx.z picking the image.  Each image brings
+// its input, its workspace regions and its outputs.
+constexpr int kMaxFilterBatch = 8;
+struct FilterImage {
+  const void* img;
+  float2* rrow;
+  float2* yplanes;
+  float* a0;
+  uint32_t* cand;
+  uint32_t* zero;
+  float* t32;
+  double* t64;
+  float* ostat;
+  float2* spc;
+  uint8_t* mim;
+  float* mmax;
+  float* mmin;
+  float* amp;
+};
+struct FilterBatch {
+  FilterImage im[kMaxFilterBatch];
+};
+
 // ---------------------------------------------------------------- forward rows
 
 template <int W, int P, typename Tin>
-__global__ void __launch_bounds__(256) k_fwd_rows(const Tin* __restrict__ img, int64_t pitch, int H,
-                                                  float2* __restrict__ rrow, uint32_t* __restrict__ zero,
-                                                  int n_zero) {
+__global__ void __launch_bounds__(256) k_fwd_rows(FilterBatch B, int64_t pitch, int H, int n_zero) {
+  const FilterImage& I = B.im[blockIdx.z];
+  const Tin* __restrict__ img = (const Tin*)I.img;
+  float2* __restrict__ rrow = I.rrow;
+  uint32_t* __restrict__ zero = I.zero;
   using PL = FftPlan<W, P>;
   constexpr int T = PL::T;
   constexpr int LINES = 256 / T;
@@ -117,8 +143,9 @@ __device__ __forceinline__ float ang_lowpass(float lr, float th, bool dead, int 
 // 64/C rows x C contiguous points.  Column lines in LDS are 4 points apart
 // modulo 32, which measured fastest for this interleaving.
 template <int H, int P, int C>
-__global__ void __launch_bounds__(C * (H / P)) k_pass_a(const float2* __restrict__ rrow, FilterConsts fc,
-                                                      float2* __restrict__ y_out) {
+__global__ void __launch_bounds__(C * (H / P)) k_pass_a(FilterBatch B, FilterConsts fc) {
+  const float2* __restrict__ rrow = B.im[blockIdx.z].rrow;
+  float2* __restrict__ y_out = B.im[blockIdx.z].yplanes;
   using PL = FftPlan<H, P>;
   constexpr int T = PL::T;
   constexpr int L = 64 / C;
@@ -203,13 +230,19 @@ struct NoiseWs {
   uint32_t* cand;   // [N_o][HW] candidate bit patterns
 };
 
-// Where the row pass leaves the threshold and the two middle order
-// statistics (diagnostics).
-struct NoiseOut {
-  float* t32;
-  double* t64;
-  float* ostat;
-};
+// The selection's histograms, state and counters live in the image's
+// zeroed region, in this order; the candidate lists in its own region.
+__host__ __device__ __forceinline__ NoiseWs noise_ws(const FilterImage& I, int n_orient, int regions) {
+  NoiseWs w;
+  w.hist1 = I.zero;
+  w.hist2 = w.hist1 + n_orient * kHist1;
+  w.hist3 = w.hist2 + n_orient * 2 * kHist2;
+  w.state = w.hist3 + n_orient * 2 * kHist3;
+  w.cnt = w.state + 8 * n_orient;
+  w.regions = regions;
+  w.cand = I.cand;
+  return w;
+}
 
 // Ranks of the two middle order statistics.
 __device__ __forceinline__ uint32_t noise_rank(int hw, int q) { return (uint32_t)(hw / 2 - 1 + q); }
@@ -228,8 +261,11 @@ __device__ __forceinline__ double noise_threshold(float v0, float v1, const Nois
 // Block = LINES rows of one orientation.  A0 = |EO_{0,o}| written as float,
 // level-1 histogram of its bit pattern (bits >> 19) merged into hist1[o].
 template <int W, int P>
-__global__ void __launch_bounds__(256) k_noise_pre(float2* __restrict__ y_in, int H, int n_scales,
-                                                   float* __restrict__ a0, NoiseWs ws) {
+__global__ void __launch_bounds__(256) k_noise_pre(FilterBatch B, int H, int n_scales, int n_orient, int regions) {
+  const FilterImage& I = B.im[blockIdx.z];
+  float2* __restrict__ y_in = I.yplanes;
+  float* __restrict__ a0 = I.a0;
+  const NoiseWs ws = noise_ws(I, n_orient, regions);
   using PL = FftPlan<W, P>;
   constexpr int T = PL::T;
   constexpr int LINES = 256 / T;
@@ -280,7 +316,10 @@ __device__ __forceinline__ void block_append(bool take, uint32_t value, uint32_t
 // Level 2: every block copies the values of the two level-1 bins from its
 // chunk of A0 into its own region of the candidate list (region b = chunk
 // b, so it cannot overflow) and histograms their next 10 bits.
-__global__ void __launch_bounds__(256) k_noise_sel1(const float* __restrict__ a0, int hw, NoiseWs ws) {
+__global__ void __launch_bounds__(256) k_noise_sel1(FilterBatch B, int hw, int n_orient, int regions) {
+  const FilterImage& I = B.im[blockIdx.z];
+  const float* __restrict__ a0 = I.a0;
+  const NoiseWs ws = noise_ws(I, n_orient, regions);
   __shared__ uint32_t h2[2][kHist2];
   __shared__ uint32_t s_count;
   __shared__ uint32_t scratch[4];
@@ -334,7 +373,8 @@ __global__ void __launch_bounds__(256) k_noise_sel1(const float* __restrict__ a0
 
 // Level 3: one block per candidate region histograms the last 9 bits of the
 // candidates that share both upper levels of a rank.
-__global__ void __launch_bounds__(256) k_noise_sel2(int hw, NoiseWs ws) {
+__global__ void __launch_bounds__(256) k_noise_sel2(FilterBatch B, int hw, int n_orient, int regions) {
+  const NoiseWs ws = noise_ws(B.im[blockIdx.z], n_orient, regions);
   __shared__ uint32_t h3[2][kHist3];
   __shared__ uint32_t scratch[4];
   __shared__ int s_bin[2];
@@ -391,7 +431,10 @@ __global__ void __launch_bounds__(256) k_noise_sel2(int hw, NoiseWs ws) {
 // One block per orientation: the last selection level, the two middle order
 // statistics (kept for diagnostics) and the threshold T_o (FP64; FP32 copy
 // for the row pass).
-__global__ void __launch_bounds__(256) k_noise_threshold(int hw, NoiseWs ws, NoiseConsts nc, NoiseOut out) {
+__global__ void __launch_bounds__(256) k_noise_threshold(FilterBatch B, int hw, int n_orient, int regions,
+                                                         NoiseConsts nc) {
+  const FilterImage& I = B.im[blockIdx.z];
+  const NoiseWs ws = noise_ws(I, n_orient, regions);
   __shared__ uint32_t scratch[4];
   __shared__ int s_bin[2];
   __shared__ uint32_t s_below[2];
@@ -406,10 +449,10 @@ __global__ void __launch_bounds__(256) k_noise_threshold(int hw, NoiseWs ws, Noi
   }
   if (threadIdx.x == 0) {
     const double tt = noise_threshold(vals[0], vals[1], nc);
-    out.ostat[2 * o] = vals[0];
-    out.ostat[2 * o + 1] = vals[1];
-    out.t32[o] = (float)tt;
-    out.t64[o] = tt;
+    I.ostat[2 * o] = vals[0];
+    I.ostat[2 * o + 1] = vals[1];
+    I.t32[o] = (float)tt;
+    I.t64[o] = tt;
   }
 }
 
@@ -440,9 +483,12 @@ __global__ void __launch_bounds__(256) k_rows_inverse(const float2* __restrict__
 // pixel's (A_o, PC_o) pair goes to `spc` (orientation-major) for
 // k_pass_b_reduce.
 template <int W, int P, int NS>
-__global__ void __launch_bounds__(W / P) k_pass_b_orient(const float2* __restrict__ y_in, int H, PCConsts pcc,
-                                                         const float* __restrict__ t_o, float2* __restrict__ spc,
-                                                         float* __restrict__ amp) {
+__global__ void __launch_bounds__(W / P) k_pass_b_orient(FilterBatch B, int H, PCConsts pcc) {
+  const FilterImage& I = B.im[blockIdx.z];
+  const float2* __restrict__ y_in = I.yplanes;
+  const float* __restrict__ t_o = I.t32;
+  float2* __restrict__ spc = I.spc;
+  float* __restrict__ amp = I.amp;
   constexpr int T = W / P;
   // scales past the first are transformed two at a time (shared exchanges)
   // where the second LDS line leaves the occupancy alone; a row team of one
@@ -509,9 +555,12 @@ __global__ void __launch_bounds__(W / P) k_pass_b_orient(const float2* __restric
 // Per pixel over orientations (ascending): MIM = first argmax of A_o,
 // moments of PC_o.  Four pixels per thread, 16-byte accesses.
 template <int NO>
-__global__ void __launch_bounds__(256) k_pass_b_reduce(const float2* __restrict__ spc, int hw, PCConsts pcc,
-                                                       uint8_t* __restrict__ mim, float* __restrict__ mmax,
-                                                       float* __restrict__ mmin) {
+__global__ void __launch_bounds__(256) k_pass_b_reduce(FilterBatch B, int hw, PCConsts pcc) {
+  const FilterImage& I = B.im[blockIdx.z];
+  const float2* __restrict__ spc = I.spc;
+  uint8_t* __restrict__ mim = I.mim;
+  float* __restrict__ mmax = I.mmax;
+  float* __restrict__ mmin = I.mmin;
   const int i = 4 * (blockIdx.x * 256 + threadIdx.x);
   if (i >= hw) return;  // hw is a multiple of 4
   float best[4], ma[4], mb[4], mc[4];

@@ -283,3 +283,22 @@ def test_detect_noalloc_validates_on_the_host():
         pass
     # no device at all: nothing has been initialised
     assert lib.rift2_detect_noalloc(fake, 2048, 2048, ctypes.byref(det), fake, fake, null) == _l.ERR_NOT_INITIALIZED
+
+
+def test_filter_batch_validates_on_the_host():
+    _l, lib = _lib()
+    pc = _l.PCParams()
+    lib.rift2_default_params(ctypes.byref(pc), None, None, None)
+    jobs = (_l.FilterJob * 9)()
+    fake = 0x1000
+    for j in jobs:
+        j.img, j.mim, j.max_moment, j.workspace, j.workspace_bytes = fake, fake, fake, fake, 1 << 40
+    null = ctypes.c_void_p(0)
+    assert lib.rift2_filter_mim_batch(0, jobs, 0, 256, 256, 256, ctypes.byref(pc), null) == _l.ERR_INVALID_ARG
+    assert lib.rift2_filter_mim_batch(9, jobs, 0, 256, 256, 256, ctypes.byref(pc), null) == _l.ERR_INVALID_ARG
+    jobs[1].mim = 0
+    assert lib.rift2_filter_mim_batch(2, jobs, 0, 256, 256, 256, ctypes.byref(pc), null) == _l.ERR_INVALID_ARG
+    jobs[1].mim = fake
+    jobs[1].workspace_bytes = 16
+    assert lib.rift2_filter_mim_batch(2, jobs, 0, 256, 256, 256, ctypes.byref(pc), null) == _l.ERR_WORKSPACE
+    assert lib.rift2_filter_mim_batch(2, jobs, 0, 250, 256, 256, ctypes.byref(pc), null) == _l.ERR_UNSUPPORTED

@@ -170,3 +170,29 @@ def test_pipelined_steps_equal_single_pairs(use_graph):
             pp.step(k, *pairs[k % n])
         _same(refs[(k - 1) % n], _snapshot(pp.matched_set(k)), f"step {k} (pair {(k - 1) % n})")
         del junk
+
+
+def test_batched_filter_pipeline_equals_two_streams():
+    """Both images' filter banks in shared launches (PairPipeline(batched=True)): eager and captured
+    replays equal the two-stream pipeline's keypoints, descriptor rows and matches."""
+    r2, dev = _gpu()
+    a, b = _translated_pair(1)
+    ta, tb = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+    pc, det, dp, mp = r2.defaults()
+    det.max_keypoints = 400
+    mp.precision = r2.PREC_BF16
+    ref = r2.PairPipeline(256, 256, pc, det, dp, mp)
+    ref.run(ta, tb)
+    want = _snapshot(ref)
+    assert len(want["matches"]) > 20
+    pipe = r2.PairPipeline(256, 256, pc, det, dp, mp, batched=True)
+    pipe.run(ta, tb)
+    _same(_snapshot(pipe), want, "batched eager")
+    pipe.run_serial(ta, tb)
+    _same(_snapshot(pipe), want, "batched serial")
+    g = pipe.capture(ta, tb)
+    for rep in range(3):
+        ref.run(tb, ta)  # other work between the replays
+        torch.cuda.synchronize()
+        g.replay()
+        _same(_snapshot(pipe), want, f"batched replay {rep}")

@@ -197,6 +197,31 @@ def _check_detect(r2, dev, m32, k, tag):
     return kp, n
 
 
+def test_filter_batch_equals_single_calls():
+    """rift2_filter_mim_batch: every image of a batch gets exactly the outputs of its own call."""
+    r2, dev = _gpu()
+    pc = _pcparams(r2)
+    rng = np.random.default_rng(11)
+    for shape, n, dt in (((256, 256), 3, np.uint8), ((768, 768), 2, np.uint8), ((512, 256), 2, np.float32),
+                         ((1024, 1024), 2, np.uint8)):
+        print(f"[filter batch] {n} x {shape} {np.dtype(dt).name}", flush=True)
+        imgs = [torch.from_numpy((rng.random(shape) * 255).astype(dt)).to(dev) for _ in range(n)]
+        outs, singles = [], []
+        for im in imgs:
+            h, w = shape
+            o = (torch.empty((h, w), dtype=torch.uint8, device=dev), torch.empty((h, w), dtype=torch.float32, device=dev),
+                 torch.empty((h, w), dtype=torch.float32, device=dev),
+                 torch.empty((pc.n_orient, h, w), dtype=torch.float32, device=dev),
+                 torch.empty(r2.filter_workspace_bytes(h, w, pc), dtype=torch.uint8, device=dev))
+            outs.append(o)
+            singles.append(r2.filter_mim(im, pc, want_min=True, want_amp=True))
+        r2.filter_mim_batch_into(imgs, pc, outs)
+        torch.cuda.synchronize()
+        for o, ref in zip(outs, singles):
+            assert torch.equal(o[0], ref["mim"]) and torch.equal(o[1], ref["M"]) and torch.equal(o[2], ref["m"])
+            assert torch.equal(o[3], ref["amp"])
+
+
 def test_detect_bitexact_on_oracle_moment():
     r2, dev = _gpu()
     a, b, _ = make_pair(0, 0)

@@ -71,8 +71,19 @@ def test_same_alone_and_in_the_mix():
     # the mix really overlapped: some request was admitted before another finished
     spans = sorted((d["admit_ms"], d["done_ms"]) for d in done)
     overlap = sum(1 for (a0, d0), (a1, _) in zip(spans, spans[1:]) if a1 < d0)
-    print(f"[serving] overlapping admissions: {overlap}", flush=True)
-    assert overlap > 0
+    # and queued same-size requests were admitted together (shared filter launches)
+    grouped = sum(1 for d in done if d["batch"] > 1)
+    print(f"[serving] overlapping admissions: {overlap}, requests admitted in a group: {grouped}", flush=True)
+    assert overlap > 0 and grouped > 0
+    eng.close()
+    # the same mix with every request admitted on its own gives the same results
+    eng = _engine(r2, 4 << 30, 6)
+    eng.set_batch(1)
+    for rid, n, a, b in reqs:
+        eng.submit(rid, a, b)
+    for d in eng.drain():
+        assert d["batch"] == 1
+        assert np.array_equal(_result(d), alone[d["id"]]), f"request {d['id']} differs unbatched"
 
 
 def test_admission_waits_for_memory_and_rejects_oversize():
