@@ -763,7 +763,8 @@ def main():
         },
         "roofline": roof,
         "mfma": mfma,
-        "stages_ms": {f: {k: round(v["ms_avg"], 5) for k, v in stages[f].items() if k != "_rows"} for f in forms},
+        "stages_ms": {f: {k: round(v["ms_avg"], 5) for k, v in stages[f].items() if k != "_rows" and v["launches"]}
+                      for f in forms},
         "cpu_baseline": cpu,
         "outliers": outliers,
         "serving": serving,
@@ -794,7 +795,8 @@ def main():
                 "pairs_per_s": round(t["pairs_per_s"], 2), "ms_per_step": round(t["ms_per_step"], 4),
                 "p50_ms": round(t["p50_ms"], 4), "p99_ms": round(t["p99_ms"], 4),
                 "descriptor_rows": t["last_pair"]["descriptor_rows"], "matches": t["last_pair"]["matches"],
-                "stages_ms": {k: round(v["ms_avg"], 5) for k, v in ring_stages[f].items() if k != "_rows"},
+                "stages_ms": {k: round(v["ms_avg"], 5) for k, v in ring_stages[f].items()
+                              if k != "_rows" and v["launches"]},
                 "rift2_speedup": round(base["pairs_per_s"] / t["pairs_per_s"], 3) if base else None,
             }
     if args.ransac > 0:

@@ -16,6 +16,8 @@
 //   k_pass_b_orient  per row and orientation: row IDFTs of the other scales;
 //                per-pixel amplitude sum and phase congruency
 //   k_pass_b_reduce  per pixel over orientations: MIM argmax and moments
+//   k_pass_b_fused   both of the above in one launch, for rows that one wave
+//                transforms (N_o = 6)
 #pragma once
 
 #include "fft.hpp"
@@ -549,6 +551,119 @@ __global__ void __launch_bounds__(W / P) k_pass_b_orient(FilterBatch B, int H, P
   if (amp) {
 #pragma unroll
     for (int m = 0; m < P; ++m) amp[(size_t)o * plane + rowo + t + T * m] = sa[m];
+  }
+}
+
+// The row pass with the orientation reduction fused in, for rows that one
+// wave transforms (W / P = 64).  One block per row: wave w computes
+// orientations w, w + NW, ... exactly as k_pass_b_orient does (its own LDS
+// line) and leaves (A_o, PC_o) in LDS instead of `spc`; after one block
+// barrier the block reduces each pixel over the orientations in ascending
+// order exactly as k_pass_b_reduce does, so the results are bit-identical to
+// the split form and the N_o x HW hand-off never reaches memory.  With two
+// orientations per wave a block holds 3 waves and about 75 KB of LDS at
+// W = 1024, so two blocks share a CU and one's tail overlaps the other's work.
+template <int W, int P, int NS, int NO, int G>
+__global__ void __launch_bounds__(64 * NO / G) k_pass_b_fused(FilterBatch B, int H, PCConsts pcc) {
+  static_assert(W / P == 64 && NO % G == 0, "one wave per row and orientation");
+  constexpr int T = 64;
+  constexpr int NW = NO / G;
+  const FilterImage& I = B.im[blockIdx.z];
+  const float2* __restrict__ y_in = I.yplanes;
+  __shared__ float2 line[NW][lds_line<W, T>()];
+  __shared__ __align__(16) float res_a[NO][W];
+  __shared__ __align__(16) float res_p[NO][W];
+  const int t = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const size_t plane = (size_t)H * W;
+  const size_t rowo = (size_t)blockIdx.x * W;
+  for (int j = 0; j < G; ++j) {
+    const int o = w + j * NW;
+    const float2* base = y_in + (size_t)(o * NS) * plane + rowo + t;
+    float2 zs[NS][P];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+#pragma unroll
+      for (int m = 0; m < P; ++m) zs[s][m] = base[(size_t)s * plane + T * m];
+    }
+#pragma unroll
+    for (int s = 1; s < NS; ++s) fft_line<+1, W, P, true>(zs[s], t, line[w]);
+    float sa[P], mx[P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) sa[m] = mx[m] = 0.0f;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        const float a = hw_sqrt(zs[s][m].x * zs[s][m].x + zs[s][m].y * zs[s][m].y);
+        sa[m] += a;
+        mx[m] = __uint_as_float(max(__float_as_uint(mx[m]), __float_as_uint(a)));
+      }
+    }
+    const float thr = I.t32[o];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      float2 z = zs[0][m];
+#pragma unroll
+      for (int s = 1; s < NS; ++s) z = cadd(z, zs[s][m]);
+      float si = 0.0f;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) si += fabsf(zs[s][m].y * z.x - zs[s][m].x * z.y);
+      const float z2 = z.x * z.x + z.y * z.y;
+      const float xe = hw_sqrt(z2) + pcc.eps;
+      const float en = (z2 - si) * hw_rcp(xe);
+      const float spread = (sa[m] * hw_rcp(mx[m] + pcc.eps) - 1.0f) * (1.0f / (float)(NS - 1));
+      const float wgt = hw_rcp(1.0f + __expf(pcc.g * (pcc.cutoff - spread)));
+      res_a[o][t + T * m] = sa[m];
+      res_p[o][t + T * m] = wgt * fmaxf(en - thr, 0.0f) * hw_rcp(sa[m] + pcc.eps);
+    }
+    if (I.amp) {
+#pragma unroll
+      for (int m = 0; m < P; ++m) I.amp[(size_t)o * plane + rowo + t + T * m] = sa[m];
+    }
+  }
+  __syncthreads();
+  for (int i = 4 * threadIdx.x; i < W; i += 4 * 64 * NW) {
+    float best[4], ma[4], mb[4], mc[4];
+    int idx[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      best[e] = -1.0f;
+      idx[e] = 0;
+      ma[e] = mb[e] = mc[e] = 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < NO; ++q) {
+      const float4 a4 = *(const float4*)&res_a[q][i];
+      const float4 p4 = *(const float4*)&res_p[q][i];
+      const float av[4] = {a4.x, a4.y, a4.z, a4.w};
+      const float pv[4] = {p4.x, p4.y, p4.z, p4.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (av[e] > best[e]) {
+          best[e] = av[e];
+          idx[e] = q;
+        }
+        const float pcc_ = pv[e] * pcc.cos_o[q], pcs_ = pv[e] * pcc.sin_o[q];
+        ma[e] += pcc_ * pcc_;
+        mb[e] += 2.0f * pcc_ * pcs_;
+        mc[e] += pcs_ * pcs_;
+      }
+    }
+    float4 mxv, mnv;
+    float* mxp = &mxv.x;
+    float* mnp = &mnv.x;
+    uint32_t packed = 0u;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float root = sqrtf(mb[e] * mb[e] + (ma[e] - mc[e]) * (ma[e] - mc[e]));
+      mxp[e] = 0.5f * (ma[e] + mc[e] + root);
+      mnp[e] = 0.5f * (ma[e] + mc[e] - root);
+      packed |= (uint32_t)idx[e] << (8 * e);
+    }
+    *(float4*)(I.mmax + rowo + i) = mxv;
+    if (I.mmin) *(float4*)(I.mmin + rowo + i) = mnv;
+    *(uint32_t*)(I.mim + rowo + i) = packed;
   }
 }
 
