@@ -209,9 +209,10 @@ rift2_status rift2_filter_mim(const void* img, int32_t dtype, int32_t H, int32_t
  * kernel of rift2_filter_mim covers all n images (1 <= n <=
  * RIFT2_MAX_FILTER_BATCH), so small images fill the device together instead
  * of one after another.  Each job is one image's rift2_filter_mim arguments
- * (same rules; its own workspace of rift2_filter_workspace_size bytes); the
- * results are those of n separate calls.  Errors as rift2_filter_mim, checked
- * for every job before anything is enqueued. */
+ * (same rules; its own workspace of rift2_filter_workspace_size bytes, which
+ * must not overlap another job's: RIFT2_ERR_INVALID_ARG); the results are
+ * those of n separate calls.  Errors as rift2_filter_mim, checked for every
+ * job before anything is enqueued. */
 #define RIFT2_MAX_FILTER_BATCH 8
 typedef struct {
   const void* img;

@@ -657,6 +657,12 @@ rift2_status filter_batch(int32_t n, const rift2_filter_job* jobs, int32_t dtype
   const FilterLayout L = filter_layout(H, W, pc);
   for (int i = 0; i < n; ++i)
     if (jobs[i].workspace_bytes < L.total) return RIFT2_ERR_WORKSPACE;
+  // the images of one launch write their workspaces concurrently
+  for (int i = 0; i < n; ++i)
+    for (int k = i + 1; k < n; ++k) {
+      const uintptr_t a = (uintptr_t)jobs[i].workspace, b = (uintptr_t)jobs[k].workspace;
+      if (a < b + L.total && b < a + L.total) return RIFT2_ERR_INVALID_ARG;
+    }
   if (!current_device_ready()) return RIFT2_ERR_NOT_INITIALIZED;
   hipStream_t st = (hipStream_t)stream;
   FilterBatch B;

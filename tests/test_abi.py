@@ -302,3 +302,19 @@ def test_filter_batch_validates_on_the_host():
     jobs[1].workspace_bytes = 16
     assert lib.rift2_filter_mim_batch(2, jobs, 0, 256, 256, 256, ctypes.byref(pc), null) == _l.ERR_WORKSPACE
     assert lib.rift2_filter_mim_batch(2, jobs, 0, 250, 256, 256, ctypes.byref(pc), null) == _l.ERR_UNSUPPORTED
+    # two jobs on one workspace (or overlapping ones) are refused before anything runs
+    jobs[1].workspace_bytes = 1 << 40
+    assert lib.rift2_filter_mim_batch(2, jobs, 0, 256, 256, 256, ctypes.byref(pc), null) == _l.ERR_INVALID_ARG
+    need = lib.rift2_filter_workspace_size(256, 256, ctypes.byref(pc))
+    jobs[1].workspace = fake + need - 256
+    assert lib.rift2_filter_mim_batch(2, jobs, 0, 256, 256, 256, ctypes.byref(pc), null) == _l.ERR_INVALID_ARG
+    try:
+        import torch
+
+        if torch.cuda.is_available():
+            return
+    except ImportError:
+        pass
+    # no device at all: disjoint workspaces pass the host checks and stop at the missing initialisation
+    jobs[1].workspace = fake + need
+    assert lib.rift2_filter_mim_batch(2, jobs, 0, 256, 256, 256, ctypes.byref(pc), null) == _l.ERR_NOT_INITIALIZED
