@@ -565,10 +565,18 @@ def serve_sweep(args, r2, torch, rates, requests, pool_per_size, saturation_requ
         arrive = np.cumsum(gaps) - gaps[0]
         eng = r2.Engine(int(args.budget_gib * (1 << 30)), max_inflight=inflight, pc=pc, det=det, dp=dp, mp=mp)
         eng.set_batch(batch)
-        # warm: one request of every size
+        # warm: two requests of every size on the idle engine.  submit queues a request and the next
+        # poll admits it and enqueues all of its launches, so the second request's submit + first
+        # poll is the host's admission and launch cost of one request
+        submit_s = []
         for j, n in enumerate(sizes):
-            eng.submit(-1 - j, *pool[(n, 0)], max_keypoints=kreq)
-        eng.drain()
+            for rep in range(2):
+                t0 = time.perf_counter()
+                eng.submit(-1 - 2 * j - rep, *pool[(n, 0)], max_keypoints=kreq)
+                got = eng.poll()
+                if rep:
+                    submit_s.append(time.perf_counter() - t0)
+                got += eng.drain()
         torch.cuda.synchronize()
         eng.close()
         eng = r2.Engine(int(args.budget_gib * (1 << 30)), max_inflight=inflight, pc=pc, det=det, dp=dp, mp=mp)
@@ -599,7 +607,7 @@ def serve_sweep(args, r2, torch, rates, requests, pool_per_size, saturation_requ
                "pairs_per_s": round(n_req / (span_ms / 1000.0), 2),
                "p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
                "gpu_ms_p50": round(percentile([d["gpu_ms"] for d in done], 50), 3), "failed": len(bad),
-               "matches": matches}
+               "matches": matches, "host_launch_us": round(1e6 * float(np.median(submit_s)), 1)}
         print(f"[serve] {json.dumps(res)}", file=sys.stderr, flush=True)
         results.append(res)
         eng.close()
