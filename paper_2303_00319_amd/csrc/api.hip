@@ -199,7 +199,7 @@ MatchLayout match_layout(int cap_a, int cap_b, int D, int precision, bool mutual
 }
 
 struct RansacLayout {
-  size_t xy, flags, key, counts, total;
+  size_t xy, flags, key, sums, counts, total;
   int n_flags;
 };
 
@@ -210,6 +210,7 @@ bool ransac_layout(int match_cap, int n_hyp, RansacLayout* L) {
   L->xy = c.take((size_t)match_cap * sizeof(int4));
   L->flags = c.take((size_t)L->n_flags * sizeof(int32_t));
   L->key = c.take(sizeof(unsigned long long));
+  L->sums = c.take((size_t)kRansacMaxRefine * 8 * sizeof(unsigned long long));
   L->counts = c.take((size_t)n_hyp * sizeof(int32_t));
   L->total = c.off;
   return true;
@@ -1024,7 +1025,7 @@ rift2_status rift2_ransac(const rift2_correspondence* matches, const int32_t* n_
                           size_t workspace_bytes, void* stream) {
   if (!matches || !n_matches_dev || !kpts_a || !kpts_b || !words || !rp || !inlier_mask || !result || !workspace)
     return RIFT2_ERR_INVALID_ARG;
-  if (kpt_cap_a < 1 || kpt_cap_b < 1 || n_hyp < 1 || rp->refine < 0 || rp->refine > 16 ||
+  if (kpt_cap_a < 1 || kpt_cap_b < 1 || n_hyp < 1 || rp->refine < 0 || rp->refine > kRansacMaxRefine ||
       !std::isfinite(rp->threshold) || !(rp->threshold > 0.0))
     return RIFT2_ERR_INVALID_ARG;
   if ((uintptr_t)words & 7u || (uintptr_t)result & 7u || (uintptr_t)workspace & 15u) return RIFT2_ERR_INVALID_ARG;
@@ -1037,18 +1038,27 @@ rift2_status rift2_ransac(const rift2_correspondence* matches, const int32_t* n_
   int32_t* flags = (int32_t*)(ws + L.flags);
   int32_t* cnt = counts ? counts : (int32_t*)(ws + L.counts);
   unsigned long long* key = (unsigned long long*)(ws + L.key);
+  unsigned long long* sums = (unsigned long long*)(ws + L.sums);
   const double tau2 = rp->threshold * rp->threshold;
+  const int refine = (int)rp->refine;
   (void)hipGetLastError();
   ProfScope ps(11, st);
+  // the gather's first block clears the refit sums: it has at least 8 * refine <= 128 threads
   hipLaunchKernelGGL(k_ransac_gather, dim3(L.n_flags), dim3(256), 0, st, (const RansacMatch*)matches, n_matches_dev,
                      match_cap, (const RansacKp*)kpts_a, kpt_cap_a, (const RansacKp*)kpts_b, kpt_cap_b, xy, flags,
-                     key);
+                     key, sums, 8 * refine);
   hipLaunchKernelGGL(k_ransac_score, dim3((n_hyp + kRansacHypPerBlock - 1) / kRansacHypPerBlock), dim3(256), 0, st,
                      (const int4*)xy, n_matches_dev, match_cap, (const int32_t*)flags, L.n_flags,
                      (const uint2*)words, n_hyp, tau2, cnt, key);
+  const int refit_blocks = (match_cap + 256 * kRefitPerThread - 1) / (256 * kRefitPerThread);
+  for (int it = 0; it < refine; ++it)
+    hipLaunchKernelGGL(k_ransac_refit_sums, dim3(refit_blocks), dim3(256), 0, st, (const int4*)xy, n_matches_dev,
+                       match_cap, (const uint2*)words, (const unsigned long long*)key, tau2, (const int32_t*)flags,
+                       L.n_flags, sums, it);
   hipLaunchKernelGGL(k_ransac_refine, dim3(1), dim3(1024), 0, st, (const int4*)xy, n_matches_dev, match_cap,
-                     (const uint2*)words, (const unsigned long long*)key, tau2, (int)rp->refine,
-                     (const int32_t*)flags, L.n_flags, inlier_mask, (RansacResult*)result);
+                     (const uint2*)words, (const unsigned long long*)key, tau2, refine,
+                     (const unsigned long long*)sums, (const int32_t*)flags, L.n_flags, inlier_mask,
+                     (RansacResult*)result);
   return launch_status();
 }
 
@@ -1071,7 +1081,7 @@ rift2_status rift2_consensus(const double* model, const rift2_correspondence* ma
   ProfScope ps(11, st);
   hipLaunchKernelGGL(k_ransac_gather, dim3(L.n_flags), dim3(256), 0, st, (const RansacMatch*)matches, n_matches_dev,
                      match_cap, (const RansacKp*)kpts_a, kpt_cap_a, (const RansacKp*)kpts_b, kpt_cap_b, xy, flags,
-                     (unsigned long long*)nullptr);
+                     (unsigned long long*)nullptr, (unsigned long long*)nullptr, 0);
   hipLaunchKernelGGL(k_consensus, dim3(1), dim3(1024), 0, st, (const int4*)xy, n_matches_dev, match_cap,
                      (const int32_t*)flags, L.n_flags, model, threshold * threshold, mask, (ConsensusOut*)result);
   return launch_status();

@@ -11,11 +11,14 @@
 //   k_ransac_score   one block per group of hypotheses: the exact fit to the
 //                    hypothesis' two sampled matches, then its consensus
 //                    count over all matches (ballot + popcount per 64)
-//   k_ransac_refine  one block: the hypothesis with the largest count (lowest
-//                    index on ties, an atomic maximum of the scoring kernel),
-//                    then least-squares refits to the
-//                    consensus set from exact integer sums, the final
-//                    inlier mask and count
+//   k_ransac_refit_sums  one launch per least-squares refit: every block
+//                    takes the model so far (the hypothesis with the largest
+//                    count, lowest index on ties, then the earlier refits) and
+//                    adds its matches' exact integer normal-equation sums
+//                    into the refit's sums (atomic int64 adds: exact, so the
+//                    order does not matter)
+//   k_ransac_refine  one block: the final model from the hypothesis and the
+//                    refits' sums, the inlier mask and count
 //   k_consensus      one block: residuals of a given model, mask, count and
 //                    the sum of the inliers' squared residuals
 //
@@ -35,6 +38,8 @@ constexpr int kRansacMaxMatches = 1 << 17;
 constexpr int kRansacCoordLimit = 1 << 13;
 constexpr int kRansacMaxHyp = 1 << 20;
 constexpr int kRansacHypPerBlock = 4;
+constexpr int kRansacMaxRefine = 16;
+constexpr int kRefitPerThread = 4;  // matches per thread of a refit-sums block (loads issued together)
 
 struct RansacKp {  // layout of rift2_keypoint
   int x, y;
@@ -128,15 +133,18 @@ __device__ __forceinline__ int sample_index(uint32_t u, int n) {
 // grid = ceil(cap / 256).  Block z writes flags[z] = 1 when one of its
 // matches refers to a keypoint index outside [0, cap_k) or to a coordinate
 // outside [0, kRansacCoordLimit), else 0 (every block writes its flag, so
-// nothing needs clearing between calls).  Also clears *best_key (if given).
+// nothing needs clearing between calls).  Also clears *best_key and the
+// n_refit_sums refit sums (if given).
 __global__ void __launch_bounds__(256) k_ransac_gather(const RansacMatch* __restrict__ m, const int32_t* __restrict__ n_dev,
                                                        int cap, const RansacKp* __restrict__ ka, int cap_ka,
                                                        const RansacKp* __restrict__ kb, int cap_kb,
                                                        int4* __restrict__ xy, int32_t* __restrict__ flags,
-                                                       unsigned long long* __restrict__ best_key) {
+                                                       unsigned long long* __restrict__ best_key,
+                                                       unsigned long long* __restrict__ refit_sums, int n_refit_sums) {
   const int n = min(*n_dev, cap);
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i == 0 && best_key) *best_key = 0ull;  // the scoring kernel that follows takes maxima into it
+  if (refit_sums && i < n_refit_sums) refit_sums[i] = 0ull;  // the refit kernels add into them
   bool bad = false;
   if (i < n) {
     const RansacMatch c = m[i];
@@ -238,32 +246,6 @@ __global__ void __launch_bounds__(256) k_ransac_score(const int4* __restrict__ x
   }
 }
 
-// Block-wide int64 sums of the eight least-squares accumulators (1024
-// threads): a shuffle tree per wave, then eight threads add the 16 wave
-// totals.  Integer sums, so the order does not matter.
-__device__ __forceinline__ LsqSums block_sum_lsq(LsqSums s, long long* sh /* 16 x 8 + 8 */) {
-  long long v[8] = {s.n, s.sx, s.sy, s.su, s.sv, s.sxx_yy, s.sxu_yv, s.sxv_yu};
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
-  }
-  const int w = threadIdx.x >> 6;
-  __syncthreads();  // sh may still be read by a previous call
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) sh[w * 8 + k] = v[k];
-  }
-  __syncthreads();
-  if (threadIdx.x < 8) {
-    long long t = 0;
-    for (int q = 0; q < 16; ++q) t += sh[q * 8 + threadIdx.x];
-    sh[128 + threadIdx.x] = t;
-  }
-  __syncthreads();
-  return LsqSums{sh[128], sh[129], sh[130], sh[131], sh[132], sh[133], sh[134], sh[135]};
-}
-
 __device__ __forceinline__ int block_sum_int(int v, int* sh /* 16 */) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -275,57 +257,136 @@ __device__ __forceinline__ int block_sum_int(int v, int* sh /* 16 */) {
   return t;
 }
 
+// The model after the first `upto` least-squares refits: the exact fit to the
+// best hypothesis' sample, then each refit's fit to its sums (8 int64 per
+// refit), stopping at the first set without a unique fit.  *go: whether the
+// model came through all `upto` refits (so a further refit would run).
+// *best = the hypothesis index, -1 when there is none.
+__device__ __forceinline__ Sim refit_chain(const int4* __restrict__ xy, int n, const uint2* __restrict__ words,
+                                           unsigned long long key, const unsigned long long* __restrict__ sums,
+                                           int upto, int* best, bool* go) {
+  Sim m{0.0, 0.0, 0.0, 0.0};
+  *best = -1;
+  *go = false;
+  if (key == 0 || n < 2) return m;
+  const int h = (int)(~(uint32_t)(key & 0xffffffffull));
+  const uint2 w = words[h];
+  if (!sim_fit_pair(xy[sample_index(w.x, n)], xy[sample_index(w.y, n)], m)) return m;  // cannot happen: counted
+  *best = h;
+  *go = true;
+  for (int j = 0; j < upto; ++j) {
+    const unsigned long long* q = sums + 8 * j;
+    const LsqSums t{(long long)q[0], (long long)q[1], (long long)q[2], (long long)q[3],
+                    (long long)q[4], (long long)q[5], (long long)q[6], (long long)q[7]};
+    Sim f;
+    if (!sim_fit_lsq(t, f)) {
+      *go = false;
+      break;
+    }
+    m = f;
+  }
+  return m;
+}
+
+// Refit `it` (grid = ceil(cap / (256 kRefitPerThread)), block 256): the
+// normal-equation sums of the matches within the threshold of the model after
+// refits 0..it-1, added into sums[8 it .. 8 it + 8).  Nothing is added when
+// the match list is invalid or the chain stopped earlier.
+__global__ void __launch_bounds__(256) k_ransac_refit_sums(const int4* __restrict__ xy, const int32_t* __restrict__ n_dev,
+                                                           int cap, const uint2* __restrict__ words,
+                                                           const unsigned long long* __restrict__ best_key, double tau2,
+                                                           const int32_t* __restrict__ flags, int n_flags,
+                                                           unsigned long long* __restrict__ sums, int it) {
+#pragma clang fp contract(off)
+  __shared__ long long sh[4 * 8];
+  __shared__ double sh_m[4];
+  __shared__ int sh_go;
+  const int tid = threadIdx.x;
+  const int n = min(*n_dev, cap);
+  const int beg = blockIdx.x * 256 * kRefitPerThread;
+  if (beg >= n) return;  // uniform: no matches here
+  if (tid < 64) {
+    const bool invalid = wave_any_flag(flags, n_flags);
+    if (tid == 0) {
+      int best;
+      bool go;
+      const Sim m = refit_chain(xy, n, words, invalid ? 0ull : *best_key, sums, it, &best, &go);
+      sh_m[0] = m.a;
+      sh_m[1] = m.b;
+      sh_m[2] = m.tx;
+      sh_m[3] = m.ty;
+      sh_go = go ? 1 : 0;
+    }
+  }
+  __syncthreads();
+  if (!sh_go) return;  // uniform
+  const Sim m{sh_m[0], sh_m[1], sh_m[2], sh_m[3]};
+  LsqSums s{0, 0, 0, 0, 0, 0, 0, 0};
+  int4 p[kRefitPerThread];
+  const int4 zero = make_int4(0, 0, 0, 0);
+#pragma unroll
+  for (int r = 0; r < kRefitPerThread; ++r) {
+    const int i = beg + r * 256 + tid;
+    p[r] = i < n ? xy[i] : zero;
+  }
+#pragma unroll
+  for (int r = 0; r < kRefitPerThread; ++r) {
+    const int i = beg + r * 256 + tid;
+    if (i < n && sim_residual_sq(m, (double)p[r].x, (double)p[r].y, (double)p[r].z, (double)p[r].w) < tau2)
+      lsq_add(s, p[r]);
+  }
+  long long v[8] = {s.n, s.sx, s.sy, s.su, s.sv, s.sxx_yy, s.sxu_yv, s.sxv_yu};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+  }
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sh[(tid >> 6) * 8 + k] = v[k];
+  }
+  __syncthreads();
+  if (tid < 8) {
+    const long long t = sh[tid] + sh[8 + tid] + sh[16 + tid] + sh[24 + tid];
+    // two's-complement addition: the signed sums come out exact
+    if (t != 0) atomicAdd(sums + 8 * it + tid, (unsigned long long)t);
+  }
+}
+
 constexpr int kRefineBatch = 8;  // matches per thread whose loads are issued together
 
-// One block of 1024 threads.  Takes the best hypothesis from *best_key
+// One block of 1024 threads.  The model: the best hypothesis from *best_key
 // (count << 32 | ~h, the maximum over all hypotheses, so the largest count
-// and among equal counts the lowest index), refines it `refine` times by
-// least squares on its consensus set (stopping early when the set has no
-// unique fit), then writes the final mask over [0, cap) and the result.
+// and among equal counts the lowest index) refined by the `refine` refits
+// whose sums k_ransac_refit_sums left (stopping at the first set without a
+// unique fit); then the final mask over [0, cap) and the result.
 __global__ void __launch_bounds__(1024) k_ransac_refine(const int4* __restrict__ xy, const int32_t* __restrict__ n_dev,
                                                         int cap, const uint2* __restrict__ words,
                                                         const unsigned long long* __restrict__ best_key, double tau2,
-                                                        int refine, const int32_t* __restrict__ flags, int n_flags,
+                                                        int refine, const unsigned long long* __restrict__ sums,
+                                                        const int32_t* __restrict__ flags, int n_flags,
                                                         uint8_t* __restrict__ mask, RansacResult* __restrict__ out) {
 #pragma clang fp contract(off)
-  __shared__ long long sh_sum[16 * 8 + 8];
   __shared__ int sh_cnt[16];
+  __shared__ double sh_m[4];
+  __shared__ int sh_best;
   const int tid = threadIdx.x;
   const bool invalid = wave_any_flag(flags, n_flags);
   const int n = invalid ? 0 : min(*n_dev, cap);
-  const unsigned long long key = invalid ? 0ull : *best_key;
-
-  Sim m{0.0, 0.0, 0.0, 0.0};
-  int best = -1;
-  if (key != 0 && n >= 2) {
-    best = (int)(~(uint32_t)(key & 0xffffffffull));
-    const uint2 w = words[best];
-    if (!sim_fit_pair(xy[sample_index(w.x, n)], xy[sample_index(w.y, n)], m)) best = -1;  // cannot happen: counted
+  if (tid == 0) {
+    int b;
+    bool go;
+    const Sim f = refit_chain(xy, n, words, invalid ? 0ull : *best_key, sums, refine, &b, &go);
+    sh_m[0] = f.a;
+    sh_m[1] = f.b;
+    sh_m[2] = f.tx;
+    sh_m[3] = f.ty;
+    sh_best = b;
   }
+  __syncthreads();
+  const Sim m{sh_m[0], sh_m[1], sh_m[2], sh_m[3]};
+  const int best = sh_best;
   const int4 zero = make_int4(0, 0, 0, 0);
-  if (best >= 0) {
-    for (int it = 0; it < refine; ++it) {
-      LsqSums s{0, 0, 0, 0, 0, 0, 0, 0};
-      for (int b0 = 0; b0 < n; b0 += 1024 * kRefineBatch) {
-        int4 p[kRefineBatch];
-#pragma unroll
-        for (int r = 0; r < kRefineBatch; ++r) {
-          const int i = b0 + r * 1024 + tid;
-          p[r] = i < n ? xy[i] : zero;
-        }
-#pragma unroll
-        for (int r = 0; r < kRefineBatch; ++r) {
-          const int i = b0 + r * 1024 + tid;
-          if (i < n && sim_residual_sq(m, (double)p[r].x, (double)p[r].y, (double)p[r].z, (double)p[r].w) < tau2)
-            lsq_add(s, p[r]);
-        }
-      }
-      const LsqSums t = block_sum_lsq(s, sh_sum);
-      Sim f;
-      if (!sim_fit_lsq(t, f)) break;
-      m = f;
-    }
-  }
   int local = 0;
   for (int b0 = 0; b0 < cap; b0 += 1024 * kRefineBatch) {
     int4 p[kRefineBatch];
