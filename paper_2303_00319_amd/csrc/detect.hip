@@ -393,11 +393,20 @@ __global__ void __launch_bounds__(1024) k_det_select2(uint32_t* __restrict__ hdr
   const uint32_t ns = pre[kSelBlocks];
   uint64_t kth = 0;
   if (k > 0 && k < n) {
-    for (uint32_t i = threadIdx.x; i < ns; i += 1024) {
-      const uint64_t key = sel_key(sel, pre, region_size, i);
-      if ((key >> 48) == bin) {
-        const uint32_t pos = atomicAdd(&n_edge, 1u);
-        if (pos < kEdgeMax) edge[pos] = key;
+    // four keys per thread per round: their loads are in flight together
+    for (uint32_t i0 = 0; i0 < ns; i0 += 4 * 1024) {
+      uint64_t key[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t i = i0 + e * 1024 + threadIdx.x;
+        key[e] = i < ns ? sel_key(sel, pre, region_size, i) : 0ull;
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (i0 + e * 1024 + threadIdx.x < ns && (key[e] >> 48) == bin) {
+          const uint32_t pos = atomicAdd(&n_edge, 1u);
+          if (pos < kEdgeMax) edge[pos] = key[e];
+        }
       }
     }
     __syncthreads();
@@ -435,22 +444,25 @@ __global__ void __launch_bounds__(1024) k_det_select2(uint32_t* __restrict__ hdr
     }
     kth = prefix;
   }
-  for (uint32_t i0 = 0; i0 < ns; i0 += 1024) {
-    const uint32_t i = i0 + threadIdx.x;
-    uint64_t key = 0;
-    bool take = false;
-    if (i < ns) {
-      key = sel_key(sel, pre, region_size, i);
-      take = key >= kth;
+  for (uint32_t i0 = 0; i0 < ns; i0 += 4 * 1024) {
+    uint64_t key[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t i = i0 + e * 1024 + threadIdx.x;
+      key[e] = i < ns ? sel_key(sel, pre, region_size, i) : 0ull;
     }
-    const uint64_t mask = __ballot(take);
-    if (mask) {
-      const int lane = threadIdx.x & 63;
-      const int leader = __ffsll((unsigned long long)mask) - 1;
-      uint32_t base = 0;
-      if (lane == leader) base = atomicAdd(&s_final, (uint32_t)__popcll(mask));
-      base = __shfl(base, leader);
-      if (take) fin[base + __popcll(mask & ((1ull << lane) - 1ull))] = key;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const bool take = i0 + e * 1024 + threadIdx.x < ns && key[e] >= kth;
+      const uint64_t mask = __ballot(take);
+      if (mask) {
+        const int lane = threadIdx.x & 63;
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&s_final, (uint32_t)__popcll(mask));
+        base = __shfl(base, leader);
+        if (take) fin[base + __popcll(mask & ((1ull << lane) - 1ull))] = key[e];
+      }
     }
   }
   __syncthreads();
