@@ -80,6 +80,8 @@ def _assert_same(gpu, ref, n, cap):
     (5, 40, 600, 1000, 25.0, 0, 100),    # wide threshold: many partial consensus sets
     (6, 100, 157, 77, 1.0, 4, 1),        # threshold 1 px: the rounding of planted points decides
     (7, 1000, 9000, 2051, 3.0, 3, 300),  # ragged capacity, hypotheses not a multiple of 16
+    (8, 3000, 57000, 256, 3.0, 16, 7),   # the most refits, each over 59 blocks of refit sums
+    (9, 25, 20000, 300, 2.0, 5, 0),      # few inliers among many matches
 ])
 def test_ransac_bitexact_on_planted_sets(seed, n_in, n_out, n_hyp, thr, refine, extra_cap):
     r2, dev = _gpu()
