@@ -183,12 +183,10 @@ RIFT2_PLAN(2048, 16, 3, 16, 16, 8, 1, 1, 1)
 RIFT2_PLAN(4096, 16, 3, 16, 16, 16, 1, 1, 1)
 RIFT2_PLAN(768, 12, 5, 4, 4, 4, 4, 3, 1)
 RIFT2_PLAN(1536, 12, 6, 4, 4, 4, 4, 2, 3)
-RIFT2_PLAN(256, 8, 3, 8, 8, 4, 1, 1, 1)
 RIFT2_PLAN(256, 4, 4, 4, 4, 4, 4, 1, 1)
 RIFT2_PLAN(512, 8, 3, 8, 8, 8, 1, 1, 1)
 RIFT2_PLAN(1024, 8, 4, 8, 8, 8, 2, 1, 1)
 RIFT2_PLAN(2048, 8, 4, 8, 8, 8, 4, 1, 1)
-RIFT2_PLAN(4096, 8, 4, 8, 8, 8, 8, 1, 1)
 #undef RIFT2_PLAN
 
 // LDS lines hold interleaved complex values (one float2 per point).  The
