@@ -272,10 +272,11 @@ __global__ void __launch_bounds__(256) k_noise_pre(FilterBatch B, int H, int n_s
   constexpr int T = PL::T;
   constexpr int LINES = 256 / T;
   __shared__ float2 lines[LINES][lds_line<W, T>()];
-  __shared__ uint32_t hist[kHist1];
+  // the block histogram reuses the lines once every team has transformed its
+  // row, so the kernel's LDS is the lines alone (4 blocks per CU at 1024)
+  static_assert(sizeof(lines) >= kHist1 * sizeof(uint32_t), "histogram fits the lines");
+  uint32_t* hist = reinterpret_cast<uint32_t*>(&lines[0][0]);
   const int o = blockIdx.y;
-  for (int i = threadIdx.x; i < kHist1; i += 256) hist[i] = 0u;
-  __syncthreads();  // the cleared histogram is visible before any wave adds to it
   const int team = threadIdx.x / T, t = threadIdx.x % T;
   const int y = blockIdx.x * LINES + team;
   const size_t plane = (size_t)H * W;
@@ -287,13 +288,19 @@ __global__ void __launch_bounds__(256) k_noise_pre(FilterBatch B, int H, int n_s
   float* dst = a0 + (size_t)o * plane + (size_t)y * W;
   // the transformed row replaces its input: pass B takes EO_{0,o} as is
   float2* eo = src;
+  uint32_t key[P];
 #pragma unroll
   for (int m = 0; m < P; ++m) {
     eo[t + T * m] = v[m];
     const float a = hw_sqrt(v[m].x * v[m].x + v[m].y * v[m].y);
     dst[t + T * m] = a;
-    atomicAdd(&hist[min(__float_as_uint(a) >> (32 - kHistBits1 - 1), (uint32_t)(kHist1 - 1))], 1u);
+    key[m] = min(__float_as_uint(a) >> (32 - kHistBits1 - 1), (uint32_t)(kHist1 - 1));
   }
+  __syncthreads();  // every team is done with its line
+  for (int i = threadIdx.x; i < kHist1; i += 256) hist[i] = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < P; ++m) atomicAdd(&hist[key[m]], 1u);
   __syncthreads();
   uint32_t* gh = ws.hist1 + (size_t)o * kHist1;
   for (int i = threadIdx.x; i < kHist1; i += 256) {
