@@ -339,7 +339,7 @@ __global__ void __launch_bounds__(256) k_noise_sel1(FilterBatch B, int hw, int n
   if (threadIdx.x == 0) s_count = 0u;
   // level 1: the bins of both ranks in the histogram k_noise_pre completed
   const uint32_t* h1 = ws.hist1 + (size_t)o * kHist1;
-  for (int q = 0; q < 2; ++q) block_find_rank<kHist1, 256, false>(h1, noise_rank(hw, q), &s_bin[q], &s_below[q], scratch);
+  block_find_two_ranks<kHist1, 256>(h1, noise_rank(hw, 0), s_bin, s_below, scratch);
   const uint32_t b0 = (uint32_t)s_bin[0], b1 = (uint32_t)s_bin[1];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     uint32_t* st = ws.state + 8 * o;
@@ -393,8 +393,15 @@ __global__ void __launch_bounds__(256) k_noise_sel2(FilterBatch B, int hw, int n
   uint32_t* st = ws.state + 8 * o;
   // level 2: the sub-bins of both ranks inside their level-1 bins
   const uint32_t* h2 = ws.hist2 + (size_t)o * 2 * kHist2;
-  for (int q = 0; q < 2; ++q)
-    block_find_rank<kHist2, 256, false>(h2 + q * kHist2, noise_rank(hw, q) - st[2 + q], &s_bin[q], &s_below[q], scratch);
+  // both ranks in one level-1 bin (the usual case): their histograms are the
+  // same and their ranks in it consecutive
+  if (st[0] == st[1]) {
+    block_find_two_ranks<kHist2, 256>(h2, noise_rank(hw, 0) - st[2], s_bin, s_below, scratch);
+  } else {
+    for (int q = 0; q < 2; ++q)
+      block_find_rank<kHist2, 256, false>(h2 + q * kHist2, noise_rank(hw, q) - st[2 + q], &s_bin[q], &s_below[q],
+                                          scratch);
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st[4] = (uint32_t)s_bin[0];
     st[5] = (uint32_t)s_bin[1];
@@ -451,11 +458,14 @@ __global__ void __launch_bounds__(256) k_noise_threshold(FilterBatch B, int hw, 
   const uint32_t* st = ws.state + 8 * o;
   const uint32_t* h3 = ws.hist3 + (size_t)o * 2 * kHist3;
   float vals[2];
-  for (int q = 0; q < 2; ++q) {
-    block_find_rank<kHist3, 256, false>(h3 + q * kHist3, noise_rank(hw, q) - st[2 + q] - st[6 + q], &s_bin[q],
-                                        &s_below[q], scratch);
-    vals[q] = __uint_as_float((((st[q] << 10) | st[4 + q]) << 9) | (uint32_t)s_bin[q]);
+  if (st[0] == st[1] && st[4] == st[5]) {
+    block_find_two_ranks<kHist3, 256>(h3, noise_rank(hw, 0) - st[2] - st[6], s_bin, s_below, scratch);
+  } else {
+    for (int q = 0; q < 2; ++q)
+      block_find_rank<kHist3, 256, false>(h3 + q * kHist3, noise_rank(hw, q) - st[2 + q] - st[6 + q], &s_bin[q],
+                                          &s_below[q], scratch);
   }
+  for (int q = 0; q < 2; ++q) vals[q] = __uint_as_float((((st[q] << 10) | st[4 + q]) << 9) | (uint32_t)s_bin[q]);
   if (threadIdx.x == 0) {
     const double tt = noise_threshold(vals[0], vals[1], nc);
     I.ostat[2 * o] = vals[0];

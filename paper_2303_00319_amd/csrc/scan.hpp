@@ -78,4 +78,46 @@ __device__ void block_find_rank(const uint32_t* hist, uint32_t r, int* bin, uint
   __syncthreads();
 }
 
+// The bins of ranks r and r + 1 (ascending) in one pass over hist[0..NB):
+// one scan, and each rank resolved by the thread whose bins hold it.  Writes
+// bin[q] / before[q] for rank r + q (shared); r + 1 must be below the total.
+template <int NB, int BLOCK>
+__device__ void block_find_two_ranks(const uint32_t* hist, uint32_t r, int* bin, uint32_t* before,
+                                     uint32_t* scratch /* >= BLOCK / 64 */) {
+  static_assert(NB % BLOCK == 0, "bins per thread");
+  constexpr int PER = NB / BLOCK;
+  const int t = threadIdx.x;
+  uint32_t c[PER];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    c[i] = hist[t * PER + i];
+    sum += c[i];
+  }
+  const uint32_t incl = block_inclusive_scan<BLOCK>(sum, scratch);
+  const uint32_t excl = incl - sum;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const uint32_t rq = r + (uint32_t)q;
+    if (excl <= rq && rq < incl) {
+      uint32_t acc = excl;
+      int hit = PER - 1;
+      uint32_t acc_hit = 0;
+      bool found = false;
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        if (!found && acc + c[i] > rq) {
+          found = true;
+          hit = i;
+          acc_hit = acc;
+        }
+        acc += c[i];
+      }
+      bin[q] = t * PER + hit;
+      before[q] = acc_hit;
+    }
+  }
+  __syncthreads();
+}
+
 }  // namespace rift2
