@@ -286,10 +286,17 @@ __global__ void __launch_bounds__(1024) k_det_bin(uint32_t* __restrict__ hdr, co
   __shared__ int sh_bin;
   __shared__ uint32_t sh_above, sh_total;
   constexpr int PER = kDetHistBins / 1024;
+  // one scan from the top bin down gives the total and, once the total fixes
+  // K, the bin of the K-th strongest key (its thread holds the bins in registers)
+  uint32_t c[PER];
   uint32_t sum = 0;
 #pragma unroll
-  for (int i = 0; i < PER; ++i) sum += hist[threadIdx.x * PER + i];
+  for (int i = 0; i < PER; ++i) {
+    c[i] = hist[kDetHistBins - 1 - (threadIdx.x * PER + i)];
+    sum += c[i];
+  }
   const uint32_t incl = block_inclusive_scan<1024>(sum, scratch);
+  const uint32_t excl = incl - sum;
   if (threadIdx.x == 1023) sh_total = incl;
   if (threadIdx.x == 0) {
     sh_bin = 0;
@@ -298,7 +305,27 @@ __global__ void __launch_bounds__(1024) k_det_bin(uint32_t* __restrict__ hdr, co
   __syncthreads();
   const uint32_t n = sh_total;
   const uint32_t k = min(kmax, n);
-  if (k > 0 && k < n) block_find_rank<kDetHistBins, 1024, true>(hist, k - 1, &sh_bin, &sh_above, scratch);
+  if (k > 0 && k < n) {
+    const uint32_t r = k - 1;
+    if (excl <= r && r < incl) {
+      uint32_t acc = excl;
+      int hit = PER - 1;
+      uint32_t acc_hit = 0;
+      bool found = false;
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        if (!found && acc + c[i] > r) {
+          found = true;
+          hit = i;
+          acc_hit = acc;
+        }
+        acc += c[i];
+      }
+      sh_bin = kDetHistBins - 1 - (int)(threadIdx.x * PER + hit);
+      sh_above = acc_hit;
+    }
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
     hdr[0] = n;
     hdr[8] = (uint32_t)sh_bin;
