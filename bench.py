@@ -25,8 +25,8 @@ pairs through RIFT's convolution-sequence ring (N_o descriptors per template
 keypoint, N_o-fold matching, no dominant index), with the same detector and
 matching precision, and RIFT2's speed-up over it.
 
-Prints one JSON line.  `--gpus` above 1 is rejected: this build runs on a
-single GPU.
+Prints one JSON line.  `--gpus` above 1 is rejected: the benchmark runs on
+one GPU.
 """
 from __future__ import annotations
 
@@ -641,8 +641,8 @@ def main():
     faulthandler.enable()
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not part of this "
-              f"build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path is not sharded across GPUs",
+              file=sys.stderr)
         sys.exit(2)
     cpu = None
     if not args.no_cpu and args.config == 1 and not args.serve:
