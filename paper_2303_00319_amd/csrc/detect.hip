@@ -350,21 +350,26 @@ __global__ void __launch_bounds__(256) k_det_select1(const uint32_t* __restrict_
   uint64_t* region = sel + (size_t)t0 * kTileCap;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   static_assert(kTileCap == 64, "one lane per candidate slot of a tile");
-  for (int t = t0 + wave; t < t1; t += 4) {
-    const uint32_t cnt = tile_cnt[t];
-    uint64_t key = 0;
-    bool take = false;
-    if ((uint32_t)lane < cnt) {
-      key = cand[(size_t)t * kTileCap + lane];
-      take = (uint32_t)(key >> 48) >= bin;
-    }
-    const uint64_t mask = __ballot(take);
-    if (mask) {
-      const int leader = __ffsll((unsigned long long)mask) - 1;
-      uint32_t base = 0;
-      if (lane == leader) base = atomicAdd(&s_count, (uint32_t)__popcll(mask));
-      base = __shfl(base, leader);
-      if (take) region[base + __popcll(mask & ((1ull << lane) - 1ull))] = key;
+  // four tiles per wave per round: the counts, then the keys, are loaded
+  // together before any is used
+  for (int tb = t0 + wave; tb < t1; tb += 16) {
+    uint32_t cnt[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) cnt[u] = tb + 4 * u < t1 ? tile_cnt[tb + 4 * u] : 0u;
+    uint64_t key[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) key[u] = (uint32_t)lane < cnt[u] ? cand[(size_t)(tb + 4 * u) * kTileCap + lane] : 0ull;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool take = (uint32_t)lane < cnt[u] && (uint32_t)(key[u] >> 48) >= bin;
+      const uint64_t mask = __ballot(take);
+      if (mask) {
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&s_count, (uint32_t)__popcll(mask));
+        base = __shfl(base, leader);
+        if (take) region[base + __popcll(mask & ((1ull << lane) - 1ull))] = key[u];
+      }
     }
   }
   __syncthreads();
