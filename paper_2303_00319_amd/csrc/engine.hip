@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "rift2.h"
+#include "sched.hpp"
 
 namespace rift2 {
 
@@ -78,59 +79,11 @@ inline bool req_layout(int H, int W, int K, const rift2_pc_params* pc, const rif
   return true;
 }
 
-// First-fit allocator over [0, size) with coalescing of freed ranges.
-class ArenaAlloc {
- public:
-  void reset(size_t size) {
-    free_.clear();
-    if (size) free_[0] = size;
-  }
-  bool alloc(size_t bytes, size_t* off) {
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        *off = it->first;
-        const size_t rest = it->second - bytes;
-        const size_t start = it->first + bytes;
-        free_.erase(it);
-        if (rest) free_[start] = rest;
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(size_t off, size_t bytes) {
-    auto it = free_.emplace(off, bytes).first;
-    auto next = std::next(it);
-    if (next != free_.end() && it->first + it->second == next->first) {
-      it->second += next->second;
-      free_.erase(next);
-    }
-    if (it != free_.begin()) {
-      auto prev = std::prev(it);
-      if (prev->first + prev->second == it->first) {
-        prev->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-
- private:
-  std::map<size_t, size_t> free_;
-};
-
 struct EngineSlot {
   hipStream_t sa = nullptr, sb = nullptr;
   hipEvent_t b_done = nullptr, admit = nullptr, done = nullptr, filt = nullptr;
 };
 
-struct EngineReq {
-  rift2_request req;
-  int H, W, K;
-  size_t off = 0, bytes = 0;
-  int slot = -1;
-  int32_t status = RIFT2_OK;
-  int32_t batch = 1;  // requests admitted together with this one
-};
 
 }  // namespace rift2
 
@@ -220,52 +173,30 @@ inline int32_t engine_launch(rift2_engine* e, EngineReq* const* g, int n) {
   return RIFT2_OK;
 }
 
-inline bool engine_same_shape(const EngineReq& a, const EngineReq& b) {
-  return a.H == b.H && a.W == b.W && a.K == b.K && a.req.dtype == b.req.dtype;
-}
 
 // Admits queued requests in arrival order while a slot and arena space are
 // free; with each admitted request go the queued requests of its shape that
-// also fit (up to e->batch, looking at most kLookahead entries ahead).  A
-// request larger than the whole arena fails at once.
-constexpr int kLookahead = 64;
+// also fit (admit_group).  A request larger than the whole arena fails at
+// once.
 
 inline void engine_pump(rift2_engine* e) {
   while (!e->pending.empty() && !e->free_slots.empty()) {
     EngineReq& q = e->pending.front();
     ReqLayout L;
-    if (!req_layout(q.H, q.W, q.K, &e->pc, &e->det, &e->dp, &e->mp, &L) || L.total > e->arena_bytes) {
+    const bool laid_out = req_layout(q.H, q.W, q.K, &e->pc, &e->det, &e->dp, &e->mp, &L);
+    if (!laid_out || L.total > e->arena_bytes) {
       rift2_completion c{};
       c.id = q.req.id;
-      c.status = L.total > e->arena_bytes ? RIFT2_ERR_WORKSPACE : RIFT2_ERR_UNSUPPORTED;
+      c.status = laid_out ? RIFT2_ERR_WORKSPACE : RIFT2_ERR_UNSUPPORTED;
       e->finished.push_back(c);
       e->pending.pop_front();
       continue;
     }
-    size_t off = 0;
-    if (!e->alloc.alloc(L.total, &off)) return;  // wait for memory to free up
-    q.off = off;
-    q.bytes = L.total;
-    q.slot = e->free_slots.back();
-    e->free_slots.pop_back();
-    std::vector<size_t> members{0};
     const int cap = std::max(1, std::min(e->batch, RIFT2_MAX_FILTER_BATCH / 2));
-    for (size_t i = 1; i < e->pending.size() && (int)i <= kLookahead && (int)members.size() < cap &&
-                       !e->free_slots.empty();
-         ++i) {
-      EngineReq& o = e->pending[i];
-      if (!engine_same_shape(o, q) || !e->alloc.alloc(L.total, &off)) continue;
-      o.off = off;
-      o.bytes = L.total;
-      o.slot = e->free_slots.back();
-      e->free_slots.pop_back();
-      members.push_back(i);
-    }
+    const std::vector<size_t> members = admit_group(e->pending, e->free_slots, e->alloc, L.total, cap);
+    if (members.empty()) return;  // wait for memory to free up
     EngineReq* group[RIFT2_MAX_FILTER_BATCH];
-    for (size_t k = 0; k < members.size(); ++k) {
-      group[k] = &e->pending[members[k]];
-      group[k]->batch = (int32_t)members.size();
-    }
+    for (size_t k = 0; k < members.size(); ++k) group[k] = &e->pending[members[k]];
     const int32_t status = engine_launch(e, group, (int)members.size());
     if (status != RIFT2_OK) {
       // part of the group may be enqueued: let it drain before the memory
