@@ -280,7 +280,7 @@ namespace {
 template <int W, int P, typename Tin>
 void launch_fwd_rows(const FilterBatch& B, int n, int64_t pitch, int H, int n_zero, hipStream_t st) {
   constexpr int LINES = 256 / FftPlan<W, P>::T;
-  hipLaunchKernelGGL((k_fwd_rows<W, P, Tin>), dim3(H / LINES, 1, n), dim3(256), 0, st, B, pitch, H, n_zero);
+  hipLaunchKernelGGL((k_fwd_rows<W, P, Tin>), dim3(H / LINES, 1, n), dim3(256), 0, st, B, pitch, n_zero);
 }
 
 template <int W, int P>
@@ -730,7 +730,6 @@ rift2_status rift2_debug_response(const void* img, int32_t dtype, int32_t H, int
   if (workspace_bytes < L.total) return RIFT2_ERR_WORKSPACE;
   if (!current_device_ready()) return RIFT2_ERR_NOT_INITIALIZED;
   hipStream_t st = (hipStream_t)stream;
-  char* ws = (char*)workspace;
   FilterBatch B;
   std::memset(&B, 0, sizeof(B));
   B.im[0] = filter_image(L, img, workspace, nullptr, nullptr, nullptr, nullptr);

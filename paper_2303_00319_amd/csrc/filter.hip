@@ -84,7 +84,7 @@ struct FilterBatch {
 // ---------------------------------------------------------------- forward rows
 
 template <int W, int P, typename Tin>
-__global__ void __launch_bounds__(256) k_fwd_rows(FilterBatch B, int64_t pitch, int H, int n_zero) {
+__global__ void __launch_bounds__(256) k_fwd_rows(FilterBatch B, int64_t pitch, int n_zero) {
   const FilterImage& I = B.im[blockIdx.z];
   const Tin* __restrict__ img = (const Tin*)I.img;
   float2* __restrict__ rrow = I.rrow;
