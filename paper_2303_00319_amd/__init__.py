@@ -54,7 +54,19 @@ def _stream(stream):
 
 
 def _ptr(t):
-    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+    """Device address of a tensor that the library reads or writes as one dense block."""
+    if t is None:
+        return ctypes.c_void_p(0)
+    if not t.is_contiguous():
+        raise ValueError("the library takes dense (contiguous) tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _img_ptr(img):
+    """Device address of an H x W image whose rows may be pitched (unit column stride)."""
+    if img.dim() != 2 or img.stride(1) != 1 or img.stride(0) < img.shape[1]:
+        raise ValueError("an image is H x W with unit column stride and a row pitch of at least W")
+    return ctypes.c_void_p(img.data_ptr())
 
 
 def _nbytes(t):
@@ -109,7 +121,7 @@ def ransac_workspace_bytes(match_cap, n_hyp):
 def filter_mim_into(img, pc, mim, mmax, mmin, amp, ws, stream=None):
     lib = _lib.load()
     h, w = img.shape
-    st = lib.rift2_filter_mim(_ptr(img), _image_dtype(img), h, w, img.stride(0), ctypes.byref(pc), _ptr(mim),
+    st = lib.rift2_filter_mim(_img_ptr(img), _image_dtype(img), h, w, img.stride(0), ctypes.byref(pc), _ptr(mim),
                               _ptr(mmax), _ptr(mmin), _ptr(amp), _ptr(ws), _nbytes(ws), _stream(stream))
     _lib.check(st, "rift2_filter_mim")
 
@@ -127,9 +139,7 @@ def filter_mim_batch_into(imgs, pc, outs, stream=None):
             raise ValueError("a batch holds images of one size, type and pitch")
     jobs = (_lib.FilterJob * n)()
     for i, (im, (mim, mmax, mmin, amp, ws)) in enumerate(zip(imgs, outs)):
-        jobs[i] = _lib.FilterJob(im.data_ptr(), mim.data_ptr(), mmax.data_ptr(),
-                                 mmin.data_ptr() if mmin is not None else None,
-                                 amp.data_ptr() if amp is not None else None, ws.data_ptr(), _nbytes(ws))
+        jobs[i] = _lib.FilterJob(_img_ptr(im), _ptr(mim), _ptr(mmax), _ptr(mmin), _ptr(amp), _ptr(ws), _nbytes(ws))
     st = lib.rift2_filter_mim_batch(n, jobs, _image_dtype(imgs[0]), h, w, imgs[0].stride(0), ctypes.byref(pc),
                                     _stream(stream))
     _lib.check(st, "rift2_filter_mim_batch")
@@ -309,7 +319,7 @@ def debug_response(img, scale, orient, pc: PCParams | None = None, workspace=Non
     eo = torch.empty((h, w, 2), dtype=torch.float32, device=img.device)
     ws = workspace if workspace is not None else torch.empty(filter_workspace_bytes(h, w, pc), dtype=torch.uint8,
                                                              device=img.device)
-    st = _lib.load().rift2_debug_response(_ptr(img), _image_dtype(img), h, w, img.stride(0), ctypes.byref(pc),
+    st = _lib.load().rift2_debug_response(_img_ptr(img), _image_dtype(img), h, w, img.stride(0), ctypes.byref(pc),
                                           int(scale), int(orient), _ptr(eo), _ptr(ws), _nbytes(ws), _stream(stream))
     _lib.check(st, "rift2_debug_response")
     return torch.view_as_complex(eo)
@@ -671,8 +681,11 @@ class Engine:
             n_out = torch.empty((1,), dtype=torch.int32, device=self.dev)  # the match stage always writes it
         ready = torch.cuda.Event()
         ready.record(torch.cuda.current_stream(self.dev))
-        r = _lib.Request(int(rid), img_a.data_ptr(), img_b.data_ptr(), _image_dtype(img_a), h, w, max_keypoints,
-                         out.data_ptr(), n_out.data_ptr(), ready.cuda_event)
+        if img_b.shape != img_a.shape or img_b.dtype != img_a.dtype:
+            raise ValueError("both images of a request have one size and type")
+        # the engine reads images with a row pitch of W
+        r = _lib.Request(int(rid), _ptr(img_a), _ptr(img_b), _image_dtype(img_a), h, w, max_keypoints,
+                         _ptr(out), _ptr(n_out), ready.cuda_event)
         _lib.check(_lib.load().rift2_engine_submit(self._h, ctypes.byref(r)), "rift2_engine_submit")
         self._live[int(rid)] = (img_a, img_b, out, n_out, ready)
         return out, n_out

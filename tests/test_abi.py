@@ -318,3 +318,21 @@ def test_filter_batch_validates_on_the_host():
     # no device at all: disjoint workspaces pass the host checks and stop at the missing initialisation
     jobs[1].workspace = fake + need
     assert lib.rift2_filter_mim_batch(2, jobs, 0, 256, 256, 256, ctypes.byref(pc), null) == _l.ERR_NOT_INITIALIZED
+
+
+def test_binding_refuses_tensor_layouts_the_library_cannot_read():
+    """Outputs, tables and workspaces are dense blocks; an image may have pitched rows but a unit column
+    stride.  Checked on host tensors: only strides are looked at."""
+    torch = pytest.importorskip("torch")
+    import paper_2303_00319_amd as r2
+
+    a = torch.zeros((64, 96), dtype=torch.float32)
+    assert r2._ptr(a).value == a.data_ptr() and r2._ptr(None).value is None
+    for bad in (a.t(), a[:, :48], a[::2]):
+        with pytest.raises(ValueError):
+            r2._ptr(bad)
+    crop = a[3:40, 5:70]
+    assert r2._img_ptr(crop).value == crop.data_ptr()
+    for bad in (a.t(), a[:, ::2], a.reshape(-1)):
+        with pytest.raises(ValueError):
+            r2._img_ptr(bad)

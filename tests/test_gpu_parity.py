@@ -183,6 +183,39 @@ def test_filter_mim_constant_image():
         assert int(n.item()) == 0
 
 
+def test_filter_mim_pitched_rows():
+    """A crop of a larger image (row pitch above W, odd byte offsets) gives the outputs of its dense
+    copy bit for bit, for every input type and in a batch; views the library cannot read are refused."""
+    r2, dev = _gpu()
+    pc = _pcparams(r2)
+    rng = np.random.default_rng(23)
+    for h, w, dt, scale in ((256, 256, np.uint8, 255), (512, 256, np.uint16, 4095), (256, 512, np.float32, 1.0)):
+        big = (rng.random((h + 9, w + 37)) * scale).astype(dt)
+        big_t = torch.from_numpy(big.view(np.int16) if dt == np.uint16 else big).to(dev)
+        crop = big_t[3:3 + h, 5:5 + w]
+        assert crop.stride(0) == w + 37 and not crop.is_contiguous()
+        print(f"[filter pitched] {h}x{w} {np.dtype(dt).name} pitch {crop.stride(0)}", flush=True)
+        got = r2.filter_mim(crop, pc, want_min=True, want_amp=True)
+        ref = r2.filter_mim(crop.contiguous(), pc, want_min=True, want_amp=True)
+        torch.cuda.synchronize()
+        for k in ("mim", "M", "m", "amp"):
+            assert torch.equal(got[k], ref[k]), f"{h}x{w} {np.dtype(dt).name}: {k} differs"
+        outs = [(torch.empty((h, w), dtype=torch.uint8, device=dev), torch.empty((h, w), dtype=torch.float32, device=dev),
+                 None, None, torch.empty(r2.filter_workspace_bytes(h, w, pc), dtype=torch.uint8, device=dev))
+                for _ in range(2)]
+        r2.filter_mim_batch_into([crop, big_t[4:4 + h, 5:5 + w]], pc, outs)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[0][0], ref["mim"]) and torch.equal(outs[0][1], ref["M"])
+    sq = torch.zeros((256, 256), dtype=torch.uint8, device=dev)
+    for bad in (sq.t(), torch.zeros((256, 512), dtype=torch.uint8, device=dev)[:, ::2]):
+        with pytest.raises(ValueError):
+            r2.filter_mim(bad, pc)
+    with pytest.raises(ValueError):
+        r2.filter_mim_into(sq, pc, torch.empty((256, 512), dtype=torch.uint8, device=dev)[:, :256],
+                           torch.empty((256, 256), dtype=torch.float32, device=dev), None, None,
+                           torch.empty(r2.filter_workspace_bytes(256, 256, pc), dtype=torch.uint8, device=dev))
+
+
 def _check_detect(r2, dev, m32, k, tag):
     print(f"[detect parity] {tag} shape={m32.shape} K={k}", flush=True)
     det = r2.defaults()[1]
