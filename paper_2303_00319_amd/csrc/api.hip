@@ -895,6 +895,8 @@ rift2_status rift2_describe(const uint8_t* mim, int32_t H, int32_t W, const rift
   }
   const uint16_t* src_rows = turned ? stage : desc;
   const float* src_inv = turned ? stage_inv : inv_norm;
+  // k_describe2's word-wide form (taken only where N_o is even)
+  const bool wide2 = ((uintptr_t)info & 15u) == 0 && ((uintptr_t)desc & 3u) == 0 && ((uintptr_t)src_rows & 3u) == 0;
   ProfScope ps(6, st);
 #define RIFT2_DESCRIBE_CASE(P_, G_, NO_)                                                                              \
   if (dp->patch_size == P_ && dp->grid == G_ && dp->n_orient == NO_) {                                               \
@@ -907,9 +909,12 @@ rift2_status rift2_describe(const uint8_t* mim, int32_t H, int32_t W, const rift
     else                                                                                                               \
       hipLaunchKernelGGL((k_describe<P_, G_, NO_>), grid, dim3(P_ * KPB), 0, st, mim, H, W, kp, n_kpts_dev, kpt_cap,   \
                          dp->dominant_num, dp->dominant_den, dp->mode, desc, inv_norm, desc_kp, info, n_desc_dev);   \
-    if (second)                                                                                                        \
-      hipLaunchKernelGGL((k_describe2<G_, NO_>), dim3(blocks2), dim3(256), 0, st, n_kpts_dev, kpt_cap, info, src_rows, \
-                         src_inv, desc, inv_norm, desc_kp, n_desc_dev);                                               \
+    if (second && wide2)                                                                                               \
+      hipLaunchKernelGGL((k_describe2<G_, NO_, NO_ % 2 == 0>), dim3(blocks2), dim3(256), 0, st, n_kpts_dev, kpt_cap,    \
+                         info, src_rows, src_inv, desc, inv_norm, desc_kp, n_desc_dev);                               \
+    else if (second)                                                                                                   \
+      hipLaunchKernelGGL((k_describe2<G_, NO_, false>), dim3(blocks2), dim3(256), 0, st, n_kpts_dev, kpt_cap, info,     \
+                         src_rows, src_inv, desc, inv_norm, desc_kp, n_desc_dev);                                     \
     return launch_status();                                                                                           \
   }
   RIFT2_DESCRIBE_CASE(96, 6, 6)

@@ -415,7 +415,29 @@ constexpr int kDesc2Kpts = 64;
 // src_rows / src_inv: where keypoint k's second row is built from -- the
 // primary rows and their norms (rotated by the stored delta), or a staging
 // area that already holds finished second rows (delta 0).
-template <int G, int NO>
+//
+// WIDE (info 16-byte aligned, rows 4-byte aligned, N_o even): the flags
+// before the block are counted four info words per load, and a cell's N_o
+// counts move as N_o / 2 words, rotated by whole words and then, for an odd
+// delta, by one 16-bit half.
+template <int NW>
+__device__ __forceinline__ void rotate_halves(const uint32_t (&x)[NW], int delta, uint32_t (&z)[NW]) {
+  // out element b = in element (b + delta) mod 2 NW; element 2k is the low half of word k
+  const int q = delta >> 1;
+  uint32_t y[NW];
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    uint32_t v = x[k];
+#pragma unroll
+    for (int r = 1; r < NW; ++r)
+      if (q == r) v = x[(k + r) % NW];
+    y[k] = v;
+  }
+#pragma unroll
+  for (int k = 0; k < NW; ++k) z[k] = (delta & 1) ? (y[k] >> 16) | (y[(k + 1) % NW] << 16) : y[k];
+}
+
+template <int G, int NO, bool WIDE>
 __global__ void __launch_bounds__(256) k_describe2(const int32_t* __restrict__ n_kpts, int kpt_cap,
                                                    const uint32_t* __restrict__ info, const uint16_t* src_rows,
                                                    const float* src_inv, uint16_t* desc, float* inv_norm,
@@ -431,8 +453,18 @@ __global__ void __launch_bounds__(256) k_describe2(const int32_t* __restrict__ n
   if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) *n_desc = 0;
   if (start >= n) return;
   uint32_t before = 0;
+  if constexpr (WIDE) {
+    // start is a multiple of kDesc2Kpts: whole 16-byte groups
+    const uint4* info4 = reinterpret_cast<const uint4*>(info);
+#pragma unroll 8
+    for (int j = threadIdx.x; j < start / 4; j += 256) {
+      const uint4 g = info4[j];
+      before += ((g.x >> 8) & 1u) + ((g.y >> 8) & 1u) + ((g.z >> 8) & 1u) + ((g.w >> 8) & 1u);
+    }
+  } else {
 #pragma unroll 4
-  for (int j = threadIdx.x; j < start; j += 256) before += (info[j] >> 8) & 1u;
+    for (int j = threadIdx.x; j < start; j += 256) before += (info[j] >> 8) & 1u;
+  }
   const uint32_t tot = block_inclusive_scan<256>(before, scratch);
   if (threadIdx.x == 255) sh_base = tot;
   if (threadIdx.x < kDesc2Kpts) {  // wave 0
@@ -456,11 +488,22 @@ __global__ void __launch_bounds__(256) k_describe2(const int32_t* __restrict__ n
     const int src_kp = flagged_kp[fi], delta = flagged_delta[fi];
     const uint16_t* src = src_rows + (size_t)src_kp * D + c * NO;
     uint16_t* dst = desc + (size_t)(n + base + fi) * D + c * NO;
+    if constexpr (WIDE) {
+      static_assert(NO % 2 == 0, "whole words per cell");
+      constexpr int NW = NO / 2;
+      uint32_t x[NW], z[NW];
 #pragma unroll
-    for (int b = 0; b < NO; ++b) {
-      int bb = b + delta;
-      if (bb >= NO) bb -= NO;
-      dst[b] = src[bb];
+      for (int k = 0; k < NW; ++k) x[k] = reinterpret_cast<const uint32_t*>(src)[k];
+      rotate_halves<NW>(x, delta, z);
+#pragma unroll
+      for (int k = 0; k < NW; ++k) reinterpret_cast<uint32_t*>(dst)[k] = z[k];
+    } else {
+#pragma unroll
+      for (int b = 0; b < NO; ++b) {
+        int bb = b + delta;
+        if (bb >= NO) bb -= NO;
+        dst[b] = src[bb];
+      }
     }
   }
   for (int fi = threadIdx.x; fi < nflag; fi += 256) {
