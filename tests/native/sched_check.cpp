@@ -85,11 +85,12 @@ static void check_allocator(std::mt19937_64& rng) {
         "released arena is not one range");
 }
 
+// Shapes 0, 3 and 4 share H and W: 3 differs in K, 4 in pixel type.
 static EngineReq make_req(int64_t id, int shape) {
-  static const int hw[4][3] = {{512, 512, 524}, {768, 768, 1179}, {1024, 1024, 2097}, {512, 512, 100}};
+  static const int hw[5][3] = {{512, 512, 524}, {768, 768, 1179}, {1024, 1024, 2097}, {512, 512, 100}, {512, 512, 524}};
   EngineReq q{};
   q.req.id = id;
-  q.req.dtype = RIFT2_U8;
+  q.req.dtype = shape == 4 ? RIFT2_U16 : RIFT2_U8;
   q.H = hw[shape][0];
   q.W = hw[shape][1];
   q.K = hw[shape][2];
@@ -114,7 +115,7 @@ static void check_groups(std::mt19937_64& rng) {
       if (rng() % 3 == 0) a.release(held[k].first, held[k].second), held[k].second = 0;
     std::deque<EngineReq> pending;
     const int nq = 1 + (int)(rng() % 90);
-    for (int i = 0; i < nq; ++i) pending.push_back(make_req(i, (int)(rng() % 4)));
+    for (int i = 0; i < nq; ++i) pending.push_back(make_req(i, (int)(rng() % 5)));
     std::vector<int> slots;
     const int ns = 1 + (int)(rng() % 8);
     for (int s = 0; s < ns; ++s) slots.push_back(100 + s);
@@ -138,7 +139,9 @@ static void check_groups(std::mt19937_64& rng) {
     for (size_t k = 0; k < m.size(); ++k) {
       const EngineReq& q = pending[m[k]];
       CHECK(k == 0 || (m[k] > m[k - 1] && m[k] <= (size_t)rift2::kLookahead), "trial %d: member order", trial);
-      CHECK(rift2::engine_same_shape(q, pending[0]), "trial %d: member %zu of another shape", trial, m[k]);
+      const EngineReq& h = pending[0];
+      CHECK(q.H == h.H && q.W == h.W && q.K == h.K && q.req.dtype == h.req.dtype,
+            "trial %d: member %zu of another shape or pixel type", trial, m[k]);
       CHECK(q.batch == (int32_t)m.size() && q.bytes == bytes, "trial %d: member fields", trial);
       CHECK(used.insert(q.slot).second, "trial %d: slot %d given twice", trial, q.slot);
       ranges.insert({q.off, q.bytes});
