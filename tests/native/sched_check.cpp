@@ -164,7 +164,10 @@ static void check_groups(std::mt19937_64& rng) {
         continue;
       }
       CHECK(pending[i].batch == 1 && pending[i].slot == -1, "trial %d: non-member %zu changed", trial, i);
-      if (rift2::engine_same_shape(pending[i], pending[0]) && i <= (size_t)rift2::kLookahead &&
+      const EngineReq& h = pending[0];
+      const bool same = pending[i].H == h.H && pending[i].W == h.W && pending[i].K == h.K &&
+                        pending[i].req.dtype == h.req.dtype;
+      if (same && i <= (size_t)rift2::kLookahead &&
           (int)m.size() < cap && !slots.empty()) {
         size_t off;
         ArenaAlloc probe = a;
