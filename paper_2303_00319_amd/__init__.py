@@ -208,6 +208,26 @@ def consensus_into(model, matches, n_matches, kpts_a, kpts_b, threshold, mask, r
 
 # ----------------------------------------------------------------- allocating convenience calls
 
+def _on_stream(fn):
+    """An allocating call given a `stream` runs with that stream current, so its outputs are allocated,
+    and their fills enqueued, on the stream its kernels run on."""
+    import functools
+    import inspect
+
+    sig = inspect.signature(fn)
+
+    @functools.wraps(fn)
+    def wrapped(*args, **kw):
+        stream = sig.bind(*args, **kw).arguments.get("stream")
+        if stream is None:
+            return fn(*args, **kw)
+        with _torch().cuda.stream(stream):
+            return fn(*args, **kw)
+
+    return wrapped
+
+
+@_on_stream
 def filter_mim(img, pc: PCParams | None = None, want_min: bool = False, want_amp: bool = False,
                workspace=None, stream=None):
     """MIM, max moment (and optionally min moment and A_o) of one H x W device image."""
@@ -234,6 +254,7 @@ def filter_mim(img, pc: PCParams | None = None, want_min: bool = False, want_amp
     return out
 
 
+@_on_stream
 def detect(moment, det: DetectParams | None = None, workspace=None, stream=None):
     """(kpts int32 [K, 3] = x, y, score bits; n int32 [1]) on the device, strongest first."""
     torch = _torch()
@@ -255,6 +276,7 @@ def rows_per_keypoint(dp):
     return {_lib.DESC_DOMINANT: 2, _lib.DESC_PLAIN: 1, _lib.DESC_RING: dp.n_orient, _lib.DESC_TURNED: 2}[dp.mode]
 
 
+@_on_stream
 def detect_union(max_moment, min_moment, det: DetectParams | None = None, workspace=None, stream=None):
     """RIFT's corner + edge union: (keypoints int32 [K, 3] = x, y, score bits; n int32 [1])."""
     torch = _torch()
@@ -271,6 +293,7 @@ def detect_union(max_moment, min_moment, det: DetectParams | None = None, worksp
     return kpts, n
 
 
+@_on_stream
 def describe(mim, kpts, n_kpts, dp: DescParams | None = None, workspace=None, stream=None):
     """(desc int16 [R K, D] holding uint16 counts, inv_norm f32 [R K], desc_kp int32 [R K], n_desc int32 [1]),
     R = rows_per_keypoint(dp)."""
@@ -292,6 +315,7 @@ def describe(mim, kpts, n_kpts, dp: DescParams | None = None, workspace=None, st
     return desc, inv, dkp, nd
 
 
+@_on_stream
 def match(desc_a, inv_a, kp_a, n_a, desc_b, inv_b, kp_b, n_b, mp: MatchParams | None = None,
           workspace=None, stream=None):
     """(matches int32 [cap_a, 3] = kp_a, kp_b, d2 bits; n int32 [1]) sorted by kp_a."""
@@ -309,6 +333,7 @@ def match(desc_a, inv_a, kp_a, n_a, desc_b, inv_b, kp_b, n_b, mp: MatchParams | 
     return out, n
 
 
+@_on_stream
 def debug_response(img, scale, orient, pc: PCParams | None = None, workspace=None, stream=None):
     """Complex response EO_{scale,orient} (complex64 H x W) of one filter of the bank, by the library's kernels."""
     torch = _torch()
@@ -325,6 +350,7 @@ def debug_response(img, scale, orient, pc: PCParams | None = None, workspace=Non
     return torch.view_as_complex(eo)
 
 
+@_on_stream
 def debug_noise(workspace, h, w, pc: PCParams | None = None, stream=None):
     """(A0 float [N_o, H, W], order statistics float [N_o, 2], T_o float64 [N_o]) that the last
     filter_mim on `workspace` left there."""
@@ -341,6 +367,7 @@ def debug_noise(workspace, h, w, pc: PCParams | None = None, stream=None):
     return a0, ostat, t_o
 
 
+@_on_stream
 def desc_normalize(desc, inv_norm, n_rows, stream=None):
     """FP32 view fl(count * inv_norm) of the first n_rows descriptor rows (rows past it are zero)."""
     torch = _torch()
@@ -371,6 +398,7 @@ def consensus_fields(result):
     return {"n_inliers": i[0], "status": i[1], "sum_sq": raw[8:16].view(_torch().float64).item()}
 
 
+@_on_stream
 def ransac(matches, n_matches, kpts_a, kpts_b, words, threshold=3.0, refine=2, stream=None):
     """RANSAC over a similarity on device matches: (result uint8 [48], mask uint8 [cap], counts int32 [n_hyp]).
 
@@ -388,6 +416,7 @@ def ransac(matches, n_matches, kpts_a, kpts_b, words, threshold=3.0, refine=2, s
     return result, mask, counts
 
 
+@_on_stream
 def consensus(model, matches, n_matches, kpts_a, kpts_b, threshold=3.0, stream=None):
     """Consensus of a model (device float64 [4]) over device matches: (result uint8 [16], mask uint8 [cap])."""
     torch = _torch()

@@ -196,3 +196,44 @@ def test_batched_filter_pipeline_equals_two_streams():
         torch.cuda.synchronize()
         g.replay()
         _same(_snapshot(pipe), want, f"batched replay {rep}")
+
+
+def test_convenience_calls_on_a_side_stream():
+    """The allocating calls given a stream allocate and fill their outputs on that stream: with the
+    current stream kept busy, every stage's results on a side stream equal those of the same calls on
+    the current stream."""
+    r2, dev = _gpu()
+    a, b = _translated_pair(2)
+    ta, tb = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+
+    def run(stream):
+        outs = []
+        for t in (ta, tb):
+            fm = r2.filter_mim(t, stream=stream)
+            kp, n = r2.detect(fm["M"], stream=stream)
+            desc, inv, dkp, nd = r2.describe(fm["mim"], kp, n, stream=stream)
+            outs.append((fm["mim"], fm["M"], kp, n, desc, inv, dkp, nd))
+        (_, _, kpa, _, da, ia, pa, na), (_, _, kpb, _, db, ib, pb, nb) = outs
+        m, nm = r2.match(da, ia, pa, na, db, ib, pb, nb, stream=stream)
+        return outs, m, nm
+
+    def host(outs, m, nm):
+        res = []
+        for mim, M, kp, n, desc, inv, dkp, nd in outs:
+            k, d = int(n.item()), int(nd.item())
+            res += [mim.cpu().numpy(), M.cpu().numpy(), kp[:k].cpu().numpy(), desc[:d].cpu().numpy(),
+                    dkp[:d].cpu().numpy()]
+        res.append(m[:int(nm.item())].cpu().numpy())
+        return res
+
+    ref = host(*run(None))
+    assert len(ref[-1]) > 0
+    side = torch.cuda.Stream(device=dev)
+    side.wait_stream(torch.cuda.current_stream(dev))
+    big = torch.randn((4096, 4096), device=dev)
+    for _ in range(6):  # about 0.8 TFLOP queued on the current stream
+        big = big @ big / 64.0
+    got = run(side)
+    side.synchronize()
+    for x, y in zip(ref, host(*got)):
+        assert x.shape == y.shape and np.array_equal(x, y)
