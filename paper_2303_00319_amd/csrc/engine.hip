@@ -118,7 +118,8 @@ inline int engine_keypoints(const rift2_request& r) {
 inline int32_t engine_launch(rift2_engine* e, EngineReq* const* g, int n) {
   const EngineReq& q0 = *g[0];
   ReqLayout L;
-  req_layout(q0.H, q0.W, q0.K, &e->pc, &e->det, &e->dp, &e->mp, &L);
+  // admission laid the group out already; a failure here would be a bug, reported rather than run
+  if (!req_layout(q0.H, q0.W, q0.K, &e->pc, &e->det, &e->dp, &e->mp, &L)) return RIFT2_ERR_UNSUPPORTED;
   rift2_detect_params det = e->det;
   det.max_keypoints = q0.K;
   const EngineSlot& s0 = e->slots[q0.slot];
