@@ -294,11 +294,13 @@ def test_detect_ties_and_random_maps():
     _check_detect(r2, dev, m, 12000, "gaussian, counting sort")
 
 
-def _check_describe(r2, dev, mim, kpts, tag, n_orient=6):
-    print(f"[describe parity] {tag} n={len(kpts)}", flush=True)
+def _check_describe(r2, dev, mim, kpts, tag, n_orient=6, patch=96, grid=6):
+    print(f"[describe parity] {tag} n={len(kpts)} patch={patch} grid={grid}", flush=True)
     dp = r2.defaults()[2]
     dp.n_orient = n_orient
-    c_ref, k_ref, _ = describe.describe(mim, kpts, oracle.DescParams(n_orient=n_orient))
+    dp.patch_size = patch
+    dp.grid = grid
+    c_ref, k_ref, _ = describe.describe(mim, kpts, oracle.DescParams(patch_size=patch, grid=grid, n_orient=n_orient))
     kp = np.zeros((max(len(kpts), 1), 3), dtype=np.int32)
     kp[:len(kpts), :2] = kpts
     kp_t = torch.from_numpy(kp).to(dev)
@@ -327,6 +329,25 @@ def test_describe_bitexact_on_oracle_mim():
     mim6 = (rng.integers(0, 2, size=(200, 200)) * 3).astype(np.uint8)
     pts = np.stack([rng.integers(48, 153, 333), rng.integers(48, 153, 333)], 1).astype(np.int32)
     _check_describe(r2, dev, mim6, pts, "two-valued")
+
+
+def test_describe_small_patch_build():
+    """The 64-pixel patch, 4 x 4 grid build against the oracle, keypoints on the extreme rows and columns
+    whose patch still fits (32 <= x <= W - 32) and a near-uniform MIM with many second rows."""
+    r2, dev = _gpu()
+    rng = np.random.default_rng(19)
+    h, w = 150, 230
+    uniform = rng.integers(0, 6, size=(h, w)).astype(np.uint8)
+    xs = np.concatenate([[32, w - 32, 32, w - 32], rng.integers(32, w - 32 + 1, 296)])
+    ys = np.concatenate([[32, 32, h - 32, h - 32], rng.integers(32, h - 32 + 1, 296)])
+    pts = np.stack([xs, ys], 1).astype(np.int32)
+    # value 2 more likely to the right, 4 to the left, a fifth of the pixels 0: a dominant index in most
+    # patches, a second row (43 of 300) where 2 and 4 balance
+    mixed = np.where(rng.random((h, w)) < np.linspace(0.0, 1.0, w)[None, :], 2, 4).astype(np.uint8)
+    mixed[rng.random((h, w)) < 0.2] = 0
+    c_ref, _ = _check_describe(r2, dev, mixed, pts, "patch 64 mixed", patch=64, grid=4)
+    assert 300 < len(c_ref) < 600
+    _check_describe(r2, dev, uniform, pts, "patch 64 uniform", patch=64, grid=4)
 
 
 def _check_match(r2, dev, ca, ka, cb, kb, precision, tag, mutual=False):

@@ -29,13 +29,16 @@ def _gpu():
     return r2, torch.device("cuda:0")
 
 
-def _check(r2, dev, mim, kpts, tag, n_orient=6, byte_offset=0):
+def _check(r2, dev, mim, kpts, tag, n_orient=6, byte_offset=0, patch=96, grid=6):
     """byte_offset > 0 places the MIM that many bytes into its device buffer (rows not 4-byte aligned)."""
-    print(f"[turned parity] {tag} n={len(kpts)} N_o={n_orient}", flush=True)
+    print(f"[turned parity] {tag} n={len(kpts)} N_o={n_orient} patch={patch} grid={grid}", flush=True)
     dp = r2.defaults()[2]
     dp.n_orient = n_orient
+    dp.patch_size = patch
+    dp.grid = grid
     dp.mode = r2.DESC_TURNED
-    c_ref, k_ref, _ = describe.describe_rotated(mim, kpts, oracle.DescParams(n_orient=n_orient))
+    c_ref, k_ref, _ = describe.describe_rotated(mim, kpts,
+                                                oracle.DescParams(patch_size=patch, grid=grid, n_orient=n_orient))
     kp = np.zeros((max(len(kpts), 1), 3), dtype=np.int32)
     kp[:len(kpts), :2] = kpts
     buf = torch.zeros(mim.size + byte_offset, dtype=torch.uint8, device=dev)
@@ -73,6 +76,18 @@ def test_turned_rows_bitexact():
     _check(r2, dev, mim3, pts, "odd width, all positions")
     _check(r2, dev, mim8, np.stack([rng.integers(0, 260, 201), rng.integers(0, 300, 201)], 1).astype(np.int32),
            "N_o=8, MIM one byte into its buffer", n_orient=8, byte_offset=1)
+
+
+def test_turned_rows_small_patch_build():
+    """The 64-pixel patch, 4 x 4 grid build: keypoints anywhere, a MIM with a dominant value in most
+    patches and a second row where two values balance (40 of 300)."""
+    r2, dev = _gpu()
+    rng = np.random.default_rng(29)
+    h, w = 150, 230
+    mixed = np.where(rng.random((h, w)) < np.linspace(0.0, 1.0, w)[None, :], 2, 4).astype(np.uint8)
+    mixed[rng.random((h, w)) < 0.2] = 0
+    pts = np.stack([rng.integers(0, w, 300), rng.integers(0, h, 300)], 1).astype(np.int32)
+    assert 0 < _check(r2, dev, mixed, pts, "patch 64 mixed", patch=64, grid=4) < 300
 
 
 def test_turned_pipeline_matches_a_rotated_pair_and_ransac_recovers_it():
