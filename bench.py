@@ -53,9 +53,9 @@ FP64_PEAK_TFLOPS = 78.6  # vector FP64, FMA counted as two flops
 # (N_s = 4, N_o = 6, 5000 keypoints), valid only for the sources they were
 # taken on (hash of the listed files).
 MEASURED_TRAFFIC = {
-    "pass_a": {"sources": ("fft.hpp", "filter.hip", "api.hip"), "sha": "385000396d5176c3", "bytes": 213165300},
-    "pass_b": {"sources": ("fft.hpp", "filter.hip", "api.hip"), "sha": "385000396d5176c3", "bytes": 206932275},
-    "match_gemm": {"sources": ("match.hip", "api.hip"), "sha": "ddb679714ee9152e", "bytes": 419415890},
+    "pass_a": {"sources": ("fft.hpp", "filter.hip", "api.hip"), "sha": "3702a38def28fffc", "bytes": 213271983},
+    "pass_b": {"sources": ("fft.hpp", "filter.hip", "api.hip"), "sha": "3702a38def28fffc", "bytes": 206931294},
+    "match_gemm": {"sources": ("match.hip", "api.hip"), "sha": "93901580267965f3", "bytes": 419081399},
 }
 
 
@@ -712,6 +712,15 @@ def main():
     n_a, n_b = timed[main_form]["last_pair"]["descriptor_rows"]
     roof = roofline(stages[main_form], args.size, args.size, args.n_scales, args.n_orient, n_a, n_b, d,
                     peak[main_form])
+    if roof["kernel"] == "match_gemm" and main_form == "fp32":
+        # what the matrix cores sustain on register-only chains of the GEMM's instruction, by waves per SIMD
+        # (the GEMM runs 3: three 4-wave blocks per CU)
+        print("[bench] FP32 MFMA calibration", file=sys.stderr, flush=True)
+        rates = {w: round(r2.mfma_f32_rate(w), 2) for w in (1, 2, 3, 4)}
+        roof["sustained"] = {"instruction": "v_mfma_f32_32x32x2f32, register operands", "waves_per_simd": 3,
+                             "tflops": rates[3], "frac_of_peak": round(rates[3] / FP32_MFMA_PEAK_TFLOPS, 4),
+                             "gemm_frac_of_sustained": round(roof["achieved"] / rates[3], 4),
+                             "tflops_by_waves_per_simd": rates}
     mfma = {}
     for f in forms:
         # sum of each profiled step's flops over the summed GEMM time

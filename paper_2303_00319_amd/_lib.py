@@ -103,7 +103,7 @@ EXPORTS = [
     "rift2_engine_submit", "rift2_engine_poll", "rift2_engine_pending", "rift2_engine_destroy",
     "rift2_ransac_workspace_size", "rift2_ransac", "rift2_consensus", "rift2_detect_union_workspace_size",
     "rift2_detect_union", "rift2_debug_response", "rift2_debug_noise", "rift2_desc_normalize",
-    "rift2_detect_noalloc", "rift2_filter_mim_batch", "rift2_engine_set_batch",
+    "rift2_detect_noalloc", "rift2_filter_mim_batch", "rift2_engine_set_batch", "rift2_debug_mfma_rate",
 ]
 STAGES = ["row_dft", "pass_a", "noise_pre", "noise_sel", "pass_b", "detect", "describe", "match_prep",
           "match_gemm", "match_merge", "pass_b_reduce", "ransac"]
@@ -171,6 +171,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rift2_debug_response.restype = ctypes.c_int
     lib.rift2_debug_noise.argtypes = [vp, sz, i32, i32, P(PCParams), vp, vp, vp, vp]
     lib.rift2_debug_noise.restype = ctypes.c_int
+    lib.rift2_debug_mfma_rate.argtypes = [i32, i32, i32, vp, P(ctypes.c_float), vp]
+    lib.rift2_debug_mfma_rate.restype = ctypes.c_int
     lib.rift2_desc_normalize.argtypes = [vp, vp, vp, i32, i32, vp, vp]
     lib.rift2_desc_normalize.restype = ctypes.c_int
     lib.rift2_profile_enable.argtypes = [ctypes.c_int]

@@ -18,6 +18,7 @@
 #include "match_fp8.hip"
 #include "ransac.hip"
 #include "engine.hip"
+#include "calib.hip"
 
 using namespace rift2;
 
@@ -772,6 +773,32 @@ rift2_status rift2_desc_normalize(const uint16_t* desc, const float* inv_norm, c
   const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
   hipLaunchKernelGGL(k_desc_normalize, dim3(blocks), dim3(256), 0, st, desc, inv_norm, n_rows_dev, cap, D, out);
   return launch_status();
+}
+
+rift2_status rift2_debug_mfma_rate(int32_t waves_per_simd, int32_t iters, int32_t reps, float* sink, float* ms,
+                                   void* stream) {
+  if (waves_per_simd < 1 || waves_per_simd > 4 || iters < 1 || reps < 1 || !sink || !ms) return RIFT2_ERR_INVALID_ARG;
+  int dev = -1, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess)
+    return RIFT2_ERR_DEVICE;
+  if (cus != kCalibCUs) return RIFT2_ERR_UNSUPPORTED;  // the sink's size assumes the full chip
+  hipStream_t st = (hipStream_t)stream;
+  // a block of 4 waves per CU and wave per SIMD: every SIMD runs waves_per_simd chains
+  const dim3 grid(kCalibCUs * waves_per_simd);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return RIFT2_ERR_DEVICE;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(k_calib_mfma_f32, grid, dim3(256), 0, st, sink, iters, 1.0f);  // warm-up
+  rift2_status r = hipEventRecord(a, st) == hipSuccess ? RIFT2_OK : RIFT2_ERR_DEVICE;
+  for (int i = 0; i < reps && r == RIFT2_OK; ++i) hipLaunchKernelGGL(k_calib_mfma_f32, grid, dim3(256), 0, st, sink, iters, 1.0f);
+  if (r == RIFT2_OK) r = launch_status();
+  if (r == RIFT2_OK && (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                        hipEventElapsedTime(ms, a, b) != hipSuccess))
+    r = RIFT2_ERR_DEVICE;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return r;
 }
 
 static rift2_status detect_launch(const float* edge, const float* corner, int32_t H, int32_t W,

@@ -336,3 +336,13 @@ def test_binding_refuses_tensor_layouts_the_library_cannot_read():
     for bad in (a.t(), a[:, ::2], a.reshape(-1)):
         with pytest.raises(ValueError):
             r2._img_ptr(bad)
+
+
+def test_mfma_calibration_validates_on_the_host():
+    _l, lib = _lib()
+    ms = ctypes.c_float(0.0)
+    sink = ctypes.c_void_p(0x1000)
+    for w, it, reps, snk, out in ((0, 10, 1, sink, ctypes.byref(ms)), (5, 10, 1, sink, ctypes.byref(ms)),
+                                  (3, 0, 1, sink, ctypes.byref(ms)), (3, 10, 0, sink, ctypes.byref(ms)),
+                                  (3, 10, 1, None, ctypes.byref(ms)), (3, 10, 1, sink, None)):
+        assert lib.rift2_debug_mfma_rate(w, it, reps, snk, out, None) == _l.ERR_INVALID_ARG

@@ -488,3 +488,14 @@ def test_end_to_end_pair_agreement():
     jac = len(got & want) / max(1, len(got | want))
     print(f"end-to-end: gpu {len(got)} matches, oracle {len(want)}, Jaccard {jac:.4f}", flush=True)
     assert len(want) > 100 and jac > 0.9
+
+
+def test_mfma_calibration_stays_below_the_peak():
+    """rift2_debug_mfma_rate: register-only FP32 MFMA chains run at a sizeable fraction of the published
+    157.3 TFLOP/s and never above it; more waves per SIMD never run much slower."""
+    r2, dev = _gpu()
+    rates = [r2.mfma_f32_rate(w, iters=1000, reps=3) for w in (1, 2, 3, 4)]
+    print(f"[mfma calibration] TFLOP/s by waves per SIMD: {[round(r, 1) for r in rates]}", flush=True)
+    for r in rates:
+        assert 0.3 * 157.3 < r < 1.01 * 157.3
+    assert rates[3] > 0.9 * rates[0]
