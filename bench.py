@@ -53,9 +53,9 @@ FP64_PEAK_TFLOPS = 78.6  # vector FP64, FMA counted as two flops
 # (N_s = 4, N_o = 6, 5000 keypoints), valid only for the sources they were
 # taken on (hash of the listed files).
 MEASURED_TRAFFIC = {
-    "pass_a": {"sources": ("fft.hpp", "filter.hip", "api.hip"), "sha": "3702a38def28fffc", "bytes": 213271983},
-    "pass_b": {"sources": ("fft.hpp", "filter.hip", "api.hip"), "sha": "3702a38def28fffc", "bytes": 206931294},
-    "match_gemm": {"sources": ("match.hip", "api.hip"), "sha": "93901580267965f3", "bytes": 419081399},
+    "pass_a": {"sources": ("fft.hpp", "filter.hip", "api.hip"), "sha": "281dbf3d450e439e", "bytes": 213194615},
+    "pass_b": {"sources": ("fft.hpp", "filter.hip", "api.hip"), "sha": "281dbf3d450e439e", "bytes": 206927935},
+    "match_gemm": {"sources": ("match.hip", "api.hip"), "sha": "d9f5de4f21d2b997", "bytes": 419617943},
 }
 
 
@@ -716,18 +716,24 @@ def main():
         # what the matrix cores sustain on register-only chains of the GEMM's instruction, by waves per SIMD
         # (the GEMM runs 3: three 4-wave blocks per CU)
         print("[bench] FP32 MFMA calibration", file=sys.stderr, flush=True)
-        rates = {w: round(r2.mfma_f32_rate(w), 2) for w in (1, 2, 3, 4)}
+        rates = {w: round(r2.mfma_rate(r2.PREC_FP32, w), 2) for w in (1, 2, 3, 4)}
         roof["sustained"] = {"instruction": "v_mfma_f32_32x32x2f32, register operands", "waves_per_simd": 3,
                              "tflops": rates[3], "frac_of_peak": round(rates[3] / FP32_MFMA_PEAK_TFLOPS, 4),
                              "gemm_frac_of_sustained": round(roof["achieved"] / rates[3], 4),
                              "tflops_by_waves_per_simd": rates}
     mfma = {}
+    # register-only chains of the GEMMs' instructions at their kernels' occupancy (FP32 3, BF16 4 waves per SIMD)
+    calib = {"fp32": (r2.PREC_FP32, 3), "bf16": (r2.PREC_BF16, 4)}
     for f in forms:
         # sum of each profiled step's flops over the summed GEMM time
         flop = sum(2.0 * ra * rb * d for ra, rb in stages[f]["_rows"])
         t = stages[f]["match_gemm"]["ms_total"] * 1e-3
         mfma[f] = {"tflops": round(flop / t / 1e12, 2), "frac": round(flop / t / (peak[f] * 1e12), 4),
                    "peak_tflops": peak[f]}
+        if f in calib:
+            sus = r2.mfma_rate(*calib[f])
+            mfma[f]["sustained_tflops"] = round(sus, 2)
+            mfma[f]["frac_of_sustained"] = round(flop / t / 1e12 / sus, 4)
     print("[bench] section 4 metrics", file=sys.stderr, flush=True)
     accuracy = {main_form: section4_metrics(r2, torch, timed[main_form]["pipe"], imgs, gts)}
     for v in variants:

@@ -259,22 +259,24 @@ rift2_status rift2_debug_noise(const void* workspace, size_t workspace_bytes, in
                                const rift2_pc_params* pc, float* a0, float* order_stats, double* t_o,
                                void* stream);
 
-/* rift2_debug_mfma_rate: calibration for the distance GEMM's roofline (the
+/* rift2_debug_mfma_rate: calibration for the distance GEMMs' rooflines (the
  * matching step of Section 4 is a dense contraction on the matrix cores).
- * Runs register-only chains of the FP32 GEMM's MFMA instruction
- * (v_mfma_f32_32x32x2f32, 4096 flops each) with `waves_per_simd` waves on
- * every SIMD of the chip, each wave 2 x 16 x `iters` instructions, `reps`
+ * Runs register-only chains of a GEMM's MFMA instruction -- precision
+ * RIFT2_PREC_FP32: v_mfma_f32_32x32x2f32, 4096 flops each; RIFT2_PREC_BF16:
+ * v_mfma_f32_32x32x16_bf16, 32768 flops each -- with `waves_per_simd` waves
+ * on every SIMD of the chip, each wave 2 x 16 x `iters` instructions, `reps`
  * launches back to back after one warm-up launch, and writes their elapsed
  * milliseconds to *ms (host memory; the call synchronises `stream`).  The
- * sustained rate is reps x 256 x 4 x waves_per_simd x 32 x iters x 4096 flops
- * / ms.
+ * sustained rate is reps x 256 x 4 x waves_per_simd x 32 x iters x (flops per
+ * instruction) / ms.
  *   waves_per_simd  1..4
  *   sink            device float, 256 x 256 x waves_per_simd entries (the
  *                   chains' sums, written so they are kept)
- * Errors: RIFT2_ERR_INVALID_ARG (range, null pointer), RIFT2_ERR_UNSUPPORTED
- * (a device without 256 compute units), RIFT2_ERR_DEVICE. */
-rift2_status rift2_debug_mfma_rate(int32_t waves_per_simd, int32_t iters, int32_t reps, float* sink, float* ms,
-                                   void* stream);
+ * Errors: RIFT2_ERR_INVALID_ARG (precision, range, null pointer),
+ * RIFT2_ERR_UNSUPPORTED (a device without 256 compute units),
+ * RIFT2_ERR_DEVICE. */
+rift2_status rift2_debug_mfma_rate(int32_t precision, int32_t waves_per_simd, int32_t iters, int32_t reps, float* sink,
+                                   float* ms, void* stream);
 
 /* FAST keypoints on `moment` (H x W float, normally the max moment map):
  * min-max normalisation to [0, 1], 16-pixel segment test with arc 9 and

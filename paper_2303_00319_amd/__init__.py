@@ -19,7 +19,7 @@ __all__ = [
     "PREC_FP32", "PREC_BF16", "PREC_FP8", "STAGES", "RansacParams", "ransac", "consensus", "ransac_workspace_bytes",
     "SIMILARITY_BYTES", "CONSENSUS_BYTES", "similarity_fields", "consensus_fields", "DESC_DOMINANT", "DESC_PLAIN",
     "DESC_RING", "DESC_TURNED", "rows_per_keypoint", "detect_union", "debug_response", "debug_noise",
-    "desc_normalize", "filter_workspace_bytes", "filter_mim_batch_into", "mfma_f32_rate",
+    "desc_normalize", "filter_workspace_bytes", "filter_mim_batch_into", "mfma_rate",
 ]
 
 
@@ -368,15 +368,18 @@ def debug_noise(workspace, h, w, pc: PCParams | None = None, stream=None):
 
 
 @_on_stream
-def mfma_f32_rate(waves_per_simd=3, iters=2000, reps=5, stream=None):
-    """Sustained FP32 MFMA rate (TFLOP/s) of register-only v_mfma_f32_32x32x2f32 chains with
-    `waves_per_simd` waves on every SIMD (rift2_debug_mfma_rate)."""
+def mfma_rate(precision=_lib.PREC_FP32, waves_per_simd=3, iters=2000, reps=5, stream=None):
+    """Sustained MFMA rate (TFLOP/s) of register-only chains of the FP32 (v_mfma_f32_32x32x2f32) or BF16
+    (v_mfma_f32_32x32x16_bf16) GEMM's instruction with `waves_per_simd` waves on every SIMD
+    (rift2_debug_mfma_rate)."""
     torch = _torch()
     sink = torch.empty((256 * 256 * waves_per_simd,), dtype=torch.float32, device="cuda")
     ms = ctypes.c_float(0.0)
-    _lib.check(_lib.load().rift2_debug_mfma_rate(int(waves_per_simd), int(iters), int(reps), _ptr(sink),
-                                                 ctypes.byref(ms), _stream(stream)), "rift2_debug_mfma_rate")
-    flops = float(reps) * 256 * 4 * waves_per_simd * 32 * iters * 4096
+    _lib.check(_lib.load().rift2_debug_mfma_rate(int(precision), int(waves_per_simd), int(iters), int(reps),
+                                                 _ptr(sink), ctypes.byref(ms), _stream(stream)),
+               "rift2_debug_mfma_rate")
+    per_instr = 4096 if precision == _lib.PREC_FP32 else 32768
+    flops = float(reps) * 256 * 4 * waves_per_simd * 32 * iters * per_instr
     return flops / (ms.value * 1e-3) / 1e12
 
 

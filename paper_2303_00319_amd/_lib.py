@@ -171,7 +171,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rift2_debug_response.restype = ctypes.c_int
     lib.rift2_debug_noise.argtypes = [vp, sz, i32, i32, P(PCParams), vp, vp, vp, vp]
     lib.rift2_debug_noise.restype = ctypes.c_int
-    lib.rift2_debug_mfma_rate.argtypes = [i32, i32, i32, vp, P(ctypes.c_float), vp]
+    lib.rift2_debug_mfma_rate.argtypes = [i32, i32, i32, i32, vp, P(ctypes.c_float), vp]
     lib.rift2_debug_mfma_rate.restype = ctypes.c_int
     lib.rift2_desc_normalize.argtypes = [vp, vp, vp, i32, i32, vp, vp]
     lib.rift2_desc_normalize.restype = ctypes.c_int

@@ -775,8 +775,9 @@ rift2_status rift2_desc_normalize(const uint16_t* desc, const float* inv_norm, c
   return launch_status();
 }
 
-rift2_status rift2_debug_mfma_rate(int32_t waves_per_simd, int32_t iters, int32_t reps, float* sink, float* ms,
-                                   void* stream) {
+rift2_status rift2_debug_mfma_rate(int32_t precision, int32_t waves_per_simd, int32_t iters, int32_t reps, float* sink,
+                                   float* ms, void* stream) {
+  if (precision != RIFT2_PREC_FP32 && precision != RIFT2_PREC_BF16) return RIFT2_ERR_INVALID_ARG;
   if (waves_per_simd < 1 || waves_per_simd > 4 || iters < 1 || reps < 1 || !sink || !ms) return RIFT2_ERR_INVALID_ARG;
   int dev = -1, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
@@ -789,9 +790,15 @@ rift2_status rift2_debug_mfma_rate(int32_t waves_per_simd, int32_t iters, int32_
   hipEvent_t a = nullptr, b = nullptr;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return RIFT2_ERR_DEVICE;
   (void)hipGetLastError();
-  hipLaunchKernelGGL(k_calib_mfma_f32, grid, dim3(256), 0, st, sink, iters, 1.0f);  // warm-up
+  auto launch = [&]() {
+    if (precision == RIFT2_PREC_FP32)
+      hipLaunchKernelGGL(k_calib_mfma_f32, grid, dim3(256), 0, st, sink, iters, 1.0f);
+    else
+      hipLaunchKernelGGL(k_calib_mfma_bf16, grid, dim3(256), 0, st, sink, iters, 1.0f);
+  };
+  launch();  // warm-up
   rift2_status r = hipEventRecord(a, st) == hipSuccess ? RIFT2_OK : RIFT2_ERR_DEVICE;
-  for (int i = 0; i < reps && r == RIFT2_OK; ++i) hipLaunchKernelGGL(k_calib_mfma_f32, grid, dim3(256), 0, st, sink, iters, 1.0f);
+  for (int i = 0; i < reps && r == RIFT2_OK; ++i) launch();
   if (r == RIFT2_OK) r = launch_status();
   if (r == RIFT2_OK && (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
                         hipEventElapsedTime(ms, a, b) != hipSuccess))

@@ -342,7 +342,8 @@ def test_mfma_calibration_validates_on_the_host():
     _l, lib = _lib()
     ms = ctypes.c_float(0.0)
     sink = ctypes.c_void_p(0x1000)
-    for w, it, reps, snk, out in ((0, 10, 1, sink, ctypes.byref(ms)), (5, 10, 1, sink, ctypes.byref(ms)),
-                                  (3, 0, 1, sink, ctypes.byref(ms)), (3, 10, 0, sink, ctypes.byref(ms)),
-                                  (3, 10, 1, None, ctypes.byref(ms)), (3, 10, 1, sink, None)):
-        assert lib.rift2_debug_mfma_rate(w, it, reps, snk, out, None) == _l.ERR_INVALID_ARG
+    for prec, w, it, reps, snk, out in ((0, 0, 10, 1, sink, ctypes.byref(ms)), (0, 5, 10, 1, sink, ctypes.byref(ms)),
+                                        (1, 3, 0, 1, sink, ctypes.byref(ms)), (1, 3, 10, 0, sink, ctypes.byref(ms)),
+                                        (0, 3, 10, 1, None, ctypes.byref(ms)), (0, 3, 10, 1, sink, None),
+                                        (2, 3, 10, 1, sink, ctypes.byref(ms)), (-1, 3, 10, 1, sink, ctypes.byref(ms))):
+        assert lib.rift2_debug_mfma_rate(prec, w, it, reps, snk, out, None) == _l.ERR_INVALID_ARG

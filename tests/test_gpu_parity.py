@@ -490,12 +490,14 @@ def test_end_to_end_pair_agreement():
     assert len(want) > 100 and jac > 0.9
 
 
-def test_mfma_calibration_stays_below_the_peak():
-    """rift2_debug_mfma_rate: register-only FP32 MFMA chains run at a sizeable fraction of the published
-    157.3 TFLOP/s and never above it; more waves per SIMD never run much slower."""
+@pytest.mark.parametrize("precision,peak", [(0, 157.3), (1, 2500.0)])
+def test_mfma_calibration_stays_below_the_peak(precision, peak):
+    """rift2_debug_mfma_rate: register-only FP32 / BF16 MFMA chains run at a sizeable fraction of the
+    published peak and never above it; more waves per SIMD never run much slower."""
     r2, dev = _gpu()
-    rates = [r2.mfma_f32_rate(w, iters=1000, reps=3) for w in (1, 2, 3, 4)]
-    print(f"[mfma calibration] TFLOP/s by waves per SIMD: {[round(r, 1) for r in rates]}", flush=True)
+    rates = [r2.mfma_rate(precision, w, iters=1000, reps=3) for w in (1, 2, 3, 4)]
+    print(f"[mfma calibration] precision {precision}: TFLOP/s by waves per SIMD {[round(r, 1) for r in rates]}",
+          flush=True)
     for r in rates:
-        assert 0.3 * 157.3 < r < 1.01 * 157.3
+        assert 0.3 * peak < r < 1.01 * peak
     assert rates[3] > 0.9 * rates[0]
