@@ -785,10 +785,14 @@ rift2_status rift2_debug_mfma_rate(int32_t precision, int32_t waves_per_simd, in
     return RIFT2_ERR_DEVICE;
   if (cus != kCalibCUs) return RIFT2_ERR_UNSUPPORTED;  // the sink's size assumes the full chip
   hipStream_t st = (hipStream_t)stream;
-  // a block of 4 waves per CU and wave per SIMD: every SIMD runs waves_per_simd chains
+  // waves_per_simd blocks of 4 waves per CU: every SIMD runs waves_per_simd waves
   const dim3 grid(kCalibCUs * waves_per_simd);
   hipEvent_t a = nullptr, b = nullptr;
-  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return RIFT2_ERR_DEVICE;
+  if (hipEventCreate(&a) != hipSuccess) return RIFT2_ERR_DEVICE;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return RIFT2_ERR_DEVICE;
+  }
   (void)hipGetLastError();
   auto launch = [&]() {
     if (precision == RIFT2_PREC_FP32)
